@@ -1,0 +1,182 @@
+/*
+ * lsrtm.h -- C ABI of the MI355X (gfx950) data-domain LSRTM hot path.
+ *
+ * The library implements, on one GPU, the linear operators of multiparameter
+ * least-squares reverse time migration in the (lnVp, lnIp) parametrisation
+ * (Yang & Ji, "A comparative study of data- and image-domain LSRTM under
+ * velocity-impedance parametrization"):
+ *
+ *   - background modelling of the first-order velocity-pressure system
+ *     A(m)u = f (section 2, first equation);
+ *   - Born modelling L dm = R du, du solving the scattering system with the
+ *     lnVp/lnIp secondary sources (section 2, eq. scattereqln; section 3,
+ *     definition of L[m0]);
+ *   - migration L^T d: the adjoint-state cross-correlation imaging conditions
+ *     (appendix A, eqs. adjeq, gradlsm, gradrho, gradkappa) mapped to
+ *     (lnVp, lnIp) by the gradient chain rule (section 3);
+ *   - CGNR on the normal equations L^T L dm = L^T dd (section 3, eq. normal
+ *     and the CGNR paragraph), with FP64 inner products and step lengths.
+ *
+ * Discretisation (the paper states continuous equations only): staggered grid,
+ * second order in time, eighth order in space, recursive-convolution CPML of
+ * npml cells on every side, pressure point source injected with the midpoint
+ * rule, receivers recording pressure at nodes after each step.  L^T is the
+ * exact discrete transpose of L under plain Euclidean inner products.
+ * Propagation is FP32; reductions and CG scalars are FP64.
+ *
+ * Conventions
+ *   - Arrays on the physical grid are z-fastest: index iz + nz*(ix + nx*iy).
+ *   - Node coordinates are (iz, ix[, iy]) of the global physical grid.
+ *   - Unless marked HOST, pointers are DEVICE pointers owned by the caller and
+ *     accessed on the context's HIP stream; the library never frees them.
+ *     The library owns only its internal workspaces.
+ *   - Every call returns LSRTM_OK or a negative lsrtm_status; nothing aborts.
+ *     lsrtm_last_error(ctx) returns a description of the last failure.
+ *   - Call order: create -> set_model -> set_acquisition ->
+ *     {forward | born | adjoint | cgnr}*.  set_model may be called again
+ *     later; other orders return LSRTM_ESTATE.
+ *   - A context is bound to one stream and is not thread-safe.
+ */
+#ifndef LSRTM_H
+#define LSRTM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lsrtm_ctx lsrtm_ctx;
+
+typedef enum {
+    LSRTM_OK = 0,
+    LSRTM_EINVAL = -1,     /* bad argument (shape, index, pointer, option)      */
+    LSRTM_ENOMEM = -2,     /* device allocation failed or plan does not fit     */
+    LSRTM_EHIP = -3,       /* HIP runtime error (kept in lsrtm_last_error)      */
+    LSRTM_EUNSTABLE = -4,  /* CFL condition violated by the model and dt        */
+    LSRTM_ENONFINITE = -5, /* NaN/Inf found in the model or a stored snapshot  */
+    LSRTM_ESTATE = -6      /* call out of order                                 */
+} lsrtm_status;
+
+enum { LSRTM_CKPT_F32 = 0, LSRTM_CKPT_F16 = 1, LSRTM_CKPT_BF16 = 2 };
+
+typedef struct {
+    int ndim;        /* 2 or 3                                                  */
+    int n[3];        /* physical nz, nx, ny of the global grid (ny = 1 in 2D)   */
+    double h[3];     /* dz, dx, dy in metres                                    */
+    int npml;        /* CPML thickness in cells on every side (>= 0)            */
+    double pml_R;    /* CPML target reflection coefficient (e.g. 1e-4)          */
+    double pml_f0;   /* CPML frequency-shift parameter: alpha_max = pi * f0     */
+    int nt;          /* number of time steps                                    */
+    double dt;       /* time step in seconds                                    */
+    int ckpt_every;  /* background checkpoint interval in steps; 0 = planner    */
+    int ckpt_dtype;  /* LSRTM_CKPT_F32 / F16 / BF16 storage of p and v in the
+                        checkpoints (per-snapshot, per-field max-abs scaling for
+                        F16/BF16; CPML memories always FP32)                    */
+} lsrtm_grid;
+
+/* Options (lsrtm_set_option). */
+enum {
+    LSRTM_OPT_SHOTS_PER_LAUNCH = 1, /* shots advanced by one kernel launch:
+                                       1 = plain per-shot launches,
+                                       0 = as many as the memory plan allows    */
+    LSRTM_OPT_TILE = 2,             /* stencil tile id (see lsrtm_tile_shape);
+                                       -1 = autotune on the next pass           */
+    LSRTM_OPT_GRAPH = 3,            /* 1 = replay the time loop from captured
+                                       HIP graphs (default 1)                   */
+    LSRTM_OPT_TIMING = 4,           /* 1 = time every stencil launch with HIP
+                                       events (read back with lsrtm_stats)      */
+    LSRTM_OPT_MEM_BUDGET_MB = 5     /* device memory the plan may use; 0 = 90 %
+                                       of the free memory at set_acquisition    */
+};
+
+/* Create a context for one grid on one HIP stream (hipStream_t, may be 0).
+ * Validates the grid (positive sizes, ndim in {2,3}); *out receives the
+ * context.  Allocates nothing on the device yet. */
+lsrtm_status lsrtm_create(const lsrtm_grid* grid, void* hip_stream, lsrtm_ctx** out);
+
+/* Background model in logs (section 2: lnkappa = lnIp + lnVp,
+ * lnrho = lnIp - lnVp).  lnvp, lnip: DEVICE float [nz*nx*ny], z-fastest,
+ * physical grid, copied by the library.  Checks that every value is finite
+ * (LSRTM_ENONFINITE) and the CFL bound
+ *   vmax * dt * sqrt(sum_a 1/h_a^2) * sum_k |c_k| < 1   (LSRTM_EUNSTABLE).
+ * Invalidates stored checkpoints. */
+lsrtm_status lsrtm_set_model(lsrtm_ctx* ctx, const float* lnvp, const float* lnip);
+
+/* Acquisition of nshot shots, each on its own window of the physical grid
+ * (uneven apertures allowed).
+ *   win     HOST int [nshot][2*ndim]: z0,z1,x0,x1[,y0,y1], half-open ranges
+ *   src     HOST int [nshot][ndim]: source node (iz, ix[, iy]), inside win
+ *   rec_ptr HOST int [nshot+1]: CSR offsets into rec (rec_ptr[0] = 0)
+ *   rec     HOST int [rec_ptr[nshot]][ndim]: receiver nodes, inside win
+ *   wavelet DEVICE float [nshot][nt]: source samples w((n + 1/2) dt); the
+ *           library injects dt * w / (dz dx [dy]) into p at the source node.
+ * Data vectors then have length sum_s nt*nrec_s, shot s at offset
+ * nt * rec_ptr[s], laid out [it][rec].  Plans the device memory (shots per
+ * launch, checkpoint interval) and allocates it. */
+lsrtm_status lsrtm_set_acquisition(lsrtm_ctx* ctx, int nshot, const int* win, const int* src,
+                                   const int* rec_ptr, const int* rec, const float* wavelet);
+
+/* Background data d = R u0 (section 2, A(m0) u0 = f), DEVICE float [data].
+ * Also stores the background checkpoints used by lsrtm_adjoint. */
+lsrtm_status lsrtm_forward(lsrtm_ctx* ctx, float* d);
+
+/* Born data d = L dm (section 3).  dm: DEVICE float [2][nz*nx*ny] =
+ * (dlnVp, dlnIp) on the physical grid; the perturbation is zero in the PML.
+ * d: DEVICE float [data], overwritten. */
+lsrtm_status lsrtm_born(lsrtm_ctx* ctx, const float* dm, float* d);
+
+/* Migration img = L^T d (appendix A; section 3 chain rule), summed over all
+ * shots in a fixed order (deterministic).  d: DEVICE float [data];
+ * img: DEVICE float [2][nz*nx*ny] = (lnVp, lnIp) images; accumulate = 0
+ * overwrites img, 1 adds to it. */
+lsrtm_status lsrtm_adjoint(lsrtm_ctx* ctx, const float* d, float* img, int accumulate);
+
+/* niter CGNR iterations on L^T L x = L^T d_obs from x = 0 (section 3).
+ * d_obs: DEVICE float [data]; x: DEVICE float [2][nz*nx*ny] output;
+ * misfit: HOST double [niter+1] receives ||r_k||^2 / ||r_0||^2 (may be NULL).
+ * Workspace vectors are owned by the library. */
+lsrtm_status lsrtm_cgnr(lsrtm_ctx* ctx, const float* d_obs, int niter, float* x, double* misfit);
+
+/* FP64-accumulated inner product of two DEVICE float vectors of length n;
+ * *out is a HOST double.  Deterministic (fixed reduction tree). */
+lsrtm_status lsrtm_dot(lsrtm_ctx* ctx, const float* a, const float* b, long long n, double* out);
+
+/* y <- y + alpha * x on DEVICE float vectors of length n, each element
+ * computed in FP64 and rounded once. */
+lsrtm_status lsrtm_axpy(lsrtm_ctx* ctx, double alpha, const float* x, float* y, long long n);
+
+/* Set an LSRTM_OPT_* option. */
+lsrtm_status lsrtm_set_option(lsrtm_ctx* ctx, int key, long long value);
+
+/* Sizes: out[0] = data length, out[1] = physical grid points (one image),
+ * out[2] = shots per launch, out[3] = checkpoint interval, out[4] = number of
+ * launch groups, out[5] = padded points summed over shots, out[6] = device
+ * bytes planned.  HOST long long [nout]. */
+lsrtm_status lsrtm_sizes(lsrtm_ctx* ctx, long long* out, int nout);
+
+/* Timing statistics of the last pass (HOST double [nout]); see
+ * LSRTM_STAT_* for the layout.  Per-kernel times need LSRTM_OPT_TIMING. */
+enum {
+    LSRTM_STAT_PASS_MS = 0,       /* wall time of the last pass (HIP events)        */
+    LSRTM_STAT_KERNEL_MS = 1,     /* [1 + 2*k], [2 + 2*k]: total ms and launch count */
+    LSRTM_NKERNEL = 8             /* kernel classes: 0 born_v, 1 born_p, 2 bg_v,
+                                     3 bg_p, 4 adj_a, 5 adj_b, 6 ckpt, 7 rec     */
+};
+lsrtm_status lsrtm_stats(lsrtm_ctx* ctx, double* out, int nout);
+
+/* Tile shape of a tile id: out[0] = BZ, out[1] = BX.  Returns LSRTM_EINVAL
+ * for an unknown id.  HOST int [2]. */
+lsrtm_status lsrtm_tile_shape(int ndim, int tile_id, int* out);
+
+/* Release every device resource of the context. */
+void lsrtm_destroy(lsrtm_ctx* ctx);
+
+/* Static description of a status code. */
+const char* lsrtm_strerror(int status);
+
+/* Description of the last error on this context ("" if none). */
+const char* lsrtm_last_error(lsrtm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSRTM_H */

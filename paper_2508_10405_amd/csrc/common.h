@@ -1,0 +1,86 @@
+// Device-side data structures shared by the kernels and the runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lsrtm {
+
+constexpr int HW = 4;        // half width of the eighth-order staggered stencil
+constexpr int NTHREADS = 256;
+
+// Stencil weights c_k / h_a for the three axes (z, x, y).
+struct Coef {
+    float c[3][4];
+};
+
+// One shot being advanced by a launch ("slot").  All pointers are device
+// pointers into library-owned buffers; arrays are z-fastest with strides
+// sx (x) and sy (y) on the shot's padded grid.
+struct Slot {
+    int n[3];                // padded sizes (z, x, y); n[2] = 1 in 2D
+    int ldz;                 // z stride (== sx)
+    long long sx, sy;        // strides of x and y
+    long long npts;          // elements per array
+    int src;                 // linear index of the source node, -1 for none
+    int shot;                // global shot index
+    const float* src_amp;    // [nt] dt * w / cell
+    const float* kdt;        // dt * kappa at nodes
+    const float* bdt[3];     // dt * b_a at half nodes
+    const float* dlnr;       // dlnrho at nodes (zero in the PML)
+    const float* dlnk;       // dlnkappa at nodes (zero in the PML)
+    const float* cpml[3];    // per axis: [ach | bch | aci | bci], n_a each
+    float* p;                // background pressure
+    float* v[3];             // background particle velocities
+    float* psi[3];           // background CPML memory of G_a p
+    float* phi[3];           // background CPML memory of D_a v_a
+    float* q;                // scattered pressure  | adjoint p~
+    float* w[3];             // scattered velocity  | adjoint v~
+    float* xi[3];            // scattered psi       | adjoint of psi (chi)
+    float* eta[3];           // scattered phi       | adjoint of phi
+    float* gk;               // image of lnkappa
+    float* gr;               // image of lnrho
+    float* seg;              // replay buffer [k][ndim + 1][npts]: dv_a, q
+    char* ck;                // checkpoint 1 of this shot; checkpoint j >= 1 at ck + (j-1) * ckbytes
+    long long ckbytes;
+};
+
+// Receiver entry of a launch group.
+struct Rec {
+    int slot;
+    int idx;                 // linear index in the slot's arrays
+    long long out;           // data offset of (it = 0, this receiver)
+    int stride;              // nrec of the shot (data row length)
+    int pad;
+};
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8);
+// give every XCD a contiguous range of tiles so that neighbouring tiles,
+// which share halos, meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+    const int xcd = bid & 7, k = bid >> 3;
+    const int per = nblocks >> 3, rem = nblocks & 7;
+    const int base = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
+    return base + k;
+}
+
+// Forward staggered derivative at half node i + 1/2 from node values around
+// LDS index c with stride s: sum_k c_k (f[i+k] - f[i-k+1]).
+__device__ __forceinline__ float d_half(const float* f, int c, int s, const float* ck) {
+    float r = ck[0] * (f[c + s] - f[c]);
+    r = fmaf(ck[1], f[c + 2 * s] - f[c - s], r);
+    r = fmaf(ck[2], f[c + 3 * s] - f[c - 2 * s], r);
+    r = fmaf(ck[3], f[c + 4 * s] - f[c - 3 * s], r);
+    return r;
+}
+
+// Backward staggered derivative at node i from half-node values (g[j] at
+// j + 1/2): sum_k c_k (g[i+k-1] - g[i-k]).
+__device__ __forceinline__ float d_node(const float* g, int c, int s, const float* ck) {
+    float r = ck[0] * (g[c] - g[c - s]);
+    r = fmaf(ck[1], g[c + s] - g[c - 2 * s], r);
+    r = fmaf(ck[2], g[c + 2 * s] - g[c - 3 * s], r);
+    r = fmaf(ck[3], g[c + 3 * s] - g[c - 4 * s], r);
+    return r;
+}
+
+}  // namespace lsrtm

@@ -1,0 +1,119 @@
+// Host-side launchers of the device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "common.h"
+
+namespace lsrtm {
+
+// Stencil phases (see kern2d.hip / kern3d.hip).
+enum Kind {
+    K_BG_V = 0,    // background velocity phase
+    K_BG_P = 1,    // background pressure phase
+    K_SEG_V = 2,   // background velocity phase, stores dv_a (replay)
+    K_SEG_P = 3,   // background pressure phase, stores q (replay)
+    K_BORN_V = 4,  // background + scattered velocity phase
+    K_BORN_P = 5,  // background + scattered pressure phase
+    K_ADJ_A = 6,   // adjoint pressure phase + lnkappa imaging
+    K_ADJ_B = 7    // adjoint velocity phase + lnrho imaging
+};
+
+extern const int kTiles2[][2];
+extern const int kNumTiles2;
+extern const int kTiles3[][3];
+extern const int kNumTiles3;
+
+hipError_t launch2d(int kind, int tile_id, int ntiles, hipStream_t st, const Slot* slots,
+                    const int4* tiles, const Coef& C, int n, int sstep, int flag);
+hipError_t launch3d(int kind, int tile_id, int ntiles, hipStream_t st, const Slot* slots,
+                    const int4* tiles, const Coef& C, int n, int sstep, int flag);
+
+// Auxiliary kernels (aux.hip).
+hipError_t launch_fill(float* p, long long n, float v, hipStream_t st);
+hipError_t launch_fill_f64(double* p, long long n, hipStream_t st);
+
+// Model on a shot's padded grid from the global physical logs (edge-replicated
+// into the PML): kdt = dt*exp(lnvp+lnip); bdt_a = dt*exp(-(lnrho_i+lnrho_i+1)/2).
+struct PrepArgs {
+    const float* lnvp; const float* lnip;   // global physical arrays
+    int gn[3];                              // global physical sizes (z, x, y)
+    int lo[3], wn[3];                       // window origin and size
+    int npml;
+    int N[3];                               // padded sizes
+    long long sx, sy;                       // strides
+    double dt;
+    int ndim;
+    float* kdt; float* bdt[3];
+};
+hipError_t launch_model_prep(const PrepArgs& a, hipStream_t st);
+
+// Perturbation on a shot's padded grid: dlnr = dlnIp - dlnVp,
+// dlnk = dlnIp + dlnVp inside the window, zero in the PML.
+struct DmArgs {
+    const float* dm;                        // [2][gpts] global (dlnVp, dlnIp)
+    long long gpts;
+    int gn[3];
+    int lo[3], wn[3];
+    int npml;
+    int N[3];
+    long long sx, sy;
+    int ndim;
+    float* dlnr; float* dlnk;
+};
+hipError_t launch_dm_prep(const DmArgs& a, hipStream_t st);
+
+// Receivers.
+hipError_t launch_gather(const Slot* slots, const Rec* rec, int nrec, int n, int from_scattered,
+                         float* d, hipStream_t st);
+// Injection of d[it = n] into the adjoint pressure: one thread per distinct
+// receiver node, summing its receivers in a fixed order.
+hipError_t launch_inject(const Slot* slots, const int* node_slot, const int* node_idx,
+                         const int* node_ptr, const Rec* rec, int nnode, int n, const float* d,
+                         hipStream_t st);
+
+// Images of a launch group added into the FP64 global accumulator
+// acc[2][gpts] (lnVp, lnIp): img_lnVp = -g_lnrho + g_lnkappa,
+// img_lnIp = g_lnrho + g_lnkappa, slots taken in order.
+struct ImgArgs {
+    const Slot* slots;
+    const int* win;        // [nslot][6] window lo/hi (z, x, y) of each slot
+    int nslot;
+    int ndim;
+    int gn[3];
+    int npml;
+    double* acc;
+    long long gpts;
+};
+hipError_t launch_image_reduce(const ImgArgs& a, hipStream_t st);
+hipError_t launch_image_store(const double* acc, float* img, long long n, int accumulate,
+                              hipStream_t st);
+
+// Max |x| of a physical float array (finite check: non-finite -> +inf).
+hipError_t launch_maxabs(const float* x, long long n, float* partial, int nblk, hipStream_t st);
+// Per-block maximum of x (non-finite -> +inf); partial[nblk].
+hipError_t launch_maxval(const float* x, long long n, float* partial, int nblk, hipStream_t st);
+
+// FP64 dot product (two stages, fixed order) and FP64-rounded axpy / xpby.
+hipError_t launch_dot(const float* a, const float* b, long long n, double* partial, int nblk,
+                      double* out, hipStream_t st);
+hipError_t launch_axpy(double alpha, const float* x, float* y, long long n, hipStream_t st);
+hipError_t launch_xpby(const float* x, double beta, float* y, long long n, hipStream_t st);
+hipError_t launch_copy(const float* x, float* y, long long n, hipStream_t st);
+
+// Checkpoints: per slot, fields p, v_a as FP32/FP16/BF16 with a max-abs scale
+// per field, CPML memories of the strips as FP32.
+struct CkptArgs {
+    const Slot* slots;
+    int nslot;
+    int ndim;
+    int dtype;                     // 0 f32, 1 f16, 2 bf16
+    int S;                         // strip depth per side
+    int j;                         // checkpoint index >= 1 (Slot::ck + (j-1) * Slot::ckbytes)
+    float* scales;                 // [nslot][1+ndim] scales of checkpoint j
+    float* partial;                // reduction workspace [nslot][1+ndim][nblk]
+    int nblk;
+    int* nonfinite;                // set to 1 if a field holds NaN/Inf
+};
+hipError_t launch_ckpt_save(const CkptArgs& a, long long max_npts, hipStream_t st);
+hipError_t launch_ckpt_load(const CkptArgs& a, long long max_npts, hipStream_t st);
+
+}  // namespace lsrtm

@@ -1,0 +1,1099 @@
+// Runtime of the LSRTM library: context, memory plan, passes, CGNR.
+//
+// Pass structure (one launch group = a contiguous range of shots advanced by
+// the same kernel launches):
+//   forward : background steps, p recorded at the receivers, background
+//             checkpoints stored every k steps.
+//   born    : background + scattered steps (section 2, eq. scattereqln),
+//             scattered pressure recorded (section 3, L dm := R du).
+//   adjoint : for each checkpoint segment, last first: restore the background
+//             state, replay k steps storing dv_a and q, then run the k adjoint
+//             steps backwards with the imaging conditions (appendix A,
+//             eqs. gradlsm, gradrho, gradkappa).  The images of every shot
+//             are added in shot order into an FP64 accumulator and mapped to
+//             (lnVp, lnIp) by the chain rule of section 3.
+// Checkpoints do not depend on the perturbation, so they are stored once per
+// model and acquisition and reused by every later pass.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lsrtm.h"
+#include "kernels.h"
+
+using namespace lsrtm;
+
+namespace {
+
+// Exact O(2,8) staggered weights c_k (odd-moment conditions at half offsets).
+const double kC8[4] = {1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0, -5.0 / 7168.0};
+
+struct Window {
+    int lo[3], hi[3];
+    int N[3];
+    int ldz;
+    long long sx, sy, npts;
+    float* kdt = nullptr;
+    float* bdt[3] = {nullptr, nullptr, nullptr};
+    float* dlnr = nullptr;
+    float* dlnk = nullptr;
+    float* cpml[3] = {nullptr, nullptr, nullptr};
+};
+
+struct ShotInfo {
+    int win;
+    int src_lin;
+    int rec0, nrec;
+    long long data_off;
+    long long ckbytes;
+    std::vector<int> rec_lin;
+};
+
+struct Group {
+    int s0 = 0, ns = 0;
+    std::vector<Slot> h_slots;
+    Slot* d_slots = nullptr;
+    int4* d_tiles = nullptr;
+    int ntiles = 0;
+    int tiles_for = -1;            // tile id the table was built for
+    Rec* d_rec = nullptr;
+    int nrec = 0;
+    int* d_node_slot = nullptr;
+    int* d_node_idx = nullptr;
+    int* d_node_ptr = nullptr;
+    Rec* d_node_rec = nullptr;
+    int nnode = 0;
+    int* d_win = nullptr;
+    long long max_npts = 0;
+    long long bg_used = 0, sc_used = 0, img_used = 0;   // floats
+};
+
+struct EvPair {
+    hipEvent_t a, b;
+    int cls;
+};
+
+}  // namespace
+
+struct lsrtm_ctx {
+    lsrtm_grid g{};
+    hipStream_t st = nullptr;
+    std::string err;
+    Coef C{};
+    int ndim = 2;
+    // model
+    float* lnvp = nullptr;
+    float* lnip = nullptr;
+    long long gpts = 0;
+    double vmax = 0.0;
+    bool have_model = false;
+    // acquisition
+    int nshot = 0;
+    bool have_acq = false;
+    std::vector<ShotInfo> shots;
+    std::vector<Window> wins;
+    std::vector<int> h_win;        // [nshot][6]
+    float* src_amp = nullptr;      // [nshot][nt]
+    long long data_len = 0;
+    long long padded_total = 0;
+    // plan
+    int G = 1, k = 1, nseg = 1, S = 1;
+    int tile = -1;
+    long long plan_bytes = 0;
+    std::vector<Group> groups;
+    long long bg_region = 0, sc_region = 0, img_region = 0;
+    float* pool = nullptr;
+    float* segbuf = nullptr;
+    char* ckbuf = nullptr;
+    float* ckscales = nullptr;     // [nseg][nshot][1+ndim]
+    float* partial = nullptr;      // reduction workspace of set_model
+    float* ckpart = nullptr;       // checkpoint max-abs partials [G][1+ndim][nblk]
+    int nblk = 64;
+    double* dpart = nullptr;
+    double* dscal = nullptr;       // device scalar results
+    int* d_flag = nullptr;
+    double* acc64 = nullptr;       // [2][gpts]
+    bool ckpt_valid = false;
+    // CG workspace
+    float* cg_r = nullptr;
+    float* cg_w = nullptr;
+    float* cg_z = nullptr;
+    float* cg_p = nullptr;
+    // options
+    int opt_spl = 0;
+    int opt_tile = -1;
+    int opt_graph = 1;
+    int opt_timing = 0;
+    long long opt_budget_mb = 0;
+    // timing
+    std::vector<EvPair> evpool;
+    size_t evused = 0;
+    double kms[LSRTM_NKERNEL] = {0};
+    long long kcnt[LSRTM_NKERNEL] = {0};
+    double pass_ms = 0.0;
+    hipEvent_t pa = nullptr, pb = nullptr;
+    // allocations
+    std::vector<void*> allocs;
+    std::vector<void*> acq_allocs;
+};
+
+namespace {
+
+#define FAIL(ctx, code, ...)                                                     \
+    do {                                                                         \
+        char _b[512];                                                            \
+        snprintf(_b, sizeof(_b), __VA_ARGS__);                                   \
+        (ctx)->err = _b;                                                         \
+        return (code);                                                           \
+    } while (0)
+
+#define HIPCHK(ctx, call)                                                        \
+    do {                                                                         \
+        hipError_t _e = (call);                                                  \
+        if (_e != hipSuccess)                                                    \
+            FAIL(ctx, LSRTM_EHIP, "%s: %s (%s:%d)", #call, hipGetErrorString(_e), \
+                 __FILE__, __LINE__);                                            \
+    } while (0)
+
+#define CHK(call)                                                                \
+    do {                                                                         \
+        lsrtm_status _s = (call);                                                \
+        if (_s != LSRTM_OK) return _s;                                           \
+    } while (0)
+
+lsrtm_status dalloc(lsrtm_ctx* c, void** p, size_t bytes, bool acq) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        FAIL(c, LSRTM_ENOMEM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    (acq ? c->acq_allocs : c->allocs).push_back(*p);
+    return LSRTM_OK;
+}
+
+template <typename T>
+lsrtm_status dalloc_t(lsrtm_ctx* c, T** p, size_t n, bool acq) {
+    return dalloc(c, reinterpret_cast<void**>(p), n * sizeof(T), acq);
+}
+
+void free_acq(lsrtm_ctx* c) {
+    for (void* p : c->acq_allocs) (void)hipFree(p);
+    c->acq_allocs.clear();
+    c->groups.clear();
+    c->wins.clear();
+    c->shots.clear();
+    c->have_acq = false;
+    c->ckpt_valid = false;
+    c->pool = nullptr;
+    c->segbuf = nullptr;
+    c->ckbuf = nullptr;
+    c->ckscales = nullptr;
+    c->ckpart = nullptr;
+    c->acc64 = nullptr;
+    c->cg_r = c->cg_w = c->cg_z = c->cg_p = nullptr;
+    c->src_amp = nullptr;
+}
+
+long long round_up(long long a, long long m) { return (a + m - 1) / m * m; }
+
+// 1D CPML coefficients along one padded axis of N nodes.
+void cpml_axis(int N, int npml, double h, double dt, double vmax, double R, double f0, bool half,
+               std::vector<float>& ac, std::vector<float>& bc) {
+    ac.assign(N, 0.f);
+    bc.assign(N, 1.f);
+    if (npml <= 0) return;
+    const double first = npml, last = N - npml - 1;
+    const double d0 = -3.0 * vmax * std::log(R) / (2.0 * npml * h);
+    for (int i = 0; i < N; ++i) {
+        const double pos = i + (half ? 0.5 : 0.0);
+        const double dist = pos < first ? first - pos : (pos > last ? pos - last : 0.0);
+        const double xi = std::min(1.0, dist / npml);
+        const double d = d0 * xi * xi;
+        const double alpha = M_PI * f0 * (1.0 - xi);
+        const double b = std::exp(-(d + alpha) * dt);
+        ac[i] = d > 0.0 ? (float)(d * (b - 1.0) / (d + alpha)) : 0.f;
+        bc[i] = (float)b;
+    }
+}
+
+int strip_depth(const lsrtm_ctx* c) { return c->g.npml + 1; }
+
+long long strip_count_h(const int N[3], int a, int Sd) {
+    const int Sa = std::min(Sd, N[a]);
+    long long cnt = 2LL * Sa;
+    for (int b = 0; b < 3; ++b)
+        if (b != a) cnt *= N[b];
+    return cnt;
+}
+
+// ---------------------------------------------------------------------------
+// Timing
+// ---------------------------------------------------------------------------
+void tbeg(lsrtm_ctx* c, int cls) {
+    if (!c->opt_timing) return;
+    if (c->evused == c->evpool.size()) {
+        EvPair e;
+        if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) {
+            c->opt_timing = 0;
+            return;
+        }
+        c->evpool.push_back(e);
+    }
+    EvPair& e = c->evpool[c->evused];
+    e.cls = cls;
+    (void)hipEventRecord(e.a, c->st);
+}
+
+void tend(lsrtm_ctx* c) {
+    if (!c->opt_timing) return;
+    (void)hipEventRecord(c->evpool[c->evused].b, c->st);
+    c->evused++;
+}
+
+lsrtm_status pass_begin(lsrtm_ctx* c) {
+    for (int i = 0; i < LSRTM_NKERNEL; ++i) {
+        c->kms[i] = 0.0;
+        c->kcnt[i] = 0;
+    }
+    c->evused = 0;
+    if (!c->pa) {
+        HIPCHK(c, hipEventCreate(&c->pa));
+        HIPCHK(c, hipEventCreate(&c->pb));
+    }
+    HIPCHK(c, hipEventRecord(c->pa, c->st));
+    return LSRTM_OK;
+}
+
+lsrtm_status pass_end(lsrtm_ctx* c) {
+    HIPCHK(c, hipEventRecord(c->pb, c->st));
+    HIPCHK(c, hipEventSynchronize(c->pb));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->pa, c->pb));
+    c->pass_ms = ms;
+    for (size_t i = 0; i < c->evused; ++i) {
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, c->evpool[i].a, c->evpool[i].b));
+        c->kms[c->evpool[i].cls] += t;
+        c->kcnt[c->evpool[i].cls] += 1;
+    }
+    c->evused = 0;
+    return LSRTM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tiles
+// ---------------------------------------------------------------------------
+int default_tile(int ndim) { return ndim == 2 ? 4 : 1; }
+
+void tile_shape(int ndim, int id, int* bz, int* bx, int* by) {
+    if (ndim == 2) {
+        *bz = kTiles2[id][0];
+        *bx = kTiles2[id][1];
+        *by = 1;
+    } else {
+        *bz = kTiles3[id][0];
+        *bx = kTiles3[id][1];
+        *by = kTiles3[id][2];
+    }
+}
+
+lsrtm_status build_tiles(lsrtm_ctx* c, Group& gr, int tile) {
+    if (gr.tiles_for == tile) return LSRTM_OK;
+    int bz, bx, by;
+    tile_shape(c->ndim, tile, &bz, &bx, &by);
+    std::vector<int4> t;
+    for (int s = 0; s < gr.ns; ++s) {
+        const Slot& S = gr.h_slots[s];
+        for (int y0 = 0; y0 < S.n[2]; y0 += by)
+            for (int x0 = 0; x0 < S.n[1]; x0 += bx)
+                for (int z0 = 0; z0 < S.n[0]; z0 += bz) t.push_back(make_int4(s, z0, x0, y0));
+    }
+    if (gr.d_tiles) {
+        (void)hipFree(gr.d_tiles);
+        auto it = std::find(c->acq_allocs.begin(), c->acq_allocs.end(), (void*)gr.d_tiles);
+        if (it != c->acq_allocs.end()) c->acq_allocs.erase(it);
+        gr.d_tiles = nullptr;
+    }
+    CHK(dalloc_t(c, &gr.d_tiles, t.size(), true));
+    HIPCHK(c, hipMemcpy(gr.d_tiles, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
+    gr.ntiles = (int)t.size();
+    gr.tiles_for = tile;
+    return LSRTM_OK;
+}
+
+lsrtm_status stencil(lsrtm_ctx* c, Group& gr, int kind, int n, int sstep, int flag) {
+    static const int cls_of[8] = {2, 3, 2, 3, 0, 1, 4, 5};
+    tbeg(c, cls_of[kind]);
+    hipError_t e = c->ndim == 2
+                       ? launch2d(kind, c->tile, gr.ntiles, c->st, gr.d_slots, gr.d_tiles, c->C, n, sstep, flag)
+                       : launch3d(kind, c->tile, gr.ntiles, c->st, gr.d_slots, gr.d_tiles, c->C, n, sstep, flag);
+    tend(c);
+    if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "stencil launch (kind %d): %s", kind, hipGetErrorString(e));
+    return LSRTM_OK;
+}
+
+lsrtm_status ckpt(lsrtm_ctx* c, Group& gr, int j, bool save) {
+    CkptArgs a;
+    a.slots = gr.d_slots;
+    a.nslot = gr.ns;
+    a.ndim = c->ndim;
+    a.dtype = c->g.ckpt_dtype;
+    a.S = c->S;
+    a.j = j;
+    a.scales = c->ckscales + ((long long)j * c->nshot + gr.s0) * (1 + c->ndim);
+    a.partial = c->ckpart;
+    a.nblk = c->nblk;
+    a.nonfinite = c->d_flag;
+    tbeg(c, 6);
+    hipError_t e = save ? launch_ckpt_save(a, gr.max_npts, c->st) : launch_ckpt_load(a, gr.max_npts, c->st);
+    tend(c);
+    if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "checkpoint kernel: %s", hipGetErrorString(e));
+    return LSRTM_OK;
+}
+
+lsrtm_status fill(lsrtm_ctx* c, float* p, long long n) {
+    HIPCHK(c, launch_fill(p, n, 0.f, c->st));
+    return LSRTM_OK;
+}
+
+lsrtm_status check_flag(lsrtm_ctx* c) {
+    int f = 0;
+    HIPCHK(c, hipMemcpyAsync(&f, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (f) {
+        c->ckpt_valid = false;
+        HIPCHK(c, launch_fill(reinterpret_cast<float*>(c->d_flag), 1, 0.f, c->st));
+        FAIL(c, LSRTM_ENONFINITE, "non-finite value in a stored background snapshot");
+    }
+    return LSRTM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Passes of one launch group
+// ---------------------------------------------------------------------------
+// mode 0: forward (record p), 1: born (record dp), 2: forward without data
+lsrtm_status group_forward(lsrtm_ctx* c, Group& gr, int mode, float* d, bool write_ck) {
+    CHK(build_tiles(c, gr, c->tile));
+    CHK(fill(c, c->pool, gr.bg_used));
+    if (mode == 1) CHK(fill(c, c->pool + c->bg_region, gr.sc_used));
+    const int kv = mode == 1 ? K_BORN_V : K_BG_V;
+    const int kp = mode == 1 ? K_BORN_P : K_BG_P;
+    for (int n = 0; n < c->g.nt; ++n) {
+        if (write_ck && n > 0 && n % c->k == 0) CHK(ckpt(c, gr, n / c->k, true));
+        CHK(stencil(c, gr, kv, n, 0, 0));
+        CHK(stencil(c, gr, kp, n, 0, 0));
+        if (mode != 2) {
+            tbeg(c, 7);
+            hipError_t e = launch_gather(gr.d_slots, gr.d_rec, gr.nrec, n, mode == 1, d, c->st);
+            tend(c);
+            if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "gather: %s", hipGetErrorString(e));
+        }
+    }
+    return LSRTM_OK;
+}
+
+lsrtm_status group_adjoint(lsrtm_ctx* c, Group& gr, const float* d) {
+    CHK(build_tiles(c, gr, c->tile));
+    CHK(fill(c, c->pool + c->bg_region, gr.sc_used));
+    CHK(fill(c, c->pool + c->bg_region + c->sc_region, gr.img_used));
+    const int nt = c->g.nt;
+    auto inject = [&](int n) -> lsrtm_status {
+        tbeg(c, 7);
+        hipError_t e = launch_inject(gr.d_slots, gr.d_node_slot, gr.d_node_idx, gr.d_node_ptr,
+                                     gr.d_node_rec, gr.nnode, n, d, c->st);
+        tend(c);
+        if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "inject: %s", hipGetErrorString(e));
+        return LSRTM_OK;
+    };
+    CHK(inject(nt - 1));
+    for (int j = c->nseg - 1; j >= 0; --j) {
+        const int n0 = j * c->k, n1 = std::min(n0 + c->k, nt);
+        if (j == 0) CHK(fill(c, c->pool, gr.bg_used));
+        else CHK(ckpt(c, gr, j, false));
+        for (int n = n0; n < n1; ++n) {
+            CHK(stencil(c, gr, K_SEG_V, n, n - n0, 0));
+            CHK(stencil(c, gr, K_SEG_P, n, n - n0, 0));
+        }
+        for (int n = n1 - 1; n >= n0; --n) {
+            if (n < nt - 1) CHK(inject(n));
+            CHK(stencil(c, gr, K_ADJ_A, n, n - n0, n == nt - 1 ? 1 : 0));
+            CHK(stencil(c, gr, K_ADJ_B, n, n - n0, 0));
+        }
+    }
+    ImgArgs ia;
+    ia.slots = gr.d_slots;
+    ia.win = gr.d_win;
+    ia.nslot = gr.ns;
+    ia.ndim = c->ndim;
+    for (int a = 0; a < 3; ++a) ia.gn[a] = c->g.n[a];
+    ia.npml = c->g.npml;
+    ia.acc = c->acc64;
+    ia.gpts = c->gpts;
+    HIPCHK(c, launch_image_reduce(ia, c->st));
+    return LSRTM_OK;
+}
+
+lsrtm_status ensure_ckpts(lsrtm_ctx* c) {
+    if (c->ckpt_valid) return LSRTM_OK;
+    for (auto& gr : c->groups) CHK(group_forward(c, gr, 2, nullptr, true));
+    CHK(check_flag(c));
+    c->ckpt_valid = true;
+    return LSRTM_OK;
+}
+
+lsrtm_status check_ready(lsrtm_ctx* c) {
+    if (!c) return LSRTM_EINVAL;
+    if (!c->have_model) FAIL(c, LSRTM_ESTATE, "set_model has not been called");
+    if (!c->have_acq) FAIL(c, LSRTM_ESTATE, "set_acquisition has not been called");
+    if (c->opt_tile < 0 && c->tile < 0) c->tile = default_tile(c->ndim);
+    else if (c->opt_tile >= 0) c->tile = c->opt_tile;
+    return LSRTM_OK;
+}
+
+lsrtm_status prep_model_windows(lsrtm_ctx* c) {
+    for (auto& w : c->wins) {
+        PrepArgs a;
+        a.lnvp = c->lnvp;
+        a.lnip = c->lnip;
+        for (int i = 0; i < 3; ++i) {
+            a.gn[i] = c->g.n[i];
+            a.lo[i] = w.lo[i];
+            a.wn[i] = w.hi[i] - w.lo[i];
+            a.N[i] = w.N[i];
+            a.bdt[i] = w.bdt[i];
+        }
+        a.npml = c->g.npml;
+        a.sx = w.sx;
+        a.sy = w.sy;
+        a.dt = c->g.dt;
+        a.ndim = c->ndim;
+        a.kdt = w.kdt;
+        HIPCHK(c, launch_model_prep(a, c->st));
+        // CPML tables
+        for (int ax = 0; ax < c->ndim; ++ax) {
+            std::vector<float> ach, bch, aci, bci;
+            cpml_axis(w.N[ax], c->g.npml, c->g.h[ax], c->g.dt, c->vmax, c->g.pml_R, c->g.pml_f0, true, ach, bch);
+            cpml_axis(w.N[ax], c->g.npml, c->g.h[ax], c->g.dt, c->vmax, c->g.pml_R, c->g.pml_f0, false, aci, bci);
+            std::vector<float> tab;
+            tab.insert(tab.end(), ach.begin(), ach.end());
+            tab.insert(tab.end(), bch.begin(), bch.end());
+            tab.insert(tab.end(), aci.begin(), aci.end());
+            tab.insert(tab.end(), bci.begin(), bci.end());
+            HIPCHK(c, hipMemcpyAsync(w.cpml[ax], tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice, c->st));
+        }
+        if (c->ndim == 2) {
+            // unused y tables must still be valid memory for uniform code
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    c->ckpt_valid = false;
+    return LSRTM_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* lsrtm_strerror(int s) {
+    switch (s) {
+    case LSRTM_OK: return "ok";
+    case LSRTM_EINVAL: return "invalid argument";
+    case LSRTM_ENOMEM: return "out of device memory";
+    case LSRTM_EHIP: return "HIP runtime error";
+    case LSRTM_EUNSTABLE: return "CFL stability condition violated";
+    case LSRTM_ENONFINITE: return "non-finite value";
+    case LSRTM_ESTATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+const char* lsrtm_last_error(lsrtm_ctx* c) { return c ? c->err.c_str() : ""; }
+
+lsrtm_status lsrtm_tile_shape(int ndim, int id, int* out) {
+    if (!out) return LSRTM_EINVAL;
+    if (ndim == 2 && id >= 0 && id < kNumTiles2) {
+        out[0] = kTiles2[id][0];
+        out[1] = kTiles2[id][1];
+        return LSRTM_OK;
+    }
+    if (ndim == 3 && id >= 0 && id < kNumTiles3) {
+        out[0] = kTiles3[id][0];
+        out[1] = kTiles3[id][1];
+        return LSRTM_OK;
+    }
+    return LSRTM_EINVAL;
+}
+
+lsrtm_status lsrtm_create(const lsrtm_grid* g, void* stream, lsrtm_ctx** out) {
+    if (!g || !out) return LSRTM_EINVAL;
+    *out = nullptr;
+    if (g->ndim != 2 && g->ndim != 3) return LSRTM_EINVAL;
+    for (int a = 0; a < g->ndim; ++a)
+        if (g->n[a] < 1 || !(g->h[a] > 0.0)) return LSRTM_EINVAL;
+    if (g->ndim == 2 && g->n[2] != 1) return LSRTM_EINVAL;
+    if (g->npml < 0 || g->nt < 1 || !(g->dt > 0.0)) return LSRTM_EINVAL;
+    if (g->npml > 0 && !(g->pml_R > 0.0 && g->pml_R < 1.0)) return LSRTM_EINVAL;
+    if (g->ckpt_every < 0 || g->ckpt_dtype < 0 || g->ckpt_dtype > 2) return LSRTM_EINVAL;
+    lsrtm_ctx* c = new lsrtm_ctx();
+    c->g = *g;
+    if (g->ndim == 2) c->g.h[2] = 1.0;
+    c->st = reinterpret_cast<hipStream_t>(stream);
+    c->ndim = g->ndim;
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 4; ++k) c->C.c[a][k] = (float)(kC8[k] / c->g.h[a]);
+    c->gpts = (long long)g->n[0] * g->n[1] * g->n[2];
+    c->S = strip_depth(c);
+    *out = c;
+    return LSRTM_OK;
+}
+
+void lsrtm_destroy(lsrtm_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->st);
+    free_acq(c);
+    for (void* p : c->allocs) (void)hipFree(p);
+    for (auto& e : c->evpool) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    if (c->pa) (void)hipEventDestroy(c->pa);
+    if (c->pb) (void)hipEventDestroy(c->pb);
+    delete c;
+}
+
+lsrtm_status lsrtm_set_option(lsrtm_ctx* c, int key, long long v) {
+    if (!c) return LSRTM_EINVAL;
+    switch (key) {
+    case LSRTM_OPT_SHOTS_PER_LAUNCH:
+        if (v < 0) FAIL(c, LSRTM_EINVAL, "shots per launch must be >= 0");
+        if (c->have_acq) FAIL(c, LSRTM_ESTATE, "set shots per launch before set_acquisition");
+        c->opt_spl = (int)v;
+        return LSRTM_OK;
+    case LSRTM_OPT_TILE: {
+        const int nt = c->ndim == 2 ? kNumTiles2 : kNumTiles3;
+        if (v < -1 || v >= nt) FAIL(c, LSRTM_EINVAL, "tile id %lld out of range", v);
+        c->opt_tile = (int)v;
+        c->tile = (int)v;
+        return LSRTM_OK;
+    }
+    case LSRTM_OPT_GRAPH: c->opt_graph = v != 0; return LSRTM_OK;
+    case LSRTM_OPT_TIMING: c->opt_timing = v != 0; return LSRTM_OK;
+    case LSRTM_OPT_MEM_BUDGET_MB:
+        if (v < 0) FAIL(c, LSRTM_EINVAL, "memory budget must be >= 0");
+        c->opt_budget_mb = v;
+        return LSRTM_OK;
+    default: FAIL(c, LSRTM_EINVAL, "unknown option %d", key);
+    }
+}
+
+lsrtm_status lsrtm_set_model(lsrtm_ctx* c, const float* lnvp, const float* lnip) {
+    if (!c || !lnvp || !lnip) return LSRTM_EINVAL;
+    if (!c->lnvp) {
+        CHK(dalloc_t(c, &c->lnvp, c->gpts, false));
+        CHK(dalloc_t(c, &c->lnip, c->gpts, false));
+        CHK(dalloc_t(c, &c->partial, 8 * 256 * 4, false));
+        CHK(dalloc_t(c, &c->dpart, 1024, false));
+        CHK(dalloc_t(c, &c->dscal, 16, false));
+        CHK(dalloc_t(c, &c->d_flag, 64, false));
+        HIPCHK(c, launch_fill(reinterpret_cast<float*>(c->d_flag), 64, 0.f, c->st));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->lnvp, lnvp, c->gpts * sizeof(float), hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->lnip, lnip, c->gpts * sizeof(float), hipMemcpyDeviceToDevice, c->st));
+    // vmax and finiteness
+    const int nb = 256;
+    std::vector<float> part(nb);
+    HIPCHK(c, launch_maxval(c->lnvp, c->gpts, c->partial, nb, c->st));
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, nb * sizeof(float), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    float mv = -INFINITY;
+    for (float x : part) mv = std::max(mv, x);
+    HIPCHK(c, launch_maxval(c->lnip, c->gpts, c->partial, nb, c->st));
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, nb * sizeof(float), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    float mi = -INFINITY;
+    for (float x : part) mi = std::max(mi, x);
+    if (!std::isfinite(mv) || !std::isfinite(mi)) {
+        c->have_model = false;
+        FAIL(c, LSRTM_ENONFINITE, "model holds NaN or Inf");
+    }
+    // the same reduction with negated sign is not needed: logs are finite
+    const double vmax = std::exp((double)mv);
+    double s2 = 0.0;
+    for (int a = 0; a < c->ndim; ++a) s2 += 1.0 / (c->g.h[a] * c->g.h[a]);
+    double csum = 0.0;
+    for (double x : kC8) csum += std::fabs(x);
+    const double cfl = vmax * c->g.dt * std::sqrt(s2) * csum;
+    if (!(cfl < 1.0)) {
+        c->have_model = false;
+        FAIL(c, LSRTM_EUNSTABLE, "CFL number %.4f >= 1 (vmax %.1f m/s, dt %g s)", cfl, vmax, c->g.dt);
+    }
+    c->vmax = vmax;
+    c->have_model = true;
+    if (c->have_acq) CHK(prep_model_windows(c));
+    c->ckpt_valid = false;
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_set_acquisition(lsrtm_ctx* c, int nshot, const int* win, const int* src,
+                                   const int* rec_ptr, const int* rec, const float* wavelet) {
+    if (!c) return LSRTM_EINVAL;
+    if (!c->have_model) FAIL(c, LSRTM_ESTATE, "set_model must precede set_acquisition");
+    if (nshot < 1 || !win || !src || !rec_ptr || !wavelet) FAIL(c, LSRTM_EINVAL, "bad acquisition arguments");
+    if (rec_ptr[0] != 0) FAIL(c, LSRTM_EINVAL, "rec_ptr[0] must be 0");
+    for (int s = 0; s < nshot; ++s)
+        if (rec_ptr[s + 1] < rec_ptr[s]) FAIL(c, LSRTM_EINVAL, "rec_ptr must be non-decreasing");
+    if (rec_ptr[nshot] > 0 && !rec) FAIL(c, LSRTM_EINVAL, "rec is NULL");
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    free_acq(c);
+    const int nd = c->ndim;
+    const int npml = c->g.npml;
+    c->nshot = nshot;
+    c->shots.resize(nshot);
+    c->h_win.assign(6 * nshot, 0);
+    std::map<std::vector<int>, int> wid;
+    c->data_len = 0;
+    c->padded_total = 0;
+    for (int s = 0; s < nshot; ++s) {
+        int lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+        for (int a = 0; a < nd; ++a) {
+            lo[a] = win[s * 2 * nd + 2 * a];
+            hi[a] = win[s * 2 * nd + 2 * a + 1];
+            if (lo[a] < 0 || hi[a] > c->g.n[a] || hi[a] <= lo[a])
+                FAIL(c, LSRTM_EINVAL, "shot %d: window [%d,%d) on axis %d outside the grid", s, lo[a], hi[a], a);
+        }
+        std::vector<int> key(lo, lo + 3);
+        key.insert(key.end(), hi, hi + 3);
+        int w;
+        auto it = wid.find(key);
+        if (it == wid.end()) {
+            Window W;
+            for (int a = 0; a < 3; ++a) {
+                W.lo[a] = lo[a];
+                W.hi[a] = hi[a];
+                W.N[a] = a < nd ? hi[a] - lo[a] + 2 * npml : 1;
+            }
+            W.ldz = (int)round_up(W.N[0], 32);
+            W.sx = W.ldz;
+            W.sy = W.sx * W.N[1];
+            W.npts = W.sy * W.N[2];
+            w = (int)c->wins.size();
+            wid[key] = w;
+            c->wins.push_back(W);
+        } else {
+            w = it->second;
+        }
+        const Window& W = c->wins[w];
+        for (int a = 0; a < 3; ++a) {
+            c->h_win[6 * s + 2 * a] = lo[a];
+            c->h_win[6 * s + 2 * a + 1] = hi[a];
+        }
+        ShotInfo& sh = c->shots[s];
+        sh.win = w;
+        auto lin = [&](const int* p, long long* out) -> bool {
+            long long i = 0;
+            const long long strides[3] = {1, W.sx, W.sy};
+            for (int a = 0; a < nd; ++a) {
+                if (p[a] < lo[a] || p[a] >= hi[a]) return false;
+                i += strides[a] * (p[a] - lo[a] + npml);
+            }
+            *out = i;
+            return true;
+        };
+        long long si;
+        if (!lin(src + s * nd, &si)) FAIL(c, LSRTM_EINVAL, "shot %d: source outside its window", s);
+        sh.src_lin = (int)si;
+        sh.rec0 = rec_ptr[s];
+        sh.nrec = rec_ptr[s + 1] - rec_ptr[s];
+        sh.rec_lin.resize(sh.nrec);
+        for (int r = 0; r < sh.nrec; ++r) {
+            long long ri;
+            if (!lin(rec + (long long)(sh.rec0 + r) * nd, &ri))
+                FAIL(c, LSRTM_EINVAL, "shot %d: receiver %d outside its window", s, r);
+            sh.rec_lin[r] = (int)ri;
+        }
+        sh.data_off = (long long)c->g.nt * sh.rec0;
+        c->data_len += (long long)c->g.nt * sh.nrec;
+        c->padded_total += (long long)W.N[0] * W.N[1] * W.N[2];
+        long long ck = (long long)(1 + nd) * W.npts * (c->g.ckpt_dtype == 0 ? 4 : 2);
+        for (int a = 0; a < nd; ++a) ck += 2 * strip_count_h(W.N, a, c->S) * 4;
+        sh.ckbytes = round_up(ck, 256);
+    }
+
+    // ---- memory plan --------------------------------------------------------
+    size_t fr = 0, tot = 0;
+    HIPCHK(c, hipMemGetInfo(&fr, &tot));
+    const long long budget = c->opt_budget_mb > 0 ? c->opt_budget_mb * 1024LL * 1024LL : (long long)(0.9 * fr);
+    const int nbg = 1 + 3 * nd, nsc = 1 + 3 * nd;
+    const int nt = c->g.nt;
+    long long model_bytes = 0;
+    for (auto& W : c->wins) model_bytes += (long long)(nd + 3) * W.npts * 4 + 4LL * nd * 4 * std::max(W.N[0], std::max(W.N[1], W.N[2]));
+    long long ck_per_shot_sum = 0;
+    for (auto& sh : c->shots) ck_per_shot_sum += sh.ckbytes;
+    const long long fixed = model_bytes + 2LL * c->gpts * 8 + (long long)nshot * nt * 4 + 2 * c->data_len * 4 +
+                            2 * 2 * c->gpts * 4 + (64LL << 20) + (long long)nshot * (1 + nd) * 64 * 4;
+    int G = c->opt_spl > 0 ? std::min(c->opt_spl, nshot) : nshot;
+    int k = 1;
+    long long need = 0;
+    for (;;) {
+        // largest group of G consecutive shots
+        long long grp_pts = 0, cur = 0;
+        for (int s = 0; s < nshot; ++s) {
+            cur += c->wins[c->shots[s].win].npts;
+            if ((s + 1) % G == 0 || s == nshot - 1) {
+                grp_pts = std::max(grp_pts, cur);
+                cur = 0;
+            }
+        }
+        const long long seg_step = grp_pts * (nd + 1) * 4;
+        if (c->g.ckpt_every > 0) {
+            k = std::min(c->g.ckpt_every, nt);
+        } else {
+            const double kk = std::sqrt((double)nt * (double)ck_per_shot_sum / (double)std::max(1LL, seg_step));
+            k = (int)std::max(1.0, std::min((double)nt, std::round(kk)));
+        }
+        const int nseg = (nt + k - 1) / k;
+        need = fixed + grp_pts * (nbg + nsc + 2) * 4LL + (long long)k * seg_step + (long long)(nseg - 1) * ck_per_shot_sum +
+               (long long)nseg * nshot * (1 + nd) * 4;
+        if (need <= budget || G == 1) break;
+        G = (G + 1) / 2;
+    }
+    if (need > budget)
+        FAIL(c, LSRTM_ENOMEM, "memory plan needs %.2f GB, budget %.2f GB", need / 1e9, budget / 1e9);
+    c->G = G;
+    c->k = k;
+    c->nseg = (nt + k - 1) / k;
+    c->plan_bytes = need;
+
+    // ---- model windows -------------------------------------------------------
+    for (auto& W : c->wins) {
+        CHK(dalloc_t(c, &W.kdt, W.npts, true));
+        for (int a = 0; a < 3; ++a) {
+            if (a < nd) CHK(dalloc_t(c, &W.bdt[a], W.npts, true));
+            else W.bdt[a] = W.kdt;
+            if (a < nd) CHK(dalloc_t(c, &W.cpml[a], 4 * W.N[a], true));
+            else W.cpml[a] = nullptr;
+        }
+        CHK(dalloc_t(c, &W.dlnr, W.npts, true));
+        CHK(dalloc_t(c, &W.dlnk, W.npts, true));
+        HIPCHK(c, launch_fill(W.kdt, W.npts, 0.f, c->st));
+        HIPCHK(c, launch_fill(W.dlnr, W.npts, 0.f, c->st));
+        HIPCHK(c, launch_fill(W.dlnk, W.npts, 0.f, c->st));
+        for (int a = 0; a < nd; ++a) HIPCHK(c, launch_fill(W.bdt[a], W.npts, 0.f, c->st));
+    }
+    // ---- groups ----------------------------------------------------------------
+    for (int s0 = 0; s0 < nshot; s0 += G) {
+        Group gr;
+        gr.s0 = s0;
+        gr.ns = std::min(G, nshot - s0);
+        long long pts = 0;
+        for (int s = s0; s < s0 + gr.ns; ++s) pts += c->wins[c->shots[s].win].npts;
+        gr.bg_used = pts * nbg;
+        gr.sc_used = pts * nsc;
+        gr.img_used = pts * 2;
+        c->bg_region = std::max(c->bg_region, gr.bg_used);
+        c->sc_region = std::max(c->sc_region, gr.sc_used);
+        c->img_region = std::max(c->img_region, gr.img_used);
+        c->groups.push_back(gr);
+    }
+    long long seg_floats = 0;
+    for (auto& gr : c->groups) {
+        long long pts = gr.bg_used / nbg;
+        seg_floats = std::max(seg_floats, (long long)c->k * (nd + 1) * pts);
+    }
+    CHK(dalloc_t(c, &c->pool, c->bg_region + c->sc_region + c->img_region, true));
+    CHK(dalloc_t(c, &c->segbuf, seg_floats, true));
+    CHK(dalloc(c, reinterpret_cast<void**>(&c->ckbuf), (size_t)std::max(1LL, (long long)(c->nseg - 1) * ck_per_shot_sum), true));
+    CHK(dalloc_t(c, &c->ckscales, (size_t)c->nseg * nshot * (1 + nd), true));
+    CHK(dalloc_t(c, &c->ckpart, (size_t)G * (1 + nd) * c->nblk, true));
+    CHK(dalloc_t(c, &c->acc64, 2 * c->gpts, true));
+    CHK(dalloc_t(c, &c->src_amp, (size_t)nshot * nt, true));
+    CHK(dalloc_t(c, &c->cg_r, std::max(1LL, c->data_len), true));
+    CHK(dalloc_t(c, &c->cg_w, std::max(1LL, c->data_len), true));
+    CHK(dalloc_t(c, &c->cg_z, 2 * c->gpts, true));
+    CHK(dalloc_t(c, &c->cg_p, 2 * c->gpts, true));
+    HIPCHK(c, launch_fill(c->pool, c->bg_region + c->sc_region + c->img_region, 0.f, c->st));
+    HIPCHK(c, launch_fill(c->src_amp, (long long)nshot * nt, 0.f, c->st));
+    double cell = 1.0;
+    for (int a = 0; a < nd; ++a) cell *= c->g.h[a];
+    HIPCHK(c, launch_axpy(c->g.dt / cell, wavelet, c->src_amp, (long long)nshot * nt, c->st));
+
+    // checkpoint offsets per shot: [j][shot] blocks -> shot-major inside each j
+    // is not needed; each shot owns nseg consecutive checkpoints.
+    std::vector<long long> ckoff(nshot);
+    {
+        long long o = 0;
+        for (int s = 0; s < nshot; ++s) {
+            ckoff[s] = o;
+            o += (long long)(c->nseg - 1) * c->shots[s].ckbytes;
+        }
+    }
+    // descriptors, receivers
+    for (auto& gr : c->groups) {
+        long long obg = 0, osc = 0, oimg = 0, oseg = 0;
+        float* bgb = c->pool;
+        float* scb = c->pool + c->bg_region;
+        float* imb = c->pool + c->bg_region + c->sc_region;
+        std::vector<Rec> recs;
+        std::vector<int> wins6;
+        std::vector<std::pair<long long, int>> nodes;   // (slot<<32 | idx, rec index)
+        for (int i = 0; i < gr.ns; ++i) {
+            const int s = gr.s0 + i;
+            const ShotInfo& sh = c->shots[s];
+            const Window& W = c->wins[sh.win];
+            Slot S;
+            memset(&S, 0, sizeof(S));
+            for (int a = 0; a < 3; ++a) S.n[a] = W.N[a];
+            S.ldz = W.ldz;
+            S.sx = W.sx;
+            S.sy = W.sy;
+            S.npts = W.npts;
+            S.src = sh.src_lin;
+            S.shot = s;
+            S.src_amp = c->src_amp + (long long)s * nt;
+            S.kdt = W.kdt;
+            for (int a = 0; a < 3; ++a) {
+                S.bdt[a] = W.bdt[a];
+                S.cpml[a] = W.cpml[a];
+            }
+            S.dlnr = W.dlnr;
+            S.dlnk = W.dlnk;
+            float* b = bgb + obg;
+            S.p = b;
+            for (int a = 0; a < 3; ++a) {
+                const bool on = a < nd;
+                S.v[a] = on ? b + (1 + a) * W.npts : nullptr;
+                S.psi[a] = on ? b + (1 + nd + a) * W.npts : nullptr;
+                S.phi[a] = on ? b + (1 + 2 * nd + a) * W.npts : nullptr;
+            }
+            float* q = scb + osc;
+            S.q = q;
+            for (int a = 0; a < 3; ++a) {
+                const bool on = a < nd;
+                S.w[a] = on ? q + (1 + a) * W.npts : nullptr;
+                S.xi[a] = on ? q + (1 + nd + a) * W.npts : nullptr;
+                S.eta[a] = on ? q + (1 + 2 * nd + a) * W.npts : nullptr;
+            }
+            S.gk = imb + oimg;
+            S.gr = imb + oimg + W.npts;
+            S.seg = c->segbuf + oseg;
+            S.ck = c->ckbuf + ckoff[s];
+            S.ckbytes = sh.ckbytes;
+            obg += (long long)nbg * W.npts;
+            osc += (long long)nsc * W.npts;
+            oimg += 2LL * W.npts;
+            oseg += (long long)c->k * (nd + 1) * W.npts;
+            gr.max_npts = std::max(gr.max_npts, W.npts);
+            gr.h_slots.push_back(S);
+            for (int r = 0; r < sh.nrec; ++r) {
+                Rec R;
+                R.slot = i;
+                R.idx = sh.rec_lin[r];
+                R.out = sh.data_off + r;
+                R.stride = sh.nrec;
+                R.pad = 0;
+                nodes.push_back({((long long)i << 32) | (unsigned)R.idx, (int)recs.size()});
+                recs.push_back(R);
+            }
+            for (int a = 0; a < 6; ++a) wins6.push_back(c->h_win[6 * s + a]);
+        }
+        CHK(dalloc_t(c, &gr.d_slots, gr.ns, true));
+        HIPCHK(c, hipMemcpy(gr.d_slots, gr.h_slots.data(), gr.ns * sizeof(Slot), hipMemcpyHostToDevice));
+        CHK(dalloc_t(c, &gr.d_win, wins6.size(), true));
+        HIPCHK(c, hipMemcpy(gr.d_win, wins6.data(), wins6.size() * sizeof(int), hipMemcpyHostToDevice));
+        gr.nrec = (int)recs.size();
+        CHK(dalloc_t(c, &gr.d_rec, std::max<size_t>(1, recs.size()), true));
+        if (!recs.empty())
+            HIPCHK(c, hipMemcpy(gr.d_rec, recs.data(), recs.size() * sizeof(Rec), hipMemcpyHostToDevice));
+        // distinct receiver nodes (stable order: receivers of one node keep
+        // their shot order)
+        std::stable_sort(nodes.begin(), nodes.end(),
+                         [](const std::pair<long long, int>& a, const std::pair<long long, int>& b) {
+                             return a.first < b.first;
+                         });
+        std::vector<int> nslot, nidx, nptr;
+        std::vector<Rec> nrec;
+        for (size_t i = 0; i < nodes.size(); ++i) {
+            if (i == 0 || nodes[i].first != nodes[i - 1].first) {
+                nslot.push_back((int)(nodes[i].first >> 32));
+                nidx.push_back((int)(nodes[i].first & 0xffffffffLL));
+                nptr.push_back((int)nrec.size());
+            }
+            nrec.push_back(recs[nodes[i].second]);
+        }
+        nptr.push_back((int)nrec.size());
+        gr.nnode = (int)nslot.size();
+        CHK(dalloc_t(c, &gr.d_node_slot, std::max<size_t>(1, nslot.size()), true));
+        CHK(dalloc_t(c, &gr.d_node_idx, std::max<size_t>(1, nidx.size()), true));
+        CHK(dalloc_t(c, &gr.d_node_ptr, nptr.size(), true));
+        CHK(dalloc_t(c, &gr.d_node_rec, std::max<size_t>(1, nrec.size()), true));
+        if (!nslot.empty()) {
+            HIPCHK(c, hipMemcpy(gr.d_node_slot, nslot.data(), nslot.size() * sizeof(int), hipMemcpyHostToDevice));
+            HIPCHK(c, hipMemcpy(gr.d_node_idx, nidx.data(), nidx.size() * sizeof(int), hipMemcpyHostToDevice));
+            HIPCHK(c, hipMemcpy(gr.d_node_rec, nrec.data(), nrec.size() * sizeof(Rec), hipMemcpyHostToDevice));
+        }
+        HIPCHK(c, hipMemcpy(gr.d_node_ptr, nptr.data(), nptr.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    c->have_acq = true;
+    CHK(prep_model_windows(c));
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_sizes(lsrtm_ctx* c, long long* out, int nout) {
+    if (!c || !out) return LSRTM_EINVAL;
+    long long v[7] = {c->data_len, c->gpts, c->G, c->k, (long long)c->groups.size(), c->padded_total, c->plan_bytes};
+    for (int i = 0; i < nout && i < 7; ++i) out[i] = v[i];
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_stats(lsrtm_ctx* c, double* out, int nout) {
+    if (!c || !out) return LSRTM_EINVAL;
+    std::vector<double> v(1 + 2 * LSRTM_NKERNEL);
+    v[0] = c->pass_ms;
+    for (int i = 0; i < LSRTM_NKERNEL; ++i) {
+        v[1 + 2 * i] = c->kms[i];
+        v[2 + 2 * i] = (double)c->kcnt[i];
+    }
+    for (int i = 0; i < nout && i < (int)v.size(); ++i) out[i] = v[i];
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_forward(lsrtm_ctx* c, float* d) {
+    CHK(check_ready(c));
+    if (!d && c->data_len > 0) FAIL(c, LSRTM_EINVAL, "d is NULL");
+    CHK(pass_begin(c));
+    for (auto& gr : c->groups) CHK(group_forward(c, gr, 0, d, true));
+    CHK(pass_end(c));
+    CHK(check_flag(c));
+    c->ckpt_valid = true;
+    return LSRTM_OK;
+}
+
+static lsrtm_status born_impl(lsrtm_ctx* c, const float* dm, float* d) {
+    for (auto& W : c->wins) {
+        DmArgs a;
+        a.dm = dm;
+        a.gpts = c->gpts;
+        for (int i = 0; i < 3; ++i) {
+            a.gn[i] = c->g.n[i];
+            a.lo[i] = W.lo[i];
+            a.wn[i] = W.hi[i] - W.lo[i];
+            a.N[i] = W.N[i];
+        }
+        a.npml = c->g.npml;
+        a.sx = W.sx;
+        a.sy = W.sy;
+        a.ndim = c->ndim;
+        a.dlnr = W.dlnr;
+        a.dlnk = W.dlnk;
+        HIPCHK(c, launch_dm_prep(a, c->st));
+    }
+    const bool write_ck = !c->ckpt_valid;
+    for (auto& gr : c->groups) CHK(group_forward(c, gr, 1, d, write_ck));
+    if (write_ck) {
+        CHK(check_flag(c));
+        c->ckpt_valid = true;
+    }
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_born(lsrtm_ctx* c, const float* dm, float* d) {
+    CHK(check_ready(c));
+    if (!dm || (!d && c->data_len > 0)) FAIL(c, LSRTM_EINVAL, "NULL argument");
+    CHK(pass_begin(c));
+    CHK(born_impl(c, dm, d));
+    CHK(pass_end(c));
+    return LSRTM_OK;
+}
+
+static lsrtm_status adjoint_impl(lsrtm_ctx* c, const float* d, float* img, int accumulate) {
+    CHK(ensure_ckpts(c));
+    HIPCHK(c, launch_fill_f64(c->acc64, 2 * c->gpts, c->st));
+    for (auto& gr : c->groups) CHK(group_adjoint(c, gr, d));
+    HIPCHK(c, launch_image_store(c->acc64, img, 2 * c->gpts, accumulate, c->st));
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_adjoint(lsrtm_ctx* c, const float* d, float* img, int accumulate) {
+    CHK(check_ready(c));
+    if (!img || (!d && c->data_len > 0)) FAIL(c, LSRTM_EINVAL, "NULL argument");
+    CHK(pass_begin(c));
+    CHK(adjoint_impl(c, d, img, accumulate));
+    CHK(pass_end(c));
+    return LSRTM_OK;
+}
+
+static lsrtm_status dot_impl(lsrtm_ctx* c, const float* a, const float* b, long long n, double* out) {
+    double r = 0.0;
+    if (n > 0) {
+        HIPCHK(c, launch_dot(a, b, n, c->dpart, 1024, c->dscal, c->st));
+        HIPCHK(c, hipMemcpyAsync(&r, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));
+    }
+    *out = r;
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_dot(lsrtm_ctx* c, const float* a, const float* b, long long n, double* out) {
+    if (!c || !out || n < 0 || (n > 0 && (!a || !b))) return LSRTM_EINVAL;
+    if (!c->dpart) {
+        CHK(dalloc_t(c, &c->dpart, 1024, false));
+        CHK(dalloc_t(c, &c->dscal, 16, false));
+    }
+    return dot_impl(c, a, b, n, out);
+}
+
+lsrtm_status lsrtm_axpy(lsrtm_ctx* c, double alpha, const float* x, float* y, long long n) {
+    if (!c || n < 0 || (n > 0 && (!x || !y))) return LSRTM_EINVAL;
+    HIPCHK(c, launch_axpy(alpha, x, y, n, c->st));
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_cgnr(lsrtm_ctx* c, const float* d_obs, int niter, float* x, double* misfit) {
+    CHK(check_ready(c));
+    if (!x || niter < 0 || (!d_obs && c->data_len > 0)) FAIL(c, LSRTM_EINVAL, "bad CGNR arguments");
+    const long long nm = 2 * c->gpts, nd = c->data_len;
+    CHK(pass_begin(c));
+    HIPCHK(c, launch_copy(d_obs, c->cg_r, nd, c->st));
+    HIPCHK(c, launch_fill(x, nm, 0.f, c->st));
+    CHK(adjoint_impl(c, c->cg_r, c->cg_z, 0));
+    HIPCHK(c, launch_copy(c->cg_z, c->cg_p, nm, c->st));
+    double zz, r0;
+    CHK(dot_impl(c, c->cg_z, c->cg_z, nm, &zz));
+    CHK(dot_impl(c, c->cg_r, c->cg_r, nd, &r0));
+    if (misfit) misfit[0] = 1.0;
+    for (int it = 0; it < niter; ++it) {
+        double rr = r0;
+        if (zz > 0.0 && r0 > 0.0) {
+            CHK(born_impl(c, c->cg_p, c->cg_w));
+            double ww;
+            CHK(dot_impl(c, c->cg_w, c->cg_w, nd, &ww));
+            if (ww > 0.0) {
+                const double alpha = zz / ww;
+                HIPCHK(c, launch_axpy(alpha, c->cg_p, x, nm, c->st));
+                HIPCHK(c, launch_axpy(-alpha, c->cg_w, c->cg_r, nd, c->st));
+                CHK(adjoint_impl(c, c->cg_r, c->cg_z, 0));
+                double zz1;
+                CHK(dot_impl(c, c->cg_z, c->cg_z, nm, &zz1));
+                const double beta = zz1 / zz;
+                HIPCHK(c, launch_xpby(c->cg_z, beta, c->cg_p, nm, c->st));
+                zz = zz1;
+            }
+            CHK(dot_impl(c, c->cg_r, c->cg_r, nd, &rr));
+        }
+        if (misfit) misfit[it + 1] = r0 > 0.0 ? rr / r0 : 0.0;
+    }
+    CHK(pass_end(c));
+    return LSRTM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,304 @@
+"""Python binding of the HIP library (ctypes; argument marshalling only).
+
+Every step of the imaging path runs in liblsrtm.so.  PyTorch provides device
+memory and the HIP stream; nothing here computes on tensors.  If the library
+is not built, importing the binding works but creating a Context raises.
+
+Array conventions (same as the C ABI): physical grid arrays are torch float32
+tensors of shape (nx, nz) in 2D and (ny, nx, nz) in 3D (z fastest); model
+perturbations and images have a leading axis of 2 for (lnVp, lnIp); data
+vectors are flat, shot s occupying nt * nrec_s values laid out [it][rec].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblsrtm.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "lsrtm.h")
+
+OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
+CKPT = {"f32": 0, "f16": 1, "bf16": 2}
+OPT_SHOTS_PER_LAUNCH, OPT_TILE, OPT_GRAPH, OPT_TIMING, OPT_MEM_BUDGET_MB = 1, 2, 3, 4, 5
+NKERNEL = 8
+KERNEL_NAMES = ("born_v", "born_p", "bg_v", "bg_p", "adj_a", "adj_b", "ckpt", "rec")
+
+_c_int, _c_double, _c_ll, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_longlong, ctypes.c_void_p
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("ndim", _c_int), ("n", _c_int * 3), ("h", _c_double * 3), ("npml", _c_int),
+                ("pml_R", _c_double), ("pml_f0", _c_double), ("nt", _c_int), ("dt", _c_double),
+                ("ckpt_every", _c_int), ("ckpt_dtype", _c_int)]
+
+
+class LsrtmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"lsrtm status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+# exported symbol -> (restype, argtypes)
+SIGNATURES = {
+    "lsrtm_create": (_c_int, [ctypes.POINTER(Grid), _vp, ctypes.POINTER(_vp)]),
+    "lsrtm_set_model": (_c_int, [_vp, _vp, _vp]),
+    "lsrtm_set_acquisition": (_c_int, [_vp, _c_int, _vp, _vp, _vp, _vp, _vp]),
+    "lsrtm_forward": (_c_int, [_vp, _vp]),
+    "lsrtm_born": (_c_int, [_vp, _vp, _vp]),
+    "lsrtm_adjoint": (_c_int, [_vp, _vp, _vp, _c_int]),
+    "lsrtm_cgnr": (_c_int, [_vp, _vp, _c_int, _vp, _vp]),
+    "lsrtm_dot": (_c_int, [_vp, _vp, _vp, _c_ll, ctypes.POINTER(_c_double)]),
+    "lsrtm_axpy": (_c_int, [_vp, _c_double, _vp, _vp, _c_ll]),
+    "lsrtm_set_option": (_c_int, [_vp, _c_int, _c_ll]),
+    "lsrtm_sizes": (_c_int, [_vp, ctypes.POINTER(_c_ll), _c_int]),
+    "lsrtm_stats": (_c_int, [_vp, ctypes.POINTER(_c_double), _c_int]),
+    "lsrtm_tile_shape": (_c_int, [_c_int, _c_int, ctypes.POINTER(_c_int)]),
+    "lsrtm_destroy": (None, [_vp]),
+    "lsrtm_strerror": (ctypes.c_char_p, [_c_int]),
+    "lsrtm_last_error": (ctypes.c_char_p, [_vp]),
+}
+
+
+def lib():
+    """Load liblsrtm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2508_10405_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else t.data_ptr()
+
+
+def _require_cuda(t, name, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.dtype != (dtype or torch.float32):
+        raise TypeError(f"{name} must be {dtype or torch.float32}")
+    return t
+
+
+class Context:
+    """One imaging problem on one GPU stream.
+
+    Parameters follow lsrtm_grid: n = (nz, nx[, ny]) physical sizes,
+    h = (dz, dx[, dy]), npml CPML cells, nt steps of dt seconds, CPML
+    parameters pml_R and pml_f0, checkpoint interval (0 = planner) and
+    checkpoint storage ("f32", "f16", "bf16").
+    """
+
+    def __init__(self, n, h, nt, dt, npml=20, pml_R=1e-4, pml_f0=10.0, ckpt_every=0,
+                 ckpt_dtype="f32", stream=None, shots_per_launch=0, tile=-1, graph=True,
+                 timing=False, mem_budget_mb=0):
+        import torch
+        L = lib()
+        self._torch = torch
+        ndim = len(n)
+        g = Grid()
+        g.ndim = ndim
+        for a in range(3):
+            g.n[a] = int(n[a]) if a < ndim else 1
+            g.h[a] = float(h[a]) if a < ndim else 1.0
+        g.npml, g.pml_R, g.pml_f0 = int(npml), float(pml_R), float(pml_f0)
+        g.nt, g.dt = int(nt), float(dt)
+        g.ckpt_every, g.ckpt_dtype = int(ckpt_every), CKPT[ckpt_dtype]
+        self.grid = g
+        self.ndim, self.n, self.nt = ndim, tuple(int(x) for x in n), int(nt)
+        self.shape = tuple(reversed(self.n))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self._h = _vp()
+        self._check(L.lsrtm_create(ctypes.byref(g), _vp(stream.cuda_stream), ctypes.byref(self._h)),
+                    "create")
+        self.set_option(OPT_SHOTS_PER_LAUNCH, shots_per_launch)
+        self.set_option(OPT_TILE, tile)
+        self.set_option(OPT_GRAPH, int(bool(graph)))
+        self.set_option(OPT_TIMING, int(bool(timing)))
+        self.set_option(OPT_MEM_BUDGET_MB, mem_budget_mb)
+        self.nrec: List[int] = []
+        self._keep = []
+
+    # -- plumbing -----------------------------------------------------------
+    def _check(self, status, what):
+        if status != OK:
+            msg = ""
+            if getattr(self, "_h", None) is not None and self._h.value:
+                msg = lib().lsrtm_last_error(self._h).decode()
+            raise LsrtmError(status, f"{what}: {lib().lsrtm_strerror(status).decode()} {msg}".strip())
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().lsrtm_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, key, value):
+        self._check(lib().lsrtm_set_option(self._h, int(key), int(value)), "set_option")
+
+    # -- problem ------------------------------------------------------------
+    def set_model(self, lnvp, lnip):
+        _require_cuda(lnvp, "lnvp")
+        _require_cuda(lnip, "lnip")
+        if tuple(lnvp.shape) != self.shape or tuple(lnip.shape) != self.shape:
+            raise ValueError(f"model shape must be {self.shape}")
+        self._check(lib().lsrtm_set_model(self._h, _vp(_ptr(lnvp)), _vp(_ptr(lnip))), "set_model")
+
+    def set_acquisition(self, win, src, rec: Sequence, wavelet):
+        """win: per shot ((z0, z1), (x0, x1)[, (y0, y1)]); src: per shot node;
+        rec: per shot int array (nrec, ndim); wavelet: CUDA float32 (nshot, nt)."""
+        nd = self.ndim
+        nshot = len(src)
+        w = np.ascontiguousarray(np.array(win, dtype=np.int32).reshape(nshot, 2 * nd))
+        s = np.ascontiguousarray(np.array(src, dtype=np.int32).reshape(nshot, nd))
+        counts = [len(r) for r in rec]
+        ptr = np.zeros(nshot + 1, dtype=np.int32)
+        ptr[1:] = np.cumsum(counts)
+        r = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.int32).reshape(-1, nd) for x in rec])
+                                 if ptr[-1] > 0 else np.zeros((0, nd), np.int32))
+        _require_cuda(wavelet, "wavelet")
+        if tuple(wavelet.shape) != (nshot, self.nt):
+            raise ValueError("wavelet must have shape (nshot, nt)")
+        self._check(lib().lsrtm_set_acquisition(
+            self._h, nshot, w.ctypes.data, s.ctypes.data, ptr.ctypes.data, r.ctypes.data,
+            _vp(_ptr(wavelet))), "set_acquisition")
+        self.nrec = counts
+        self.nshot = nshot
+
+    # -- sizes --------------------------------------------------------------
+    def sizes(self):
+        out = (_c_ll * 7)()
+        self._check(lib().lsrtm_sizes(self._h, out, 7), "sizes")
+        keys = ("data_len", "grid_points", "shots_per_launch", "ckpt_every", "groups",
+                "padded_points", "plan_bytes")
+        return dict(zip(keys, [int(x) for x in out]))
+
+    @property
+    def data_len(self) -> int:
+        return self.sizes()["data_len"]
+
+    def stats(self):
+        m = 1 + 2 * NKERNEL
+        out = (_c_double * m)()
+        self._check(lib().lsrtm_stats(self._h, out, m), "stats")
+        d = {"pass_ms": out[0]}
+        for k, name in enumerate(KERNEL_NAMES):
+            d[name] = (out[1 + 2 * k], int(out[2 + 2 * k]))
+        return d
+
+    def split(self, d) -> list:
+        """Flat data vector -> list of per-shot (nt, nrec_s) views."""
+        out, o = [], 0
+        for c in self.nrec:
+            out.append(d[o:o + self.nt * c].view(self.nt, c))
+            o += self.nt * c
+        return out
+
+    # -- operators ----------------------------------------------------------
+    def _data(self, d):
+        torch = self._torch
+        if d is None:
+            d = torch.empty(self.data_len, dtype=torch.float32, device="cuda")
+        _require_cuda(d, "d")
+        if d.numel() != self.data_len:
+            raise ValueError(f"data vector must have {self.data_len} values")
+        return d
+
+    def _image(self, img):
+        torch = self._torch
+        if img is None:
+            img = torch.empty((2,) + self.shape, dtype=torch.float32, device="cuda")
+        _require_cuda(img, "img")
+        if tuple(img.shape) != (2,) + self.shape:
+            raise ValueError(f"image must have shape {(2,) + self.shape}")
+        return img
+
+    def forward(self, d=None):
+        d = self._data(d)
+        self._check(lib().lsrtm_forward(self._h, _vp(_ptr(d))), "forward")
+        return d
+
+    def born(self, dm, d=None):
+        _require_cuda(dm, "dm")
+        if tuple(dm.shape) != (2,) + self.shape:
+            raise ValueError(f"dm must have shape {(2,) + self.shape}")
+        d = self._data(d)
+        self._check(lib().lsrtm_born(self._h, _vp(_ptr(dm)), _vp(_ptr(d))), "born")
+        return d
+
+    def adjoint(self, d, img=None, accumulate=False):
+        _require_cuda(d, "d")
+        if d.numel() != self.data_len:
+            raise ValueError(f"data vector must have {self.data_len} values")
+        img = self._image(img)
+        self._check(lib().lsrtm_adjoint(self._h, _vp(_ptr(d)), _vp(_ptr(img)), int(bool(accumulate))),
+                    "adjoint")
+        return img
+
+    def cgnr(self, d_obs, niter, x=None):
+        _require_cuda(d_obs, "d_obs")
+        x = self._image(x)
+        mis = (_c_double * (niter + 1))()
+        self._check(lib().lsrtm_cgnr(self._h, _vp(_ptr(d_obs)), int(niter), _vp(_ptr(x)), mis), "cgnr")
+        return x, [float(v) for v in mis]
+
+    def dot(self, a, b) -> float:
+        _require_cuda(a, "a")
+        _require_cuda(b, "b")
+        if a.numel() != b.numel():
+            raise ValueError("length mismatch")
+        out = _c_double()
+        self._check(lib().lsrtm_dot(self._h, _vp(_ptr(a)), _vp(_ptr(b)), a.numel(), ctypes.byref(out)),
+                    "dot")
+        return out.value
+
+    def axpy(self, alpha, x, y):
+        _require_cuda(x, "x")
+        _require_cuda(y, "y")
+        if x.numel() != y.numel():
+            raise ValueError("length mismatch")
+        self._check(lib().lsrtm_axpy(self._h, float(alpha), _vp(_ptr(x)), _vp(_ptr(y)), x.numel()), "axpy")
+        return y
+
+
+def tile_shape(ndim: int, tile_id: int):
+    out = (_c_int * 2)()
+    st = lib().lsrtm_tile_shape(int(ndim), int(tile_id), out)
+    if st != OK:
+        raise LsrtmError(st, "unknown tile id")
+    return int(out[0]), int(out[1])
+
+
+def context_for(w, device="cuda", **opts) -> Context:
+    """Context with model and acquisition of a workload description (an object
+    with h, dt, nt, npml, pml_R, pml_freq, lnvp, lnip, win, src, rec, wavelet)."""
+    import torch
+    n = tuple(reversed(w.lnvp.shape))
+    ctx = Context(n, w.h, w.nt, w.dt, npml=w.npml, pml_R=w.pml_R, pml_f0=w.pml_freq, **opts)
+    ctx.set_model(torch.from_numpy(np.ascontiguousarray(w.lnvp, np.float32)).to(device),
+                  torch.from_numpy(np.ascontiguousarray(w.lnip, np.float32)).to(device))
+    ctx.set_acquisition(w.win, w.src, w.rec,
+                        torch.from_numpy(np.ascontiguousarray(w.wavelet, np.float32)).to(device))
+    return ctx

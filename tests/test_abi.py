@@ -1,0 +1,87 @@
+"""The C-ABI library loads and exports every entry point include/lsrtm.h
+declares; host-side argument validation (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2508_10405_amd import lsrtm
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lsrtm.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:lsrtm_status|void|const char\s*\*)\s*(lsrtm_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_api():
+    names = _declared()
+    for n in ("lsrtm_create", "lsrtm_set_model", "lsrtm_set_acquisition", "lsrtm_forward", "lsrtm_born",
+              "lsrtm_adjoint", "lsrtm_cgnr", "lsrtm_dot", "lsrtm_destroy", "lsrtm_strerror"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = lsrtm.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+        assert name in lsrtm.SIGNATURES, name
+
+
+def test_create_validates_grid_on_host():
+    L = lsrtm.lib()
+
+    def create(**kw):
+        g = lsrtm.Grid()
+        g.ndim = kw.get("ndim", 2)
+        n = kw.get("n", (10, 12, 1))
+        for a in range(3):
+            g.n[a] = n[a]
+            g.h[a] = kw.get("h", 10.0)
+        g.npml, g.pml_R, g.pml_f0 = kw.get("npml", 4), kw.get("R", 1e-4), 10.0
+        g.nt, g.dt = kw.get("nt", 10), kw.get("dt", 1e-3)
+        g.ckpt_every, g.ckpt_dtype = kw.get("ck", 0), kw.get("ckd", 0)
+        h = ctypes.c_void_p()
+        st = L.lsrtm_create(ctypes.byref(g), None, ctypes.byref(h))
+        if st == 0:
+            L.lsrtm_destroy(h)
+        return st
+
+    assert create() == lsrtm.OK
+    assert create(ndim=3, n=(5, 6, 7)) == lsrtm.OK
+    assert create(ndim=4) == lsrtm.EINVAL
+    assert create(n=(0, 12, 1)) == lsrtm.EINVAL
+    assert create(n=(10, 12, 3)) == lsrtm.EINVAL      # 2D needs ny = 1
+    assert create(h=-1.0) == lsrtm.EINVAL
+    assert create(nt=0) == lsrtm.EINVAL
+    assert create(dt=0.0) == lsrtm.EINVAL
+    assert create(npml=-1) == lsrtm.EINVAL
+    assert create(R=1.5) == lsrtm.EINVAL
+    assert create(ckd=3) == lsrtm.EINVAL
+    assert L.lsrtm_create(None, None, None) == lsrtm.EINVAL
+
+
+def test_strerror_and_tiles():
+    L = lsrtm.lib()
+    assert L.lsrtm_strerror(lsrtm.EUNSTABLE).decode().startswith("CFL")
+    assert lsrtm.tile_shape(2, 4) == (64, 8)
+    with pytest.raises(lsrtm.LsrtmError):
+        lsrtm.tile_shape(2, 99)
+
+
+def test_calls_before_setup_report_state():
+    L = lsrtm.lib()
+    g = lsrtm.Grid()
+    g.ndim = 2
+    g.n[0], g.n[1], g.n[2] = 10, 12, 1
+    g.h[0] = g.h[1] = g.h[2] = 10.0
+    g.npml, g.pml_R, g.pml_f0, g.nt, g.dt = 4, 1e-4, 10.0, 10, 1e-3
+    h = ctypes.c_void_p()
+    assert L.lsrtm_create(ctypes.byref(g), None, ctypes.byref(h)) == 0
+    assert L.lsrtm_born(h, ctypes.c_void_p(16), ctypes.c_void_p(16)) == lsrtm.ESTATE
+    assert L.lsrtm_set_acquisition(h, 1, None, None, None, None, None) == lsrtm.ESTATE
+    assert L.lsrtm_set_option(h, 99, 0) == lsrtm.EINVAL
+    assert L.lsrtm_set_option(h, lsrtm.OPT_TILE, 42) == lsrtm.EINVAL
+    L.lsrtm_destroy(h)

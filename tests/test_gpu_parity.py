@@ -1,0 +1,223 @@
+"""GPU (FP32, HIP) against the FP64 oracle, through the C ABI.
+
+Bar: relative L2 error <= 1e-4 on seismograms and images, the tolerance the
+benchmark target states for FP32 propagation against the FP64 oracle.  Sizes
+are chosen so that grids span several tiles with ragged tails, shots use
+uneven windows, and the oracle finishes in seconds.
+"""
+import numpy as np
+import pytest
+
+from oracle import lsrtm_oracle as O
+from paper_2508_10405_amd import synth
+from gpu_common import concat, f64, oracle_problem, rel, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _ctx(torch, w, **opts):
+    from paper_2508_10405_amd import lsrtm
+    print(f"[case] {w.name} nshot={w.nshot} nt={w.nt} npml={w.npml} opts={opts}", flush=True)
+    return lsrtm.context_for(w, **opts)
+
+
+CASES = [
+    # n (nz, nx), nt, npml, nshot, uneven
+    ((37, 45), 160, 4, 1, False),
+    ((70, 83), 220, 20, 3, True),
+    ((129, 17), 150, 6, 2, True),
+]
+
+
+@pytest.mark.parametrize("n,nt,npml,nshot,uneven", CASES)
+def test_forward_born_adjoint_vs_oracle(torch, n, nt, npml, nshot, uneven):
+    w = synth.small(n, nt=nt, npml=npml, seed=sum(n), nshot=nshot, uneven=uneven)
+    prob = oracle_problem(w)
+    lnvp, lnip = f64(w.lnvp), f64(w.lnip)
+    ctx = _ctx(torch, w)
+    # background data
+    d0 = ctx.forward().cpu().numpy()
+    ref0 = concat(O.forward(prob, lnvp, lnip))
+    e = rel(d0, ref0)
+    print("forward rel", e)
+    assert e <= TOL
+    # Born data
+    dm = to_dev(torch, w.dm)
+    dd = ctx.born(dm).cpu().numpy()
+    refd = O.born(prob, lnvp, lnip, f64(w.dm))
+    e = rel(dd, concat(refd))
+    print("born rel", e)
+    assert e <= TOL
+    # adjoint image of seeded data
+    rng = np.random.default_rng(7)
+    ys = [rng.standard_normal((nt, len(r))) for r in w.rec]
+    img = ctx.adjoint(to_dev(torch, concat(ys))).cpu().numpy()
+    refi = O.adjoint(prob, lnvp, lnip, ys)
+    for k in range(2):
+        e = rel(img[k], refi[k])
+        print("adjoint rel", k, e)
+        assert e <= TOL
+
+
+def test_dot_product_gpu(torch):
+    w = synth.small((61, 77), nt=200, npml=10, seed=3, nshot=2, uneven=True)
+    ctx = _ctx(torch, w)
+    rng = np.random.default_rng(2)
+    x = to_dev(torch, rng.standard_normal((2,) + w.shape))
+    y = to_dev(torch, rng.standard_normal(ctx.data_len))
+    Lx = ctx.born(x)
+    Lty = ctx.adjoint(y)
+    a = ctx.dot(Lx, y)
+    b = ctx.dot(x.view(-1), Lty.view(-1))
+    print("dot", a, b, abs(a - b) / abs(a))
+    assert abs(a - b) <= TOL * abs(a)
+
+
+def test_replay_is_bitwise(torch):
+    """FP32 checkpoint replay reproduces the stored-everything history bit for
+    bit: images for every checkpoint interval are identical."""
+    w = synth.small((45, 66), nt=97, npml=8, seed=5, nshot=2, uneven=True)
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal(sum(w.nt * len(r) for r in w.rec))
+    imgs = []
+    for k in (1, 7, 32, 97):
+        from paper_2508_10405_amd import lsrtm
+        ctx = lsrtm.context_for(w, ckpt_every=k)
+        imgs.append(ctx.adjoint(to_dev(torch, y)).cpu().numpy())
+        ctx.close()
+    for im in imgs[1:]:
+        assert np.array_equal(im, imgs[0])
+
+
+def test_batched_equals_per_shot_and_tiles(torch):
+    """Batching shots into one launch, and every tile shape, give bitwise the
+    same data and images as plain per-shot launches."""
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((50, 90), nt=120, npml=6, seed=9, nshot=4, uneven=True)
+    dm = to_dev(torch, w.dm)
+    rng = np.random.default_rng(4)
+    y = to_dev(torch, rng.standard_normal(sum(w.nt * len(r) for r in w.rec)))
+    ref = None
+    for spl in (1, 0, 3):
+        for tile in range(9):
+            ctx = lsrtm.context_for(w, shots_per_launch=spl, tile=tile)
+            d = ctx.born(dm).cpu().numpy()
+            im = ctx.adjoint(y).cpu().numpy()
+            ctx.close()
+            if ref is None:
+                ref = (d, im)
+            else:
+                assert np.array_equal(d, ref[0]), (spl, tile)
+                assert np.array_equal(im, ref[1]), (spl, tile)
+
+
+def test_run_twice_deterministic(torch):
+    w = synth.small((40, 60), nt=90, npml=5, seed=12, nshot=3, uneven=True)
+    ctx = _ctx(torch, w)
+    dm = to_dev(torch, w.dm)
+    a = ctx.born(dm).cpu().numpy()
+    b = ctx.born(dm).cpu().numpy()
+    assert np.array_equal(a, b)
+    y = to_dev(torch, np.random.default_rng(0).standard_normal(ctx.data_len))
+    assert np.array_equal(ctx.adjoint(y).cpu().numpy(), ctx.adjoint(y).cpu().numpy())
+
+
+def test_adjoint_accumulate(torch):
+    w = synth.small((30, 40), nt=60, npml=4, seed=2, nshot=1)
+    ctx = _ctx(torch, w)
+    y = to_dev(torch, np.random.default_rng(0).standard_normal(ctx.data_len))
+    a = ctx.adjoint(y)
+    b = a.clone()
+    ctx.adjoint(y, img=b, accumulate=True)
+    np.testing.assert_allclose(b.cpu().numpy(), 2 * a.cpu().numpy(), rtol=1e-6, atol=0)
+
+
+def test_cgnr_vs_oracle(torch):
+    """Three CGNR iterations: iterate and normalised misfit history against
+    the FP64 oracle's CGNR on the same operators."""
+    w = synth.small((36, 52), nt=110, npml=6, seed=14, nshot=2, uneven=True)
+    prob = oracle_problem(w)
+    lnvp, lnip = f64(w.lnvp), f64(w.lnip)
+    dobs = O.born(prob, lnvp, lnip, f64(w.dm))
+    x_ref, hist_ref = O.cgnr(lambda m: O.born(prob, lnvp, lnip, m),
+                             lambda d: O.adjoint(prob, lnvp, lnip, d), dobs, 3)
+    ctx = _ctx(torch, w)
+    x, hist = ctx.cgnr(to_dev(torch, concat(dobs)), 3)
+    e = rel(x.cpu().numpy(), x_ref)
+    print("cgnr x rel", e, hist, hist_ref)
+    assert e <= 1e-3
+    assert np.allclose(hist, hist_ref, atol=1e-4)
+    assert all(hist[i + 1] <= hist[i] for i in range(3))
+
+
+def test_config1_full(torch):
+    """Config 1 at full size (100 x 200, nt = 1000, 200 receivers)."""
+    w = synth.config1()
+    prob = oracle_problem(w)
+    lnvp, lnip = f64(w.lnvp), f64(w.lnip)
+    ctx = _ctx(torch, w)
+    dd = ctx.born(to_dev(torch, w.dm)).cpu().numpy()
+    refd = O.born(prob, lnvp, lnip, f64(w.dm))
+    e = rel(dd, concat(refd))
+    print("config1 born rel", e)
+    assert e <= TOL
+    img = ctx.adjoint(to_dev(torch, concat(refd))).cpu().numpy()
+    refi = O.adjoint(prob, lnvp, lnip, refd, ckpt_every=50)
+    for k in range(2):
+        e = rel(img[k], refi[k])
+        print("config1 adjoint rel", k, e)
+        assert e <= TOL
+
+
+@pytest.mark.parametrize("dtype,bound", [("f16", 1e-3), ("bf16", 2e-2)])
+def test_compressed_checkpoints_error(torch, dtype, bound):
+    """FP16/BF16 snapshots with per-snapshot max-abs scaling: the image error
+    against the FP64 oracle is reported; the bound is this build's stated one."""
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((60, 80), nt=300, npml=10, seed=21, nshot=2, uneven=True)
+    prob = oracle_problem(w)
+    lnvp, lnip = f64(w.lnvp), f64(w.lnip)
+    rng = np.random.default_rng(5)
+    ys = [rng.standard_normal((w.nt, len(r))) for r in w.rec]
+    refi = O.adjoint(prob, lnvp, lnip, ys)
+    for k in (10, 50):
+        ctx = lsrtm.context_for(w, ckpt_every=k, ckpt_dtype=dtype)
+        img = ctx.adjoint(to_dev(torch, concat(ys))).cpu().numpy()
+        ctx.close()
+        e = max(rel(img[i], refi[i]) for i in range(2))
+        print(f"[compressed] {dtype} k={k} image rel err {e:.3e}")
+        assert e <= bound
+
+
+def test_error_paths(torch):
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((20, 30), nt=20, npml=4, seed=1)
+    # CFL violation
+    ctx = lsrtm.Context(w.n, w.h, w.nt, 0.05, npml=4)
+    with pytest.raises(lsrtm.LsrtmError) as ei:
+        ctx.set_model(to_dev(torch, w.lnvp), to_dev(torch, w.lnip))
+    assert ei.value.status == lsrtm.EUNSTABLE
+    # NaN model
+    ctx = lsrtm.Context(w.n, w.h, w.nt, w.dt, npml=4)
+    bad = w.lnvp.copy()
+    bad[3, 4] = np.nan
+    with pytest.raises(lsrtm.LsrtmError) as ei:
+        ctx.set_model(to_dev(torch, bad), to_dev(torch, w.lnip))
+    assert ei.value.status == lsrtm.ENONFINITE
+    # call order
+    ctx = lsrtm.Context(w.n, w.h, w.nt, w.dt, npml=4)
+    with pytest.raises(lsrtm.LsrtmError) as ei:
+        ctx.born(to_dev(torch, w.dm))
+    assert ei.value.status == lsrtm.ESTATE
+    ctx.set_model(to_dev(torch, w.lnvp), to_dev(torch, w.lnip))
+    # receiver outside its window
+    with pytest.raises(lsrtm.LsrtmError) as ei:
+        ctx.set_acquisition([((0, 20), (0, 10))], [(1, 2)], [np.array([[1, 15]])],
+                            to_dev(torch, w.wavelet[:1]))
+    assert ei.value.status == lsrtm.EINVAL
