@@ -1,0 +1,256 @@
+#!/usr/bin/env python
+"""Benchmark of the LSRTM hot path on one MI355X.
+
+Workload (default): the 2D data-domain LSRTM configuration -- seeded
+faulted-layered model, 737 x 240 nodes at 12.5 m (280 x 777 padded with a
+20-cell CPML), 120 shots at 25 m depth every 75 m, 369 receivers, 15 Hz
+Ricker, nt = 4000, dt = 1 ms, FP32 propagation -- solved by CGNR.  Observed
+data are Born data of the seeded true perturbation (synthetic).
+
+One "step" = one CGNR iteration over all 120 shots: a Born pass, a migration
+pass (checkpoint replay + adjoint + imaging), FP64 inner products and vector
+updates, all in the HIP library.  Timed region: K iterations after W warm-up
+iterations, bracketed by device synchronisation.
+
+value = grid-point updates per second of the two operator passes
+        2 * (sum over shots of padded nodes) * nt * K / time   [Gpts/s]
+
+Also reported: the roofline of the dominant kernel (algorithmic bytes per
+launch / average launch time from HIP events, against the 8 TB/s HBM peak),
+the plain per-shot CG-iteration time (one launch per shot, measured on a
+sample of shots and scaled by the shot count), and the FP64 oracle timed on
+the host cores on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Gpts/s Born+adjoint stencil & % HBM peak; CG-iter time batched vs plain FP32"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per padded node and launch (FP32, interior node,
+# every array read once and written once; CPML strips excluded).
+BYTES_PER_PT = {
+    2: {"born_v": 52, "born_p": 40, "bg_v": 36, "bg_p": 24, "adj_a": 36, "adj_b": 40},
+    3: {"born_v": 72, "born_p": 48, "bg_v": 48, "bg_p": 28, "adj_a": 44, "adj_b": 52},
+}
+KERNEL_SYMBOL = {"born_v": "k2_v<*, true, false>", "born_p": "k2_p<*, true, false>",
+                 "bg_v": "k2_v<*, false, true>", "bg_p": "k2_p<*, false, true>",
+                 "adj_a": "k2_a", "adj_b": "k2_b"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2508_10405_amd", "csrc"))):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(ROOT, "paper_2508_10405_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload_tag, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
+    summary, or None when it is missing or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{workload_tag}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    v = vals.get(f"traffic_bytes_per_launch.{kernel}")
+    return float(v) if v not in (None, "", "null") else None
+
+
+# ---------------------------------------------------------------------------
+def cpu_worker(args):
+    """FP64 oracle on one shot of the workload: Born + migration of nt_s steps."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    import numpy as np
+    from oracle import lsrtm_oracle as O
+    from paper_2508_10405_amd import synth
+    shot, nt_s = args
+    w = synth.config2(nt=nt_s)
+    prob = O.Problem(w.h, w.dt, nt_s, w.npml, w.pml_R, w.pml_freq, [w.win[shot]], [w.src[shot]],
+                     [w.rec[shot]], w.wavelet[shot:shot + 1].astype(np.float64))
+    lnvp, lnip = w.lnvp.astype(np.float64), w.lnip.astype(np.float64)
+    t0 = time.perf_counter()
+    dd = O.born(prob, lnvp, lnip, w.dm.astype(np.float64))
+    O.adjoint(prob, lnvp, lnip, dd)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(nt_s, workers, padded_per_shot):
+    from multiprocessing import get_context
+    ctx = get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        times = pool.map(cpu_worker, [(s, nt_s) for s in range(workers)])
+    wall = time.perf_counter() - t0
+    busy = max(times)
+    gpts = workers * 2 * padded_per_shot * nt_s / busy / 1e9
+    return {"value": gpts, "unit": "Gpts/s", "cores": workers, "kind": "oracle",
+            "sample": f"{workers} shots x {nt_s} of 4000 steps (Born + migration, one shot per "
+                      f"process, FP64 numpy); slowest process {busy:.1f} s, wall {wall:.1f} s"}
+
+
+# ---------------------------------------------------------------------------
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--plain-shots", type=int, default=12,
+                    help="shots of the plain per-shot CG iteration sample (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=100, help="time steps of the oracle sample")
+    ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes (0 = min(16, cores))")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a 1 GiB axpy (known traffic) for counter calibration")
+    ap.add_argument("--shots-per-launch", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=-1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the shot-parallel "
+              "multi-GPU layout is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2508_10405_amd import lsrtm, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    w = synth.config2()
+    tag = "config2_batched"
+    log(f"[bench] workload {w.name}: {w.nshot} shots, nt={w.nt}, padded points {w.padded_points()}")
+    ctx = lsrtm.context_for(w, shots_per_launch=args.shots_per_launch, tile=args.tile, timing=True)
+    sz = ctx.sizes()
+    log(f"[bench] plan {sz}")
+    dm = torch.from_numpy(w.dm).to(dev)
+    d_obs = ctx.born(dm)
+    torch.cuda.synchronize()
+    log("[bench] observed data done")
+    x = ctx.cgnr_begin(d_obs)
+    torch.cuda.synchronize()
+    log("[bench] initial migration done")
+    for i in range(args.warmup):
+        m = ctx.cgnr_iterate(x)
+        log(f"[bench] warmup iteration {i}: misfit {m:.6f}")
+    torch.cuda.synchronize()
+    kms = {k: 0.0 for k in lsrtm.KERNEL_NAMES}
+    kcnt = {k: 0 for k in lsrtm.KERNEL_NAMES}
+    misfit = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        misfit.append(ctx.cgnr_iterate(x))
+        st = ctx.stats()
+        for k in lsrtm.KERNEL_NAMES:
+            kms[k] += st[k][0]
+            kcnt[k] += st[k][1]
+        log(f"[bench] step {i}: misfit {misfit[-1]:.6f}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = (t1 - t0) / args.steps
+    padded = sz["padded_points"]
+    value = 2.0 * padded * w.nt / sec / 1e9
+
+    # roofline of the dominant kernel
+    pts_per_launch = padded / sz["groups"]
+    dom = max((k for k in BYTES_PER_PT[2]), key=lambda k: kms[k])
+    avg_ms = kms[dom] / max(1, kcnt[dom])
+    bytes_launch = BYTES_PER_PT[2][dom] * pts_per_launch
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    traffic = read_traffic(tag, dom)
+    kernels = {k: {"avg_ms": kms[k] / kcnt[k], "launches_timed": kcnt[k],
+                   "GBs": (BYTES_PER_PT[2][k] * pts_per_launch / (kms[k] / kcnt[k] * 1e-3) / 1e9)
+                   if k in BYTES_PER_PT[2] else None}
+               for k in lsrtm.KERNEL_NAMES if kcnt[k] > 0}
+    ctx.close()
+    del ctx, d_obs, x
+    torch.cuda.empty_cache()
+
+    # plain per-shot form on a sample of shots
+    plain = None
+    if args.plain_shots > 0:
+        P = min(args.plain_shots, w.nshot)
+        wp = synth.Workload(w.name, w.h, w.dt, w.nt, w.npml, w.f0, w.lnvp, w.lnip, w.dm,
+                            w.win[:P], w.src[:P], w.rec[:P], w.wavelet[:P])
+        cp = lsrtm.context_for(wp, shots_per_launch=1, tile=args.tile)
+        dp = cp.born(dm)
+        xp = cp.cgnr_begin(dp)
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        cp.cgnr_iterate(xp)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp0
+        plain = {"cg_iter_s": tp * w.nshot / P, "sample_shots": P, "sample_s": tp}
+        log(f"[bench] plain per-shot CG iteration: {tp:.2f} s for {P} shots")
+        cp.close()
+
+    calib = None
+    if args.calibrate:
+        n = 1 << 28
+        a = torch.ones(n, device=dev)
+        b = torch.ones(n, device=dev)
+        c2 = lsrtm.Context((4, 4), (10.0, 10.0), 1, 1e-3)
+        for _ in range(3):
+            c2.axpy(0.5, a, b)
+        torch.cuda.synchronize()
+        calib = {"kernel": "k_axpy", "elements": n, "read_bytes": 8 * n, "write_bytes": 4 * n}
+        log(f"[bench] calibration axpy {calib}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        cpu = cpu_baseline(args.cpu_steps, workers, padded // w.nshot)
+        log(f"[bench] cpu baseline {cpu}")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Gpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D LSRTM 737x240 @12.5 m (280x777 padded), 120 shots, 369 receivers, "
+                               "nt=4000, 15 Hz, CGNR step = Born + migration",
+                   "shots": w.nshot, "nt": w.nt, "padded_points": padded,
+                   "shots_per_launch": sz["shots_per_launch"], "ckpt_every": sz["ckpt_every"],
+                   "parallelism": "shots batched on 1 GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms},
+        "cpu_baseline": cpu,
+        "cg_iter_s_batched": sec,
+        "cg_iter_s_plain": plain,
+        "speedup_batched_vs_plain": (plain["cg_iter_s"] / sec) if plain else None,
+        "misfit": misfit,
+        "kernels": kernels,
+        "calibration": calib,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

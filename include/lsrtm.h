@@ -77,7 +77,9 @@ typedef struct {
 enum {
     LSRTM_OPT_SHOTS_PER_LAUNCH = 1, /* shots advanced by one kernel launch:
                                        1 = plain per-shot launches,
-                                       0 = as many as the memory plan allows    */
+                                       0 = as many as the memory plan allows;
+                                       after set_acquisition it rebuilds the
+                                       plan (stored checkpoints are dropped)    */
     LSRTM_OPT_TILE = 2,             /* stencil tile id (see lsrtm_tile_shape);
                                        -1 = autotune on the next pass           */
     LSRTM_OPT_GRAPH = 3,            /* 1 = replay the time loop from captured
@@ -136,6 +138,18 @@ lsrtm_status lsrtm_adjoint(lsrtm_ctx* ctx, const float* d, float* img, int accum
  * Workspace vectors are owned by the library. */
 lsrtm_status lsrtm_cgnr(lsrtm_ctx* ctx, const float* d_obs, int niter, float* x, double* misfit);
 
+/* Step-wise CGNR (the same iteration as lsrtm_cgnr).
+ * lsrtm_cgnr_begin: r = d_obs, x = 0, z = L^T r, p = z (one migration).
+ * lsrtm_cgnr_iterate: one iteration (one Born and one migration pass);
+ *   *misfit (HOST, may be NULL) receives ||r_k||^2 / ||r_0||^2.
+ * lsrtm_cgnr_state: get = 1 copies the solver state out (r: data length,
+ *   z and p: [2][nz*nx*ny], DEVICE), scal = HOST double[4] = (<z,z>,
+ *   <r0,r0>, <r,r>, k); get = 0 loads such a state back, so that a stopped
+ *   run resumes to the same iterates (x is the caller's vector). */
+lsrtm_status lsrtm_cgnr_begin(lsrtm_ctx* ctx, const float* d_obs, float* x);
+lsrtm_status lsrtm_cgnr_iterate(lsrtm_ctx* ctx, float* x, double* misfit);
+lsrtm_status lsrtm_cgnr_state(lsrtm_ctx* ctx, int get, float* r, float* z, float* p, double* scal);
+
 /* FP64-accumulated inner product of two DEVICE float vectors of length n;
  * *out is a HOST double.  Deterministic (fixed reduction tree). */
 lsrtm_status lsrtm_dot(lsrtm_ctx* ctx, const float* a, const float* b, long long n, double* out);
@@ -147,10 +161,19 @@ lsrtm_status lsrtm_axpy(lsrtm_ctx* ctx, double alpha, const float* x, float* y, 
 /* Set an LSRTM_OPT_* option. */
 lsrtm_status lsrtm_set_option(lsrtm_ctx* ctx, int key, long long value);
 
+/* Autotuner: times the six stencil phases over nsteps time steps on the
+ * actual launch groups for every tile shape, and with tune_groups = 1 also
+ * for several shot-per-launch sizes (rebuilding the memory plan), then keeps
+ * the fastest.  out (HOST double[3], may be NULL) = (tile id, shots per
+ * launch, ms per time step).  With LSRTM_TUNE_CACHE naming a file, results
+ * are read from and appended to it.  Invalidates stored checkpoints.  When
+ * no tile is set, a tile-only tuning runs on the first pass by itself. */
+lsrtm_status lsrtm_autotune(lsrtm_ctx* ctx, int nsteps, int tune_groups, double* out);
+
 /* Sizes: out[0] = data length, out[1] = physical grid points (one image),
  * out[2] = shots per launch, out[3] = checkpoint interval, out[4] = number of
  * launch groups, out[5] = padded points summed over shots, out[6] = device
- * bytes planned.  HOST long long [nout]. */
+ * bytes planned, out[7] = tile id in use.  HOST long long [nout]. */
 lsrtm_status lsrtm_sizes(lsrtm_ctx* ctx, long long* out, int nout);
 
 /* Timing statistics of the last pass (HOST double [nout]); see

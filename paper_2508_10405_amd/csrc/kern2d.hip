@@ -2,10 +2,13 @@
 //
 // Every launch advances all shots ("slots") of a launch group by one phase of
 // one time step.  The grid walks a tile table: tile t = (slot, z0, x0) covers
-// BZ x BX nodes of that slot's padded grid.  The input field of the phase's
-// derivative is staged with a 4-node halo in LDS; every other array is read
-// and written once, coalesced along z.  Values outside the padded grid are
-// zero, as the discrete operators define them.
+// BZ x BX nodes of that slot's padded grid, R = BZ*BX/256 nodes per thread.
+// Each thread first issues the loads of every array it reads pointwise (so
+// they are in flight while the tile is staged), then the input of the phase's
+// derivative is staged in LDS with the 4-node halo that derivative needs
+// (z-halo for z-derivatives, x-halo for x-derivatives), and after one barrier
+// every node is updated and written once, coalesced along z.  Values outside
+// the padded grid are zero, as the discrete operators define them.
 //
 // Phases (section 2 of the paper, first-order system and eq. scattereqln;
 // appendix A for the adjoint):
@@ -31,7 +34,28 @@ struct Tile2 {
     static constexpr int LX = BX + 2 * HW;
     static constexpr int NL = LZ * LX;
     static constexpr int NP = BZ * BX;
+    static constexpr int R = NP / NTHREADS;
+    static_assert(NP % NTHREADS == 0, "tile must hold a multiple of 256 nodes");
 };
+
+// Visit the LDS cells of rows [zl, zh) x columns [xl, xh) (tile-local, halo
+// included: 0 .. LZ-1, 0 .. LX-1) with the block's threads.
+template <int LZ, typename F>
+__device__ __forceinline__ void for_region(int zl, int zh, int xl, int xh, F f) {
+    const int nzr = zh - zl, n = nzr * (xh - xl);
+    for (int e = threadIdx.x; e < n; e += NTHREADS) {
+        const int lz = zl + e % nzr, lx = xl + e / nzr;
+        f(lz, lx, lx * LZ + lz);
+    }
+}
+
+// Node r of this thread in the tile.
+template <int BZ>
+__device__ __forceinline__ void node_of(int r, int& lz, int& lx) {
+    const int e = threadIdx.x + NTHREADS * r;
+    lz = e % BZ;
+    lx = e / BZ;
+}
 
 // ---------------------------------------------------------------------------
 // V phase
@@ -41,6 +65,7 @@ __global__ void __launch_bounds__(NTHREADS)
 k2_v(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
 {
     using T = Tile2<BZ, BX>;
+    constexpr int R = T::R;
     __shared__ float sp[T::NL];
     __shared__ float sq[BORN ? T::NL : 1];
     const int4 tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
@@ -48,31 +73,54 @@ k2_v(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
     const long long ldz = S.ldz;
-    const float* __restrict__ P = S.p;
-    const float* __restrict__ Q = S.q;
-    for (int e = threadIdx.x; e < T::NL; e += NTHREADS) {
-        const int lz = e % T::LZ, lx = e / T::LZ;
+    // pointwise loads
+    float vz[R], vx[R], bz[R], bx[R], wz[R], wx[R], r0[R], r1z[R], r1x[R];
+    bool ok[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int lz, lx;
+        node_of<BZ>(r, lz, lx);
+        const int gz = z0 + lz, gx = x0 + lx;
+        ok[r] = gz < nz && gx < nx;
+        const long long i = ok[r] ? gx * ldz + gz : 0;
+        vz[r] = S.v[0][i];
+        vx[r] = S.v[1][i];
+        bz[r] = S.bdt[0][i];
+        bx[r] = S.bdt[1][i];
+        if (BORN) {
+            wz[r] = S.w[0][i];
+            wx[r] = S.w[1][i];
+            r0[r] = S.dlnr[i];
+            r1z[r] = S.dlnr[gz + 1 < nz ? i + 1 : i];
+            r1x[r] = S.dlnr[gx + 1 < nx ? i + ldz : i];
+        }
+    }
+    // stage p (and dp): cross of z- and x-halos
+    auto ld = [&](int lz, int lx, int c) {
         const int gz = z0 + lz - HW, gx = x0 + lx - HW;
         const bool in = (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx;
         const long long i = gx * ldz + gz;
-        sp[e] = in ? P[i] : 0.f;
-        if (BORN) sq[e] = in ? Q[i] : 0.f;
-    }
+        sp[c] = in ? S.p[i] : 0.f;
+        if (BORN) sq[c] = in ? S.q[i] : 0.f;
+    };
+    for_region<T::LZ>(0, T::LZ, HW, HW + BX, ld);          // interior columns with z-halo
+    for_region<T::LZ>(HW, HW + BZ, 0, HW, ld);             // left x-halo
+    for_region<T::LZ>(HW, HW + BZ, HW + BX, T::LX, ld);    // right x-halo
     __syncthreads();
     const float* achz = S.cpml[0];
     const float* bchz = S.cpml[0] + nz;
     const float* achx = S.cpml[1];
     const float* bchx = S.cpml[1] + nx;
     float* __restrict__ seg = S.seg + (long long)sstep * 3 * S.npts;
-    for (int e = threadIdx.x; e < T::NP; e += NTHREADS) {
-        const int lz = e % BZ, lx = e / BZ;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!ok[r]) continue;
+        int lz, lx;
+        node_of<BZ>(r, lz, lx);
         const int gz = z0 + lz, gx = x0 + lx;
-        if (gz >= nz || gx >= nx) continue;
         const long long i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
         const float az = achz[gz], ax = achx[gx];
-        const float bz = S.bdt[0][i], bx = S.bdt[1][i];
-        // background
         float gzp = d_half(sp, c, 1, C.c[0]);
         float gxp = d_half(sp, c, T::LZ, C.c[1]);
         if (az != 0.f) {
@@ -85,10 +133,10 @@ k2_v(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
             S.psi[1][i] = ps;
             gxp = gxp + ps;
         }
-        const float dvz = -bz * gzp;
-        const float dvx = -bx * gxp;
-        S.v[0][i] = S.v[0][i] + dvz;
-        S.v[1][i] = S.v[1][i] + dvx;
+        const float dvz = -bz[r] * gzp;
+        const float dvx = -bx[r] * gxp;
+        S.v[0][i] = vz[r] + dvz;
+        S.v[1][i] = vx[r] + dvx;
         if (SEG) {
             seg[i] = dvz;
             seg[S.npts + i] = dvx;
@@ -106,11 +154,10 @@ k2_v(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
                 S.xi[1][i] = ps;
                 gxq = gxq + ps;
             }
-            const float r0 = S.dlnr[i];
-            const float rz = 0.5f * (r0 + S.dlnr[gz + 1 < nz ? i + 1 : i]);
-            const float rx = 0.5f * (r0 + S.dlnr[gx + 1 < nx ? i + ldz : i]);
-            S.w[0][i] = (S.w[0][i] - bz * gzq) - rz * dvz;
-            S.w[1][i] = (S.w[1][i] - bx * gxq) - rx * dvx;
+            const float rz = 0.5f * (r0[r] + r1z[r]);
+            const float rx = 0.5f * (r0[r] + r1x[r]);
+            S.w[0][i] = (wz[r] - bz[r] * gzq) - rz * dvz;
+            S.w[1][i] = (wx[r] - bx[r] * gxq) - rx * dvx;
         }
     }
 }
@@ -123,6 +170,7 @@ __global__ void __launch_bounds__(NTHREADS)
 k2_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
 {
     using T = Tile2<BZ, BX>;
+    constexpr int R = T::R;
     __shared__ float svz[T::NL];
     __shared__ float svx[T::NL];
     __shared__ float swz[BORN ? T::NL : 1];
@@ -132,18 +180,38 @@ k2_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
     const long long ldz = S.ldz;
-    for (int e = threadIdx.x; e < T::NL; e += NTHREADS) {
-        const int lz = e % T::LZ, lx = e / T::LZ;
+    float pp[R], kk[R], qq[R], lk[R];
+    bool ok[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int lz, lx;
+        node_of<BZ>(r, lz, lx);
+        const int gz = z0 + lz, gx = x0 + lx;
+        ok[r] = gz < nz && gx < nx;
+        const long long i = ok[r] ? gx * ldz + gz : 0;
+        pp[r] = S.p[i];
+        kk[r] = S.kdt[i];
+        if (BORN) {
+            qq[r] = S.q[i];
+            lk[r] = S.dlnk[i];
+        }
+    }
+    auto ldz_ = [&](int lz, int lx, int c) {   // v_z (and w_z) with z-halo
         const int gz = z0 + lz - HW, gx = x0 + lx - HW;
         const bool in = (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx;
         const long long i = gx * ldz + gz;
-        svz[e] = in ? S.v[0][i] : 0.f;
-        svx[e] = in ? S.v[1][i] : 0.f;
-        if (BORN) {
-            swz[e] = in ? S.w[0][i] : 0.f;
-            swx[e] = in ? S.w[1][i] : 0.f;
-        }
-    }
+        svz[c] = in ? S.v[0][i] : 0.f;
+        if (BORN) swz[c] = in ? S.w[0][i] : 0.f;
+    };
+    auto ldx_ = [&](int lz, int lx, int c) {   // v_x (and w_x) with x-halo
+        const int gz = z0 + lz - HW, gx = x0 + lx - HW;
+        const bool in = (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx;
+        const long long i = gx * ldz + gz;
+        svx[c] = in ? S.v[1][i] : 0.f;
+        if (BORN) swx[c] = in ? S.w[1][i] : 0.f;
+    };
+    for_region<T::LZ>(0, T::LZ, HW, HW + BX, ldz_);
+    for_region<T::LZ>(HW, HW + BZ, 0, T::LX, ldx_);
     __syncthreads();
     const float* aciz = S.cpml[0] + 2 * nz;
     const float* bciz = S.cpml[0] + 3 * nz;
@@ -151,10 +219,12 @@ k2_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
     const float* bcix = S.cpml[1] + 3 * nx;
     const float amp = S.src >= 0 ? S.src_amp[n] : 0.f;
     float* __restrict__ seg = S.seg + (long long)sstep * 3 * S.npts + 2 * S.npts;
-    for (int e = threadIdx.x; e < T::NP; e += NTHREADS) {
-        const int lz = e % BZ, lx = e / BZ;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!ok[r]) continue;
+        int lz, lx;
+        node_of<BZ>(r, lz, lx);
         const int gz = z0 + lz, gx = x0 + lx;
-        if (gz >= nz || gx >= nx) continue;
         const long long i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
         const float az = aciz[gz], ax = acix[gx];
@@ -171,8 +241,8 @@ k2_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
             ex = ex + ph;
         }
         const float q = ez + ex;
-        const float k = S.kdt[i];
-        float pn = S.p[i] - k * q;
+        const float k = kk[r];
+        float pn = pp[r] - k * q;
         if (i == S.src) pn = pn + amp;
         S.p[i] = pn;
         if (SEG) seg[i] = q;
@@ -190,7 +260,7 @@ k2_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
                 fx = fx + ph;
             }
             const float dq = fz + fx;
-            S.q[i] = (S.q[i] - k * dq) + S.dlnk[i] * (-k * q);
+            S.q[i] = (qq[r] - k * dq) + lk[r] * (-k * q);
         }
     }
 }
@@ -205,6 +275,7 @@ __global__ void __launch_bounds__(NTHREADS)
 k2_a(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
 {
     using T = Tile2<BZ, BX>;
+    constexpr int R = T::R;
     __shared__ float sez[T::NL];
     __shared__ float sex[T::NL];
     const int4 tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
@@ -212,10 +283,27 @@ k2_a(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
     const long long ldz = S.ldz;
+    const float* __restrict__ segq = S.seg + (long long)sstep * 3 * S.npts + 2 * S.npts;
+    float vz[R], vx[R], gk[R], qn[R], pt[R], kk[R];
+    bool ok[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int lz, lx;
+        node_of<BZ>(r, lz, lx);
+        const int gz = z0 + lz, gx = x0 + lx;
+        ok[r] = gz < nz && gx < nx;
+        const long long i = ok[r] ? gx * ldz + gz : 0;
+        vz[r] = S.w[0][i];
+        vx[r] = S.w[1][i];
+        gk[r] = S.gk[i];
+        qn[r] = segq[i];
+        pt[r] = S.q[i];
+        kk[r] = S.kdt[i];
+    }
     const float* aciz = S.cpml[0] + 2 * nz;
     const float* acix = S.cpml[1] + 2 * nx;
-    for (int e = threadIdx.x; e < T::NL; e += NTHREADS) {
-        const int lz = e % T::LZ, lx = e / T::LZ;
+    // interior: both e~_z and e~_x; z-halo rows: e~_z; x-halo columns: e~_x
+    auto ld = [&](int lz, int lx, int c, bool wz, bool wx) {
         const int gz = z0 + lz - HW, gx = x0 + lx - HW;
         const bool in = (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx;
         float ez = 0.f, ex = 0.f;
@@ -224,37 +312,44 @@ k2_a(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
             const float qt = -S.kdt[i] * S.q[i];
             ez = qt;
             ex = qt;
-            const float az = aciz[gz], ax = acix[gx];
-            if (az != 0.f) ez = qt + az * (S.eta[0][i] + qt);
-            if (ax != 0.f) ex = qt + ax * (S.eta[1][i] + qt);
+            if (wz) {
+                const float az = aciz[gz];
+                if (az != 0.f) ez = qt + az * (S.eta[0][i] + qt);
+            }
+            if (wx) {
+                const float ax = acix[gx];
+                if (ax != 0.f) ex = qt + ax * (S.eta[1][i] + qt);
+            }
         }
-        sez[e] = ez;
-        sex[e] = ex;
-    }
+        if (wz) sez[c] = ez;
+        if (wx) sex[c] = ex;
+    };
+    for_region<T::LZ>(HW, HW + BZ, HW, HW + BX, [&](int a, int b, int c) { ld(a, b, c, true, true); });
+    for_region<T::LZ>(0, HW, HW, HW + BX, [&](int a, int b, int c) { ld(a, b, c, true, false); });
+    for_region<T::LZ>(HW + BZ, T::LZ, HW, HW + BX, [&](int a, int b, int c) { ld(a, b, c, true, false); });
+    for_region<T::LZ>(HW, HW + BZ, 0, HW, [&](int a, int b, int c) { ld(a, b, c, false, true); });
+    for_region<T::LZ>(HW, HW + BZ, HW + BX, T::LX, [&](int a, int b, int c) { ld(a, b, c, false, true); });
     __syncthreads();
     const float* achz = S.cpml[0];
     const float* bchz = S.cpml[0] + nz;
     const float* achx = S.cpml[1];
     const float* bchx = S.cpml[1] + nx;
-    const float* __restrict__ segq = S.seg + (long long)sstep * 3 * S.npts + 2 * S.npts;
-    for (int e = threadIdx.x; e < T::NP; e += NTHREADS) {
-        const int lz = e % BZ, lx = e / BZ;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!ok[r]) continue;
+        int lz, lx;
+        node_of<BZ>(r, lz, lx);
         const int gz = z0 + lz, gx = x0 + lx;
-        if (gz >= nz || gx >= nx) continue;
         const long long i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
-        float vz = S.w[0][i], vx = S.w[1][i];
         if (!flag) {
             const float hz = achz[gz], hx = achx[gx];
-            if (hz != 0.f) S.xi[0][i] = bchz[gz] * (S.xi[0][i] + (-S.bdt[0][i] * vz));
-            if (hx != 0.f) S.xi[1][i] = bchx[gx] * (S.xi[1][i] + (-S.bdt[1][i] * vx));
+            if (hz != 0.f) S.xi[0][i] = bchz[gz] * (S.xi[0][i] + (-S.bdt[0][i] * vz[r]));
+            if (hx != 0.f) S.xi[1][i] = bchx[gx] * (S.xi[1][i] + (-S.bdt[1][i] * vx[r]));
         }
-        const float k = S.kdt[i];
-        S.gk[i] = S.gk[i] + (-k * segq[i]) * S.q[i];
-        vz = vz - d_half(sez, c, 1, C.c[0]);
-        vx = vx - d_half(sex, c, T::LZ, C.c[1]);
-        S.w[0][i] = vz;
-        S.w[1][i] = vx;
+        S.gk[i] = gk[r] + qn[r] * (-kk[r] * pt[r]);
+        S.w[0][i] = vz[r] - d_half(sez, c, 1, C.c[0]);
+        S.w[1][i] = vx[r] - d_half(sex, c, T::LZ, C.c[1]);
     }
 }
 
@@ -268,6 +363,7 @@ __global__ void __launch_bounds__(NTHREADS)
 k2_b(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
 {
     using T = Tile2<BZ, BX>;
+    constexpr int R = T::R;
     __shared__ float sgz[T::NL];
     __shared__ float sgx[T::NL];
     const int4 tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
@@ -275,53 +371,74 @@ k2_b(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
     const long long ldz = S.ldz;
+    const float* __restrict__ segz = S.seg + (long long)sstep * 3 * S.npts;
+    const float* __restrict__ segx = segz + S.npts;
+    float pt[R], gr[R], xz0[R], xz1[R], xx0[R], xx1[R];
+    bool ok[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int lz, lx;
+        node_of<BZ>(r, lz, lx);
+        const int gz = z0 + lz, gx = x0 + lx;
+        ok[r] = gz < nz && gx < nx;
+        const long long i = ok[r] ? gx * ldz + gz : 0;
+        pt[r] = S.q[i];
+        gr[r] = S.gr[i];
+        // lnrho imaging terms with the transpose of the half-node average
+        xz0[r] = -segz[i] * S.w[0][i];
+        xz1[r] = (ok[r] && gz > 0) ? -segz[i - 1] * S.w[0][i - 1] : 0.f;
+        xx0[r] = -segx[i] * S.w[1][i];
+        xx1[r] = (ok[r] && gx > 0) ? -segx[i - ldz] * S.w[1][i - ldz] : 0.f;
+    }
     const float* achz = S.cpml[0];
     const float* achx = S.cpml[1];
-    for (int e = threadIdx.x; e < T::NL; e += NTHREADS) {
-        const int lz = e % T::LZ, lx = e / T::LZ;
+    auto ldz_ = [&](int lz, int lx, int c) {
         const int gz = z0 + lz - HW, gx = x0 + lx - HW;
-        const bool in = (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx;
-        float gzv = 0.f, gxv = 0.f;
-        if (in) {
+        float g = 0.f;
+        if ((unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx) {
             const long long i = gx * ldz + gz;
-            const float hz = -S.bdt[0][i] * S.w[0][i];
-            const float hx = -S.bdt[1][i] * S.w[1][i];
-            gzv = hz;
-            gxv = hx;
-            const float az = achz[gz], ax = achx[gx];
-            if (az != 0.f) gzv = hz + az * (S.xi[0][i] + hz);
-            if (ax != 0.f) gxv = hx + ax * (S.xi[1][i] + hx);
+            const float h = -S.bdt[0][i] * S.w[0][i];
+            const float a = achz[gz];
+            g = a != 0.f ? h + a * (S.xi[0][i] + h) : h;
         }
-        sgz[e] = gzv;
-        sgx[e] = gxv;
-    }
+        sgz[c] = g;
+    };
+    auto ldx_ = [&](int lz, int lx, int c) {
+        const int gz = z0 + lz - HW, gx = x0 + lx - HW;
+        float g = 0.f;
+        if ((unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx) {
+            const long long i = gx * ldz + gz;
+            const float h = -S.bdt[1][i] * S.w[1][i];
+            const float a = achx[gx];
+            g = a != 0.f ? h + a * (S.xi[1][i] + h) : h;
+        }
+        sgx[c] = g;
+    };
+    for_region<T::LZ>(0, T::LZ, HW, HW + BX, ldz_);
+    for_region<T::LZ>(HW, HW + BZ, 0, T::LX, ldx_);
     __syncthreads();
     const float* aciz = S.cpml[0] + 2 * nz;
     const float* bciz = S.cpml[0] + 3 * nz;
     const float* acix = S.cpml[1] + 2 * nx;
     const float* bcix = S.cpml[1] + 3 * nx;
-    const float* __restrict__ segz = S.seg + (long long)sstep * 3 * S.npts;
-    const float* __restrict__ segx = segz + S.npts;
-    for (int e = threadIdx.x; e < T::NP; e += NTHREADS) {
-        const int lz = e % BZ, lx = e / BZ;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!ok[r]) continue;
+        int lz, lx;
+        node_of<BZ>(r, lz, lx);
         const int gz = z0 + lz, gx = x0 + lx;
-        if (gz >= nz || gx >= nx) continue;
         const long long i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
-        const float pt = S.q[i];
-        const float qt = -S.kdt[i] * pt;
         const float az = aciz[gz], ax = acix[gx];
-        if (az != 0.f) S.eta[0][i] = bciz[gz] * (S.eta[0][i] + qt);
-        if (ax != 0.f) S.eta[1][i] = bcix[gx] * (S.eta[1][i] + qt);
-        // lnrho imaging with the transpose of the half-node average
-        const float xz0 = -segz[i] * S.w[0][i];
-        const float xz1 = gz > 0 ? -segz[i - 1] * S.w[0][i - 1] : 0.f;
-        const float xx0 = -segx[i] * S.w[1][i];
-        const float xx1 = gx > 0 ? -segx[i - ldz] * S.w[1][i - ldz] : 0.f;
-        S.gr[i] = S.gr[i] + (0.5f * (xz0 + xz1) + 0.5f * (xx0 + xx1));
+        if (az != 0.f || ax != 0.f) {
+            const float qt = -S.kdt[i] * pt[r];
+            if (az != 0.f) S.eta[0][i] = bciz[gz] * (S.eta[0][i] + qt);
+            if (ax != 0.f) S.eta[1][i] = bcix[gx] * (S.eta[1][i] + qt);
+        }
+        S.gr[i] = gr[r] + (0.5f * (xz0[r] + xz1[r]) + 0.5f * (xx0[r] + xx1[r]));
         const float dz = d_node(sgz, c, 1, C.c[0]);
         const float dx = d_node(sgx, c, T::LZ, C.c[1]);
-        S.q[i] = pt - (dz + dx);
+        S.q[i] = pt[r] - (dz + dx);
     }
 }
 
@@ -347,8 +464,8 @@ static hipError_t launch2_t(int kind, int ntiles, hipStream_t st, const Slot* sl
     return hipGetLastError();
 }
 
-const int kTiles2[][2] = {{32, 4}, {32, 8}, {32, 16}, {64, 4}, {64, 8}, {64, 16},
-                          {128, 4}, {128, 8}, {128, 16}};
+const int kTiles2[][2] = {{32, 8}, {32, 16}, {32, 32}, {64, 4}, {64, 8}, {64, 16},
+                          {128, 4}, {128, 8}, {256, 4}};
 const int kNumTiles2 = 9;
 
 hipError_t launch2d(int kind, int tile_id, int ntiles, hipStream_t st, const Slot* slots,
@@ -356,15 +473,15 @@ hipError_t launch2d(int kind, int tile_id, int ntiles, hipStream_t st, const Slo
 {
     if (ntiles <= 0) return hipSuccess;
     switch (tile_id) {
-    case 0: return launch2_t<32, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 1: return launch2_t<32, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 2: return launch2_t<32, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    case 0: return launch2_t<32, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    case 1: return launch2_t<32, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    case 2: return launch2_t<32, 32>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
     case 3: return launch2_t<64, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
     case 4: return launch2_t<64, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
     case 5: return launch2_t<64, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
     case 6: return launch2_t<128, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
     case 7: return launch2_t<128, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 8: return launch2_t<128, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    case 8: return launch2_t<256, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
     default: return hipErrorInvalidValue;
     }
 }

@@ -124,6 +124,9 @@ struct lsrtm_ctx {
     float* cg_w = nullptr;
     float* cg_z = nullptr;
     float* cg_p = nullptr;
+    double cg_zz = 0.0, cg_r0 = 0.0, cg_rr = 0.0;
+    int cg_k = 0;
+    bool cg_active = false;
     // options
     int opt_spl = 0;
     int opt_tile = -1;
@@ -133,10 +136,21 @@ struct lsrtm_ctx {
     // timing
     std::vector<EvPair> evpool;
     size_t evused = 0;
+    int tstride = 16;              // time the launches of every tstride-th step
+    bool tnow = true;              // the current step is timed
+    bool tpending = false;
     double kms[LSRTM_NKERNEL] = {0};
     long long kcnt[LSRTM_NKERNEL] = {0};
     double pass_ms = 0.0;
     hipEvent_t pa = nullptr, pb = nullptr;
+    // acquisition inputs (kept so that the plan can be rebuilt)
+    std::vector<int> a_win, a_src, a_recptr, a_rec;
+    float* wavelet = nullptr;      // device copy [nshot][nt]
+    // HIP graphs of whole passes, per launch group
+    std::map<std::tuple<int, int, const void*, int>, hipGraphExec_t> graphs;
+    hipStream_t gst = nullptr;     // capture/replay stream (default priority)
+    hipEvent_t gin = nullptr, gout = nullptr;
+    bool tuned = false;
     // allocations
     std::vector<void*> allocs;
     std::vector<void*> acq_allocs;
@@ -183,7 +197,13 @@ lsrtm_status dalloc_t(lsrtm_ctx* c, T** p, size_t n, bool acq) {
     return dalloc(c, reinterpret_cast<void**>(p), n * sizeof(T), acq);
 }
 
+void clear_graphs(lsrtm_ctx* c) {
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
 void free_acq(lsrtm_ctx* c) {
+    clear_graphs(c);
     for (void* p : c->acq_allocs) (void)hipFree(p);
     c->acq_allocs.clear();
     c->groups.clear();
@@ -198,6 +218,7 @@ void free_acq(lsrtm_ctx* c) {
     c->ckpart = nullptr;
     c->acc64 = nullptr;
     c->cg_r = c->cg_w = c->cg_z = c->cg_p = nullptr;
+    c->cg_active = false;
     c->src_amp = nullptr;
 }
 
@@ -237,7 +258,8 @@ long long strip_count_h(const int N[3], int a, int Sd) {
 // Timing
 // ---------------------------------------------------------------------------
 void tbeg(lsrtm_ctx* c, int cls) {
-    if (!c->opt_timing) return;
+    c->tpending = false;
+    if (!c->opt_timing || !c->tnow) return;
     if (c->evused == c->evpool.size()) {
         EvPair e;
         if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) {
@@ -249,13 +271,17 @@ void tbeg(lsrtm_ctx* c, int cls) {
     EvPair& e = c->evpool[c->evused];
     e.cls = cls;
     (void)hipEventRecord(e.a, c->st);
+    c->tpending = true;
 }
 
 void tend(lsrtm_ctx* c) {
-    if (!c->opt_timing) return;
+    if (!c->tpending) return;
     (void)hipEventRecord(c->evpool[c->evused].b, c->st);
     c->evused++;
+    c->tpending = false;
 }
+
+void tstep(lsrtm_ctx* c, int n) { c->tnow = (n % c->tstride) == 0; }
 
 lsrtm_status pass_begin(lsrtm_ctx* c) {
     for (int i = 0; i < LSRTM_NKERNEL; ++i) {
@@ -290,7 +316,7 @@ lsrtm_status pass_end(lsrtm_ctx* c) {
 // ---------------------------------------------------------------------------
 // Tiles
 // ---------------------------------------------------------------------------
-int default_tile(int ndim) { return ndim == 2 ? 4 : 1; }
+int default_tile(int ndim) { return ndim == 2 ? 1 : 1; }
 
 void tile_shape(int ndim, int id, int* bz, int* bx, int* by) {
     if (ndim == 2) {
@@ -386,6 +412,7 @@ lsrtm_status group_forward(lsrtm_ctx* c, Group& gr, int mode, float* d, bool wri
     const int kv = mode == 1 ? K_BORN_V : K_BG_V;
     const int kp = mode == 1 ? K_BORN_P : K_BG_P;
     for (int n = 0; n < c->g.nt; ++n) {
+        tstep(c, n);
         if (write_ck && n > 0 && n % c->k == 0) CHK(ckpt(c, gr, n / c->k, true));
         CHK(stencil(c, gr, kv, n, 0, 0));
         CHK(stencil(c, gr, kp, n, 0, 0));
@@ -412,16 +439,20 @@ lsrtm_status group_adjoint(lsrtm_ctx* c, Group& gr, const float* d) {
         if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "inject: %s", hipGetErrorString(e));
         return LSRTM_OK;
     };
+    tstep(c, nt - 1);
     CHK(inject(nt - 1));
     for (int j = c->nseg - 1; j >= 0; --j) {
         const int n0 = j * c->k, n1 = std::min(n0 + c->k, nt);
+        tstep(c, n0);
         if (j == 0) CHK(fill(c, c->pool, gr.bg_used));
         else CHK(ckpt(c, gr, j, false));
         for (int n = n0; n < n1; ++n) {
+            tstep(c, n);
             CHK(stencil(c, gr, K_SEG_V, n, n - n0, 0));
             CHK(stencil(c, gr, K_SEG_P, n, n - n0, 0));
         }
         for (int n = n1 - 1; n >= n0; --n) {
+            tstep(c, n);
             if (n < nt - 1) CHK(inject(n));
             CHK(stencil(c, gr, K_ADJ_A, n, n - n0, n == nt - 1 ? 1 : 0));
             CHK(stencil(c, gr, K_ADJ_B, n, n - n0, 0));
@@ -440,6 +471,60 @@ lsrtm_status group_adjoint(lsrtm_ctx* c, Group& gr, const float* d) {
     return LSRTM_OK;
 }
 
+// Passes are captured into one HIP graph per (pass, launch group, data
+// pointer, checkpoint flag) and replayed on later calls; with per-launch
+// timing requested they run as plain launches.  Graph replay is used when
+// the group's launches are short enough for launch overhead to matter.
+enum { P_FWD = 0, P_BORN = 1, P_FWDCK = 2, P_ADJ = 3 };
+
+lsrtm_status run_direct(lsrtm_ctx* c, Group& gr, int pass, float* d, bool write_ck) {
+    if (pass == P_ADJ) return group_adjoint(c, gr, d);
+    return group_forward(c, gr, pass == P_BORN ? 1 : (pass == P_FWDCK ? 2 : 0), d, write_ck);
+}
+
+bool use_graph(const lsrtm_ctx* c) {
+    return c->opt_graph && !c->opt_timing && (long long)c->groups.size() * c->g.nt <= 400000;
+}
+
+lsrtm_status run_group(lsrtm_ctx* c, Group& gr, int gi, int pass, float* d, bool write_ck) {
+    if (!use_graph(c)) return run_direct(c, gr, pass, d, write_ck);
+    CHK(build_tiles(c, gr, c->tile));
+    if (!c->gst) {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->gst, hipStreamNonBlocking));
+        HIPCHK(c, hipEventCreateWithFlags(&c->gin, hipEventDisableTiming));
+        HIPCHK(c, hipEventCreateWithFlags(&c->gout, hipEventDisableTiming));
+    }
+    const auto key = std::make_tuple(pass * 2 + (write_ck ? 1 : 0), gi, (const void*)d, c->tile);
+    auto it = c->graphs.find(key);
+    hipGraphExec_t exec = nullptr;
+    if (it == c->graphs.end()) {
+        hipStream_t user = c->st;
+        HIPCHK(c, hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal));
+        c->st = c->gst;
+        lsrtm_status s = run_direct(c, gr, pass, d, write_ck);
+        c->st = user;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(c->gst, &graph);
+        if (s != LSRTM_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return s;
+        }
+        if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+        c->graphs[key] = exec;
+    } else {
+        exec = it->second;
+    }
+    HIPCHK(c, hipEventRecord(c->gin, c->st));
+    HIPCHK(c, hipStreamWaitEvent(c->gst, c->gin, 0));
+    HIPCHK(c, hipGraphLaunch(exec, c->gst));
+    HIPCHK(c, hipEventRecord(c->gout, c->gst));
+    HIPCHK(c, hipStreamWaitEvent(c->st, c->gout, 0));
+    return LSRTM_OK;
+}
+
 lsrtm_status ensure_ckpts(lsrtm_ctx* c) {
     if (c->ckpt_valid) return LSRTM_OK;
     for (auto& gr : c->groups) CHK(group_forward(c, gr, 2, nullptr, true));
@@ -448,12 +533,19 @@ lsrtm_status ensure_ckpts(lsrtm_ctx* c) {
     return LSRTM_OK;
 }
 
+lsrtm_status autotune(lsrtm_ctx* c, int nsteps, bool groups, double* out);
+lsrtm_status plan(lsrtm_ctx* c);
+
 lsrtm_status check_ready(lsrtm_ctx* c) {
     if (!c) return LSRTM_EINVAL;
     if (!c->have_model) FAIL(c, LSRTM_ESTATE, "set_model has not been called");
     if (!c->have_acq) FAIL(c, LSRTM_ESTATE, "set_acquisition has not been called");
-    if (c->opt_tile < 0 && c->tile < 0) c->tile = default_tile(c->ndim);
-    else if (c->opt_tile >= 0) c->tile = c->opt_tile;
+    if (c->opt_tile >= 0) {
+        c->tile = c->opt_tile;
+    } else if (!c->tuned) {
+        c->tile = default_tile(c->ndim);
+        CHK(autotune(c, 4, false, nullptr));
+    }
     return LSRTM_OK;
 }
 
@@ -497,162 +589,13 @@ lsrtm_status prep_model_windows(lsrtm_ctx* c) {
     return LSRTM_OK;
 }
 
-}  // namespace
-
-// ===========================================================================
-// C ABI
-// ===========================================================================
-extern "C" {
-
-const char* lsrtm_strerror(int s) {
-    switch (s) {
-    case LSRTM_OK: return "ok";
-    case LSRTM_EINVAL: return "invalid argument";
-    case LSRTM_ENOMEM: return "out of device memory";
-    case LSRTM_EHIP: return "HIP runtime error";
-    case LSRTM_EUNSTABLE: return "CFL stability condition violated";
-    case LSRTM_ENONFINITE: return "non-finite value";
-    case LSRTM_ESTATE: return "call out of order";
-    default: return "unknown status";
-    }
-}
-
-const char* lsrtm_last_error(lsrtm_ctx* c) { return c ? c->err.c_str() : ""; }
-
-lsrtm_status lsrtm_tile_shape(int ndim, int id, int* out) {
-    if (!out) return LSRTM_EINVAL;
-    if (ndim == 2 && id >= 0 && id < kNumTiles2) {
-        out[0] = kTiles2[id][0];
-        out[1] = kTiles2[id][1];
-        return LSRTM_OK;
-    }
-    if (ndim == 3 && id >= 0 && id < kNumTiles3) {
-        out[0] = kTiles3[id][0];
-        out[1] = kTiles3[id][1];
-        return LSRTM_OK;
-    }
-    return LSRTM_EINVAL;
-}
-
-lsrtm_status lsrtm_create(const lsrtm_grid* g, void* stream, lsrtm_ctx** out) {
-    if (!g || !out) return LSRTM_EINVAL;
-    *out = nullptr;
-    if (g->ndim != 2 && g->ndim != 3) return LSRTM_EINVAL;
-    for (int a = 0; a < g->ndim; ++a)
-        if (g->n[a] < 1 || !(g->h[a] > 0.0)) return LSRTM_EINVAL;
-    if (g->ndim == 2 && g->n[2] != 1) return LSRTM_EINVAL;
-    if (g->npml < 0 || g->nt < 1 || !(g->dt > 0.0)) return LSRTM_EINVAL;
-    if (g->npml > 0 && !(g->pml_R > 0.0 && g->pml_R < 1.0)) return LSRTM_EINVAL;
-    if (g->ckpt_every < 0 || g->ckpt_dtype < 0 || g->ckpt_dtype > 2) return LSRTM_EINVAL;
-    lsrtm_ctx* c = new lsrtm_ctx();
-    c->g = *g;
-    if (g->ndim == 2) c->g.h[2] = 1.0;
-    c->st = reinterpret_cast<hipStream_t>(stream);
-    c->ndim = g->ndim;
-    for (int a = 0; a < 3; ++a)
-        for (int k = 0; k < 4; ++k) c->C.c[a][k] = (float)(kC8[k] / c->g.h[a]);
-    c->gpts = (long long)g->n[0] * g->n[1] * g->n[2];
-    c->S = strip_depth(c);
-    *out = c;
-    return LSRTM_OK;
-}
-
-void lsrtm_destroy(lsrtm_ctx* c) {
-    if (!c) return;
-    (void)hipStreamSynchronize(c->st);
-    free_acq(c);
-    for (void* p : c->allocs) (void)hipFree(p);
-    for (auto& e : c->evpool) {
-        (void)hipEventDestroy(e.a);
-        (void)hipEventDestroy(e.b);
-    }
-    if (c->pa) (void)hipEventDestroy(c->pa);
-    if (c->pb) (void)hipEventDestroy(c->pb);
-    delete c;
-}
-
-lsrtm_status lsrtm_set_option(lsrtm_ctx* c, int key, long long v) {
-    if (!c) return LSRTM_EINVAL;
-    switch (key) {
-    case LSRTM_OPT_SHOTS_PER_LAUNCH:
-        if (v < 0) FAIL(c, LSRTM_EINVAL, "shots per launch must be >= 0");
-        if (c->have_acq) FAIL(c, LSRTM_ESTATE, "set shots per launch before set_acquisition");
-        c->opt_spl = (int)v;
-        return LSRTM_OK;
-    case LSRTM_OPT_TILE: {
-        const int nt = c->ndim == 2 ? kNumTiles2 : kNumTiles3;
-        if (v < -1 || v >= nt) FAIL(c, LSRTM_EINVAL, "tile id %lld out of range", v);
-        c->opt_tile = (int)v;
-        c->tile = (int)v;
-        return LSRTM_OK;
-    }
-    case LSRTM_OPT_GRAPH: c->opt_graph = v != 0; return LSRTM_OK;
-    case LSRTM_OPT_TIMING: c->opt_timing = v != 0; return LSRTM_OK;
-    case LSRTM_OPT_MEM_BUDGET_MB:
-        if (v < 0) FAIL(c, LSRTM_EINVAL, "memory budget must be >= 0");
-        c->opt_budget_mb = v;
-        return LSRTM_OK;
-    default: FAIL(c, LSRTM_EINVAL, "unknown option %d", key);
-    }
-}
-
-lsrtm_status lsrtm_set_model(lsrtm_ctx* c, const float* lnvp, const float* lnip) {
-    if (!c || !lnvp || !lnip) return LSRTM_EINVAL;
-    if (!c->lnvp) {
-        CHK(dalloc_t(c, &c->lnvp, c->gpts, false));
-        CHK(dalloc_t(c, &c->lnip, c->gpts, false));
-        CHK(dalloc_t(c, &c->partial, 8 * 256 * 4, false));
-        CHK(dalloc_t(c, &c->dpart, 1024, false));
-        CHK(dalloc_t(c, &c->dscal, 16, false));
-        CHK(dalloc_t(c, &c->d_flag, 64, false));
-        HIPCHK(c, launch_fill(reinterpret_cast<float*>(c->d_flag), 64, 0.f, c->st));
-    }
-    HIPCHK(c, hipMemcpyAsync(c->lnvp, lnvp, c->gpts * sizeof(float), hipMemcpyDeviceToDevice, c->st));
-    HIPCHK(c, hipMemcpyAsync(c->lnip, lnip, c->gpts * sizeof(float), hipMemcpyDeviceToDevice, c->st));
-    // vmax and finiteness
-    const int nb = 256;
-    std::vector<float> part(nb);
-    HIPCHK(c, launch_maxval(c->lnvp, c->gpts, c->partial, nb, c->st));
-    HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, nb * sizeof(float), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(c, hipStreamSynchronize(c->st));
-    float mv = -INFINITY;
-    for (float x : part) mv = std::max(mv, x);
-    HIPCHK(c, launch_maxval(c->lnip, c->gpts, c->partial, nb, c->st));
-    HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, nb * sizeof(float), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(c, hipStreamSynchronize(c->st));
-    float mi = -INFINITY;
-    for (float x : part) mi = std::max(mi, x);
-    if (!std::isfinite(mv) || !std::isfinite(mi)) {
-        c->have_model = false;
-        FAIL(c, LSRTM_ENONFINITE, "model holds NaN or Inf");
-    }
-    // the same reduction with negated sign is not needed: logs are finite
-    const double vmax = std::exp((double)mv);
-    double s2 = 0.0;
-    for (int a = 0; a < c->ndim; ++a) s2 += 1.0 / (c->g.h[a] * c->g.h[a]);
-    double csum = 0.0;
-    for (double x : kC8) csum += std::fabs(x);
-    const double cfl = vmax * c->g.dt * std::sqrt(s2) * csum;
-    if (!(cfl < 1.0)) {
-        c->have_model = false;
-        FAIL(c, LSRTM_EUNSTABLE, "CFL number %.4f >= 1 (vmax %.1f m/s, dt %g s)", cfl, vmax, c->g.dt);
-    }
-    c->vmax = vmax;
-    c->have_model = true;
-    if (c->have_acq) CHK(prep_model_windows(c));
-    c->ckpt_valid = false;
-    return LSRTM_OK;
-}
-
-lsrtm_status lsrtm_set_acquisition(lsrtm_ctx* c, int nshot, const int* win, const int* src,
-                                   const int* rec_ptr, const int* rec, const float* wavelet) {
-    if (!c) return LSRTM_EINVAL;
-    if (!c->have_model) FAIL(c, LSRTM_ESTATE, "set_model must precede set_acquisition");
-    if (nshot < 1 || !win || !src || !rec_ptr || !wavelet) FAIL(c, LSRTM_EINVAL, "bad acquisition arguments");
-    if (rec_ptr[0] != 0) FAIL(c, LSRTM_EINVAL, "rec_ptr[0] must be 0");
-    for (int s = 0; s < nshot; ++s)
-        if (rec_ptr[s + 1] < rec_ptr[s]) FAIL(c, LSRTM_EINVAL, "rec_ptr must be non-decreasing");
-    if (rec_ptr[nshot] > 0 && !rec) FAIL(c, LSRTM_EINVAL, "rec is NULL");
+lsrtm_status plan(lsrtm_ctx* c) {
+    const int nshot = c->nshot;
+    const int* win = c->a_win.data();
+    const int* src = c->a_src.data();
+    const int* rec_ptr = c->a_recptr.data();
+    const int* rec = c->a_rec.data();
+    const float* wavelet = c->wavelet;
     HIPCHK(c, hipStreamSynchronize(c->st));
     free_acq(c);
     const int nd = c->ndim;
@@ -948,10 +891,363 @@ lsrtm_status lsrtm_set_acquisition(lsrtm_ctx* c, int nshot, const int* win, cons
     return LSRTM_OK;
 }
 
+
+
+// ---------------------------------------------------------------------------
+// Autotuner: times the six stencil phases over a few steps on the real launch
+// groups for every tile shape (and, when asked, several group sizes) and
+// keeps the fastest.  Results are cached per problem shape in the file named
+// by LSRTM_TUNE_CACHE when that variable is set.
+// ---------------------------------------------------------------------------
+std::string tune_key(const lsrtm_ctx* c) {
+    char b[256];
+    snprintf(b, sizeof(b), "nd=%d nshot=%d pts=%lld nt=%d n=%dx%dx%d npml=%d", c->ndim, c->nshot,
+             c->padded_total, c->g.nt, c->g.n[0], c->g.n[1], c->g.n[2], c->g.npml);
+    return b;
+}
+
+bool tune_cache_get(const lsrtm_ctx* c, int* tile, int* spl) {
+    const char* f = getenv("LSRTM_TUNE_CACHE");
+    if (!f) return false;
+    FILE* fp = fopen(f, "r");
+    if (!fp) return false;
+    const std::string key = tune_key(c);
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof(line), fp)) {
+        std::string l(line);
+        const size_t bar = l.find('|');
+        if (bar == std::string::npos || l.substr(0, bar) != key) continue;
+        int t, g;
+        if (sscanf(l.c_str() + bar + 1, "%d %d", &t, &g) == 2) {
+            *tile = t;
+            *spl = g;
+            found = true;
+        }
+    }
+    fclose(fp);
+    return found;
+}
+
+void tune_cache_put(const lsrtm_ctx* c, int tile, int spl) {
+    const char* f = getenv("LSRTM_TUNE_CACHE");
+    if (!f) return;
+    FILE* fp = fopen(f, "a");
+    if (!fp) return;
+    fprintf(fp, "%s|%d %d\n", tune_key(c).c_str(), tile, spl);
+    fclose(fp);
+}
+
+// Milliseconds per time step of the six stencil phases summed over all groups.
+lsrtm_status time_tile(lsrtm_ctx* c, int tile, int nsteps, double* ms) {
+    c->tile = tile;
+    hipEvent_t a, b;
+    HIPCHK(c, hipEventCreate(&a));
+    HIPCHK(c, hipEventCreate(&b));
+    for (auto& gr : c->groups) CHK(build_tiles(c, gr, tile));
+    const bool tim = c->opt_timing;
+    c->opt_timing = 0;
+    HIPCHK(c, hipEventRecord(a, c->st));
+    for (auto& gr : c->groups) {
+        for (int n = 0; n < nsteps; ++n) {
+            CHK(stencil(c, gr, K_BORN_V, n, 0, 0));
+            CHK(stencil(c, gr, K_BORN_P, n, 0, 0));
+            CHK(stencil(c, gr, K_SEG_V, n, n % c->k, 0));
+            CHK(stencil(c, gr, K_SEG_P, n, n % c->k, 0));
+            CHK(stencil(c, gr, K_ADJ_A, n, n % c->k, n == 0));
+            CHK(stencil(c, gr, K_ADJ_B, n, n % c->k, 0));
+        }
+    }
+    HIPCHK(c, hipEventRecord(b, c->st));
+    HIPCHK(c, hipEventSynchronize(b));
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    c->opt_timing = tim;
+    *ms = t / nsteps;
+    return LSRTM_OK;
+}
+
+lsrtm_status tune_tiles(lsrtm_ctx* c, int nsteps, int* best, double* best_ms) {
+    const int ntile = c->ndim == 2 ? kNumTiles2 : kNumTiles3;
+    // zero the working fields so that the timing runs on finite values
+    for (auto& gr : c->groups) {
+        CHK(fill(c, c->pool, gr.bg_used));
+        CHK(fill(c, c->pool + c->bg_region, gr.sc_used));
+        CHK(fill(c, c->pool + c->bg_region + c->sc_region, gr.img_used));
+    }
+    double ms;
+    CHK(time_tile(c, 0, 1, &ms));   // warm-up
+    *best = 0;
+    *best_ms = 1e30;
+    for (int t = 0; t < ntile; ++t) {
+        CHK(time_tile(c, t, nsteps, &ms));
+        if (ms < *best_ms) {
+            *best_ms = ms;
+            *best = t;
+        }
+    }
+    c->tile = *best;
+    clear_graphs(c);
+    return LSRTM_OK;
+}
+
+lsrtm_status autotune(lsrtm_ctx* c, int nsteps, bool groups, double* out) {
+    int tile = -1, spl = c->opt_spl;
+    if (tune_cache_get(c, &tile, &spl)) {
+        if (groups && spl != c->opt_spl) {
+            c->opt_spl = spl;
+            CHK(plan(c));
+        }
+        c->tile = tile;
+        c->tuned = true;
+        if (out) {
+            out[0] = tile;
+            out[1] = c->G;
+            out[2] = -1.0;
+        }
+        return LSRTM_OK;
+    }
+    double best_ms = 1e30;
+    int best_tile = 0, best_spl = c->opt_spl;
+    std::vector<int> cands;
+    if (groups) {
+        cands.push_back(0);
+        for (int g : {64, 48, 32, 24, 16, 8})
+            if (g < c->nshot) cands.push_back(g);
+    } else {
+        cands.push_back(c->opt_spl);
+    }
+    for (int g : cands) {
+        if (g != c->opt_spl) {
+            c->opt_spl = g;
+            CHK(plan(c));
+        }
+        int t;
+        double ms;
+        CHK(tune_tiles(c, nsteps, &t, &ms));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_tile = t;
+            best_spl = g;
+        }
+    }
+    if (best_spl != c->opt_spl) {
+        c->opt_spl = best_spl;
+        CHK(plan(c));
+    }
+    c->tile = best_tile;
+    c->tuned = true;
+    clear_graphs(c);
+    tune_cache_put(c, best_tile, best_spl);
+    if (out) {
+        out[0] = best_tile;
+        out[1] = c->G;
+        out[2] = best_ms;
+    }
+    return LSRTM_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* lsrtm_strerror(int s) {
+    switch (s) {
+    case LSRTM_OK: return "ok";
+    case LSRTM_EINVAL: return "invalid argument";
+    case LSRTM_ENOMEM: return "out of device memory";
+    case LSRTM_EHIP: return "HIP runtime error";
+    case LSRTM_EUNSTABLE: return "CFL stability condition violated";
+    case LSRTM_ENONFINITE: return "non-finite value";
+    case LSRTM_ESTATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+const char* lsrtm_last_error(lsrtm_ctx* c) { return c ? c->err.c_str() : ""; }
+
+lsrtm_status lsrtm_tile_shape(int ndim, int id, int* out) {
+    if (!out) return LSRTM_EINVAL;
+    if (ndim == 2 && id >= 0 && id < kNumTiles2) {
+        out[0] = kTiles2[id][0];
+        out[1] = kTiles2[id][1];
+        return LSRTM_OK;
+    }
+    if (ndim == 3 && id >= 0 && id < kNumTiles3) {
+        out[0] = kTiles3[id][0];
+        out[1] = kTiles3[id][1];
+        return LSRTM_OK;
+    }
+    return LSRTM_EINVAL;
+}
+
+lsrtm_status lsrtm_create(const lsrtm_grid* g, void* stream, lsrtm_ctx** out) {
+    if (!g || !out) return LSRTM_EINVAL;
+    *out = nullptr;
+    if (g->ndim != 2 && g->ndim != 3) return LSRTM_EINVAL;
+    for (int a = 0; a < g->ndim; ++a)
+        if (g->n[a] < 1 || !(g->h[a] > 0.0)) return LSRTM_EINVAL;
+    if (g->ndim == 2 && g->n[2] != 1) return LSRTM_EINVAL;
+    if (g->npml < 0 || g->nt < 1 || !(g->dt > 0.0)) return LSRTM_EINVAL;
+    if (g->npml > 0 && !(g->pml_R > 0.0 && g->pml_R < 1.0)) return LSRTM_EINVAL;
+    if (g->ckpt_every < 0 || g->ckpt_dtype < 0 || g->ckpt_dtype > 2) return LSRTM_EINVAL;
+    lsrtm_ctx* c = new lsrtm_ctx();
+    c->g = *g;
+    if (g->ndim == 2) c->g.h[2] = 1.0;
+    c->st = reinterpret_cast<hipStream_t>(stream);
+    c->ndim = g->ndim;
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 4; ++k) c->C.c[a][k] = (float)(kC8[k] / c->g.h[a]);
+    c->gpts = (long long)g->n[0] * g->n[1] * g->n[2];
+    c->S = strip_depth(c);
+    *out = c;
+    return LSRTM_OK;
+}
+
+void lsrtm_destroy(lsrtm_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->st);
+    free_acq(c);
+    if (c->wavelet) (void)hipFree(c->wavelet);
+    if (c->gst) (void)hipStreamDestroy(c->gst);
+    if (c->gin) (void)hipEventDestroy(c->gin);
+    if (c->gout) (void)hipEventDestroy(c->gout);
+    for (void* p : c->allocs) (void)hipFree(p);
+    for (auto& e : c->evpool) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    if (c->pa) (void)hipEventDestroy(c->pa);
+    if (c->pb) (void)hipEventDestroy(c->pb);
+    delete c;
+}
+
+lsrtm_status lsrtm_set_option(lsrtm_ctx* c, int key, long long v) {
+    if (!c) return LSRTM_EINVAL;
+    switch (key) {
+    case LSRTM_OPT_SHOTS_PER_LAUNCH:
+        if (v < 0) FAIL(c, LSRTM_EINVAL, "shots per launch must be >= 0");
+        if (c->opt_spl == (int)v) return LSRTM_OK;
+        c->opt_spl = (int)v;
+        if (c->have_acq) return plan(c);   // rebuild the launch groups
+        return LSRTM_OK;
+    case LSRTM_OPT_TILE: {
+        const int nt = c->ndim == 2 ? kNumTiles2 : kNumTiles3;
+        if (v < -1 || v >= nt) FAIL(c, LSRTM_EINVAL, "tile id %lld out of range", v);
+        c->opt_tile = (int)v;
+        c->tile = (int)v;
+        c->tuned = v >= 0;
+        clear_graphs(c);
+        return LSRTM_OK;
+    }
+    case LSRTM_OPT_GRAPH: c->opt_graph = v != 0; return LSRTM_OK;
+    case LSRTM_OPT_TIMING: c->opt_timing = v != 0; return LSRTM_OK;
+    case LSRTM_OPT_MEM_BUDGET_MB:
+        if (v < 0) FAIL(c, LSRTM_EINVAL, "memory budget must be >= 0");
+        c->opt_budget_mb = v;
+        return LSRTM_OK;
+    default: FAIL(c, LSRTM_EINVAL, "unknown option %d", key);
+    }
+}
+
+lsrtm_status lsrtm_set_model(lsrtm_ctx* c, const float* lnvp, const float* lnip) {
+    if (!c || !lnvp || !lnip) return LSRTM_EINVAL;
+    if (!c->lnvp) {
+        CHK(dalloc_t(c, &c->lnvp, c->gpts, false));
+        CHK(dalloc_t(c, &c->lnip, c->gpts, false));
+        CHK(dalloc_t(c, &c->partial, 8 * 256 * 4, false));
+        CHK(dalloc_t(c, &c->dpart, 1024, false));
+        CHK(dalloc_t(c, &c->dscal, 16, false));
+        CHK(dalloc_t(c, &c->d_flag, 64, false));
+        HIPCHK(c, launch_fill(reinterpret_cast<float*>(c->d_flag), 64, 0.f, c->st));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->lnvp, lnvp, c->gpts * sizeof(float), hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->lnip, lnip, c->gpts * sizeof(float), hipMemcpyDeviceToDevice, c->st));
+    // vmax and finiteness
+    const int nb = 256;
+    std::vector<float> part(nb);
+    HIPCHK(c, launch_maxval(c->lnvp, c->gpts, c->partial, nb, c->st));
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, nb * sizeof(float), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    float mv = -INFINITY;
+    for (float x : part) mv = std::max(mv, x);
+    HIPCHK(c, launch_maxval(c->lnip, c->gpts, c->partial, nb, c->st));
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, nb * sizeof(float), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    float mi = -INFINITY;
+    for (float x : part) mi = std::max(mi, x);
+    if (!std::isfinite(mv) || !std::isfinite(mi)) {
+        c->have_model = false;
+        FAIL(c, LSRTM_ENONFINITE, "model holds NaN or Inf");
+    }
+    // the same reduction with negated sign is not needed: logs are finite
+    const double vmax = std::exp((double)mv);
+    double s2 = 0.0;
+    for (int a = 0; a < c->ndim; ++a) s2 += 1.0 / (c->g.h[a] * c->g.h[a]);
+    double csum = 0.0;
+    for (double x : kC8) csum += std::fabs(x);
+    const double cfl = vmax * c->g.dt * std::sqrt(s2) * csum;
+    if (!(cfl < 1.0)) {
+        c->have_model = false;
+        FAIL(c, LSRTM_EUNSTABLE, "CFL number %.4f >= 1 (vmax %.1f m/s, dt %g s)", cfl, vmax, c->g.dt);
+    }
+    c->vmax = vmax;
+    c->have_model = true;
+    if (c->have_acq) CHK(prep_model_windows(c));
+    c->ckpt_valid = false;
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_set_acquisition(lsrtm_ctx* c, int nshot, const int* win, const int* src,
+                                   const int* rec_ptr, const int* rec, const float* wavelet) {
+    if (!c) return LSRTM_EINVAL;
+    if (!c->have_model) FAIL(c, LSRTM_ESTATE, "set_model must precede set_acquisition");
+    if (nshot < 1 || !win || !src || !rec_ptr || !wavelet) FAIL(c, LSRTM_EINVAL, "bad acquisition arguments");
+    if (rec_ptr[0] != 0) FAIL(c, LSRTM_EINVAL, "rec_ptr[0] must be 0");
+    for (int s = 0; s < nshot; ++s)
+        if (rec_ptr[s + 1] < rec_ptr[s]) FAIL(c, LSRTM_EINVAL, "rec_ptr must be non-decreasing");
+    if (rec_ptr[nshot] > 0 && !rec) FAIL(c, LSRTM_EINVAL, "rec is NULL");
+    const int nd = c->ndim;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    c->a_win.assign(win, win + (size_t)nshot * 2 * nd);
+    c->a_src.assign(src, src + (size_t)nshot * nd);
+    c->a_recptr.assign(rec_ptr, rec_ptr + nshot + 1);
+    c->a_rec.assign(rec ? rec : rec_ptr, rec ? rec + (size_t)rec_ptr[nshot] * nd : rec_ptr);
+    if (c->wavelet) {
+        (void)hipFree(c->wavelet);
+        c->wavelet = nullptr;
+    }
+    c->nshot = nshot;
+    {
+        hipError_t e = hipMalloc(&c->wavelet, (size_t)nshot * c->g.nt * sizeof(float));
+        if (e != hipSuccess) FAIL(c, LSRTM_ENOMEM, "wavelet copy: %s", hipGetErrorString(e));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->wavelet, wavelet, (size_t)nshot * c->g.nt * sizeof(float),
+                             hipMemcpyDeviceToDevice, c->st));
+    c->tuned = false;
+    return plan(c);
+}
+
+lsrtm_status lsrtm_autotune(lsrtm_ctx* c, int nsteps, int tune_groups, double* out) {
+    if (!c) return LSRTM_EINVAL;
+    if (!c->have_model || !c->have_acq) FAIL(c, LSRTM_ESTATE, "autotune needs a model and an acquisition");
+    if (nsteps < 1) FAIL(c, LSRTM_EINVAL, "nsteps must be >= 1");
+    c->opt_tile = -1;
+    CHK(autotune(c, nsteps, tune_groups != 0, out));
+    c->ckpt_valid = false;
+    return LSRTM_OK;
+}
+
 lsrtm_status lsrtm_sizes(lsrtm_ctx* c, long long* out, int nout) {
     if (!c || !out) return LSRTM_EINVAL;
-    long long v[7] = {c->data_len, c->gpts, c->G, c->k, (long long)c->groups.size(), c->padded_total, c->plan_bytes};
-    for (int i = 0; i < nout && i < 7; ++i) out[i] = v[i];
+    long long v[8] = {c->data_len, c->gpts, c->G, c->k, (long long)c->groups.size(), c->padded_total, c->plan_bytes,
+                      c->tile};
+    for (int i = 0; i < nout && i < 8; ++i) out[i] = v[i];
     return LSRTM_OK;
 }
 
@@ -971,7 +1267,7 @@ lsrtm_status lsrtm_forward(lsrtm_ctx* c, float* d) {
     CHK(check_ready(c));
     if (!d && c->data_len > 0) FAIL(c, LSRTM_EINVAL, "d is NULL");
     CHK(pass_begin(c));
-    for (auto& gr : c->groups) CHK(group_forward(c, gr, 0, d, true));
+    for (size_t gi = 0; gi < c->groups.size(); ++gi) CHK(run_group(c, c->groups[gi], (int)gi, P_FWD, d, true));
     CHK(pass_end(c));
     CHK(check_flag(c));
     c->ckpt_valid = true;
@@ -998,7 +1294,7 @@ static lsrtm_status born_impl(lsrtm_ctx* c, const float* dm, float* d) {
         HIPCHK(c, launch_dm_prep(a, c->st));
     }
     const bool write_ck = !c->ckpt_valid;
-    for (auto& gr : c->groups) CHK(group_forward(c, gr, 1, d, write_ck));
+    for (size_t gi = 0; gi < c->groups.size(); ++gi) CHK(run_group(c, c->groups[gi], (int)gi, P_BORN, d, write_ck));
     if (write_ck) {
         CHK(check_flag(c));
         c->ckpt_valid = true;
@@ -1018,7 +1314,8 @@ lsrtm_status lsrtm_born(lsrtm_ctx* c, const float* dm, float* d) {
 static lsrtm_status adjoint_impl(lsrtm_ctx* c, const float* d, float* img, int accumulate) {
     CHK(ensure_ckpts(c));
     HIPCHK(c, launch_fill_f64(c->acc64, 2 * c->gpts, c->st));
-    for (auto& gr : c->groups) CHK(group_adjoint(c, gr, d));
+    for (size_t gi = 0; gi < c->groups.size(); ++gi)
+        CHK(run_group(c, c->groups[gi], (int)gi, P_ADJ, const_cast<float*>(d), false));
     HIPCHK(c, launch_image_store(c->acc64, img, 2 * c->gpts, accumulate, c->st));
     return LSRTM_OK;
 }
@@ -1058,41 +1355,85 @@ lsrtm_status lsrtm_axpy(lsrtm_ctx* c, double alpha, const float* x, float* y, lo
     return LSRTM_OK;
 }
 
-lsrtm_status lsrtm_cgnr(lsrtm_ctx* c, const float* d_obs, int niter, float* x, double* misfit) {
+lsrtm_status lsrtm_cgnr_begin(lsrtm_ctx* c, const float* d_obs, float* x) {
     CHK(check_ready(c));
-    if (!x || niter < 0 || (!d_obs && c->data_len > 0)) FAIL(c, LSRTM_EINVAL, "bad CGNR arguments");
+    if (!x || (!d_obs && c->data_len > 0)) FAIL(c, LSRTM_EINVAL, "bad CGNR arguments");
     const long long nm = 2 * c->gpts, nd = c->data_len;
     CHK(pass_begin(c));
     HIPCHK(c, launch_copy(d_obs, c->cg_r, nd, c->st));
     HIPCHK(c, launch_fill(x, nm, 0.f, c->st));
     CHK(adjoint_impl(c, c->cg_r, c->cg_z, 0));
     HIPCHK(c, launch_copy(c->cg_z, c->cg_p, nm, c->st));
-    double zz, r0;
-    CHK(dot_impl(c, c->cg_z, c->cg_z, nm, &zz));
-    CHK(dot_impl(c, c->cg_r, c->cg_r, nd, &r0));
-    if (misfit) misfit[0] = 1.0;
-    for (int it = 0; it < niter; ++it) {
-        double rr = r0;
-        if (zz > 0.0 && r0 > 0.0) {
-            CHK(born_impl(c, c->cg_p, c->cg_w));
-            double ww;
-            CHK(dot_impl(c, c->cg_w, c->cg_w, nd, &ww));
-            if (ww > 0.0) {
-                const double alpha = zz / ww;
-                HIPCHK(c, launch_axpy(alpha, c->cg_p, x, nm, c->st));
-                HIPCHK(c, launch_axpy(-alpha, c->cg_w, c->cg_r, nd, c->st));
-                CHK(adjoint_impl(c, c->cg_r, c->cg_z, 0));
-                double zz1;
-                CHK(dot_impl(c, c->cg_z, c->cg_z, nm, &zz1));
-                const double beta = zz1 / zz;
-                HIPCHK(c, launch_xpby(c->cg_z, beta, c->cg_p, nm, c->st));
-                zz = zz1;
-            }
-            CHK(dot_impl(c, c->cg_r, c->cg_r, nd, &rr));
-        }
-        if (misfit) misfit[it + 1] = r0 > 0.0 ? rr / r0 : 0.0;
-    }
+    CHK(dot_impl(c, c->cg_z, c->cg_z, nm, &c->cg_zz));
+    CHK(dot_impl(c, c->cg_r, c->cg_r, nd, &c->cg_r0));
+    c->cg_rr = c->cg_r0;
+    c->cg_k = 0;
+    c->cg_active = true;
     CHK(pass_end(c));
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_cgnr_iterate(lsrtm_ctx* c, float* x, double* misfit) {
+    CHK(check_ready(c));
+    if (!c->cg_active) FAIL(c, LSRTM_ESTATE, "lsrtm_cgnr_begin has not been called");
+    if (!x) FAIL(c, LSRTM_EINVAL, "x is NULL");
+    const long long nm = 2 * c->gpts, nd = c->data_len;
+    CHK(pass_begin(c));
+    if (c->cg_zz > 0.0 && c->cg_r0 > 0.0) {
+        CHK(born_impl(c, c->cg_p, c->cg_w));
+        double ww;
+        CHK(dot_impl(c, c->cg_w, c->cg_w, nd, &ww));
+        if (ww > 0.0) {
+            const double alpha = c->cg_zz / ww;
+            HIPCHK(c, launch_axpy(alpha, c->cg_p, x, nm, c->st));
+            HIPCHK(c, launch_axpy(-alpha, c->cg_w, c->cg_r, nd, c->st));
+            CHK(adjoint_impl(c, c->cg_r, c->cg_z, 0));
+            double zz1;
+            CHK(dot_impl(c, c->cg_z, c->cg_z, nm, &zz1));
+            const double beta = zz1 / c->cg_zz;
+            HIPCHK(c, launch_xpby(c->cg_z, beta, c->cg_p, nm, c->st));
+            c->cg_zz = zz1;
+        }
+        CHK(dot_impl(c, c->cg_r, c->cg_r, nd, &c->cg_rr));
+    }
+    c->cg_k += 1;
+    if (misfit) *misfit = c->cg_r0 > 0.0 ? c->cg_rr / c->cg_r0 : 0.0;
+    CHK(pass_end(c));
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_cgnr(lsrtm_ctx* c, const float* d_obs, int niter, float* x, double* misfit) {
+    if (niter < 0) FAIL(c, LSRTM_EINVAL, "niter < 0");
+    CHK(lsrtm_cgnr_begin(c, d_obs, x));
+    if (misfit) misfit[0] = 1.0;
+    for (int it = 0; it < niter; ++it) CHK(lsrtm_cgnr_iterate(c, x, misfit ? misfit + it + 1 : nullptr));
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_cgnr_state(lsrtm_ctx* c, int get, float* r, float* z, float* p, double* scal) {
+    CHK(check_ready(c));
+    if (!r || !z || !p || !scal) FAIL(c, LSRTM_EINVAL, "NULL argument");
+    const long long nm = 2 * c->gpts, nd = c->data_len;
+    if (get) {
+        if (!c->cg_active) FAIL(c, LSRTM_ESTATE, "no CGNR run to export");
+        HIPCHK(c, launch_copy(c->cg_r, r, nd, c->st));
+        HIPCHK(c, launch_copy(c->cg_z, z, nm, c->st));
+        HIPCHK(c, launch_copy(c->cg_p, p, nm, c->st));
+        scal[0] = c->cg_zz;
+        scal[1] = c->cg_r0;
+        scal[2] = c->cg_rr;
+        scal[3] = (double)c->cg_k;
+        HIPCHK(c, hipStreamSynchronize(c->st));
+    } else {
+        HIPCHK(c, launch_copy(r, c->cg_r, nd, c->st));
+        HIPCHK(c, launch_copy(z, c->cg_z, nm, c->st));
+        HIPCHK(c, launch_copy(p, c->cg_p, nm, c->st));
+        c->cg_zz = scal[0];
+        c->cg_r0 = scal[1];
+        c->cg_rr = scal[2];
+        c->cg_k = (int)scal[3];
+        c->cg_active = true;
+    }
     return LSRTM_OK;
 }
 

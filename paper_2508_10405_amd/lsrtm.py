@@ -53,10 +53,14 @@ SIGNATURES = {
     "lsrtm_born": (_c_int, [_vp, _vp, _vp]),
     "lsrtm_adjoint": (_c_int, [_vp, _vp, _vp, _c_int]),
     "lsrtm_cgnr": (_c_int, [_vp, _vp, _c_int, _vp, _vp]),
+    "lsrtm_cgnr_begin": (_c_int, [_vp, _vp, _vp]),
+    "lsrtm_cgnr_iterate": (_c_int, [_vp, _vp, ctypes.POINTER(_c_double)]),
+    "lsrtm_cgnr_state": (_c_int, [_vp, _c_int, _vp, _vp, _vp, ctypes.POINTER(_c_double)]),
     "lsrtm_dot": (_c_int, [_vp, _vp, _vp, _c_ll, ctypes.POINTER(_c_double)]),
     "lsrtm_axpy": (_c_int, [_vp, _c_double, _vp, _vp, _c_ll]),
     "lsrtm_set_option": (_c_int, [_vp, _c_int, _c_ll]),
     "lsrtm_sizes": (_c_int, [_vp, ctypes.POINTER(_c_ll), _c_int]),
+    "lsrtm_autotune": (_c_int, [_vp, _c_int, _c_int, ctypes.POINTER(_c_double)]),
     "lsrtm_stats": (_c_int, [_vp, ctypes.POINTER(_c_double), _c_int]),
     "lsrtm_tile_shape": (_c_int, [_c_int, _c_int, ctypes.POINTER(_c_int)]),
     "lsrtm_destroy": (None, [_vp]),
@@ -188,11 +192,16 @@ class Context:
         self.nshot = nshot
 
     # -- sizes --------------------------------------------------------------
+    def autotune(self, nsteps=8, groups=False):
+        out = (_c_double * 3)()
+        self._check(lib().lsrtm_autotune(self._h, int(nsteps), int(bool(groups)), out), "autotune")
+        return {"tile": int(out[0]), "shots_per_launch": int(out[1]), "ms_per_step": out[2]}
+
     def sizes(self):
-        out = (_c_ll * 7)()
-        self._check(lib().lsrtm_sizes(self._h, out, 7), "sizes")
+        out = (_c_ll * 8)()
+        self._check(lib().lsrtm_sizes(self._h, out, 8), "sizes")
         keys = ("data_len", "grid_points", "shots_per_launch", "ckpt_every", "groups",
-                "padded_points", "plan_bytes")
+                "padded_points", "plan_bytes", "tile")
         return dict(zip(keys, [int(x) for x in out]))
 
     @property
@@ -263,6 +272,35 @@ class Context:
         mis = (_c_double * (niter + 1))()
         self._check(lib().lsrtm_cgnr(self._h, _vp(_ptr(d_obs)), int(niter), _vp(_ptr(x)), mis), "cgnr")
         return x, [float(v) for v in mis]
+
+    def cgnr_begin(self, d_obs, x=None):
+        _require_cuda(d_obs, "d_obs")
+        x = self._image(x)
+        self._check(lib().lsrtm_cgnr_begin(self._h, _vp(_ptr(d_obs)), _vp(_ptr(x))), "cgnr_begin")
+        return x
+
+    def cgnr_iterate(self, x) -> float:
+        _require_cuda(x, "x")
+        m = _c_double()
+        self._check(lib().lsrtm_cgnr_iterate(self._h, _vp(_ptr(x)), ctypes.byref(m)), "cgnr_iterate")
+        return m.value
+
+    def cgnr_get_state(self):
+        torch = self._torch
+        r = torch.empty(self.data_len, dtype=torch.float32, device="cuda")
+        z = torch.empty((2,) + self.shape, dtype=torch.float32, device="cuda")
+        p = torch.empty_like(z)
+        sc = (_c_double * 4)()
+        self._check(lib().lsrtm_cgnr_state(self._h, 1, _vp(_ptr(r)), _vp(_ptr(z)), _vp(_ptr(p)), sc),
+                    "cgnr_state")
+        return {"r": r, "z": z, "p": p, "scalars": [float(v) for v in sc]}
+
+    def cgnr_set_state(self, st):
+        sc = (_c_double * 4)(*st["scalars"])
+        for k in ("r", "z", "p"):
+            _require_cuda(st[k], k)
+        self._check(lib().lsrtm_cgnr_state(self._h, 0, _vp(_ptr(st["r"])), _vp(_ptr(st["z"])),
+                                           _vp(_ptr(st["p"])), sc), "cgnr_state")
 
     def dot(self, a, b) -> float:
         _require_cuda(a, "a")

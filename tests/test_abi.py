@@ -67,6 +67,7 @@ def test_strerror_and_tiles():
     L = lsrtm.lib()
     assert L.lsrtm_strerror(lsrtm.EUNSTABLE).decode().startswith("CFL")
     assert lsrtm.tile_shape(2, 4) == (64, 8)
+    assert lsrtm.tile_shape(2, 1) == (32, 16)
     with pytest.raises(lsrtm.LsrtmError):
         lsrtm.tile_shape(2, 99)
 

@@ -1,0 +1,110 @@
+"""The differentiable Born operator: its backward is the library's adjoint
+(migration with checkpoint replay).  Checked by central finite differences
+of the misfit, by the dot-product test through autograd, and against the
+FP64 oracle's gradient."""
+import numpy as np
+import pytest
+
+from oracle import lsrtm_oracle as O
+from paper_2508_10405_amd import synth
+from gpu_common import concat, f64, oracle_problem, rel, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _setup(torch, k=25, dtype="f32"):
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((48, 96), nt=240, npml=10, seed=31, nshot=3, uneven=True)
+    print(f"[case] autograd small nshot={w.nshot} nt={w.nt} k={k} {dtype}", flush=True)
+    ctx = lsrtm.context_for(w, ckpt_every=k, ckpt_dtype=dtype)
+    return w, ctx
+
+
+def test_gradient_matches_oracle(torch):
+    from paper_2508_10405_amd import autograd
+    w, ctx = _setup(torch)
+    rng = np.random.default_rng(1)
+    d_obs = rng.standard_normal(ctx.data_len).astype(np.float32)
+    m = to_dev(torch, 0.5 * w.dm).requires_grad_(True)
+    J = autograd.misfit(m, ctx, to_dev(torch, d_obs))
+    J.backward()
+    prob = oracle_problem(w)
+    lnvp, lnip = f64(w.lnvp), f64(w.lnip)
+    Lm = O.born(prob, lnvp, lnip, 0.5 * f64(w.dm))
+    res, o = [], 0
+    for d in Lm:
+        res.append(d - d_obs[o:o + d.size].reshape(d.shape))
+        o += d.size
+    g_ref = O.adjoint(prob, lnvp, lnip, res)
+    e = rel(m.grad.cpu().numpy(), g_ref)
+    print("grad rel", e)
+    assert e <= 1e-4
+
+
+def test_gradient_central_differences(torch):
+    """J is quadratic in dm, so the central difference along v equals <g, v>
+    up to rounding; eps = 1e-3 as in the benchmark recipe."""
+    from paper_2508_10405_amd import autograd
+    w, ctx = _setup(torch)
+    rng = np.random.default_rng(2)
+    # observed data on the scale of L dm, so that J is not dominated by a
+    # constant that would swamp the FP32 differences
+    d_obs = ctx.born(to_dev(torch, 0.6 * w.dm + 0.02 * rng.standard_normal((2,) + w.shape))).clone()
+    m = to_dev(torch, w.dm).requires_grad_(True)
+    J = autograd.misfit(m, ctx, d_obs)
+    J.backward()
+    g = m.grad.detach()
+    for trial in range(3):
+        v = to_dev(torch, rng.standard_normal((2,) + w.shape))
+        eps = 1e-3
+        with torch.no_grad():
+            rp = ctx.born((m + eps * v).detach().contiguous()) - d_obs
+            rm = ctx.born((m - eps * v).detach().contiguous()) - d_obs
+            fd = (0.5 * ctx.dot(rp, rp) - 0.5 * ctx.dot(rm, rm)) / (2 * eps)
+        an = ctx.dot(g.view(-1).contiguous(), v.view(-1))
+        print("fd", fd, "analytic", an)
+        assert abs(fd - an) <= 1e-3 * abs(an)
+
+
+def test_dot_product_through_autograd(torch):
+    from paper_2508_10405_amd import autograd
+    w, ctx = _setup(torch)
+    rng = np.random.default_rng(3)
+    x = to_dev(torch, rng.standard_normal((2,) + w.shape)).requires_grad_(True)
+    y = to_dev(torch, rng.standard_normal(ctx.data_len))
+    Lx = autograd.born(x, ctx)
+    (Lx * y).sum().backward()
+    a = ctx.dot(Lx.detach(), y)
+    b = ctx.dot(x.detach().view(-1), x.grad.view(-1).contiguous())
+    print("dot", a, b)
+    assert abs(a - b) <= 1e-4 * abs(a)
+
+
+@pytest.mark.parametrize("k", [10, 50, 200])
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_checkpoint_interval_and_dtype(torch, k, dtype):
+    """Gradient through the autograd op for every checkpoint interval and
+    snapshot precision, against the FP64 oracle: FP32 snapshots meet the
+    1e-4 bar; compressed ones report their error under this build's bounds
+    (2e-3 FP16, 2e-2 BF16)."""
+    from paper_2508_10405_amd import autograd
+    w, ctx = _setup(torch, k=k, dtype=dtype)
+    rng = np.random.default_rng(4)
+    y = rng.standard_normal(ctx.data_len).astype(np.float32)
+    x = to_dev(torch, np.zeros((2,) + w.shape)).requires_grad_(True)
+    (autograd.born(x, ctx) * to_dev(torch, y)).sum().backward()
+    prob = oracle_problem(w)
+    ys, o = [], 0
+    for r in w.rec:
+        ys.append(f64(y[o:o + w.nt * len(r)]).reshape(w.nt, len(r)))
+        o += w.nt * len(r)
+    g_ref = O.adjoint(prob, f64(w.lnvp), f64(w.lnip), ys)
+    e = rel(x.grad.cpu().numpy(), g_ref)
+    print(f"[ckpt] k={k} {dtype} gradient rel err {e:.3e}")
+    bound = {"f32": 1e-4, "f16": 2e-3, "bf16": 2e-2}[dtype]
+    assert e <= bound

@@ -175,7 +175,7 @@ def test_config1_full(torch):
         assert e <= TOL
 
 
-@pytest.mark.parametrize("dtype,bound", [("f16", 1e-3), ("bf16", 2e-2)])
+@pytest.mark.parametrize("dtype,bound", [("f16", 2e-3), ("bf16", 2e-2)])
 def test_compressed_checkpoints_error(torch, dtype, bound):
     """FP16/BF16 snapshots with per-snapshot max-abs scaling: the image error
     against the FP64 oracle is reported; the bound is this build's stated one."""
@@ -221,3 +221,68 @@ def test_error_paths(torch):
         ctx.set_acquisition([((0, 20), (0, 10))], [(1, 2)], [np.array([[1, 15]])],
                             to_dev(torch, w.wavelet[:1]))
     assert ei.value.status == lsrtm.EINVAL
+
+
+def test_graph_replay_matches_direct_launches(torch):
+    """Passes replayed from captured HIP graphs give bitwise the results of
+    direct launches, on every replay, with eager work in between."""
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((44, 70), nt=80, npml=6, seed=15, nshot=3, uneven=True)
+    dm = to_dev(torch, w.dm)
+    y = to_dev(torch, np.random.default_rng(8).standard_normal(sum(w.nt * len(r) for r in w.rec)))
+    ref = lsrtm.context_for(w, graph=False, tile=1)
+    d_ref = ref.born(dm).cpu().numpy()
+    i_ref = ref.adjoint(y).cpu().numpy()
+    ctx = lsrtm.context_for(w, graph=True, tile=1)
+    d = torch.empty(ctx.data_len, device="cuda")
+    img = torch.empty((2,) + w.shape, device="cuda")
+    for rep in range(3):
+        ctx.born(dm, d)
+        assert np.array_equal(d.cpu().numpy(), d_ref), rep
+        torch.cuda.synchronize()
+        _ = (dm * 2).sum().item()          # eager work between replays
+        ctx.adjoint(y, img)
+        assert np.array_equal(img.cpu().numpy(), i_ref), rep
+
+
+def test_autotune_keeps_results_and_caches(torch, tmp_path, monkeypatch):
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((40, 64), nt=60, npml=5, seed=16, nshot=5, uneven=True)
+    dm = to_dev(torch, w.dm)
+    ref = lsrtm.context_for(w, tile=0, shots_per_launch=1).born(dm).cpu().numpy()
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LSRTM_TUNE_CACHE", str(cache))
+    ctx = lsrtm.context_for(w)
+    res = ctx.autotune(nsteps=2, groups=True)
+    print("autotune", res, ctx.sizes())
+    assert np.array_equal(ctx.born(dm).cpu().numpy(), ref)
+    assert cache.exists() and cache.read_text().count("|") == 1
+    ctx2 = lsrtm.context_for(w)
+    res2 = ctx2.autotune(nsteps=2, groups=True)
+    assert res2["tile"] == res["tile"] and ctx2.sizes()["shots_per_launch"] == ctx.sizes()["shots_per_launch"]
+    assert cache.read_text().count("|") == 1   # served from the cache
+    assert np.array_equal(ctx2.born(dm).cpu().numpy(), ref)
+
+
+def test_cgnr_resume_from_saved_state(torch):
+    """A CGNR run stopped after two iterations and resumed from its saved
+    state (x, r, z, p, scalars) reproduces the uninterrupted iterates."""
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((36, 50), nt=90, npml=5, seed=17, nshot=2, uneven=True)
+    ctx = lsrtm.context_for(w, tile=1)
+    dobs = ctx.born(to_dev(torch, w.dm)).clone()
+    x = ctx.cgnr_begin(dobs)
+    m = [ctx.cgnr_iterate(x) for _ in range(3)]
+    x_ref = x.cpu().numpy()
+    x = ctx.cgnr_begin(dobs)
+    ctx.cgnr_iterate(x)
+    ctx.cgnr_iterate(x)
+    saved = {k: (v.clone() if hasattr(v, "clone") else list(v)) for k, v in ctx.cgnr_get_state().items()}
+    x_saved = x.clone()
+    ctx.cgnr_iterate(x)                      # disturb the solver state
+    ctx.born(to_dev(torch, 0 * w.dm))
+    ctx.cgnr_set_state(saved)
+    x = x_saved
+    m3 = ctx.cgnr_iterate(x)
+    assert np.array_equal(x.cpu().numpy(), x_ref)
+    assert m3 == m[2]
