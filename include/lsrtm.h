@@ -86,8 +86,13 @@ enum {
                                        HIP graphs (default 1)                   */
     LSRTM_OPT_TIMING = 4,           /* 1 = time every stencil launch with HIP
                                        events (read back with lsrtm_stats)      */
-    LSRTM_OPT_MEM_BUDGET_MB = 5     /* device memory the plan may use; 0 = 90 %
+    LSRTM_OPT_MEM_BUDGET_MB = 5,    /* device memory the plan may use; 0 = 90 %
                                        of the free memory at set_acquisition    */
+    LSRTM_OPT_CKPT_PER_GROUP = 6    /* 1 = keep background checkpoints only for
+                                       the active launch group and regenerate
+                                       them before each group's migration (the
+                                       planner picks this by itself when the
+                                       checkpoints of all shots do not fit)     */
 };
 
 /* Create a context for one grid on one HIP stream (hipStream_t, may be 0).
@@ -173,7 +178,8 @@ lsrtm_status lsrtm_autotune(lsrtm_ctx* ctx, int nsteps, int tune_groups, double*
 /* Sizes: out[0] = data length, out[1] = physical grid points (one image),
  * out[2] = shots per launch, out[3] = checkpoint interval, out[4] = number of
  * launch groups, out[5] = padded points summed over shots, out[6] = device
- * bytes planned, out[7] = tile id in use.  HOST long long [nout]. */
+ * bytes planned, out[7] = tile id in use, out[8] = 1 if checkpoints are held
+ * per launch group.  HOST long long [nout]. */
 lsrtm_status lsrtm_sizes(lsrtm_ctx* ctx, long long* out, int nout);
 
 /* Timing statistics of the last pass (HOST double [nout]); see

@@ -119,6 +119,7 @@ struct lsrtm_ctx {
     int* d_flag = nullptr;
     double* acc64 = nullptr;       // [2][gpts]
     bool ckpt_valid = false;
+    bool ck_group = false;         // checkpoints held for the active group only
     // CG workspace
     float* cg_r = nullptr;
     float* cg_w = nullptr;
@@ -133,6 +134,7 @@ struct lsrtm_ctx {
     int opt_graph = 1;
     int opt_timing = 0;
     long long opt_budget_mb = 0;
+    int opt_ckg = 0;
     // timing
     std::vector<EvPair> evpool;
     size_t evused = 0;
@@ -684,34 +686,51 @@ lsrtm_status plan(lsrtm_ctx* c) {
     for (auto& sh : c->shots) ck_per_shot_sum += sh.ckbytes;
     const long long fixed = model_bytes + 2LL * c->gpts * 8 + (long long)nshot * nt * 4 + 2 * c->data_len * 4 +
                             2 * 2 * c->gpts * 4 + (64LL << 20) + (long long)nshot * (1 + nd) * 64 * 4;
-    int G = c->opt_spl > 0 ? std::min(c->opt_spl, nshot) : nshot;
-    int k = 1;
+    long long max_ck = 0, max_npts = 0;
+    for (auto& sh : c->shots) max_ck = std::max(max_ck, sh.ckbytes);
+    for (auto& W : c->wins) max_npts = std::max(max_npts, W.npts);
+    // Two checkpoint layouts: every shot keeps its checkpoints for the whole
+    // lifetime of the plan (written once, reused by every pass), or, when that
+    // does not fit, only the shots of the active launch group hold them and
+    // each migration pass first re-runs the group's background.
+    const int G0 = c->opt_spl > 0 ? std::min(c->opt_spl, nshot) : nshot;
+    int G = G0, k = 1;
     long long need = 0;
-    for (;;) {
-        // largest group of G consecutive shots
-        long long grp_pts = 0, cur = 0;
-        for (int s = 0; s < nshot; ++s) {
-            cur += c->wins[c->shots[s].win].npts;
-            if ((s + 1) % G == 0 || s == nshot - 1) {
-                grp_pts = std::max(grp_pts, cur);
-                cur = 0;
+    bool ckg = false, fits = false;
+    for (int mode = c->opt_ckg ? 1 : 0; mode < 2 && !fits; ++mode) {
+        ckg = mode == 1;
+        G = G0;
+        for (;;) {
+            long long grp_pts = 0, cur = 0;
+            for (int s = 0; s < nshot; ++s) {
+                cur += c->wins[c->shots[s].win].npts;
+                if ((s + 1) % G == 0 || s == nshot - 1) {
+                    grp_pts = std::max(grp_pts, cur);
+                    cur = 0;
+                }
             }
+            const long long seg_step = grp_pts * (nd + 1) * 4;
+            const double ck_mem = ckg ? (double)G * max_ck : (double)ck_per_shot_sum;
+            if (c->g.ckpt_every > 0) {
+                k = std::min(c->g.ckpt_every, nt);
+            } else {
+                const double kk = std::sqrt((double)nt * ck_mem / (double)std::max(1LL, seg_step));
+                k = (int)std::max(1.0, std::min((double)nt, std::round(kk)));
+            }
+            const int nseg = (nt + k - 1) / k;
+            need = fixed + grp_pts * (nbg + nsc + 2) * 4LL + (long long)k * seg_step +
+                   (long long)((nseg - 1) * ck_mem) + (long long)nseg * nshot * (1 + nd) * 4;
+            if (need <= budget) {
+                fits = true;
+                break;
+            }
+            if (G == 1) break;
+            G = (G + 1) / 2;
         }
-        const long long seg_step = grp_pts * (nd + 1) * 4;
-        if (c->g.ckpt_every > 0) {
-            k = std::min(c->g.ckpt_every, nt);
-        } else {
-            const double kk = std::sqrt((double)nt * (double)ck_per_shot_sum / (double)std::max(1LL, seg_step));
-            k = (int)std::max(1.0, std::min((double)nt, std::round(kk)));
-        }
-        const int nseg = (nt + k - 1) / k;
-        need = fixed + grp_pts * (nbg + nsc + 2) * 4LL + (long long)k * seg_step + (long long)(nseg - 1) * ck_per_shot_sum +
-               (long long)nseg * nshot * (1 + nd) * 4;
-        if (need <= budget || G == 1) break;
-        G = (G + 1) / 2;
     }
-    if (need > budget)
+    if (!fits)
         FAIL(c, LSRTM_ENOMEM, "memory plan needs %.2f GB, budget %.2f GB", need / 1e9, budget / 1e9);
+    c->ck_group = ckg;
     c->G = G;
     c->k = k;
     c->nseg = (nt + k - 1) / k;
@@ -755,7 +774,8 @@ lsrtm_status plan(lsrtm_ctx* c) {
     }
     CHK(dalloc_t(c, &c->pool, c->bg_region + c->sc_region + c->img_region, true));
     CHK(dalloc_t(c, &c->segbuf, seg_floats, true));
-    CHK(dalloc(c, reinterpret_cast<void**>(&c->ckbuf), (size_t)std::max(1LL, (long long)(c->nseg - 1) * ck_per_shot_sum), true));
+    const long long ck_total = c->ck_group ? (long long)(c->nseg - 1) * G * max_ck : (long long)(c->nseg - 1) * ck_per_shot_sum;
+    CHK(dalloc(c, reinterpret_cast<void**>(&c->ckbuf), (size_t)std::max(1LL, ck_total), true));
     CHK(dalloc_t(c, &c->ckscales, (size_t)c->nseg * nshot * (1 + nd), true));
     CHK(dalloc_t(c, &c->ckpart, (size_t)G * (1 + nd) * c->nblk, true));
     CHK(dalloc_t(c, &c->acc64, 2 * c->gpts, true));
@@ -829,8 +849,13 @@ lsrtm_status plan(lsrtm_ctx* c) {
             S.gk = imb + oimg;
             S.gr = imb + oimg + W.npts;
             S.seg = c->segbuf + oseg;
-            S.ck = c->ckbuf + ckoff[s];
-            S.ckbytes = sh.ckbytes;
+            if (c->ck_group) {
+                S.ck = c->ckbuf + (long long)i * (c->nseg - 1) * max_ck;
+                S.ckbytes = max_ck;
+            } else {
+                S.ck = c->ckbuf + ckoff[s];
+                S.ckbytes = sh.ckbytes;
+            }
             obg += (long long)nbg * W.npts;
             osc += (long long)nsc * W.npts;
             oimg += 2LL * W.npts;
@@ -1151,6 +1176,11 @@ lsrtm_status lsrtm_set_option(lsrtm_ctx* c, int key, long long v) {
         if (v < 0) FAIL(c, LSRTM_EINVAL, "memory budget must be >= 0");
         c->opt_budget_mb = v;
         return LSRTM_OK;
+    case LSRTM_OPT_CKPT_PER_GROUP:
+        if (c->opt_ckg == (v != 0)) return LSRTM_OK;
+        c->opt_ckg = v != 0;
+        if (c->have_acq) return plan(c);
+        return LSRTM_OK;
     default: FAIL(c, LSRTM_EINVAL, "unknown option %d", key);
     }
 }
@@ -1245,9 +1275,9 @@ lsrtm_status lsrtm_autotune(lsrtm_ctx* c, int nsteps, int tune_groups, double* o
 
 lsrtm_status lsrtm_sizes(lsrtm_ctx* c, long long* out, int nout) {
     if (!c || !out) return LSRTM_EINVAL;
-    long long v[8] = {c->data_len, c->gpts, c->G, c->k, (long long)c->groups.size(), c->padded_total, c->plan_bytes,
-                      c->tile};
-    for (int i = 0; i < nout && i < 8; ++i) out[i] = v[i];
+    long long v[9] = {c->data_len, c->gpts, c->G, c->k, (long long)c->groups.size(), c->padded_total, c->plan_bytes,
+                      c->tile, c->ck_group ? 1 : 0};
+    for (int i = 0; i < nout && i < 9; ++i) out[i] = v[i];
     return LSRTM_OK;
 }
 
@@ -1267,10 +1297,11 @@ lsrtm_status lsrtm_forward(lsrtm_ctx* c, float* d) {
     CHK(check_ready(c));
     if (!d && c->data_len > 0) FAIL(c, LSRTM_EINVAL, "d is NULL");
     CHK(pass_begin(c));
-    for (size_t gi = 0; gi < c->groups.size(); ++gi) CHK(run_group(c, c->groups[gi], (int)gi, P_FWD, d, true));
+    for (size_t gi = 0; gi < c->groups.size(); ++gi)
+        CHK(run_group(c, c->groups[gi], (int)gi, P_FWD, d, !c->ck_group));
     CHK(pass_end(c));
     CHK(check_flag(c));
-    c->ckpt_valid = true;
+    c->ckpt_valid = !c->ck_group;
     return LSRTM_OK;
 }
 
@@ -1293,7 +1324,7 @@ static lsrtm_status born_impl(lsrtm_ctx* c, const float* dm, float* d) {
         a.dlnk = W.dlnk;
         HIPCHK(c, launch_dm_prep(a, c->st));
     }
-    const bool write_ck = !c->ckpt_valid;
+    const bool write_ck = !c->ckpt_valid && !c->ck_group;
     for (size_t gi = 0; gi < c->groups.size(); ++gi) CHK(run_group(c, c->groups[gi], (int)gi, P_BORN, d, write_ck));
     if (write_ck) {
         CHK(check_flag(c));
@@ -1312,10 +1343,13 @@ lsrtm_status lsrtm_born(lsrtm_ctx* c, const float* dm, float* d) {
 }
 
 static lsrtm_status adjoint_impl(lsrtm_ctx* c, const float* d, float* img, int accumulate) {
-    CHK(ensure_ckpts(c));
+    if (!c->ck_group) CHK(ensure_ckpts(c));
     HIPCHK(c, launch_fill_f64(c->acc64, 2 * c->gpts, c->st));
-    for (size_t gi = 0; gi < c->groups.size(); ++gi)
+    for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+        if (c->ck_group) CHK(run_group(c, c->groups[gi], (int)gi, P_FWDCK, nullptr, true));
         CHK(run_group(c, c->groups[gi], (int)gi, P_ADJ, const_cast<float*>(d), false));
+    }
+    if (c->ck_group) CHK(check_flag(c));
     HIPCHK(c, launch_image_store(c->acc64, img, 2 * c->gpts, accumulate, c->st));
     return LSRTM_OK;
 }

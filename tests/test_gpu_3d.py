@@ -1,0 +1,82 @@
+"""3D propagator (GPU, FP32) against the FP64 oracle and its properties."""
+import numpy as np
+import pytest
+
+from oracle import lsrtm_oracle as O
+from paper_2508_10405_amd import synth
+from gpu_common import concat, f64, oracle_problem, rel, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+CASES3 = [
+    # n (nz, nx, ny), nt, npml, nshot, uneven
+    ((14, 17, 11), 70, 4, 2, True),
+    ((70, 9, 38), 60, 5, 1, False),
+]
+
+
+@pytest.mark.parametrize("n,nt,npml,nshot,uneven", CASES3)
+def test_3d_vs_oracle(torch, n, nt, npml, nshot, uneven):
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small(n, nt=nt, npml=npml, seed=sum(n) + 3, nshot=nshot, uneven=uneven, h=12.5)
+    print(f"[case] 3D {n} nt={nt} npml={npml} nshot={nshot}", flush=True)
+    prob = oracle_problem(w)
+    lnvp, lnip = f64(w.lnvp), f64(w.lnip)
+    ctx = lsrtm.context_for(w)
+    d0 = ctx.forward().cpu().numpy()
+    e = rel(d0, concat(O.forward(prob, lnvp, lnip)))
+    print("3d forward rel", e)
+    assert e <= TOL
+    dd = ctx.born(to_dev(torch, w.dm)).cpu().numpy()
+    e = rel(dd, concat(O.born(prob, lnvp, lnip, f64(w.dm))))
+    print("3d born rel", e)
+    assert e <= TOL
+    rng = np.random.default_rng(1)
+    ys = [rng.standard_normal((nt, len(r))) for r in w.rec]
+    img = ctx.adjoint(to_dev(torch, concat(ys))).cpu().numpy()
+    refi = O.adjoint(prob, lnvp, lnip, ys)
+    for k in range(2):
+        e = rel(img[k], refi[k])
+        print("3d adjoint rel", k, e)
+        assert e <= TOL
+
+
+def test_3d_invariances(torch):
+    """Tiles, batching, replay interval and per-group checkpoints do not
+    change a single bit of the 3D results."""
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((20, 18, 70), nt=50, npml=4, seed=5, nshot=3, uneven=True, h=12.5)
+    dm = to_dev(torch, w.dm)
+    y = to_dev(torch, np.random.default_rng(2).standard_normal(sum(w.nt * len(r) for r in w.rec)))
+    ref = None
+    for opts in ({"tile": 0}, {"tile": 1, "shots_per_launch": 1}, {"tile": 2, "ckpt_every": 7},
+                 {"tile": 3, "ckpt_every": 50}, {"tile": 4, "ckpt_per_group": True, "shots_per_launch": 2},
+                 {"tile": 5, "graph": False}):
+        ctx = lsrtm.context_for(w, **opts)
+        out = (ctx.born(dm).cpu().numpy(), ctx.adjoint(y).cpu().numpy())
+        ctx.close()
+        if ref is None:
+            ref = out
+        else:
+            assert np.array_equal(out[0], ref[0]), opts
+            assert np.array_equal(out[1], ref[1]), opts
+
+
+def test_3d_dot_product(torch):
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((24, 30, 26), nt=80, npml=6, seed=8, nshot=2, uneven=True, h=12.5)
+    ctx = lsrtm.context_for(w)
+    rng = np.random.default_rng(3)
+    x = to_dev(torch, rng.standard_normal((2,) + w.shape))
+    y = to_dev(torch, rng.standard_normal(ctx.data_len))
+    a = ctx.dot(ctx.born(x), y)
+    b = ctx.dot(x.view(-1), ctx.adjoint(y).view(-1))
+    print("3d dot", a, b)
+    assert abs(a - b) <= TOL * abs(a)
