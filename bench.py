@@ -58,9 +58,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload_tag, kernel):
+def read_traffic(workload_tag, kernel, pts_per_launch):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
-    summary, or None when it is missing or the kernels changed since."""
+    summary (calibrated bytes per padded node times the nodes of a launch),
+    or None when it is missing or the kernels changed since."""
     path = os.path.join(ROOT, "profiles", f"pmc_{workload_tag}.md")
     if not os.path.exists(path):
         return None
@@ -72,8 +73,8 @@ def read_traffic(workload_tag, kernel):
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha") != kernel_source_hash():
         return None
-    v = vals.get(f"traffic_bytes_per_launch.{kernel}")
-    return float(v) if v not in (None, "", "null") else None
+    v = vals.get(f"traffic_bytes_per_point.{kernel}")
+    return float(v) * pts_per_launch if v not in (None, "", "null") else None
 
 
 # ---------------------------------------------------------------------------
@@ -121,8 +122,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a 1 GiB axpy (known traffic) for counter calibration")
-    ap.add_argument("--shots-per-launch", type=int, default=0)
+    ap.add_argument("--shots-per-launch", type=int, default=-1,
+                    help="-1 = autotuned together with the tile shape")
     ap.add_argument("--tile", type=int, default=-1)
+    ap.add_argument("--tune-steps", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the shot-parallel "
@@ -138,7 +141,11 @@ def main():
     w = synth.config2()
     tag = "config2_batched"
     log(f"[bench] workload {w.name}: {w.nshot} shots, nt={w.nt}, padded points {w.padded_points()}")
-    ctx = lsrtm.context_for(w, shots_per_launch=args.shots_per_launch, tile=args.tile, timing=True)
+    ctx = lsrtm.context_for(w, shots_per_launch=max(0, args.shots_per_launch), tile=args.tile, timing=True)
+    if args.tile < 0:
+        t0 = time.perf_counter()
+        tuned = ctx.autotune(nsteps=args.tune_steps, groups=args.shots_per_launch < 0)
+        log(f"[bench] autotune {tuned} in {time.perf_counter() - t0:.1f} s")
     sz = ctx.sizes()
     log(f"[bench] plan {sz}")
     dm = torch.from_numpy(w.dm).to(dev)
@@ -175,7 +182,7 @@ def main():
     avg_ms = kms[dom] / max(1, kcnt[dom])
     bytes_launch = BYTES_PER_PT[2][dom] * pts_per_launch
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    traffic = read_traffic(tag, dom)
+    traffic = read_traffic(tag, dom, pts_per_launch)
     kernels = {k: {"avg_ms": kms[k] / kcnt[k], "launches_timed": kcnt[k],
                    "GBs": (BYTES_PER_PT[2][k] * pts_per_launch / (kms[k] / kcnt[k] * 1e-3) / 1e9)
                    if k in BYTES_PER_PT[2] else None}
@@ -190,7 +197,7 @@ def main():
         P = min(args.plain_shots, w.nshot)
         wp = synth.Workload(w.name, w.h, w.dt, w.nt, w.npml, w.f0, w.lnvp, w.lnip, w.dm,
                             w.win[:P], w.src[:P], w.rec[:P], w.wavelet[:P])
-        cp = lsrtm.context_for(wp, shots_per_launch=1, tile=args.tile)
+        cp = lsrtm.context_for(wp, shots_per_launch=1, tile=args.tile, graph=False)
         dp = cp.born(dm)
         xp = cp.cgnr_begin(dp)
         torch.cuda.synchronize()
@@ -208,10 +215,16 @@ def main():
         a = torch.ones(n, device=dev)
         b = torch.ones(n, device=dev)
         c2 = lsrtm.Context((4, 4), (10.0, 10.0), 1, 1e-3)
+        c2.axpy(0.5, a, b)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(3):
             c2.axpy(0.5, a, b)
+        e1.record()
         torch.cuda.synchronize()
-        calib = {"kernel": "k_axpy", "elements": n, "read_bytes": 8 * n, "write_bytes": 4 * n}
+        ms = e0.elapsed_time(e1) / 3
+        calib = {"kernel": "k_axpy", "elements": n, "read_bytes": 8 * n, "write_bytes": 4 * n,
+                 "avg_ms": ms, "GBs": 12 * n / (ms * 1e-3) / 1e9}
         log(f"[bench] calibration axpy {calib}")
 
     cpu = None
@@ -237,6 +250,7 @@ def main():
                                "nt=4000, 15 Hz, CGNR step = Born + migration",
                    "shots": w.nshot, "nt": w.nt, "padded_points": padded,
                    "shots_per_launch": sz["shots_per_launch"], "ckpt_every": sz["ckpt_every"],
+                   "tile": list(lsrtm.tile_shape(2, sz["tile"])),
                    "parallelism": "shots batched on 1 GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
