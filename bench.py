@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # every array read once and written once; CPML strips excluded).
 BYTES_PER_PT = {
     2: {"born_v": 52, "born_p": 40, "bg_v": 36, "bg_p": 24, "adj_a": 36, "adj_b": 40},
-    3: {"born_v": 72, "born_p": 48, "bg_v": 48, "bg_p": 28, "adj_a": 44, "adj_b": 52},
+    3: {"born_v": 72, "born_p": 48, "bg_v": 52, "bg_p": 28, "adj_a": 44, "adj_b": 52},
 }
 KERNEL_SYMBOL = {"born_v": "k2_v<*, true, false>", "born_p": "k2_p<*, true, false>",
                  "bg_v": "k2_v<*, false, true>", "bg_p": "k2_p<*, false, true>",
@@ -126,6 +126,9 @@ def main():
                     help="-1 = autotuned together with the tile shape")
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--tune-steps", type=int, default=8)
+    ap.add_argument("--workload", default="config2", choices=("config2", "config3", "config5"),
+                    help="config2 = the benchmark workload; config3 (uneven apertures) and config5 (3D, "
+                         "BF16 checkpoints) are measured on request")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the shot-parallel "
@@ -138,10 +141,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    w = synth.config2()
-    tag = "config2_batched"
+    w = {"config2": synth.config2, "config3": synth.config3, "config5": synth.config5}[args.workload]()
+    tag = f"{args.workload}_batched"
+    nd = w.ndim
+    ckdt = "bf16" if args.workload == "config5" else "f32"
     log(f"[bench] workload {w.name}: {w.nshot} shots, nt={w.nt}, padded points {w.padded_points()}")
-    ctx = lsrtm.context_for(w, shots_per_launch=max(0, args.shots_per_launch), tile=args.tile, timing=True)
+    ctx = lsrtm.context_for(w, shots_per_launch=max(0, args.shots_per_launch), tile=args.tile, timing=True,
+                            ckpt_dtype=ckdt)
     if args.tile < 0:
         t0 = time.perf_counter()
         tuned = ctx.autotune(nsteps=args.tune_steps, groups=args.shots_per_launch < 0)
@@ -178,14 +184,14 @@ def main():
 
     # roofline of the dominant kernel
     pts_per_launch = padded / sz["groups"]
-    dom = max((k for k in BYTES_PER_PT[2]), key=lambda k: kms[k])
+    dom = max((k for k in BYTES_PER_PT[nd]), key=lambda k: kms[k])
     avg_ms = kms[dom] / max(1, kcnt[dom])
-    bytes_launch = BYTES_PER_PT[2][dom] * pts_per_launch
+    bytes_launch = BYTES_PER_PT[nd][dom] * pts_per_launch
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     traffic = read_traffic(tag, dom, pts_per_launch)
     kernels = {k: {"avg_ms": kms[k] / kcnt[k], "launches_timed": kcnt[k],
-                   "GBs": (BYTES_PER_PT[2][k] * pts_per_launch / (kms[k] / kcnt[k] * 1e-3) / 1e9)
-                   if k in BYTES_PER_PT[2] else None}
+                   "GBs": (BYTES_PER_PT[nd][k] * pts_per_launch / (kms[k] / kcnt[k] * 1e-3) / 1e9)
+                   if k in BYTES_PER_PT[nd] else None}
                for k in lsrtm.KERNEL_NAMES if kcnt[k] > 0}
     ctx.close()
     del ctx, d_obs, x
@@ -193,7 +199,7 @@ def main():
 
     # plain per-shot form on a sample of shots
     plain = None
-    if args.plain_shots > 0:
+    if args.plain_shots > 0 and nd == 2:
         P = min(args.plain_shots, w.nshot)
         wp = synth.Workload(w.name, w.h, w.dt, w.nt, w.npml, w.f0, w.lnvp, w.lnip, w.dm,
                             w.win[:P], w.src[:P], w.rec[:P], w.wavelet[:P])
@@ -228,7 +234,7 @@ def main():
         log(f"[bench] calibration axpy {calib}")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "config2":
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
         cpu = cpu_baseline(args.cpu_steps, workers, padded // w.nshot)
         log(f"[bench] cpu baseline {cpu}")
@@ -246,11 +252,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "2D LSRTM 737x240 @12.5 m (280x777 padded), 120 shots, 369 receivers, "
-                               "nt=4000, 15 Hz, CGNR step = Born + migration",
+        "config": {"workload": {"config2": "2D LSRTM 737x240 @12.5 m (280x777 padded), 120 shots, 369 receivers, "
+                                           "nt=4000, 15 Hz, CGNR step = Born + migration",
+                                "config3": "2D LSRTM, 256 shots on uneven windows of 200..737 x 240 nodes, "
+                                           "nt=4000, 15 Hz, CGNR step = Born + migration",
+                                "config5": "3D LSRTM 400x400x200 @12.5 m (440x440x240 padded), 16 shots, "
+                                           "80x80 receivers, nt=2500, 20 Hz, BF16 checkpoints, "
+                                           "CGNR step = Born + migration"}[args.workload],
                    "shots": w.nshot, "nt": w.nt, "padded_points": padded,
                    "shots_per_launch": sz["shots_per_launch"], "ckpt_every": sz["ckpt_every"],
-                   "tile": list(lsrtm.tile_shape(2, sz["tile"])),
+                   "tile": list(lsrtm.tile_shape(nd, sz["tile"])), "ckpt_dtype": ckdt,
+                   "ckpt_per_group": bool(sz["ckpt_per_group"]),
                    "parallelism": "shots batched on 1 GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

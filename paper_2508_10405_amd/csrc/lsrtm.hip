@@ -226,6 +226,14 @@ void free_acq(lsrtm_ctx* c) {
 
 long long round_up(long long a, long long m) { return (a + m - 1) / m * m; }
 
+// Consecutive launch groups of at most G shots, sizes balanced to within one.
+std::vector<int> group_sizes(int nshot, int G) {
+    const int ng = (nshot + G - 1) / G;
+    std::vector<int> v(ng, nshot / ng);
+    for (int i = 0; i < nshot % ng; ++i) v[i] += 1;
+    return v;
+}
+
 // 1D CPML coefficients along one padded axis of N nodes.
 void cpml_axis(int N, int npml, double h, double dt, double vmax, double R, double f0, bool half,
                std::vector<float>& ac, std::vector<float>& bc) {
@@ -552,6 +560,9 @@ lsrtm_status check_ready(lsrtm_ctx* c) {
 }
 
 lsrtm_status prep_model_windows(lsrtm_ctx* c) {
+    // host tables stay alive until the stream synchronisation below
+    std::vector<std::vector<float>> tabs;
+    tabs.reserve(3 * c->wins.size());
     for (auto& w : c->wins) {
         PrepArgs a;
         a.lnvp = c->lnvp;
@@ -575,15 +586,13 @@ lsrtm_status prep_model_windows(lsrtm_ctx* c) {
             std::vector<float> ach, bch, aci, bci;
             cpml_axis(w.N[ax], c->g.npml, c->g.h[ax], c->g.dt, c->vmax, c->g.pml_R, c->g.pml_f0, true, ach, bch);
             cpml_axis(w.N[ax], c->g.npml, c->g.h[ax], c->g.dt, c->vmax, c->g.pml_R, c->g.pml_f0, false, aci, bci);
-            std::vector<float> tab;
+            tabs.emplace_back();
+            std::vector<float>& tab = tabs.back();
             tab.insert(tab.end(), ach.begin(), ach.end());
             tab.insert(tab.end(), bch.begin(), bch.end());
             tab.insert(tab.end(), aci.begin(), aci.end());
             tab.insert(tab.end(), bci.begin(), bci.end());
             HIPCHK(c, hipMemcpyAsync(w.cpml[ax], tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice, c->st));
-        }
-        if (c->ndim == 2) {
-            // unused y tables must still be valid memory for uniform code
         }
     }
     HIPCHK(c, hipStreamSynchronize(c->st));
@@ -701,12 +710,13 @@ lsrtm_status plan(lsrtm_ctx* c) {
         ckg = mode == 1;
         G = G0;
         for (;;) {
-            long long grp_pts = 0, cur = 0;
-            for (int s = 0; s < nshot; ++s) {
-                cur += c->wins[c->shots[s].win].npts;
-                if ((s + 1) % G == 0 || s == nshot - 1) {
+            long long grp_pts = 0;
+            {
+                int s = 0;
+                for (int gs : group_sizes(nshot, G)) {
+                    long long cur = 0;
+                    for (int e = 0; e < gs; ++e, ++s) cur += c->wins[c->shots[s].win].npts;
                     grp_pts = std::max(grp_pts, cur);
-                    cur = 0;
                 }
             }
             const long long seg_step = grp_pts * (nd + 1) * 4;
@@ -731,7 +741,7 @@ lsrtm_status plan(lsrtm_ctx* c) {
     if (!fits)
         FAIL(c, LSRTM_ENOMEM, "memory plan needs %.2f GB, budget %.2f GB", need / 1e9, budget / 1e9);
     c->ck_group = ckg;
-    c->G = G;
+    c->G = group_sizes(nshot, G)[0];
     c->k = k;
     c->nseg = (nt + k - 1) / k;
     c->plan_bytes = need;
@@ -753,12 +763,14 @@ lsrtm_status plan(lsrtm_ctx* c) {
         for (int a = 0; a < nd; ++a) HIPCHK(c, launch_fill(W.bdt[a], W.npts, 0.f, c->st));
     }
     // ---- groups ----------------------------------------------------------------
-    for (int s0 = 0; s0 < nshot; s0 += G) {
+    int s0 = 0;
+    for (int gs : group_sizes(nshot, G)) {
         Group gr;
         gr.s0 = s0;
-        gr.ns = std::min(G, nshot - s0);
+        gr.ns = gs;
+        s0 += gs;
         long long pts = 0;
-        for (int s = s0; s < s0 + gr.ns; ++s) pts += c->wins[c->shots[s].win].npts;
+        for (int s = gr.s0; s < gr.s0 + gr.ns; ++s) pts += c->wins[c->shots[s].win].npts;
         gr.bg_used = pts * nbg;
         gr.sc_used = pts * nsc;
         gr.img_used = pts * 2;
