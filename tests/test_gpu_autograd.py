@@ -108,3 +108,34 @@ def test_checkpoint_interval_and_dtype(torch, k, dtype):
     print(f"[ckpt] k={k} {dtype} gradient rel err {e:.3e}")
     bound = {"f32": 1e-4, "f16": 2e-3, "bf16": 2e-2}[dtype]
     assert e <= bound
+
+
+def test_config4_checkpoint_table(torch):
+    """Config-4 geometry (480 x 160 at 12.5 m, 15 Hz), one shot, the first 400
+    steps: gradient of the misfit through the autograd op for every checkpoint
+    interval and snapshot precision against the FP64 oracle (the table the
+    design notes quote)."""
+    from paper_2508_10405_amd import autograd, lsrtm
+    full = synth.config4(nt=400)
+    s = 15
+    w = synth.Workload(full.name, full.h, full.dt, full.nt, full.npml, full.f0, full.lnvp, full.lnip,
+                       full.dm, full.win[s:s + 1], full.src[s:s + 1], full.rec[s:s + 1],
+                       full.wavelet[s:s + 1])
+    prob = oracle_problem(w)
+    lnvp, lnip = f64(w.lnvp), f64(w.lnip)
+    d_obs = O.born(prob, lnvp, lnip, f64(w.dm))
+    m0 = 0.5 * f64(w.dm)
+    Lm = O.born(prob, lnvp, lnip, m0)
+    g_ref = O.adjoint(prob, lnvp, lnip, [Lm[0] - d_obs[0]], ckpt_every=50)
+    rows = []
+    for dtype in ("f32", "f16", "bf16"):
+        for k in (10, 50, 200):
+            ctx = lsrtm.context_for(w, ckpt_every=k, ckpt_dtype=dtype)
+            m = to_dev(torch, m0).requires_grad_(True)
+            J = autograd.misfit(m, ctx, to_dev(torch, concat(d_obs)))
+            J.backward()
+            e = rel(m.grad.cpu().numpy(), g_ref)
+            rows.append((dtype, k, e))
+            print(f"[config4 table] {dtype} k={k} gradient rel err {e:.3e}", flush=True)
+            ctx.close()
+            assert e <= {"f32": 1e-4, "f16": 2e-3, "bf16": 2e-2}[dtype]
