@@ -40,6 +40,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PT = {
     2: {"born_v": 52, "born_p": 40, "bg_v": 36, "bg_p": 24, "adj_a": 36, "adj_b": 40},
     3: {"born_v": 72, "born_p": 48, "bg_v": 52, "bg_p": 28, "adj_a": 44, "adj_b": 52},
+    # fused 2D schedule: one kernel per step, reported under the velocity-phase class
+    "2f": {"born_v": 68, "bg_v": 48, "adj_a": 64},
 }
 KERNEL_SYMBOL = {"born_v": "k2_v<*, true, false>", "born_p": "k2_p<*, true, false>",
                  "bg_v": "k2_v<*, false, true>", "bg_p": "k2_p<*, false, true>",
@@ -132,7 +134,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the shot-parallel "
-              "multi-GPU layout is described in DESIGN.md but not built", file=sys.stderr)
+              "multi-GPU layout is not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -154,6 +156,7 @@ def main():
         log(f"[bench] autotune {tuned} in {time.perf_counter() - t0:.1f} s")
     sz = ctx.sizes()
     log(f"[bench] plan {sz}")
+    btab = BYTES_PER_PT["2f" if (nd == 2 and sz["fused"]) else nd]
     dm = torch.from_numpy(w.dm).to(dev)
     d_obs = ctx.born(dm)
     torch.cuda.synchronize()
@@ -184,14 +187,14 @@ def main():
 
     # roofline of the dominant kernel
     pts_per_launch = padded / sz["groups"]
-    dom = max((k for k in BYTES_PER_PT[nd]), key=lambda k: kms[k])
+    dom = max((k for k in btab), key=lambda k: kms[k])
     avg_ms = kms[dom] / max(1, kcnt[dom])
-    bytes_launch = BYTES_PER_PT[nd][dom] * pts_per_launch
+    bytes_launch = btab[dom] * pts_per_launch
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    traffic = read_traffic(tag, dom, pts_per_launch)
+    traffic = read_traffic(tag + ("_fused" if (nd == 2 and sz["fused"]) else ""), dom, pts_per_launch)
     kernels = {k: {"avg_ms": kms[k] / kcnt[k], "launches_timed": kcnt[k],
-                   "GBs": (BYTES_PER_PT[nd][k] * pts_per_launch / (kms[k] / kcnt[k] * 1e-3) / 1e9)
-                   if k in BYTES_PER_PT[nd] else None}
+                   "GBs": (btab[k] * pts_per_launch / (kms[k] / kcnt[k] * 1e-3) / 1e9)
+                   if k in btab else None}
                for k in lsrtm.KERNEL_NAMES if kcnt[k] > 0}
     ctx.close()
     del ctx, d_obs, x
@@ -263,6 +266,7 @@ def main():
                    "shots_per_launch": sz["shots_per_launch"], "ckpt_every": sz["ckpt_every"],
                    "tile": list(lsrtm.tile_shape(nd, sz["tile"])), "ckpt_dtype": ckdt,
                    "ckpt_per_group": bool(sz["ckpt_per_group"]),
+                   "schedule": "fused step" if sz["fused"] else "two-phase step",
                    "parallelism": "shots batched on 1 GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

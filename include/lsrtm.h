@@ -88,11 +88,16 @@ enum {
                                        events (read back with lsrtm_stats)      */
     LSRTM_OPT_MEM_BUDGET_MB = 5,    /* device memory the plan may use; 0 = 90 %
                                        of the free memory at set_acquisition    */
-    LSRTM_OPT_CKPT_PER_GROUP = 6    /* 1 = keep background checkpoints only for
+    LSRTM_OPT_CKPT_PER_GROUP = 6,   /* 1 = keep background checkpoints only for
                                        the active launch group and regenerate
                                        them before each group's migration (the
                                        planner picks this by itself when the
                                        checkpoints of all shots do not fit)     */
+    LSRTM_OPT_FUSED = 7             /* 2D: 1 = one kernel per time step (the
+                                       velocity and pressure updates fused,
+                                       double-buffered fields; default), 0 = a
+                                       velocity and a pressure kernel per step.
+                                       Both give identical results.             */
 };
 
 /* Create a context for one grid on one HIP stream (hipStream_t, may be 0).
@@ -166,10 +171,10 @@ lsrtm_status lsrtm_axpy(lsrtm_ctx* ctx, double alpha, const float* x, float* y, 
 /* Set an LSRTM_OPT_* option. */
 lsrtm_status lsrtm_set_option(lsrtm_ctx* ctx, int key, long long value);
 
-/* Autotuner: times the six stencil phases over nsteps time steps on the
- * actual launch groups for every tile shape, and with tune_groups = 1 also
- * for several shot-per-launch sizes (rebuilding the memory plan), then keeps
- * the fastest.  out (HOST double[3], may be NULL) = (tile id, shots per
+/* Autotuner: times the stencil kernels of a Born, replay and adjoint step
+ * over nsteps time steps on the actual launch groups for every tile shape,
+ * and with tune_groups = 1 also for several shot-per-launch sizes and (2D)
+ * both step schedules (rebuilding the memory plan), then keeps the fastest.  out (HOST double[3], may be NULL) = (tile id, shots per
  * launch, ms per time step).  With LSRTM_TUNE_CACHE naming a file, results
  * are read from and appended to it.  Invalidates stored checkpoints.  When
  * no tile is set, a tile-only tuning runs on the first pass by itself. */
@@ -179,7 +184,8 @@ lsrtm_status lsrtm_autotune(lsrtm_ctx* ctx, int nsteps, int tune_groups, double*
  * out[2] = shots per launch, out[3] = checkpoint interval, out[4] = number of
  * launch groups, out[5] = padded points summed over shots, out[6] = device
  * bytes planned, out[7] = tile id in use, out[8] = 1 if checkpoints are held
- * per launch group.  HOST long long [nout]. */
+ * per launch group, out[9] = 1 for the fused 2D schedule.  HOST long long
+ * [nout]. */
 lsrtm_status lsrtm_sizes(lsrtm_ctx* ctx, long long* out, int nout);
 
 /* Timing statistics of the last pass (HOST double [nout]); see

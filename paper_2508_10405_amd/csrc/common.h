@@ -39,6 +39,16 @@ struct Slot {
     float* eta[3];           // scattered phi       | adjoint of phi
     float* gk;               // image of lnkappa
     float* gr;               // image of lnrho
+    // second buffers of the fused one-kernel-per-step schedule: the step
+    // reads the fields above and writes the ones below (roles swap every
+    // step).  Null when the two-phase schedule is in use.
+    float* pn;
+    float* vn[3];
+    float* psin[3];
+    float* qn;
+    float* wn[3];
+    float* xin[3];
+    float* etan[3];
     float* seg;              // replay buffer [k][ndim + 1][npts]: dv_a, q
     char* ck;                // checkpoint 1 of this shot; checkpoint j >= 1 at ck + (j-1) * ckbytes
     long long ckbytes;

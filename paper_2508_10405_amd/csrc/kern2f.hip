@@ -1,0 +1,492 @@
+// Fused 2D time steps: one kernel per step instead of a velocity and a
+// pressure phase (and one adjoint kernel instead of two).
+//
+// A tile of BZ x BX nodes stages the pressure of the previous step on a cross
+// with a 7-node halo, computes the new velocities on the tile plus the 4-node
+// halo the pressure update needs (redundantly with the neighbouring tiles),
+// keeps them in LDS and then updates the pressure of the tile.  Every field
+// that a tile reads at halo nodes is double-buffered (read "cur", write
+// "next", roles swapped every step), so no tile overwrites a value another
+// tile still reads; the background phi (read only at its own node) is
+// updated in place, the scattered/adjoint phi is double-buffered like the
+// rest because the adjoint reads it at halo nodes.
+// Each expression is the one of the two-phase kernels (kern2d.hip) with the
+// same operation order, so both schedules give identical bits.  Per-shot HBM
+// traffic per node and step: 48 B (Born, was 72), 36 B (replay, was 48), 52 B
+// (adjoint, was 64).
+#include "common.h"
+#include "kernels.h"
+
+namespace lsrtm {
+
+template <int BZ, int BX>
+struct F2 {
+    static constexpr int PZ = BZ + 14;        // cross rows -7 .. BZ+6
+    static constexpr int PX = BX + 14;        // cross cols -7 .. BX+6
+    static constexpr int NPL = PZ * PX;
+    static constexpr int VZ = BZ + 7;         // velocity rows -4 .. BZ+2
+    static constexpr int VX = BX + 7;         // velocity cols -4 .. BX+2
+    static constexpr int NVZ = VZ * BX;
+    static constexpr int NVX = BZ * VX;
+    static constexpr int NP = BZ * BX;
+    static constexpr int R = NP / NTHREADS;
+    static_assert(NP % NTHREADS == 0, "tile must hold a multiple of 256 nodes");
+};
+
+// Visit tile-local nodes (lz, lx) of rows [z0, z1) x cols [x0, x1).
+template <typename Fn>
+__device__ __forceinline__ void rect(int z0, int z1, int x0, int x1, Fn f) {
+    const int nzr = z1 - z0, n = nzr * (x1 - x0);
+    for (int e = threadIdx.x; e < n; e += NTHREADS) f(z0 + e % nzr, x0 + e / nzr);
+}
+
+// ---------------------------------------------------------------------------
+// Forward step: background (+ scattered for BORN, + replay store for SEG)
+// ---------------------------------------------------------------------------
+template <int BZ, int BX, bool BORN, bool SEG>
+__global__ void __launch_bounds__(NTHREADS)
+k2f_step(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+{
+    using T = F2<BZ, BX>;
+    constexpr int R = T::R;
+    __shared__ float sp[T::NPL];
+    __shared__ float sq[BORN ? T::NPL : 1];
+    __shared__ float svz[T::NVZ];
+    __shared__ float svx[T::NVX];
+    __shared__ float swz[BORN ? T::NVZ : 1];
+    __shared__ float swx[BORN ? T::NVX : 1];
+    const int4 tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const Slot& S = slots[tl.x];
+    const int z0 = tl.y, x0 = tl.z;
+    const int nz = S.n[0], nx = S.n[1];
+    const long long ldz = S.ldz;
+    // pointwise loads of the pressure update
+    float kk[R], lk[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = threadIdx.x + NTHREADS * r;
+        const int gz = z0 + e % BZ, gx = x0 + e / BZ;
+        const long long i = (gz < nz && gx < nx) ? gx * ldz + gz : 0;
+        kk[r] = S.kdt[i];
+        if (BORN) lk[r] = S.dlnk[i];
+    }
+    // velocity regions: v_z on rows -4 .. BZ+2 of the tile columns, v_x on
+    // cols -4 .. BX+2 of the tile rows; their pointwise inputs are loaded now
+    constexpr int NZR = BZ + 7, NXR = BZ;
+    constexpr int RZ = (T::NVZ + NTHREADS - 1) / NTHREADS;
+    constexpr int RX = (T::NVX + NTHREADS - 1) / NTHREADS;
+    float zv[RZ], zb[RZ], zw[RZ], zr0[RZ], zr1[RZ];
+    float xv[RX], xb[RX], xw[RX], xr0[RX], xr1[RX];
+    long long zi[RZ], xi_[RX];
+    bool zin[RZ], xin_[RX];
+#pragma unroll
+    for (int t = 0; t < RZ; ++t) {
+        const int e = threadIdx.x + NTHREADS * t;
+        const int lz = -4 + e % NZR, lx = e / NZR;
+        const int gz = z0 + lz, gx = x0 + lx;
+        zin[t] = e < T::NVZ && (unsigned)gz < (unsigned)nz && gx < nx;
+        const long long i = zin[t] ? gx * ldz + gz : 0;
+        zi[t] = i;
+        zv[t] = S.v[0][i];
+        zb[t] = S.bdt[0][i];
+        if (BORN) {
+            zw[t] = S.w[0][i];
+            zr0[t] = S.dlnr[i];
+            zr1[t] = S.dlnr[(zin[t] && gz + 1 < nz) ? i + 1 : i];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < RX; ++t) {
+        const int e = threadIdx.x + NTHREADS * t;
+        const int lz = e % NXR, lx = -4 + e / NXR;
+        const int gz = z0 + lz, gx = x0 + lx;
+        xin_[t] = e < T::NVX && gz < nz && (unsigned)gx < (unsigned)nx;
+        const long long i = xin_[t] ? gx * ldz + gz : 0;
+        xi_[t] = i;
+        xv[t] = S.v[1][i];
+        xb[t] = S.bdt[1][i];
+        if (BORN) {
+            xw[t] = S.w[1][i];
+            xr0[t] = S.dlnr[i];
+            xr1[t] = S.dlnr[(xin_[t] && gx + 1 < nx) ? i + ldz : i];
+        }
+    }
+    // stage p (and dp) of the previous step on the cross
+    auto ldp = [&](int lz, int lx) {
+        const int gz = z0 + lz, gx = x0 + lx;
+        const bool in = (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx;
+        const long long i = gx * ldz + gz;
+        const int c = (lx + 7) * T::PZ + lz + 7;
+        sp[c] = in ? S.p[i] : 0.f;
+        if (BORN) sq[c] = in ? S.q[i] : 0.f;
+    };
+    rect(-7, BZ + 7, 0, BX, ldp);
+    rect(0, BZ, -7, 0, ldp);
+    rect(0, BZ, BX, BX + 7, ldp);
+    __syncthreads();
+    const float* achz = S.cpml[0];
+    const float* bchz = S.cpml[0] + nz;
+    const float* achx = S.cpml[1];
+    const float* bchx = S.cpml[1] + nx;
+    float* __restrict__ seg = S.seg + (long long)sstep * 3 * S.npts;
+#pragma unroll
+    for (int t = 0; t < RZ; ++t) {
+        const int e = threadIdx.x + NTHREADS * t;
+        if (e >= T::NVZ) continue;
+        const int lz = -4 + e % NZR, lx = e / NZR;
+        const int gz = z0 + lz;
+        const int cv = lx * T::VZ + lz + 4;
+        if (!zin[t]) {
+            svz[cv] = 0.f;
+            if (BORN) swz[cv] = 0.f;
+            continue;
+        }
+        const bool own = lz >= 0 && lz < BZ;
+        const long long i = zi[t];
+        const int c = (lx + 7) * T::PZ + lz + 7;
+        const float az = achz[gz];
+        const float bz = zb[t];
+        float g = d_half(sp, c, 1, C.c[0]);
+        if (az != 0.f) {
+            const float ps = fmaf(bchz[gz], S.psi[0][i], az * g);
+            if (own) S.psin[0][i] = ps;
+            g = g + ps;
+        }
+        const float dv = -bz * g;
+        const float vn = zv[t] + dv;
+        svz[cv] = vn;
+        if (own) {
+            S.vn[0][i] = vn;
+            if (SEG) seg[i] = dv;
+        }
+        if (BORN) {
+            float gq = d_half(sq, c, 1, C.c[0]);
+            if (az != 0.f) {
+                const float ps = fmaf(bchz[gz], S.xi[0][i], az * gq);
+                if (own) S.xin[0][i] = ps;
+                gq = gq + ps;
+            }
+            const float wn = (zw[t] - bz * gq) - 0.5f * (zr0[t] + zr1[t]) * dv;
+            swz[cv] = wn;
+            if (own) S.wn[0][i] = wn;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < RX; ++t) {
+        const int e = threadIdx.x + NTHREADS * t;
+        if (e >= T::NVX) continue;
+        const int lz = e % NXR, lx = -4 + e / NXR;
+        const int gx = x0 + lx;
+        const int cv = (lx + 4) * BZ + lz;
+        if (!xin_[t]) {
+            svx[cv] = 0.f;
+            if (BORN) swx[cv] = 0.f;
+            continue;
+        }
+        const bool own = lx >= 0 && lx < BX;
+        const long long i = xi_[t];
+        const int c = (lx + 7) * T::PZ + lz + 7;
+        const float ax = achx[gx];
+        const float bx = xb[t];
+        float g = d_half(sp, c, T::PZ, C.c[1]);
+        if (ax != 0.f) {
+            const float ps = fmaf(bchx[gx], S.psi[1][i], ax * g);
+            if (own) S.psin[1][i] = ps;
+            g = g + ps;
+        }
+        const float dv = -bx * g;
+        const float vn = xv[t] + dv;
+        svx[cv] = vn;
+        if (own) {
+            S.vn[1][i] = vn;
+            if (SEG) seg[S.npts + i] = dv;
+        }
+        if (BORN) {
+            float gq = d_half(sq, c, T::PZ, C.c[1]);
+            if (ax != 0.f) {
+                const float ps = fmaf(bchx[gx], S.xi[1][i], ax * gq);
+                if (own) S.xin[1][i] = ps;
+                gq = gq + ps;
+            }
+            const float wn = (xw[t] - bx * gq) - 0.5f * (xr0[t] + xr1[t]) * dv;
+            swx[cv] = wn;
+            if (own) S.wn[1][i] = wn;
+        }
+    }
+    __syncthreads();
+    // pressure of the tile
+    const float* aciz = S.cpml[0] + 2 * nz;
+    const float* bciz = S.cpml[0] + 3 * nz;
+    const float* acix = S.cpml[1] + 2 * nx;
+    const float* bcix = S.cpml[1] + 3 * nx;
+    const float amp = S.src >= 0 ? S.src_amp[n] : 0.f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = threadIdx.x + NTHREADS * r;
+        const int lz = e % BZ, lx = e / BZ;
+        const int gz = z0 + lz, gx = x0 + lx;
+        if (gz >= nz || gx >= nx) continue;
+        const long long i = gx * ldz + gz;
+        const int cz = lx * T::VZ + lz + 4;
+        const int cx = (lx + 4) * BZ + lz;
+        const int cp = (lx + 7) * T::PZ + lz + 7;
+        const float az = aciz[gz], ax = acix[gx];
+        float ez = d_node(svz, cz, 1, C.c[0]);
+        float ex = d_node(svx, cx, BZ, C.c[1]);
+        if (az != 0.f) {
+            const float ph = fmaf(bciz[gz], S.phi[0][i], az * ez);
+            S.phi[0][i] = ph;
+            ez = ez + ph;
+        }
+        if (ax != 0.f) {
+            const float ph = fmaf(bcix[gx], S.phi[1][i], ax * ex);
+            S.phi[1][i] = ph;
+            ex = ex + ph;
+        }
+        const float q = ez + ex;
+        const float k = kk[r];
+        float pn = sp[cp] - k * q;
+        if (i == S.src) pn = pn + amp;
+        S.pn[i] = pn;
+        if (SEG) seg[2 * S.npts + i] = q;
+        if (BORN) {
+            float fz = d_node(swz, cz, 1, C.c[0]);
+            float fx = d_node(swx, cx, BZ, C.c[1]);
+            if (az != 0.f) {
+                const float ph = fmaf(bciz[gz], S.eta[0][i], az * fz);
+                S.etan[0][i] = ph;
+                fz = fz + ph;
+            }
+            if (ax != 0.f) {
+                const float ph = fmaf(bcix[gx], S.eta[1][i], ax * fx);
+                S.etan[1][i] = ph;
+                fx = fx + ph;
+            }
+            const float dq = fz + fx;
+            S.qn[i] = (sq[cp] - k * dq) + lk[r] * (-k * q);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint step (transpose of the forward step): phase A on the tile plus the
+// velocity halo, then phase B on the tile.  flag = 1 on the first reverse
+// step (no pending update of chi).
+// ---------------------------------------------------------------------------
+template <int BZ, int BX>
+__global__ void __launch_bounds__(NTHREADS)
+k2f_adj(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+{
+    using T = F2<BZ, BX>;
+    constexpr int R = T::R;
+    __shared__ float sez[(BZ + 14) * BX];     // e~_z rows -7 .. BZ+6
+    __shared__ float sex[BZ * (BX + 14)];     // e~_x cols -7 .. BX+6
+    __shared__ float sgz[T::NVZ];             // g~_z rows -4 .. BZ+2
+    __shared__ float sgx[T::NVX];             // g~_x cols -4 .. BX+2
+    __shared__ float sxz[T::NVZ];             // -dv_z v~_z (lnrho imaging)
+    __shared__ float sxx[T::NVX];
+    const int4 tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const Slot& S = slots[tl.x];
+    const int z0 = tl.y, x0 = tl.z;
+    const int nz = S.n[0], nx = S.n[1];
+    const long long ldz = S.ldz;
+    const float* __restrict__ segz = S.seg + (long long)sstep * 3 * S.npts;
+    const float* __restrict__ segx = segz + S.npts;
+    const float* __restrict__ segq = segz + 2 * S.npts;
+    float pt[R], kk[R], gk[R], qn[R], gr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = threadIdx.x + NTHREADS * r;
+        const int gz = z0 + e % BZ, gx = x0 + e / BZ;
+        const long long i = (gz < nz && gx < nx) ? gx * ldz + gz : 0;
+        pt[r] = S.q[i];
+        kk[r] = S.kdt[i];
+        gk[r] = S.gk[i];
+        qn[r] = segq[i];
+        gr[r] = S.gr[i];
+    }
+    const float* aciz = S.cpml[0] + 2 * nz;
+    const float* bciz = S.cpml[0] + 3 * nz;
+    const float* acix = S.cpml[1] + 2 * nx;
+    const float* bcix = S.cpml[1] + 3 * nx;
+    // velocity regions (as in the forward step): pointwise inputs loaded now
+    constexpr int NZR = BZ + 7, NXR = BZ;
+    constexpr int RZ = (T::NVZ + NTHREADS - 1) / NTHREADS;
+    constexpr int RX = (T::NVX + NTHREADS - 1) / NTHREADS;
+    float zv[RZ], zb[RZ], zs[RZ], xv[RX], xb[RX], xs[RX];
+    long long zi[RZ], xi_[RX];
+    bool zin[RZ], xin_[RX];
+#pragma unroll
+    for (int t = 0; t < RZ; ++t) {
+        const int e = threadIdx.x + NTHREADS * t;
+        const int lz = -4 + e % NZR, lx = e / NZR;
+        const int gz = z0 + lz, gx = x0 + lx;
+        zin[t] = e < T::NVZ && (unsigned)gz < (unsigned)nz && gx < nx;
+        const long long i = zin[t] ? gx * ldz + gz : 0;
+        zi[t] = i;
+        zv[t] = S.w[0][i];
+        zb[t] = S.bdt[0][i];
+        zs[t] = segz[i];
+    }
+#pragma unroll
+    for (int t = 0; t < RX; ++t) {
+        const int e = threadIdx.x + NTHREADS * t;
+        const int lz = e % NXR, lx = -4 + e / NXR;
+        const int gz = z0 + lz, gx = x0 + lx;
+        xin_[t] = e < T::NVX && gz < nz && (unsigned)gx < (unsigned)nx;
+        const long long i = xin_[t] ? gx * ldz + gz : 0;
+        xi_[t] = i;
+        xv[t] = S.w[1][i];
+        xb[t] = S.bdt[1][i];
+        xs[t] = segx[i];
+    }
+    rect(-7, BZ + 7, 0, BX, [&](int lz, int lx) {
+        const int gz = z0 + lz, gx = x0 + lx;
+        float e = 0.f;
+        if ((unsigned)gz < (unsigned)nz && gx < nx) {
+            const long long i = gx * ldz + gz;
+            const float qt = -S.kdt[i] * S.q[i];
+            const float a = aciz[gz];
+            e = a != 0.f ? qt + a * (S.eta[0][i] + qt) : qt;
+        }
+        sez[lx * (BZ + 14) + lz + 7] = e;
+    });
+    rect(0, BZ, -7, BX + 7, [&](int lz, int lx) {
+        const int gz = z0 + lz, gx = x0 + lx;
+        float e = 0.f;
+        if (gz < nz && (unsigned)gx < (unsigned)nx) {
+            const long long i = gx * ldz + gz;
+            const float qt = -S.kdt[i] * S.q[i];
+            const float a = acix[gx];
+            e = a != 0.f ? qt + a * (S.eta[1][i] + qt) : qt;
+        }
+        sex[(lx + 7) * BZ + lz] = e;
+    });
+    __syncthreads();
+    const float* achz = S.cpml[0];
+    const float* bchz = S.cpml[0] + nz;
+    const float* achx = S.cpml[1];
+    const float* bchx = S.cpml[1] + nx;
+    // phase A for v~_z on rows -4 .. BZ+2, then g~_z and the imaging term
+#pragma unroll
+    for (int t = 0; t < RZ; ++t) {
+        const int e = threadIdx.x + NTHREADS * t;
+        if (e >= T::NVZ) continue;
+        const int lz = -4 + e % NZR, lx = e / NZR;
+        const int gz = z0 + lz;
+        const int cv = lx * T::VZ + lz + 4;
+        if (!zin[t]) {
+            sgz[cv] = 0.f;
+            sxz[cv] = 0.f;
+            continue;
+        }
+        const bool own = lz >= 0 && lz < BZ;
+        const long long i = zi[t];
+        const float vo = zv[t];
+        const float b = zb[t];
+        const float a = achz[gz];
+        float chi = 0.f;
+        if (a != 0.f) {
+            chi = S.xi[0][i];
+            if (!flag) chi = bchz[gz] * (chi + (-b * vo));
+            if (own) S.xin[0][i] = chi;
+        }
+        const float vn = vo - d_half(sez, lx * (BZ + 14) + lz + 7, 1, C.c[0]);
+        if (own) S.wn[0][i] = vn;
+        const float h = -b * vn;
+        sgz[cv] = a != 0.f ? h + a * (chi + h) : h;
+        sxz[cv] = -zs[t] * vn;
+    }
+#pragma unroll
+    for (int t = 0; t < RX; ++t) {
+        const int e = threadIdx.x + NTHREADS * t;
+        if (e >= T::NVX) continue;
+        const int lz = e % NXR, lx = -4 + e / NXR;
+        const int gx = x0 + lx;
+        const int cv = (lx + 4) * BZ + lz;
+        if (!xin_[t]) {
+            sgx[cv] = 0.f;
+            sxx[cv] = 0.f;
+            continue;
+        }
+        const bool own = lx >= 0 && lx < BX;
+        const long long i = xi_[t];
+        const float vo = xv[t];
+        const float b = xb[t];
+        const float a = achx[gx];
+        float chi = 0.f;
+        if (a != 0.f) {
+            chi = S.xi[1][i];
+            if (!flag) chi = bchx[gx] * (chi + (-b * vo));
+            if (own) S.xin[1][i] = chi;
+        }
+        const float vn = vo - d_half(sex, (lx + 7) * BZ + lz, BZ, C.c[1]);
+        if (own) S.wn[1][i] = vn;
+        const float h = -b * vn;
+        sgx[cv] = a != 0.f ? h + a * (chi + h) : h;
+        sxx[cv] = -xs[t] * vn;
+    }
+    __syncthreads();
+    // phase B on the tile
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = threadIdx.x + NTHREADS * r;
+        const int lz = e % BZ, lx = e / BZ;
+        const int gz = z0 + lz, gx = x0 + lx;
+        if (gz >= nz || gx >= nx) continue;
+        const long long i = gx * ldz + gz;
+        const int cz = lx * T::VZ + lz + 4;
+        const int cx = (lx + 4) * BZ + lz;
+        const float az = aciz[gz], ax = acix[gx];
+        if (az != 0.f || ax != 0.f) {
+            const float qt = -kk[r] * pt[r];
+            if (az != 0.f) S.etan[0][i] = bciz[gz] * (S.eta[0][i] + qt);
+            if (ax != 0.f) S.etan[1][i] = bcix[gx] * (S.eta[1][i] + qt);
+        }
+        S.gk[i] = gk[r] + qn[r] * (-kk[r] * pt[r]);
+        const float xz1 = gz > 0 ? sxz[cz - 1] : 0.f;
+        const float xx1 = gx > 0 ? sxx[cx - BZ] : 0.f;
+        S.gr[i] = gr[r] + (0.5f * (sxz[cz] + xz1) + 0.5f * (sxx[cx] + xx1));
+        const float dz = d_node(sgz, cz, 1, C.c[0]);
+        const float dx = d_node(sgx, cx, BZ, C.c[1]);
+        S.qn[i] = pt[r] - (dz + dx);
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <int BZ, int BX>
+static hipError_t launch2f_t(int kind, int ntiles, hipStream_t st, const Slot* slots,
+                             const int4* tiles, const Coef& C, int n, int sstep, int flag)
+{
+    dim3 g(ntiles), b(NTHREADS);
+    switch (kind) {
+    case K_BG_V:   k2f_step<BZ, BX, false, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
+    case K_SEG_V:  k2f_step<BZ, BX, false, true><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
+    case K_BORN_V: k2f_step<BZ, BX, true, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
+    case K_ADJ_A:  k2f_adj<BZ, BX><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Fused schedule: kind is the velocity-phase kind of the step (K_BG_V,
+// K_SEG_V, K_BORN_V) or K_ADJ_A for the adjoint step.
+hipError_t launch2f(int kind, int tile_id, int ntiles, hipStream_t st, const Slot* slots,
+                    const int4* tiles, const Coef& C, int n, int sstep, int flag)
+{
+    if (ntiles <= 0) return hipSuccess;
+    switch (tile_id) {
+    case 0: return launch2f_t<32, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    case 1: return launch2f_t<32, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    case 2: return launch2f_t<32, 32>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    case 3: return launch2f_t<64, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    case 4: return launch2f_t<64, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    case 5: return launch2f_t<64, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    case 6: return launch2f_t<128, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    case 7: return launch2f_t<128, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    case 8: return launch2f_t<256, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace lsrtm

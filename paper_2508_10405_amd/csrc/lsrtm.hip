@@ -57,7 +57,8 @@ struct ShotInfo {
 struct Group {
     int s0 = 0, ns = 0;
     std::vector<Slot> h_slots;
-    Slot* d_slots = nullptr;
+    Slot* d_slots = nullptr;       // descriptors (fused schedule: even steps)
+    Slot* d_alt = nullptr;         // fused schedule: roles of the two buffers swapped
     int4* d_tiles = nullptr;
     int ntiles = 0;
     int tiles_for = -1;            // tile id the table was built for
@@ -120,6 +121,7 @@ struct lsrtm_ctx {
     double* acc64 = nullptr;       // [2][gpts]
     bool ckpt_valid = false;
     bool ck_group = false;         // checkpoints held for the active group only
+    bool fused = false;            // 2D one-kernel-per-step schedule
     // CG workspace
     float* cg_r = nullptr;
     float* cg_w = nullptr;
@@ -135,6 +137,7 @@ struct lsrtm_ctx {
     int opt_timing = 0;
     long long opt_budget_mb = 0;
     int opt_ckg = 0;
+    int opt_fused = 1;
     // timing
     std::vector<EvPair> evpool;
     size_t evused = 0;
@@ -364,20 +367,23 @@ lsrtm_status build_tiles(lsrtm_ctx* c, Group& gr, int tile) {
     return LSRTM_OK;
 }
 
-lsrtm_status stencil(lsrtm_ctx* c, Group& gr, int kind, int n, int sstep, int flag) {
+const Slot* desc(const Group& gr, int par) { return ((par & 1) && gr.d_alt) ? gr.d_alt : gr.d_slots; }
+
+lsrtm_status stencil(lsrtm_ctx* c, Group& gr, int kind, int n, int sstep, int flag, const Slot* sl) {
     static const int cls_of[8] = {2, 3, 2, 3, 0, 1, 4, 5};
     tbeg(c, cls_of[kind]);
-    hipError_t e = c->ndim == 2
-                       ? launch2d(kind, c->tile, gr.ntiles, c->st, gr.d_slots, gr.d_tiles, c->C, n, sstep, flag)
-                       : launch3d(kind, c->tile, gr.ntiles, c->st, gr.d_slots, gr.d_tiles, c->C, n, sstep, flag);
+    hipError_t e;
+    if (c->ndim == 3) e = launch3d(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag);
+    else if (c->fused) e = launch2f(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag);
+    else e = launch2d(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag);
     tend(c);
     if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "stencil launch (kind %d): %s", kind, hipGetErrorString(e));
     return LSRTM_OK;
 }
 
-lsrtm_status ckpt(lsrtm_ctx* c, Group& gr, int j, bool save) {
+lsrtm_status ckpt(lsrtm_ctx* c, Group& gr, int j, bool save, const Slot* sl) {
     CkptArgs a;
-    a.slots = gr.d_slots;
+    a.slots = sl;
     a.nslot = gr.ns;
     a.ndim = c->ndim;
     a.dtype = c->g.ckpt_dtype;
@@ -414,21 +420,25 @@ lsrtm_status check_flag(lsrtm_ctx* c) {
 // ---------------------------------------------------------------------------
 // Passes of one launch group
 // ---------------------------------------------------------------------------
-// mode 0: forward (record p), 1: born (record dp), 2: forward without data
+// mode 0: forward (record p), 1: born (record dp), 2: forward without data.
+// With the fused schedule the step reads the buffers of parity n % 2 and
+// writes the other ones.
 lsrtm_status group_forward(lsrtm_ctx* c, Group& gr, int mode, float* d, bool write_ck) {
     CHK(build_tiles(c, gr, c->tile));
     CHK(fill(c, c->pool, gr.bg_used));
     if (mode == 1) CHK(fill(c, c->pool + c->bg_region, gr.sc_used));
     const int kv = mode == 1 ? K_BORN_V : K_BG_V;
     const int kp = mode == 1 ? K_BORN_P : K_BG_P;
+    const bool fz = c->fused;
     for (int n = 0; n < c->g.nt; ++n) {
         tstep(c, n);
-        if (write_ck && n > 0 && n % c->k == 0) CHK(ckpt(c, gr, n / c->k, true));
-        CHK(stencil(c, gr, kv, n, 0, 0));
-        CHK(stencil(c, gr, kp, n, 0, 0));
+        const Slot* cur = desc(gr, fz ? n : 0);
+        if (write_ck && n > 0 && n % c->k == 0) CHK(ckpt(c, gr, n / c->k, true, cur));
+        CHK(stencil(c, gr, kv, n, 0, 0, cur));
+        if (!fz) CHK(stencil(c, gr, kp, n, 0, 0, cur));
         if (mode != 2) {
             tbeg(c, 7);
-            hipError_t e = launch_gather(gr.d_slots, gr.d_rec, gr.nrec, n, mode == 1, d, c->st);
+            hipError_t e = launch_gather(desc(gr, fz ? n + 1 : 0), gr.d_rec, gr.nrec, n, mode == 1, d, c->st);
             tend(c);
             if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "gather: %s", hipGetErrorString(e));
         }
@@ -441,9 +451,12 @@ lsrtm_status group_adjoint(lsrtm_ctx* c, Group& gr, const float* d) {
     CHK(fill(c, c->pool + c->bg_region, gr.sc_used));
     CHK(fill(c, c->pool + c->bg_region + c->sc_region, gr.img_used));
     const int nt = c->g.nt;
+    const bool fz = c->fused;
+    // parity of the adjoint fields: number of reverse steps done
+    auto apar = [&](int n) { return fz ? (nt - 1 - n) : 0; };
     auto inject = [&](int n) -> lsrtm_status {
         tbeg(c, 7);
-        hipError_t e = launch_inject(gr.d_slots, gr.d_node_slot, gr.d_node_idx, gr.d_node_ptr,
+        hipError_t e = launch_inject(desc(gr, apar(n)), gr.d_node_slot, gr.d_node_idx, gr.d_node_ptr,
                                      gr.d_node_rec, gr.nnode, n, d, c->st);
         tend(c);
         if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "inject: %s", hipGetErrorString(e));
@@ -455,17 +468,19 @@ lsrtm_status group_adjoint(lsrtm_ctx* c, Group& gr, const float* d) {
         const int n0 = j * c->k, n1 = std::min(n0 + c->k, nt);
         tstep(c, n0);
         if (j == 0) CHK(fill(c, c->pool, gr.bg_used));
-        else CHK(ckpt(c, gr, j, false));
+        else CHK(ckpt(c, gr, j, false, desc(gr, fz ? n0 : 0)));
         for (int n = n0; n < n1; ++n) {
             tstep(c, n);
-            CHK(stencil(c, gr, K_SEG_V, n, n - n0, 0));
-            CHK(stencil(c, gr, K_SEG_P, n, n - n0, 0));
+            const Slot* cur = desc(gr, fz ? n : 0);
+            CHK(stencil(c, gr, K_SEG_V, n, n - n0, 0, cur));
+            if (!fz) CHK(stencil(c, gr, K_SEG_P, n, n - n0, 0, cur));
         }
         for (int n = n1 - 1; n >= n0; --n) {
             tstep(c, n);
             if (n < nt - 1) CHK(inject(n));
-            CHK(stencil(c, gr, K_ADJ_A, n, n - n0, n == nt - 1 ? 1 : 0));
-            CHK(stencil(c, gr, K_ADJ_B, n, n - n0, 0));
+            const Slot* cur = desc(gr, apar(n));
+            CHK(stencil(c, gr, K_ADJ_A, n, n - n0, n == nt - 1 ? 1 : 0, cur));
+            if (!fz) CHK(stencil(c, gr, K_ADJ_B, n, n - n0, 0, cur));
         }
     }
     ImgArgs ia;
@@ -687,7 +702,9 @@ lsrtm_status plan(lsrtm_ctx* c) {
     size_t fr = 0, tot = 0;
     HIPCHK(c, hipMemGetInfo(&fr, &tot));
     const long long budget = c->opt_budget_mb > 0 ? c->opt_budget_mb * 1024LL * 1024LL : (long long)(0.9 * fr);
-    const int nbg = 1 + 3 * nd, nsc = 1 + 3 * nd;
+    c->fused = nd == 2 && c->opt_fused;
+    const int nbg = 1 + 3 * nd + (c->fused ? 1 + 2 * nd : 0);   // p, v, psi, phi [, p', v', psi']
+    const int nsc = 1 + 3 * nd + (c->fused ? 1 + 3 * nd : 0);   // q, w, xi, eta [, q', w', xi', eta']
     const int nt = c->g.nt;
     long long model_bytes = 0;
     for (auto& W : c->wins) model_bytes += (long long)(nd + 3) * W.npts * 4 + 4LL * nd * 4 * std::max(W.N[0], std::max(W.N[1], W.N[2]));
@@ -858,6 +875,17 @@ lsrtm_status plan(lsrtm_ctx* c) {
                 S.xi[a] = on ? q + (1 + nd + a) * W.npts : nullptr;
                 S.eta[a] = on ? q + (1 + 2 * nd + a) * W.npts : nullptr;
             }
+            if (c->fused) {
+                S.pn = b + (1 + 3 * nd) * W.npts;
+                S.qn = q + (1 + 3 * nd) * W.npts;
+                for (int a = 0; a < nd; ++a) {
+                    S.vn[a] = b + (2 + 3 * nd + a) * W.npts;
+                    S.psin[a] = b + (2 + 4 * nd + a) * W.npts;
+                    S.wn[a] = q + (2 + 3 * nd + a) * W.npts;
+                    S.xin[a] = q + (2 + 4 * nd + a) * W.npts;
+                    S.etan[a] = q + (2 + 5 * nd + a) * W.npts;
+                }
+            }
             S.gk = imb + oimg;
             S.gr = imb + oimg + W.npts;
             S.seg = c->segbuf + oseg;
@@ -888,6 +916,22 @@ lsrtm_status plan(lsrtm_ctx* c) {
         }
         CHK(dalloc_t(c, &gr.d_slots, gr.ns, true));
         HIPCHK(c, hipMemcpy(gr.d_slots, gr.h_slots.data(), gr.ns * sizeof(Slot), hipMemcpyHostToDevice));
+        if (c->fused) {
+            std::vector<Slot> alt = gr.h_slots;
+            for (Slot& S : alt) {
+                std::swap(S.p, S.pn);
+                std::swap(S.q, S.qn);
+                for (int a = 0; a < 3; ++a) {
+                    std::swap(S.v[a], S.vn[a]);
+                    std::swap(S.psi[a], S.psin[a]);
+                    std::swap(S.w[a], S.wn[a]);
+                    std::swap(S.xi[a], S.xin[a]);
+                    std::swap(S.eta[a], S.etan[a]);
+                }
+            }
+            CHK(dalloc_t(c, &gr.d_alt, gr.ns, true));
+            HIPCHK(c, hipMemcpy(gr.d_alt, alt.data(), gr.ns * sizeof(Slot), hipMemcpyHostToDevice));
+        }
         CHK(dalloc_t(c, &gr.d_win, wins6.size(), true));
         HIPCHK(c, hipMemcpy(gr.d_win, wins6.data(), wins6.size() * sizeof(int), hipMemcpyHostToDevice));
         gr.nrec = (int)recs.size();
@@ -943,7 +987,7 @@ std::string tune_key(const lsrtm_ctx* c) {
     return b;
 }
 
-bool tune_cache_get(const lsrtm_ctx* c, int* tile, int* spl) {
+bool tune_cache_get(const lsrtm_ctx* c, int* tile, int* spl, int* fused) {
     const char* f = getenv("LSRTM_TUNE_CACHE");
     if (!f) return false;
     FILE* fp = fopen(f, "r");
@@ -955,10 +999,11 @@ bool tune_cache_get(const lsrtm_ctx* c, int* tile, int* spl) {
         std::string l(line);
         const size_t bar = l.find('|');
         if (bar == std::string::npos || l.substr(0, bar) != key) continue;
-        int t, g;
-        if (sscanf(l.c_str() + bar + 1, "%d %d", &t, &g) == 2) {
+        int t, g, f;
+        if (sscanf(l.c_str() + bar + 1, "%d %d %d", &t, &g, &f) == 3) {
             *tile = t;
             *spl = g;
+            *fused = f;
             found = true;
         }
     }
@@ -966,12 +1011,12 @@ bool tune_cache_get(const lsrtm_ctx* c, int* tile, int* spl) {
     return found;
 }
 
-void tune_cache_put(const lsrtm_ctx* c, int tile, int spl) {
+void tune_cache_put(const lsrtm_ctx* c, int tile, int spl, int fused) {
     const char* f = getenv("LSRTM_TUNE_CACHE");
     if (!f) return;
     FILE* fp = fopen(f, "a");
     if (!fp) return;
-    fprintf(fp, "%s|%d %d\n", tune_key(c).c_str(), tile, spl);
+    fprintf(fp, "%s|%d %d %d\n", tune_key(c).c_str(), tile, spl, fused);
     fclose(fp);
 }
 
@@ -987,12 +1032,13 @@ lsrtm_status time_tile(lsrtm_ctx* c, int tile, int nsteps, double* ms) {
     HIPCHK(c, hipEventRecord(a, c->st));
     for (auto& gr : c->groups) {
         for (int n = 0; n < nsteps; ++n) {
-            CHK(stencil(c, gr, K_BORN_V, n, 0, 0));
-            CHK(stencil(c, gr, K_BORN_P, n, 0, 0));
-            CHK(stencil(c, gr, K_SEG_V, n, n % c->k, 0));
-            CHK(stencil(c, gr, K_SEG_P, n, n % c->k, 0));
-            CHK(stencil(c, gr, K_ADJ_A, n, n % c->k, n == 0));
-            CHK(stencil(c, gr, K_ADJ_B, n, n % c->k, 0));
+            const Slot* sl = desc(gr, c->fused ? n : 0);
+            CHK(stencil(c, gr, K_BORN_V, n, 0, 0, sl));
+            if (!c->fused) CHK(stencil(c, gr, K_BORN_P, n, 0, 0, sl));
+            CHK(stencil(c, gr, K_SEG_V, n, n % c->k, 0, sl));
+            if (!c->fused) CHK(stencil(c, gr, K_SEG_P, n, n % c->k, 0, sl));
+            CHK(stencil(c, gr, K_ADJ_A, n, n % c->k, n == 0, sl));
+            if (!c->fused) CHK(stencil(c, gr, K_ADJ_B, n, n % c->k, 0, sl));
         }
     }
     HIPCHK(c, hipEventRecord(b, c->st));
@@ -1031,10 +1077,11 @@ lsrtm_status tune_tiles(lsrtm_ctx* c, int nsteps, int* best, double* best_ms) {
 }
 
 lsrtm_status autotune(lsrtm_ctx* c, int nsteps, bool groups, double* out) {
-    int tile = -1, spl = c->opt_spl;
-    if (tune_cache_get(c, &tile, &spl)) {
-        if (groups && spl != c->opt_spl) {
+    int tile = -1, spl = c->opt_spl, fused = c->opt_fused;
+    if (tune_cache_get(c, &tile, &spl, &fused)) {
+        if (groups && (spl != c->opt_spl || fused != c->opt_fused)) {
             c->opt_spl = spl;
+            c->opt_fused = fused;
             CHK(plan(c));
         }
         c->tile = tile;
@@ -1047,7 +1094,7 @@ lsrtm_status autotune(lsrtm_ctx* c, int nsteps, bool groups, double* out) {
         return LSRTM_OK;
     }
     double best_ms = 1e30;
-    int best_tile = 0, best_spl = c->opt_spl;
+    int best_tile = 0, best_spl = c->opt_spl, best_fused = c->opt_fused;
     std::vector<int> cands;
     if (groups) {
         cands.push_back(0);
@@ -1056,28 +1103,37 @@ lsrtm_status autotune(lsrtm_ctx* c, int nsteps, bool groups, double* out) {
     } else {
         cands.push_back(c->opt_spl);
     }
-    for (int g : cands) {
-        if (g != c->opt_spl) {
-            c->opt_spl = g;
-            CHK(plan(c));
-        }
-        int t;
-        double ms;
-        CHK(tune_tiles(c, nsteps, &t, &ms));
-        if (ms < best_ms) {
-            best_ms = ms;
-            best_tile = t;
-            best_spl = g;
+    // 2D: both schedules (fused one-kernel steps and two-phase steps)
+    std::vector<int> scheds;
+    if (groups && c->ndim == 2) scheds = {1, 0};
+    else scheds = {c->opt_fused};
+    for (int f : scheds) {
+        for (int g : cands) {
+            if (g != c->opt_spl || f != c->opt_fused) {
+                c->opt_spl = g;
+                c->opt_fused = f;
+                CHK(plan(c));
+            }
+            int t;
+            double ms;
+            CHK(tune_tiles(c, nsteps, &t, &ms));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_tile = t;
+                best_spl = g;
+                best_fused = f;
+            }
         }
     }
-    if (best_spl != c->opt_spl) {
+    if (best_spl != c->opt_spl || best_fused != c->opt_fused) {
         c->opt_spl = best_spl;
+        c->opt_fused = best_fused;
         CHK(plan(c));
     }
     c->tile = best_tile;
     c->tuned = true;
     clear_graphs(c);
-    tune_cache_put(c, best_tile, best_spl);
+    tune_cache_put(c, best_tile, best_spl, best_fused);
     if (out) {
         out[0] = best_tile;
         out[1] = c->G;
@@ -1188,6 +1244,11 @@ lsrtm_status lsrtm_set_option(lsrtm_ctx* c, int key, long long v) {
         if (v < 0) FAIL(c, LSRTM_EINVAL, "memory budget must be >= 0");
         c->opt_budget_mb = v;
         return LSRTM_OK;
+    case LSRTM_OPT_FUSED:
+        if (c->opt_fused == (v != 0)) return LSRTM_OK;
+        c->opt_fused = v != 0;
+        if (c->have_acq) return plan(c);
+        return LSRTM_OK;
     case LSRTM_OPT_CKPT_PER_GROUP:
         if (c->opt_ckg == (v != 0)) return LSRTM_OK;
         c->opt_ckg = v != 0;
@@ -1287,9 +1348,9 @@ lsrtm_status lsrtm_autotune(lsrtm_ctx* c, int nsteps, int tune_groups, double* o
 
 lsrtm_status lsrtm_sizes(lsrtm_ctx* c, long long* out, int nout) {
     if (!c || !out) return LSRTM_EINVAL;
-    long long v[9] = {c->data_len, c->gpts, c->G, c->k, (long long)c->groups.size(), c->padded_total, c->plan_bytes,
-                      c->tile, c->ck_group ? 1 : 0};
-    for (int i = 0; i < nout && i < 9; ++i) out[i] = v[i];
+    long long v[10] = {c->data_len, c->gpts, c->G, c->k, (long long)c->groups.size(), c->padded_total, c->plan_bytes,
+                       c->tile, c->ck_group ? 1 : 0, c->fused ? 1 : 0};
+    for (int i = 0; i < nout && i < 10; ++i) out[i] = v[i];
     return LSRTM_OK;
 }
 

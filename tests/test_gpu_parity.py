@@ -86,9 +86,9 @@ def test_replay_is_bitwise(torch):
     rng = np.random.default_rng(3)
     y = rng.standard_normal(sum(w.nt * len(r) for r in w.rec))
     imgs = []
-    for k in (1, 7, 32, 97):
+    for k, fused in ((1, True), (7, True), (32, True), (97, True), (7, False), (97, False)):
         from paper_2508_10405_amd import lsrtm
-        ctx = lsrtm.context_for(w, ckpt_every=k)
+        ctx = lsrtm.context_for(w, ckpt_every=k, fused=fused)
         imgs.append(ctx.adjoint(to_dev(torch, y)).cpu().numpy())
         ctx.close()
     for im in imgs[1:]:
@@ -96,25 +96,26 @@ def test_replay_is_bitwise(torch):
 
 
 def test_batched_equals_per_shot_and_tiles(torch):
-    """Batching shots into one launch, and every tile shape, give bitwise the
-    same data and images as plain per-shot launches."""
+    """Batching shots into one launch, every tile shape, and the fused
+    one-kernel-per-step schedule against the two-phase one, all give bitwise
+    the same data and images as plain per-shot launches."""
     from paper_2508_10405_amd import lsrtm
     w = synth.small((50, 90), nt=120, npml=6, seed=9, nshot=4, uneven=True)
     dm = to_dev(torch, w.dm)
     rng = np.random.default_rng(4)
     y = to_dev(torch, rng.standard_normal(sum(w.nt * len(r) for r in w.rec)))
     ref = None
-    for spl in (1, 0, 3):
+    for spl, fused in ((1, True), (0, True), (3, True), (2, False)):
         for tile in range(9):
-            ctx = lsrtm.context_for(w, shots_per_launch=spl, tile=tile)
+            ctx = lsrtm.context_for(w, shots_per_launch=spl, tile=tile, fused=fused)
             d = ctx.born(dm).cpu().numpy()
             im = ctx.adjoint(y).cpu().numpy()
             ctx.close()
             if ref is None:
                 ref = (d, im)
             else:
-                assert np.array_equal(d, ref[0]), (spl, tile)
-                assert np.array_equal(im, ref[1]), (spl, tile)
+                assert np.array_equal(d, ref[0]), (spl, tile, fused)
+                assert np.array_equal(im, ref[1]), (spl, tile, fused)
 
 
 def test_run_twice_deterministic(torch):
