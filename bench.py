@@ -127,7 +127,7 @@ def main():
     ap.add_argument("--shots-per-launch", type=int, default=-1,
                     help="-1 = autotuned together with the tile shape")
     ap.add_argument("--tile", type=int, default=-1)
-    ap.add_argument("--tune-steps", type=int, default=8)
+    ap.add_argument("--tune-steps", type=int, default=24)
     ap.add_argument("--workload", default="config2", choices=("config2", "config3", "config5"),
                     help="config2 = the benchmark workload; config3 (uneven apertures) and config5 (3D, "
                          "BF16 checkpoints) are measured on request")

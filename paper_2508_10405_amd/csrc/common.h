@@ -63,6 +63,36 @@ struct Rec {
     int pad;
 };
 
+// Receivers handled inside the 2D stencil kernels: per tile, the receivers
+// whose node lies in the tile (Rec::idx = tile-local node lz + BZ * lx).
+struct TileRec {
+    const int* ptr;          // [ntiles + 1] ranges into rec; nullptr = none
+    const Rec* rec;
+    float* d;                // record the new pressure here (forward / Born)
+    const float* y;          // inject y[n - 1] into the new adjoint pressure
+};
+
+// Record v for every receiver of tile tix at tile-local node e, step n.
+__device__ __forceinline__ void tile_gather(const TileRec& tr, int tix, int e, int n, float v) {
+    const int r1 = tr.ptr[tix + 1];
+    for (int j = tr.ptr[tix]; j < r1; ++j) {
+        const Rec R = tr.rec[j];
+        if (R.idx == e) tr.d[R.out + (long long)n * R.stride] = v;
+    }
+}
+
+// Sum of the data of step n over the receivers of tile tix at node e (in
+// list order).
+__device__ __forceinline__ float tile_inject(const TileRec& tr, int tix, int e, int n) {
+    float s = 0.f;
+    const int r1 = tr.ptr[tix + 1];
+    for (int j = tr.ptr[tix]; j < r1; ++j) {
+        const Rec R = tr.rec[j];
+        if (R.idx == e) s = s + tr.y[R.out + (long long)n * R.stride];
+    }
+    return s;
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8);
 // give every XCD a contiguous range of tiles so that neighbouring tiles,
 // which share halos, meet in the same L2.

@@ -62,13 +62,14 @@ __device__ __forceinline__ void node_of(int r, int& lz, int& lx) {
 // ---------------------------------------------------------------------------
 template <int BZ, int BX, bool BORN, bool SEG>
 __global__ void __launch_bounds__(NTHREADS)
-k2_v(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+k2_v(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
     __shared__ float sp[T::NL];
     __shared__ float sq[BORN ? T::NL : 1];
-    const int4 tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const int tix = xcd_remap(blockIdx.x, gridDim.x);
+    const int4 tl = tiles[tix];
     const Slot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
@@ -167,7 +168,7 @@ k2_v(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
 // ---------------------------------------------------------------------------
 template <int BZ, int BX, bool BORN, bool SEG>
 __global__ void __launch_bounds__(NTHREADS)
-k2_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+k2_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
@@ -175,7 +176,8 @@ k2_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
     __shared__ float svx[T::NL];
     __shared__ float swz[BORN ? T::NL : 1];
     __shared__ float swx[BORN ? T::NL : 1];
-    const int4 tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const int tix = xcd_remap(blockIdx.x, gridDim.x);
+    const int4 tl = tiles[tix];
     const Slot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
@@ -246,6 +248,7 @@ k2_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
         if (i == S.src) pn = pn + amp;
         S.p[i] = pn;
         if (SEG) seg[i] = q;
+        if (!BORN && tr.d) tile_gather(tr, tix, lz + BZ * lx, n, pn);
         if (BORN) {
             float fz = d_node(swz, c, 1, C.c[0]);
             float fx = d_node(swx, c, T::LZ, C.c[1]);
@@ -260,7 +263,9 @@ k2_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
                 fx = fx + ph;
             }
             const float dq = fz + fx;
-            S.q[i] = (qq[r] - k * dq) + lk[r] * (-k * q);
+            const float qn = (qq[r] - k * dq) + lk[r] * (-k * q);
+            S.q[i] = qn;
+            if (tr.d) tile_gather(tr, tix, lz + BZ * lx, n, qn);
         }
     }
 }
@@ -272,13 +277,14 @@ k2_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
 // ---------------------------------------------------------------------------
 template <int BZ, int BX>
 __global__ void __launch_bounds__(NTHREADS)
-k2_a(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+k2_a(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
     __shared__ float sez[T::NL];
     __shared__ float sex[T::NL];
-    const int4 tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const int tix = xcd_remap(blockIdx.x, gridDim.x);
+    const int4 tl = tiles[tix];
     const Slot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
@@ -360,13 +366,14 @@ k2_a(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
 // ---------------------------------------------------------------------------
 template <int BZ, int BX>
 __global__ void __launch_bounds__(NTHREADS)
-k2_b(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+k2_b(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
     __shared__ float sgz[T::NL];
     __shared__ float sgx[T::NL];
-    const int4 tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const int tix = xcd_remap(blockIdx.x, gridDim.x);
+    const int4 tl = tiles[tix];
     const Slot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
@@ -438,7 +445,9 @@ k2_b(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
         S.gr[i] = gr[r] + (0.5f * (xz0[r] + xz1[r]) + 0.5f * (xx0[r] + xx1[r]));
         const float dz = d_node(sgz, c, 1, C.c[0]);
         const float dx = d_node(sgx, c, T::LZ, C.c[1]);
-        S.q[i] = pt[r] - (dz + dx);
+        float pn = pt[r] - (dz + dx);
+        if (tr.y && n > 0) pn = pn + tile_inject(tr, tix, lz + BZ * lx, n - 1);
+        S.q[i] = pn;
     }
 }
 
@@ -447,18 +456,18 @@ k2_b(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
 // ---------------------------------------------------------------------------
 template <int BZ, int BX>
 static hipError_t launch2_t(int kind, int ntiles, hipStream_t st, const Slot* slots,
-                            const int4* tiles, const Coef& C, int n, int sstep, int flag)
+                            const int4* tiles, const Coef& C, int n, int sstep, int flag, const TileRec& tr)
 {
     dim3 g(ntiles), b(NTHREADS);
     switch (kind) {
-    case K_BG_V:    k2_v<BZ, BX, false, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_BG_P:    k2_p<BZ, BX, false, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_SEG_V:   k2_v<BZ, BX, false, true><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_SEG_P:   k2_p<BZ, BX, false, true><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_BORN_V:  k2_v<BZ, BX, true, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_BORN_P:  k2_p<BZ, BX, true, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_ADJ_A:   k2_a<BZ, BX><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_ADJ_B:   k2_b<BZ, BX><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
+    case K_BG_V:    k2_v<BZ, BX, false, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
+    case K_BG_P:    k2_p<BZ, BX, false, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
+    case K_SEG_V:   k2_v<BZ, BX, false, true><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
+    case K_SEG_P:   k2_p<BZ, BX, false, true><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
+    case K_BORN_V:  k2_v<BZ, BX, true, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
+    case K_BORN_P:  k2_p<BZ, BX, true, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
+    case K_ADJ_A:   k2_a<BZ, BX><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
+    case K_ADJ_B:   k2_b<BZ, BX><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -469,19 +478,19 @@ const int kTiles2[][2] = {{32, 8}, {32, 16}, {32, 32}, {64, 4}, {64, 8}, {64, 16
 const int kNumTiles2 = 9;
 
 hipError_t launch2d(int kind, int tile_id, int ntiles, hipStream_t st, const Slot* slots,
-                    const int4* tiles, const Coef& C, int n, int sstep, int flag)
+                    const int4* tiles, const Coef& C, int n, int sstep, int flag, const TileRec& tr)
 {
     if (ntiles <= 0) return hipSuccess;
     switch (tile_id) {
-    case 0: return launch2_t<32, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 1: return launch2_t<32, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 2: return launch2_t<32, 32>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 3: return launch2_t<64, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 4: return launch2_t<64, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 5: return launch2_t<64, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 6: return launch2_t<128, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 7: return launch2_t<128, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 8: return launch2_t<256, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    case 0: return launch2_t<32, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 1: return launch2_t<32, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 2: return launch2_t<32, 32>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 3: return launch2_t<64, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 4: return launch2_t<64, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 5: return launch2_t<64, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 6: return launch2_t<128, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 7: return launch2_t<128, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 8: return launch2_t<256, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
     default: return hipErrorInvalidValue;
     }
 }

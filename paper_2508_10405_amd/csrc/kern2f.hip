@@ -45,7 +45,7 @@ __device__ __forceinline__ void rect(int z0, int z1, int x0, int x1, Fn f) {
 // ---------------------------------------------------------------------------
 template <int BZ, int BX, bool BORN, bool SEG>
 __global__ void __launch_bounds__(NTHREADS)
-k2f_step(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+k2f_step(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
 {
     using T = F2<BZ, BX>;
     constexpr int R = T::R;
@@ -55,7 +55,8 @@ k2f_step(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
     __shared__ float svx[T::NVX];
     __shared__ float swz[BORN ? T::NVZ : 1];
     __shared__ float swx[BORN ? T::NVX : 1];
-    const int4 tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const int tix = xcd_remap(blockIdx.x, gridDim.x);
+    const int4 tl = tiles[tix];
     const Slot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
@@ -249,6 +250,7 @@ k2f_step(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
         if (i == S.src) pn = pn + amp;
         S.pn[i] = pn;
         if (SEG) seg[2 * S.npts + i] = q;
+        if (!BORN && tr.d) tile_gather(tr, tix, e, n, pn);
         if (BORN) {
             float fz = d_node(swz, cz, 1, C.c[0]);
             float fx = d_node(swx, cx, BZ, C.c[1]);
@@ -263,7 +265,9 @@ k2f_step(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
                 fx = fx + ph;
             }
             const float dq = fz + fx;
-            S.qn[i] = (sq[cp] - k * dq) + lk[r] * (-k * q);
+            const float qn = (sq[cp] - k * dq) + lk[r] * (-k * q);
+            S.qn[i] = qn;
+            if (tr.d) tile_gather(tr, tix, e, n, qn);
         }
     }
 }
@@ -275,7 +279,7 @@ k2f_step(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
 // ---------------------------------------------------------------------------
 template <int BZ, int BX>
 __global__ void __launch_bounds__(NTHREADS)
-k2f_adj(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+k2f_adj(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
 {
     using T = F2<BZ, BX>;
     constexpr int R = T::R;
@@ -285,7 +289,8 @@ k2f_adj(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, 
     __shared__ float sgx[T::NVX];             // g~_x cols -4 .. BX+2
     __shared__ float sxz[T::NVZ];             // -dv_z v~_z (lnrho imaging)
     __shared__ float sxx[T::NVX];
-    const int4 tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const int tix = xcd_remap(blockIdx.x, gridDim.x);
+    const int4 tl = tiles[tix];
     const Slot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
@@ -449,21 +454,23 @@ k2f_adj(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, 
         S.gr[i] = gr[r] + (0.5f * (sxz[cz] + xz1) + 0.5f * (sxx[cx] + xx1));
         const float dz = d_node(sgz, cz, 1, C.c[0]);
         const float dx = d_node(sgx, cx, BZ, C.c[1]);
-        S.qn[i] = pt[r] - (dz + dx);
+        float pn = pt[r] - (dz + dx);
+        if (tr.y && n > 0) pn = pn + tile_inject(tr, tix, e, n - 1);
+        S.qn[i] = pn;
     }
 }
 
 // ---------------------------------------------------------------------------
 template <int BZ, int BX>
 static hipError_t launch2f_t(int kind, int ntiles, hipStream_t st, const Slot* slots,
-                             const int4* tiles, const Coef& C, int n, int sstep, int flag)
+                             const int4* tiles, const Coef& C, int n, int sstep, int flag, const TileRec& tr)
 {
     dim3 g(ntiles), b(NTHREADS);
     switch (kind) {
-    case K_BG_V:   k2f_step<BZ, BX, false, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_SEG_V:  k2f_step<BZ, BX, false, true><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_BORN_V: k2f_step<BZ, BX, true, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_ADJ_A:  k2f_adj<BZ, BX><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
+    case K_BG_V:   k2f_step<BZ, BX, false, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
+    case K_SEG_V:  k2f_step<BZ, BX, false, true><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
+    case K_BORN_V: k2f_step<BZ, BX, true, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
+    case K_ADJ_A:  k2f_adj<BZ, BX><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -472,19 +479,19 @@ static hipError_t launch2f_t(int kind, int ntiles, hipStream_t st, const Slot* s
 // Fused schedule: kind is the velocity-phase kind of the step (K_BG_V,
 // K_SEG_V, K_BORN_V) or K_ADJ_A for the adjoint step.
 hipError_t launch2f(int kind, int tile_id, int ntiles, hipStream_t st, const Slot* slots,
-                    const int4* tiles, const Coef& C, int n, int sstep, int flag)
+                    const int4* tiles, const Coef& C, int n, int sstep, int flag, const TileRec& tr)
 {
     if (ntiles <= 0) return hipSuccess;
     switch (tile_id) {
-    case 0: return launch2f_t<32, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 1: return launch2f_t<32, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 2: return launch2f_t<32, 32>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 3: return launch2f_t<64, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 4: return launch2f_t<64, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 5: return launch2f_t<64, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 6: return launch2f_t<128, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 7: return launch2f_t<128, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 8: return launch2f_t<256, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    case 0: return launch2f_t<32, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 1: return launch2f_t<32, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 2: return launch2f_t<32, 32>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 3: return launch2f_t<64, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 4: return launch2f_t<64, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 5: return launch2f_t<64, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 6: return launch2f_t<128, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 7: return launch2f_t<128, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 8: return launch2f_t<256, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
     default: return hipErrorInvalidValue;
     }
 }

@@ -70,6 +70,9 @@ struct Group {
     Rec* d_node_rec = nullptr;
     int nnode = 0;
     int* d_win = nullptr;
+    int* d_trp = nullptr;          // 2D: receivers per tile (CSR over the tile table)
+    Rec* d_trec = nullptr;
+    std::vector<Rec> h_rec;        // receivers of the group (host copy)
     long long max_npts = 0;
     long long bg_used = 0, sc_used = 0, img_used = 0;   // floats
 };
@@ -364,18 +367,56 @@ lsrtm_status build_tiles(lsrtm_ctx* c, Group& gr, int tile) {
     HIPCHK(c, hipMemcpy(gr.d_tiles, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
     gr.ntiles = (int)t.size();
     gr.tiles_for = tile;
+    if (c->ndim == 2) {
+        // receivers by tile: tile of node (z, x) of slot s and its tile-local index
+        std::vector<long long> base(gr.ns + 1, 0);
+        for (int s = 0; s < gr.ns; ++s) {
+            const Slot& S = gr.h_slots[s];
+            base[s + 1] = base[s] + (long long)((S.n[0] + bz - 1) / bz) * ((S.n[1] + bx - 1) / bx);
+        }
+        std::vector<std::vector<Rec>> per(gr.ntiles);
+        for (const Rec& R : gr.h_rec) {
+            const Slot& S = gr.h_slots[R.slot];
+            const int z = R.idx % S.ldz, x = R.idx / S.ldz;
+            const int ntz = (S.n[0] + bz - 1) / bz;
+            const long long ti = base[R.slot] + (long long)(x / bx) * ntz + z / bz;
+            Rec T = R;
+            T.idx = (z % bz) + bz * (x % bx);
+            per[ti].push_back(T);
+        }
+        std::vector<int> ptr(gr.ntiles + 1, 0);
+        std::vector<Rec> all;
+        for (int i = 0; i < gr.ntiles; ++i) {
+            all.insert(all.end(), per[i].begin(), per[i].end());
+            ptr[i + 1] = (int)all.size();
+        }
+        for (void** pp : {(void**)&gr.d_trp, (void**)&gr.d_trec}) {
+            if (*pp) {
+                (void)hipFree(*pp);
+                auto it = std::find(c->acq_allocs.begin(), c->acq_allocs.end(), *pp);
+                if (it != c->acq_allocs.end()) c->acq_allocs.erase(it);
+                *pp = nullptr;
+            }
+        }
+        CHK(dalloc_t(c, &gr.d_trp, ptr.size(), true));
+        CHK(dalloc_t(c, &gr.d_trec, std::max<size_t>(1, all.size()), true));
+        HIPCHK(c, hipMemcpy(gr.d_trp, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice));
+        if (!all.empty())
+            HIPCHK(c, hipMemcpy(gr.d_trec, all.data(), all.size() * sizeof(Rec), hipMemcpyHostToDevice));
+    }
     return LSRTM_OK;
 }
 
 const Slot* desc(const Group& gr, int par) { return ((par & 1) && gr.d_alt) ? gr.d_alt : gr.d_slots; }
 
-lsrtm_status stencil(lsrtm_ctx* c, Group& gr, int kind, int n, int sstep, int flag, const Slot* sl) {
+lsrtm_status stencil(lsrtm_ctx* c, Group& gr, int kind, int n, int sstep, int flag, const Slot* sl,
+                     TileRec tr = TileRec{nullptr, nullptr, nullptr, nullptr}) {
     static const int cls_of[8] = {2, 3, 2, 3, 0, 1, 4, 5};
     tbeg(c, cls_of[kind]);
     hipError_t e;
     if (c->ndim == 3) e = launch3d(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag);
-    else if (c->fused) e = launch2f(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag);
-    else e = launch2d(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag);
+    else if (c->fused) e = launch2f(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag, tr);
+    else e = launch2d(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag, tr);
     tend(c);
     if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "stencil launch (kind %d): %s", kind, hipGetErrorString(e));
     return LSRTM_OK;
@@ -434,9 +475,12 @@ lsrtm_status group_forward(lsrtm_ctx* c, Group& gr, int mode, float* d, bool wri
         tstep(c, n);
         const Slot* cur = desc(gr, fz ? n : 0);
         if (write_ck && n > 0 && n % c->k == 0) CHK(ckpt(c, gr, n / c->k, true, cur));
-        CHK(stencil(c, gr, kv, n, 0, 0, cur));
-        if (!fz) CHK(stencil(c, gr, kp, n, 0, 0, cur));
-        if (mode != 2) {
+        // 2D kernels record the receivers themselves
+        const TileRec tr{gr.d_trp, gr.d_trec, mode != 2 ? d : nullptr, nullptr};
+        const TileRec none{nullptr, nullptr, nullptr, nullptr};
+        CHK(stencil(c, gr, kv, n, 0, 0, cur, fz ? tr : none));
+        if (!fz) CHK(stencil(c, gr, kp, n, 0, 0, cur, tr));
+        if (mode != 2 && c->ndim == 3) {
             tbeg(c, 7);
             hipError_t e = launch_gather(desc(gr, fz ? n + 1 : 0), gr.d_rec, gr.nrec, n, mode == 1, d, c->st);
             tend(c);
@@ -475,12 +519,16 @@ lsrtm_status group_adjoint(lsrtm_ctx* c, Group& gr, const float* d) {
             CHK(stencil(c, gr, K_SEG_V, n, n - n0, 0, cur));
             if (!fz) CHK(stencil(c, gr, K_SEG_P, n, n - n0, 0, cur));
         }
+        // 2D: the adjoint velocity kernel of step n injects the data of step
+        // n - 1 into the new adjoint pressure; 3D uses the injection kernel
+        const TileRec tr{gr.d_trp, gr.d_trec, nullptr, d};
+        const TileRec none{nullptr, nullptr, nullptr, nullptr};
         for (int n = n1 - 1; n >= n0; --n) {
             tstep(c, n);
-            if (n < nt - 1) CHK(inject(n));
+            if (n < nt - 1 && c->ndim == 3) CHK(inject(n));
             const Slot* cur = desc(gr, apar(n));
-            CHK(stencil(c, gr, K_ADJ_A, n, n - n0, n == nt - 1 ? 1 : 0, cur));
-            if (!fz) CHK(stencil(c, gr, K_ADJ_B, n, n - n0, 0, cur));
+            CHK(stencil(c, gr, K_ADJ_A, n, n - n0, n == nt - 1 ? 1 : 0, cur, fz ? tr : none));
+            if (!fz) CHK(stencil(c, gr, K_ADJ_B, n, n - n0, 0, cur, tr));
         }
     }
     ImgArgs ia;
@@ -935,6 +983,7 @@ lsrtm_status plan(lsrtm_ctx* c) {
         CHK(dalloc_t(c, &gr.d_win, wins6.size(), true));
         HIPCHK(c, hipMemcpy(gr.d_win, wins6.data(), wins6.size() * sizeof(int), hipMemcpyHostToDevice));
         gr.nrec = (int)recs.size();
+        gr.h_rec = recs;
         CHK(dalloc_t(c, &gr.d_rec, std::max<size_t>(1, recs.size()), true));
         if (!recs.empty())
             HIPCHK(c, hipMemcpy(gr.d_rec, recs.data(), recs.size() * sizeof(Rec), hipMemcpyHostToDevice));
