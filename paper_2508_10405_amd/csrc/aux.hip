@@ -117,8 +117,8 @@ __global__ void k_gather(const Slot* __restrict__ slots, const Rec* __restrict__
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrec) return;
     const Rec R = rec[r];
-    const Slot& S = slots[R.slot];
-    const float* f = from_scattered ? S.q : S.p;
+    const DSlot& S = dev_slots(slots)[R.slot];
+    const gfloat* f = from_scattered ? S.q : S.p;
     d[R.out + (long long)n * R.stride] = f[R.idx];
 }
 
@@ -136,7 +136,7 @@ __global__ void k_inject(const Slot* __restrict__ slots, const int* __restrict__
     if (u >= nnode) return;
     float s = 0.f;
     for (int r = node_ptr[u]; r < node_ptr[u + 1]; ++r) s = s + d[rec[r].out + (long long)n * rec[r].stride];
-    float* q = slots[node_slot[u]].q;
+    gfloat* q = dev_slots(slots)[node_slot[u]].q;
     const int i = node_idx[u];
     q[i] = q[i] + s;
 }
@@ -166,7 +166,7 @@ __global__ void k_image_reduce(ImgArgs a) {
             const int* w = a.win + 6 * s;
             if (z < w[0] || z >= w[1] || x < w[2] || x >= w[3]) continue;
             if (ndim == 3 && (y < w[4] || y >= w[5])) continue;
-            const Slot& S = a.slots[s];
+            const DSlot& S = dev_slots(a.slots)[s];
             const long long i = (z - w[0] + a.npml) + S.sx * (x - w[2] + a.npml) +
                                 (ndim == 3 ? S.sy * (long long)(y - w[4] + a.npml) : 0LL);
             const double gr = S.gr[i], gk = S.gk[i];
@@ -314,10 +314,10 @@ hipError_t launch_copy(const float* x, float* y, long long n, hipStream_t st) {
 // Checkpoints
 // ---------------------------------------------------------------------------
 // Field f of a slot: 0 = p, 1 + a = v_a.
-__device__ __forceinline__ float* slot_field(const Slot& S, int f) { return f == 0 ? S.p : S.v[f - 1]; }
+__device__ __forceinline__ gfloat* slot_field(const DSlot& S, int f) { return f == 0 ? S.p : S.v[f - 1]; }
 
 // Strip element e of axis a -> linear index (z, x, y layout with strides).
-__device__ __forceinline__ long long strip_index(const Slot& S, int ndim, int a, int Sd, long long e) {
+__device__ __forceinline__ long long strip_index(const DSlot& S, int ndim, int a, int Sd, long long e) {
     const int nz = S.n[0], nx = S.n[1];
     const int Sa = Sd < S.n[a] ? Sd : S.n[a];
     int c[3] = {0, 0, 0};
@@ -345,13 +345,15 @@ __device__ __forceinline__ long long strip_index(const Slot& S, int ndim, int a,
     return c[0] + S.sx * c[1] + S.sy * c[2];
 }
 
-__device__ __forceinline__ long long strip_count(const Slot& S, int a, int Sd) {
+__device__ __forceinline__ long long strip_count(const DSlot& S, int a, int Sd) {
     const int Sa = Sd < S.n[a] ? Sd : S.n[a];
     long long c = 2LL * Sa;
     for (int b = 0; b < 3; ++b)
         if (b != a) c *= S.n[b];
     return c;
 }
+
+using gu16 = __attribute__((address_space(1))) unsigned short;
 
 __device__ __forceinline__ unsigned short f2bf_rne(float x) {
     unsigned int u = __float_as_uint(x);
@@ -362,8 +364,8 @@ __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float
 
 // grid: (blocks, 1 + ndim, nslot); partial max |x| per block.
 __global__ void k_ckpt_maxabs(CkptArgs a) {
-    const Slot& S = a.slots[blockIdx.z];
-    const float* f = slot_field(S, blockIdx.y);
+    const DSlot& S = dev_slots(a.slots)[blockIdx.z];
+    const gfloat* f = slot_field(S, blockIdx.y);
     float m = 0.f;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < S.npts;
          i += (long long)gridDim.x * blockDim.x)
@@ -389,37 +391,37 @@ __global__ void k_ckpt_scale(CkptArgs a) {
 
 // grid: (blocks, 1 + ndim, nslot): pack the fields.
 __global__ void k_ckpt_pack(CkptArgs a) {
-    const Slot& S = a.slots[blockIdx.z];
+    const DSlot& S = dev_slots(a.slots)[blockIdx.z];
     const int f = blockIdx.y;
-    const float* src = slot_field(S, f);
-    char* base = S.ck + (long long)(a.j - 1) * S.ckbytes;
+    const gfloat* src = slot_field(S, f);
+    gchar* base = S.ck + (long long)(a.j - 1) * S.ckbytes;
     const float s = a.scales[blockIdx.z * (1 + a.ndim) + f];
     const float inv = s > 0.f ? 1.f / s : 0.f;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < S.npts;
          i += (long long)gridDim.x * blockDim.x) {
         const float x = src[i];
         if (a.dtype == 0) {
-            reinterpret_cast<float*>(base)[f * S.npts + i] = x;
+            reinterpret_cast<gfloat*>(base)[f * S.npts + i] = x;
         } else if (a.dtype == 1) {
-            reinterpret_cast<__half*>(base)[f * S.npts + i] = __float2half_rn(x * inv);
+            reinterpret_cast<gu16*>(base)[f * S.npts + i] = __half_as_ushort(__float2half_rn(x * inv));
         } else {
-            reinterpret_cast<unsigned short*>(base)[f * S.npts + i] = f2bf_rne(x * inv);
+            reinterpret_cast<gu16*>(base)[f * S.npts + i] = f2bf_rne(x * inv);
         }
     }
 }
 
 __global__ void k_ckpt_unpack(CkptArgs a) {
-    const Slot& S = a.slots[blockIdx.z];
+    const DSlot& S = dev_slots(a.slots)[blockIdx.z];
     const int f = blockIdx.y;
-    float* dst = slot_field(S, f);
-    const char* base = S.ck + (long long)(a.j - 1) * S.ckbytes;
+    gfloat* dst = slot_field(S, f);
+    const gchar* base = S.ck + (long long)(a.j - 1) * S.ckbytes;
     const float s = a.scales[blockIdx.z * (1 + a.ndim) + f];
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < S.npts;
          i += (long long)gridDim.x * blockDim.x) {
         float x;
-        if (a.dtype == 0) x = reinterpret_cast<const float*>(base)[f * S.npts + i];
-        else if (a.dtype == 1) x = __half2float(reinterpret_cast<const __half*>(base)[f * S.npts + i]) * s;
-        else x = bf2f(reinterpret_cast<const unsigned short*>(base)[f * S.npts + i]) * s;
+        if (a.dtype == 0) x = reinterpret_cast<const gfloat*>(base)[f * S.npts + i];
+        else if (a.dtype == 1) x = __half2float(__ushort_as_half(reinterpret_cast<const gu16*>(base)[f * S.npts + i])) * s;
+        else x = bf2f(reinterpret_cast<const gu16*>(base)[f * S.npts + i]) * s;
         dst[i] = x;
     }
 }
@@ -428,13 +430,13 @@ __global__ void k_ckpt_unpack(CkptArgs a) {
 // Memory m: psi_a for m = 2a, phi_a for m = 2a + 1.
 template <bool SAVE>
 __global__ void k_ckpt_strips(CkptArgs a) {
-    const Slot& S = a.slots[blockIdx.z];
+    const DSlot& S = dev_slots(a.slots)[blockIdx.z];
     const int m = blockIdx.y, ax = m >> 1;
-    float* f = (m & 1) ? S.phi[ax] : S.psi[ax];
+    gfloat* f = (m & 1) ? S.phi[ax] : S.psi[ax];
     const int esz = a.dtype == 0 ? 4 : 2;
     long long off = (long long)(1 + a.ndim) * S.npts * esz;
     for (int mm = 0; mm < m; ++mm) off += strip_count(S, mm >> 1, a.S) * 4;
-    float* buf = reinterpret_cast<float*>(S.ck + (long long)(a.j - 1) * S.ckbytes + off);
+    gfloat* buf = reinterpret_cast<gfloat*>(S.ck + (long long)(a.j - 1) * S.ckbytes + off);
     const long long cnt = strip_count(S, ax, a.S);
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < cnt;
          e += (long long)gridDim.x * blockDim.x) {

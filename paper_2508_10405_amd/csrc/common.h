@@ -13,46 +13,75 @@ struct Coef {
     float c[3][4];
 };
 
+// Global (address space 1) element types.  Kernels read the per-shot
+// pointers out of a table in device memory, so the compiler cannot tell
+// their address space; typing them as global lets it emit global_load /
+// global_store instead of flat accesses (which share the LDS counter and
+// force waits on both).
+using gfloat = __attribute__((address_space(1))) float;
+using gchar = __attribute__((address_space(1))) char;
+
 // One shot being advanced by a launch ("slot").  All pointers are device
 // pointers into library-owned buffers; arrays are z-fastest with strides
-// sx (x) and sy (y) on the shot's padded grid.
-struct Slot {
+// sx (x) and sy (y) on the shot's padded grid.  The host fills SlotT<0>
+// (plain pointers); kernels read the same bytes as SlotT<1> (global).
+template <int AS>
+struct AddrSpace {
+    using F = __attribute__((address_space(AS))) float;
+    using C = __attribute__((address_space(AS))) char;
+};
+template <>
+struct AddrSpace<0> {   // the language's default (generic) pointers
+    using F = float;
+    using C = char;
+};
+
+template <int AS>
+struct SlotT {
+    using F = typename AddrSpace<AS>::F;
+    using C = typename AddrSpace<AS>::C;
     int n[3];                // padded sizes (z, x, y); n[2] = 1 in 2D
     int ldz;                 // z stride (== sx)
     long long sx, sy;        // strides of x and y
     long long npts;          // elements per array
     int src;                 // linear index of the source node, -1 for none
     int shot;                // global shot index
-    const float* src_amp;    // [nt] dt * w / cell
-    const float* kdt;        // dt * kappa at nodes
-    const float* bdt[3];     // dt * b_a at half nodes
-    const float* dlnr;       // dlnrho at nodes (zero in the PML)
-    const float* dlnk;       // dlnkappa at nodes (zero in the PML)
-    const float* cpml[3];    // per axis: [ach | bch | aci | bci], n_a each
-    float* p;                // background pressure
-    float* v[3];             // background particle velocities
-    float* psi[3];           // background CPML memory of G_a p
-    float* phi[3];           // background CPML memory of D_a v_a
-    float* q;                // scattered pressure  | adjoint p~
-    float* w[3];             // scattered velocity  | adjoint v~
-    float* xi[3];            // scattered psi       | adjoint of psi (chi)
-    float* eta[3];           // scattered phi       | adjoint of phi
-    float* gk;               // image of lnkappa
-    float* gr;               // image of lnrho
+    const F* src_amp;        // [nt] dt * w / cell
+    const F* kdt;            // dt * kappa at nodes
+    const F* bdt[3];         // dt * b_a at half nodes
+    const F* dlnr;           // dlnrho at nodes (zero in the PML)
+    const F* dlnk;           // dlnkappa at nodes (zero in the PML)
+    const F* cpml[3];        // per axis: [ach | bch | aci | bci], n_a each
+    F* p;                    // background pressure
+    F* v[3];                 // background particle velocities
+    F* psi[3];               // background CPML memory of G_a p
+    F* phi[3];               // background CPML memory of D_a v_a
+    F* q;                    // scattered pressure  | adjoint p~
+    F* w[3];                 // scattered velocity  | adjoint v~
+    F* xi[3];                // scattered psi       | adjoint of psi (chi)
+    F* eta[3];               // scattered phi       | adjoint of phi
+    F* gk;                   // image of lnkappa
+    F* gr;                   // image of lnrho
     // second buffers of the fused one-kernel-per-step schedule: the step
     // reads the fields above and writes the ones below (roles swap every
     // step).  Null when the two-phase schedule is in use.
-    float* pn;
-    float* vn[3];
-    float* psin[3];
-    float* qn;
-    float* wn[3];
-    float* xin[3];
-    float* etan[3];
-    float* seg;              // replay buffer [k][ndim + 1][npts]: dv_a, q
-    char* ck;                // checkpoint 1 of this shot; checkpoint j >= 1 at ck + (j-1) * ckbytes
+    F* pn;
+    F* vn[3];
+    F* psin[3];
+    F* qn;
+    F* wn[3];
+    F* xin[3];
+    F* etan[3];
+    F* seg;                  // replay buffer [k][ndim + 1][npts]: dv_a, q
+    C* ck;                   // checkpoint 1 of this shot; checkpoint j >= 1 at ck + (j-1) * ckbytes
     long long ckbytes;
 };
+using Slot = SlotT<0>;
+using DSlot = SlotT<1>;
+static_assert(sizeof(Slot) == sizeof(DSlot), "host and device slot layouts differ");
+
+// Device view of a slot table filled by the host.
+__host__ __device__ inline const DSlot* dev_slots(const Slot* s) { return reinterpret_cast<const DSlot*>(s); }
 
 // Receiver entry of a launch group.
 struct Rec {

@@ -62,7 +62,7 @@ __device__ __forceinline__ void node_of(int r, int& lz, int& lx) {
 // ---------------------------------------------------------------------------
 template <int BZ, int BX, bool BORN, bool SEG>
 __global__ void __launch_bounds__(NTHREADS)
-k2_v(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
+k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
@@ -70,7 +70,7 @@ k2_v(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
     __shared__ float sq[BORN ? T::NL : 1];
     const int tix = xcd_remap(blockIdx.x, gridDim.x);
     const int4 tl = tiles[tix];
-    const Slot& S = slots[tl.x];
+    const DSlot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
     const long long ldz = S.ldz;
@@ -108,11 +108,11 @@ k2_v(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
     for_region<T::LZ>(HW, HW + BZ, 0, HW, ld);             // left x-halo
     for_region<T::LZ>(HW, HW + BZ, HW + BX, T::LX, ld);    // right x-halo
     __syncthreads();
-    const float* achz = S.cpml[0];
-    const float* bchz = S.cpml[0] + nz;
-    const float* achx = S.cpml[1];
-    const float* bchx = S.cpml[1] + nx;
-    float* __restrict__ seg = S.seg + (long long)sstep * 3 * S.npts;
+    const gfloat* achz = S.cpml[0];
+    const gfloat* bchz = S.cpml[0] + nz;
+    const gfloat* achx = S.cpml[1];
+    const gfloat* bchx = S.cpml[1] + nx;
+    gfloat* __restrict__ seg = S.seg + (long long)sstep * 3 * S.npts;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (!ok[r]) continue;
@@ -168,7 +168,7 @@ k2_v(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
 // ---------------------------------------------------------------------------
 template <int BZ, int BX, bool BORN, bool SEG>
 __global__ void __launch_bounds__(NTHREADS)
-k2_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
+k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
@@ -178,7 +178,7 @@ k2_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
     __shared__ float swx[BORN ? T::NL : 1];
     const int tix = xcd_remap(blockIdx.x, gridDim.x);
     const int4 tl = tiles[tix];
-    const Slot& S = slots[tl.x];
+    const DSlot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
     const long long ldz = S.ldz;
@@ -215,12 +215,12 @@ k2_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
     for_region<T::LZ>(0, T::LZ, HW, HW + BX, ldz_);
     for_region<T::LZ>(HW, HW + BZ, 0, T::LX, ldx_);
     __syncthreads();
-    const float* aciz = S.cpml[0] + 2 * nz;
-    const float* bciz = S.cpml[0] + 3 * nz;
-    const float* acix = S.cpml[1] + 2 * nx;
-    const float* bcix = S.cpml[1] + 3 * nx;
+    const gfloat* aciz = S.cpml[0] + 2 * nz;
+    const gfloat* bciz = S.cpml[0] + 3 * nz;
+    const gfloat* acix = S.cpml[1] + 2 * nx;
+    const gfloat* bcix = S.cpml[1] + 3 * nx;
     const float amp = S.src >= 0 ? S.src_amp[n] : 0.f;
-    float* __restrict__ seg = S.seg + (long long)sstep * 3 * S.npts + 2 * S.npts;
+    gfloat* __restrict__ seg = S.seg + (long long)sstep * 3 * S.npts + 2 * S.npts;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (!ok[r]) continue;
@@ -277,7 +277,7 @@ k2_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
 // ---------------------------------------------------------------------------
 template <int BZ, int BX>
 __global__ void __launch_bounds__(NTHREADS)
-k2_a(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
+k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
@@ -285,11 +285,11 @@ k2_a(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
     __shared__ float sex[T::NL];
     const int tix = xcd_remap(blockIdx.x, gridDim.x);
     const int4 tl = tiles[tix];
-    const Slot& S = slots[tl.x];
+    const DSlot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
     const long long ldz = S.ldz;
-    const float* __restrict__ segq = S.seg + (long long)sstep * 3 * S.npts + 2 * S.npts;
+    const gfloat* __restrict__ segq = S.seg + (long long)sstep * 3 * S.npts + 2 * S.npts;
     float vz[R], vx[R], gk[R], qn[R], pt[R], kk[R];
     bool ok[R];
 #pragma unroll
@@ -306,8 +306,8 @@ k2_a(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
         pt[r] = S.q[i];
         kk[r] = S.kdt[i];
     }
-    const float* aciz = S.cpml[0] + 2 * nz;
-    const float* acix = S.cpml[1] + 2 * nx;
+    const gfloat* aciz = S.cpml[0] + 2 * nz;
+    const gfloat* acix = S.cpml[1] + 2 * nx;
     // interior: both e~_z and e~_x; z-halo rows: e~_z; x-halo columns: e~_x
     auto ld = [&](int lz, int lx, int c, bool wz, bool wx) {
         const int gz = z0 + lz - HW, gx = x0 + lx - HW;
@@ -336,10 +336,10 @@ k2_a(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
     for_region<T::LZ>(HW, HW + BZ, 0, HW, [&](int a, int b, int c) { ld(a, b, c, false, true); });
     for_region<T::LZ>(HW, HW + BZ, HW + BX, T::LX, [&](int a, int b, int c) { ld(a, b, c, false, true); });
     __syncthreads();
-    const float* achz = S.cpml[0];
-    const float* bchz = S.cpml[0] + nz;
-    const float* achx = S.cpml[1];
-    const float* bchx = S.cpml[1] + nx;
+    const gfloat* achz = S.cpml[0];
+    const gfloat* bchz = S.cpml[0] + nz;
+    const gfloat* achx = S.cpml[1];
+    const gfloat* bchx = S.cpml[1] + nx;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (!ok[r]) continue;
@@ -366,7 +366,7 @@ k2_a(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
 // ---------------------------------------------------------------------------
 template <int BZ, int BX>
 __global__ void __launch_bounds__(NTHREADS)
-k2_b(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
+k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
@@ -374,12 +374,12 @@ k2_b(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
     __shared__ float sgx[T::NL];
     const int tix = xcd_remap(blockIdx.x, gridDim.x);
     const int4 tl = tiles[tix];
-    const Slot& S = slots[tl.x];
+    const DSlot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
     const long long ldz = S.ldz;
-    const float* __restrict__ segz = S.seg + (long long)sstep * 3 * S.npts;
-    const float* __restrict__ segx = segz + S.npts;
+    const gfloat* __restrict__ segz = S.seg + (long long)sstep * 3 * S.npts;
+    const gfloat* __restrict__ segx = segz + S.npts;
     float pt[R], gr[R], xz0[R], xz1[R], xx0[R], xx1[R];
     bool ok[R];
 #pragma unroll
@@ -397,8 +397,8 @@ k2_b(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
         xx0[r] = -segx[i] * S.w[1][i];
         xx1[r] = (ok[r] && gx > 0) ? -segx[i - ldz] * S.w[1][i - ldz] : 0.f;
     }
-    const float* achz = S.cpml[0];
-    const float* achx = S.cpml[1];
+    const gfloat* achz = S.cpml[0];
+    const gfloat* achx = S.cpml[1];
     auto ldz_ = [&](int lz, int lx, int c) {
         const int gz = z0 + lz - HW, gx = x0 + lx - HW;
         float g = 0.f;
@@ -424,10 +424,10 @@ k2_b(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
     for_region<T::LZ>(0, T::LZ, HW, HW + BX, ldz_);
     for_region<T::LZ>(HW, HW + BZ, 0, T::LX, ldx_);
     __syncthreads();
-    const float* aciz = S.cpml[0] + 2 * nz;
-    const float* bciz = S.cpml[0] + 3 * nz;
-    const float* acix = S.cpml[1] + 2 * nx;
-    const float* bcix = S.cpml[1] + 3 * nx;
+    const gfloat* aciz = S.cpml[0] + 2 * nz;
+    const gfloat* bciz = S.cpml[0] + 3 * nz;
+    const gfloat* acix = S.cpml[1] + 2 * nx;
+    const gfloat* bcix = S.cpml[1] + 3 * nx;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (!ok[r]) continue;
@@ -459,15 +459,16 @@ static hipError_t launch2_t(int kind, int ntiles, hipStream_t st, const Slot* sl
                             const int4* tiles, const Coef& C, int n, int sstep, int flag, const TileRec& tr)
 {
     dim3 g(ntiles), b(NTHREADS);
+    const DSlot* ds = dev_slots(slots);
     switch (kind) {
-    case K_BG_V:    k2_v<BZ, BX, false, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
-    case K_BG_P:    k2_p<BZ, BX, false, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
-    case K_SEG_V:   k2_v<BZ, BX, false, true><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
-    case K_SEG_P:   k2_p<BZ, BX, false, true><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
-    case K_BORN_V:  k2_v<BZ, BX, true, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
-    case K_BORN_P:  k2_p<BZ, BX, true, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
-    case K_ADJ_A:   k2_a<BZ, BX><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
-    case K_ADJ_B:   k2_b<BZ, BX><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
+    case K_BG_V:    k2_v<BZ, BX, false, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
+    case K_BG_P:    k2_p<BZ, BX, false, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
+    case K_SEG_V:   k2_v<BZ, BX, false, true><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
+    case K_SEG_P:   k2_p<BZ, BX, false, true><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
+    case K_BORN_V:  k2_v<BZ, BX, true, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
+    case K_BORN_P:  k2_p<BZ, BX, true, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
+    case K_ADJ_A:   k2_a<BZ, BX><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
+    case K_ADJ_B:   k2_b<BZ, BX><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

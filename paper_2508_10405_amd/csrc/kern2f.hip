@@ -45,7 +45,7 @@ __device__ __forceinline__ void rect(int z0, int z1, int x0, int x1, Fn f) {
 // ---------------------------------------------------------------------------
 template <int BZ, int BX, bool BORN, bool SEG>
 __global__ void __launch_bounds__(NTHREADS)
-k2f_step(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
+k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
 {
     using T = F2<BZ, BX>;
     constexpr int R = T::R;
@@ -57,7 +57,7 @@ k2f_step(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
     __shared__ float swx[BORN ? T::NVX : 1];
     const int tix = xcd_remap(blockIdx.x, gridDim.x);
     const int4 tl = tiles[tix];
-    const Slot& S = slots[tl.x];
+    const DSlot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
     const long long ldz = S.ldz;
@@ -125,11 +125,11 @@ k2f_step(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
     rect(0, BZ, -7, 0, ldp);
     rect(0, BZ, BX, BX + 7, ldp);
     __syncthreads();
-    const float* achz = S.cpml[0];
-    const float* bchz = S.cpml[0] + nz;
-    const float* achx = S.cpml[1];
-    const float* bchx = S.cpml[1] + nx;
-    float* __restrict__ seg = S.seg + (long long)sstep * 3 * S.npts;
+    const gfloat* achz = S.cpml[0];
+    const gfloat* bchz = S.cpml[0] + nz;
+    const gfloat* achx = S.cpml[1];
+    const gfloat* bchx = S.cpml[1] + nx;
+    gfloat* __restrict__ seg = S.seg + (long long)sstep * 3 * S.npts;
 #pragma unroll
     for (int t = 0; t < RZ; ++t) {
         const int e = threadIdx.x + NTHREADS * t;
@@ -216,10 +216,10 @@ k2f_step(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
     }
     __syncthreads();
     // pressure of the tile
-    const float* aciz = S.cpml[0] + 2 * nz;
-    const float* bciz = S.cpml[0] + 3 * nz;
-    const float* acix = S.cpml[1] + 2 * nx;
-    const float* bcix = S.cpml[1] + 3 * nx;
+    const gfloat* aciz = S.cpml[0] + 2 * nz;
+    const gfloat* bciz = S.cpml[0] + 3 * nz;
+    const gfloat* acix = S.cpml[1] + 2 * nx;
+    const gfloat* bcix = S.cpml[1] + 3 * nx;
     const float amp = S.src >= 0 ? S.src_amp[n] : 0.f;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -279,7 +279,7 @@ k2f_step(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
 // ---------------------------------------------------------------------------
 template <int BZ, int BX>
 __global__ void __launch_bounds__(NTHREADS)
-k2f_adj(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
+k2f_adj(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag, TileRec tr)
 {
     using T = F2<BZ, BX>;
     constexpr int R = T::R;
@@ -291,13 +291,13 @@ k2f_adj(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, 
     __shared__ float sxx[T::NVX];
     const int tix = xcd_remap(blockIdx.x, gridDim.x);
     const int4 tl = tiles[tix];
-    const Slot& S = slots[tl.x];
+    const DSlot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
     const long long ldz = S.ldz;
-    const float* __restrict__ segz = S.seg + (long long)sstep * 3 * S.npts;
-    const float* __restrict__ segx = segz + S.npts;
-    const float* __restrict__ segq = segz + 2 * S.npts;
+    const gfloat* __restrict__ segz = S.seg + (long long)sstep * 3 * S.npts;
+    const gfloat* __restrict__ segx = segz + S.npts;
+    const gfloat* __restrict__ segq = segz + 2 * S.npts;
     float pt[R], kk[R], gk[R], qn[R], gr[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -310,10 +310,10 @@ k2f_adj(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, 
         qn[r] = segq[i];
         gr[r] = S.gr[i];
     }
-    const float* aciz = S.cpml[0] + 2 * nz;
-    const float* bciz = S.cpml[0] + 3 * nz;
-    const float* acix = S.cpml[1] + 2 * nx;
-    const float* bcix = S.cpml[1] + 3 * nx;
+    const gfloat* aciz = S.cpml[0] + 2 * nz;
+    const gfloat* bciz = S.cpml[0] + 3 * nz;
+    const gfloat* acix = S.cpml[1] + 2 * nx;
+    const gfloat* bcix = S.cpml[1] + 3 * nx;
     // velocity regions (as in the forward step): pointwise inputs loaded now
     constexpr int NZR = BZ + 7, NXR = BZ;
     constexpr int RZ = (T::NVZ + NTHREADS - 1) / NTHREADS;
@@ -368,10 +368,10 @@ k2f_adj(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, 
         sex[(lx + 7) * BZ + lz] = e;
     });
     __syncthreads();
-    const float* achz = S.cpml[0];
-    const float* bchz = S.cpml[0] + nz;
-    const float* achx = S.cpml[1];
-    const float* bchx = S.cpml[1] + nx;
+    const gfloat* achz = S.cpml[0];
+    const gfloat* bchz = S.cpml[0] + nz;
+    const gfloat* achx = S.cpml[1];
+    const gfloat* bchx = S.cpml[1] + nx;
     // phase A for v~_z on rows -4 .. BZ+2, then g~_z and the imaging term
 #pragma unroll
     for (int t = 0; t < RZ; ++t) {
@@ -466,11 +466,12 @@ static hipError_t launch2f_t(int kind, int ntiles, hipStream_t st, const Slot* s
                              const int4* tiles, const Coef& C, int n, int sstep, int flag, const TileRec& tr)
 {
     dim3 g(ntiles), b(NTHREADS);
+    const DSlot* ds = dev_slots(slots);
     switch (kind) {
-    case K_BG_V:   k2f_step<BZ, BX, false, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
-    case K_SEG_V:  k2f_step<BZ, BX, false, true><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
-    case K_BORN_V: k2f_step<BZ, BX, true, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
-    case K_ADJ_A:  k2f_adj<BZ, BX><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag, tr); break;
+    case K_BG_V:   k2f_step<BZ, BX, false, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
+    case K_SEG_V:  k2f_step<BZ, BX, false, true><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
+    case K_BORN_V: k2f_step<BZ, BX, true, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
+    case K_ADJ_A:  k2f_adj<BZ, BX><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

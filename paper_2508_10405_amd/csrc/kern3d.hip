@@ -48,7 +48,7 @@ __device__ __forceinline__ float d_queue(const float* Q, const float* ck) {
     using T = Tile3<BZ, BX>;                                                  \
     constexpr int R = T::R;                                                   \
     const int4 tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];                  \
-    const Slot& S = slots[tl.x];                                              \
+    const DSlot& S = slots[tl.x];                                              \
     const int z0 = tl.y, x0 = tl.z, y0 = tl.w;                                \
     const int nz = S.n[0], nx = S.n[1], ny = S.n[2];                          \
     const long long sx = S.sx, sy = S.sy;                                     \
@@ -69,13 +69,13 @@ __device__ __forceinline__ float d_queue(const float* Q, const float* ck) {
 // ---------------------------------------------------------------------------
 template <int BZ, int BX, int BY, bool BORN, bool SEG>
 __global__ void __launch_bounds__(NTHREADS)
-k3_v(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
 {
     TILE3_SETUP
     __shared__ float sp[T::NL];
     __shared__ float sq[BORN ? T::NL : 1];
     float Qp[R][8], Qq[R][8];
-    auto at = [&](const float* f, int r, int y) -> float {
+    auto at = [&](const gfloat* f, int r, int y) -> float {
         return (ok[r] && (unsigned)y < (unsigned)ny) ? f[ib[r] + y * sy] : 0.f;
     };
 #pragma unroll
@@ -85,13 +85,13 @@ k3_v(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
             Qp[r][m + 1] = at(S.p, r, y0 - 3 + m);
             if (BORN) Qq[r][m + 1] = at(S.q, r, y0 - 3 + m);
         }
-    const float* achz = S.cpml[0];
-    const float* bchz = S.cpml[0] + nz;
-    const float* achx = S.cpml[1];
-    const float* bchx = S.cpml[1] + nx;
-    const float* achy = S.cpml[2];
-    const float* bchy = S.cpml[2] + ny;
-    float* __restrict__ seg = S.seg + (long long)sstep * 4 * S.npts;
+    const gfloat* achz = S.cpml[0];
+    const gfloat* bchz = S.cpml[0] + nz;
+    const gfloat* achx = S.cpml[1];
+    const gfloat* bchx = S.cpml[1] + nx;
+    const gfloat* achy = S.cpml[2];
+    const gfloat* bchy = S.cpml[2] + ny;
+    gfloat* __restrict__ seg = S.seg + (long long)sstep * 4 * S.npts;
     for (int y = y0; y < y1; ++y) {
         const long long py = y * sy;
         float vz[R], vx[R], vy[R], bz[R], bx[R], by[R], wz[R], wx[R], wy[R], r0[R], r1z[R], r1x[R], r1y[R];
@@ -210,7 +210,7 @@ k3_v(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
 // ---------------------------------------------------------------------------
 template <int BZ, int BX, int BY, bool BORN, bool SEG>
 __global__ void __launch_bounds__(NTHREADS)
-k3_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
 {
     TILE3_SETUP
     __shared__ float svz[T::NL];
@@ -218,7 +218,7 @@ k3_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
     __shared__ float swz[BORN ? T::NL : 1];
     __shared__ float swx[BORN ? T::NL : 1];
     float Qv[R][8], Qw[R][8];
-    auto at = [&](const float* f, int r, int y) -> float {
+    auto at = [&](const gfloat* f, int r, int y) -> float {
         return (ok[r] && (unsigned)y < (unsigned)ny) ? f[ib[r] + y * sy] : 0.f;
     };
 #pragma unroll
@@ -228,14 +228,14 @@ k3_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
             Qv[r][m + 1] = at(S.v[2], r, y0 - 4 + m);
             if (BORN) Qw[r][m + 1] = at(S.w[2], r, y0 - 4 + m);
         }
-    const float* aciz = S.cpml[0] + 2 * nz;
-    const float* bciz = S.cpml[0] + 3 * nz;
-    const float* acix = S.cpml[1] + 2 * nx;
-    const float* bcix = S.cpml[1] + 3 * nx;
-    const float* aciy = S.cpml[2] + 2 * ny;
-    const float* bciy = S.cpml[2] + 3 * ny;
+    const gfloat* aciz = S.cpml[0] + 2 * nz;
+    const gfloat* bciz = S.cpml[0] + 3 * nz;
+    const gfloat* acix = S.cpml[1] + 2 * nx;
+    const gfloat* bcix = S.cpml[1] + 3 * nx;
+    const gfloat* aciy = S.cpml[2] + 2 * ny;
+    const gfloat* bciy = S.cpml[2] + 3 * ny;
     const float amp = S.src >= 0 ? S.src_amp[n] : 0.f;
-    float* __restrict__ seg = S.seg + (long long)sstep * 4 * S.npts + 3 * S.npts;
+    gfloat* __restrict__ seg = S.seg + (long long)sstep * 4 * S.npts + 3 * S.npts;
     for (int y = y0; y < y1; ++y) {
         const long long py = y * sy;
         float pp[R], kk[R], qq[R], lk[R];
@@ -337,21 +337,21 @@ k3_p(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
 // ---------------------------------------------------------------------------
 template <int BZ, int BX, int BY>
 __global__ void __launch_bounds__(NTHREADS)
-k3_a(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
 {
     TILE3_SETUP
     __shared__ float sez[T::NL];
     __shared__ float sex[T::NL];
-    const float* aciz = S.cpml[0] + 2 * nz;
-    const float* acix = S.cpml[1] + 2 * nx;
-    const float* aciy = S.cpml[2] + 2 * ny;
-    const float* achz = S.cpml[0];
-    const float* bchz = S.cpml[0] + nz;
-    const float* achx = S.cpml[1];
-    const float* bchx = S.cpml[1] + nx;
-    const float* achy = S.cpml[2];
-    const float* bchy = S.cpml[2] + ny;
-    const float* __restrict__ segq = S.seg + (long long)sstep * 4 * S.npts + 3 * S.npts;
+    const gfloat* aciz = S.cpml[0] + 2 * nz;
+    const gfloat* acix = S.cpml[1] + 2 * nx;
+    const gfloat* aciy = S.cpml[2] + 2 * ny;
+    const gfloat* achz = S.cpml[0];
+    const gfloat* bchz = S.cpml[0] + nz;
+    const gfloat* achx = S.cpml[1];
+    const gfloat* bchx = S.cpml[1] + nx;
+    const gfloat* achy = S.cpml[2];
+    const gfloat* bchy = S.cpml[2] + ny;
+    const gfloat* __restrict__ segq = S.seg + (long long)sstep * 4 * S.npts + 3 * S.npts;
     // E[m] = e~_y(y + m - 3);  QT[m] = q~(y + m), q~ = -dt kappa p~
     float E[R][8], QT[R][5];
     auto qt_at = [&](int r, int y) -> float {
@@ -461,23 +461,23 @@ k3_a(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int
 // ---------------------------------------------------------------------------
 template <int BZ, int BX, int BY>
 __global__ void __launch_bounds__(NTHREADS)
-k3_b(const Slot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+k3_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
 {
     TILE3_SETUP
     __shared__ float sgz[T::NL];
     __shared__ float sgx[T::NL];
-    const float* achz = S.cpml[0];
-    const float* achx = S.cpml[1];
-    const float* achy = S.cpml[2];
-    const float* aciz = S.cpml[0] + 2 * nz;
-    const float* bciz = S.cpml[0] + 3 * nz;
-    const float* acix = S.cpml[1] + 2 * nx;
-    const float* bcix = S.cpml[1] + 3 * nx;
-    const float* aciy = S.cpml[2] + 2 * ny;
-    const float* bciy = S.cpml[2] + 3 * ny;
-    const float* __restrict__ segz = S.seg + (long long)sstep * 4 * S.npts;
-    const float* __restrict__ segx = segz + S.npts;
-    const float* __restrict__ segy = segz + 2 * S.npts;
+    const gfloat* achz = S.cpml[0];
+    const gfloat* achx = S.cpml[1];
+    const gfloat* achy = S.cpml[2];
+    const gfloat* aciz = S.cpml[0] + 2 * nz;
+    const gfloat* bciz = S.cpml[0] + 3 * nz;
+    const gfloat* acix = S.cpml[1] + 2 * nx;
+    const gfloat* bcix = S.cpml[1] + 3 * nx;
+    const gfloat* aciy = S.cpml[2] + 2 * ny;
+    const gfloat* bciy = S.cpml[2] + 3 * ny;
+    const gfloat* __restrict__ segz = S.seg + (long long)sstep * 4 * S.npts;
+    const gfloat* __restrict__ segx = segz + S.npts;
+    const gfloat* __restrict__ segy = segz + 2 * S.npts;
     // Gq[m] = g~_y(y + m - 4);  Xp = -dv_y v~_y on the previous plane
     float Gq[R][8], Xp[R];
     auto gy_at = [&](int r, int y) -> float {
@@ -571,15 +571,16 @@ static hipError_t launch3_t(int kind, int ntiles, hipStream_t st, const Slot* sl
                             const int4* tiles, const Coef& C, int n, int sstep, int flag)
 {
     dim3 g(ntiles), b(NTHREADS);
+    const DSlot* ds = dev_slots(slots);
     switch (kind) {
-    case K_BG_V:    k3_v<BZ, BX, BY, false, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_BG_P:    k3_p<BZ, BX, BY, false, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_SEG_V:   k3_v<BZ, BX, BY, false, true><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_SEG_P:   k3_p<BZ, BX, BY, false, true><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_BORN_V:  k3_v<BZ, BX, BY, true, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_BORN_P:  k3_p<BZ, BX, BY, true, false><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_ADJ_A:   k3_a<BZ, BX, BY><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
-    case K_ADJ_B:   k3_b<BZ, BX, BY><<<g, b, 0, st>>>(slots, tiles, C, n, sstep, flag); break;
+    case K_BG_V:    k3_v<BZ, BX, BY, false, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
+    case K_BG_P:    k3_p<BZ, BX, BY, false, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
+    case K_SEG_V:   k3_v<BZ, BX, BY, false, true><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
+    case K_SEG_P:   k3_p<BZ, BX, BY, false, true><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
+    case K_BORN_V:  k3_v<BZ, BX, BY, true, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
+    case K_BORN_P:  k3_p<BZ, BX, BY, true, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
+    case K_ADJ_A:   k3_a<BZ, BX, BY><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
+    case K_ADJ_B:   k3_b<BZ, BX, BY><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -1079,13 +1079,22 @@ lsrtm_status time_tile(lsrtm_ctx* c, int tile, int nsteps, double* ms) {
     const bool tim = c->opt_timing;
     c->opt_timing = 0;
     HIPCHK(c, hipEventRecord(a, c->st));
+    // the passes' order per group: Born steps, then replayed background
+    // steps, then adjoint steps, so that what stays cached between launches
+    // is what stays cached in a real pass
     for (auto& gr : c->groups) {
         for (int n = 0; n < nsteps; ++n) {
             const Slot* sl = desc(gr, c->fused ? n : 0);
             CHK(stencil(c, gr, K_BORN_V, n, 0, 0, sl));
             if (!c->fused) CHK(stencil(c, gr, K_BORN_P, n, 0, 0, sl));
+        }
+        for (int n = 0; n < nsteps; ++n) {
+            const Slot* sl = desc(gr, c->fused ? n : 0);
             CHK(stencil(c, gr, K_SEG_V, n, n % c->k, 0, sl));
             if (!c->fused) CHK(stencil(c, gr, K_SEG_P, n, n % c->k, 0, sl));
+        }
+        for (int n = 0; n < nsteps; ++n) {
+            const Slot* sl = desc(gr, c->fused ? n : 0);
             CHK(stencil(c, gr, K_ADJ_A, n, n % c->k, n == 0, sl));
             if (!c->fused) CHK(stencil(c, gr, K_ADJ_B, n, n % c->k, 0, sl));
         }
