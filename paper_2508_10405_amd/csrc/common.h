@@ -46,6 +46,8 @@ struct SlotT {
     long long npts;          // elements per array
     int src;                 // linear index of the source node, -1 for none
     int shot;                // global shot index
+    int npml;                // CPML width in nodes (every side, every axis)
+    int pad_;
     const F* src_amp;        // [nt] dt * w / cell
     const F* kdt;            // dt * kappa at nodes
     const F* bdt[3];         // dt * b_a at half nodes
@@ -131,6 +133,12 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
     const int base = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
     return base + k;
 }
+
+// Whether the CPML coefficients of index g (node or half node) on an axis
+// of n nodes may be nonzero: the absorbing strips are the first npml and the
+// last npml + 1 indices (the half node just outside the last interior node
+// already lies in the strip).
+__device__ __forceinline__ bool in_pml(int g, int n, int npml) { return g < npml || g >= n - npml - 1; }
 
 // Forward staggered derivative at half node i + 1/2 from node values around
 // LDS index c with stride s: sum_k c_k (f[i+k] - f[i-k+1]).

@@ -3,12 +3,16 @@
 // Every launch advances all shots ("slots") of a launch group by one phase of
 // one time step.  The grid walks a tile table: tile t = (slot, z0, x0) covers
 // BZ x BX nodes of that slot's padded grid, R = BZ*BX/256 nodes per thread.
-// Each thread first issues the loads of every array it reads pointwise (so
-// they are in flight while the tile is staged), then the input of the phase's
-// derivative is staged in LDS with the 4-node halo that derivative needs
-// (z-halo for z-derivatives, x-halo for x-derivatives), and after one barrier
-// every node is updated and written once, coalesced along z.  Values outside
-// the padded grid are zero, as the discrete operators define them.
+// The input of the phase's derivative is staged in LDS with the 4-node halo
+// that derivative needs (z-halo for z-derivatives, x-halo for
+// x-derivatives).  Each thread issues every global load it makes before the
+// barrier at once -- the arrays it reads pointwise and its share of the
+// staged cells, from addresses that are always valid (clamped to element 0
+// where a cell lies outside the grid or a value is not needed), so that no
+// branch separates them -- and only then combines the values and writes LDS.
+// After one barrier every node is updated and written once, coalesced along
+// z.  Values outside the padded grid are zero, as the discrete operators
+// define them.
 //
 // Phases (section 2 of the paper, first-order system and eq. scattereqln;
 // appendix A for the adjoint):
@@ -38,16 +42,44 @@ struct Tile2 {
     static_assert(NP % NTHREADS == 0, "tile must hold a multiple of 256 nodes");
 };
 
-// Visit the LDS cells of rows [zl, zh) x columns [xl, xh) (tile-local, halo
-// included: 0 .. LZ-1, 0 .. LX-1) with the block's threads.
-template <int LZ, typename F>
-__device__ __forceinline__ void for_region(int zl, int zh, int xl, int xh, F f) {
-    const int nzr = zh - zl, n = nzr * (xh - xl);
-    for (int e = threadIdx.x; e < n; e += NTHREADS) {
-        const int lz = zl + e % nzr, lx = xl + e / nzr;
-        f(lz, lx, lx * LZ + lz);
+// A set of LDS cells staged by the block: rows ZL + jz (jz < NZ) and columns
+// XL + jx (jx < NX) of the tile (halo included, LDS row length LZ), where an
+// index jz >= HW moves down by ZS rows and jx >= HW right by XS columns, so
+// that the two halo strips of one axis form one set.  Cell k of the set goes
+// to thread k % 256, pass k / 256.
+template <int LZ, int ZL, int NZ, int XL, int NX, int ZS = 0, int XS = 0>
+struct Region {
+    static constexpr int N = NZ * NX;
+    static constexpr int IT = (N + NTHREADS - 1) / NTHREADS;
+    __device__ static __forceinline__ void cell(int t, int& lz, int& lx) {
+        const int e = threadIdx.x + NTHREADS * t;
+        const int jz = e % NZ, jx = e / NZ;
+        lz = ZL + jz + (jz >= HW ? ZS : 0);
+        lx = XL + jx + (jx >= HW ? XS : 0);
     }
-}
+    // ld(lz, lx, vals) issues the K loads of a cell.  Passes past the end of
+    // the set load too (clamped addresses) but store nothing.
+    template <int K, typename LD>
+    __device__ static __forceinline__ void load(LD ld, float (&v)[IT][K]) {
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            int lz, lx;
+            cell(t, lz, lx);
+            ld(lz, lx, v[t]);
+        }
+    }
+    // st(lz, lx, c, vals) combines them and writes LDS cell c.
+    template <int K, typename ST>
+    __device__ static __forceinline__ void store(ST st, float (&v)[IT][K]) {
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            if (N % NTHREADS != 0 && threadIdx.x + NTHREADS * t >= N) continue;
+            int lz, lx;
+            cell(t, lz, lx);
+            st(lz, lx, lx * LZ + lz, v[t]);
+        }
+    }
+};
 
 // Node r of this thread in the tile.
 template <int BZ>
@@ -66,6 +98,9 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
+    constexpr int K = BORN ? 2 : 1;
+    using RZ = Region<T::LZ, 0, T::LZ, HW, BX>;          // interior columns with the z-halo
+    using RX = Region<T::LZ, HW, BZ, 0, 2 * HW, 0, BX>;  // both x-halo strips
     __shared__ float sp[T::NL];
     __shared__ float sq[BORN ? T::NL : 1];
     const int tix = xcd_remap(blockIdx.x, gridDim.x);
@@ -97,16 +132,24 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         }
     }
     // stage p (and dp): cross of z- and x-halos
-    auto ld = [&](int lz, int lx, int c) {
-        const int gz = z0 + lz - HW, gx = x0 + lx - HW;
-        const bool in = (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx;
-        const long long i = gx * ldz + gz;
-        sp[c] = in ? S.p[i] : 0.f;
-        if (BORN) sq[c] = in ? S.q[i] : 0.f;
+    auto inside = [&](int lz, int lx) {
+        return (unsigned)(z0 + lz - HW) < (unsigned)nz && (unsigned)(x0 + lx - HW) < (unsigned)nx;
     };
-    for_region<T::LZ>(0, T::LZ, HW, HW + BX, ld);          // interior columns with z-halo
-    for_region<T::LZ>(HW, HW + BZ, 0, HW, ld);             // left x-halo
-    for_region<T::LZ>(HW, HW + BZ, HW + BX, T::LX, ld);    // right x-halo
+    auto ld = [&](int lz, int lx, float* v) {
+        const long long i = inside(lz, lx) ? (x0 + lx - HW) * ldz + (z0 + lz - HW) : 0;
+        v[0] = S.p[i];
+        if (BORN) v[1] = S.q[i];
+    };
+    auto st = [&](int lz, int lx, int c, const float* v) {
+        const bool in = inside(lz, lx);
+        sp[c] = in ? v[0] : 0.f;
+        if (BORN) sq[c] = in ? v[1] : 0.f;
+    };
+    float hz[RZ::IT][K], hx[RX::IT][K];
+    RZ::load(ld, hz);
+    RX::load(ld, hx);
+    RZ::store(st, hz);
+    RX::store(st, hx);
     __syncthreads();
     const gfloat* achz = S.cpml[0];
     const gfloat* bchz = S.cpml[0] + nz;
@@ -172,6 +215,9 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
+    constexpr int K = BORN ? 2 : 1;
+    using RZ = Region<T::LZ, 0, T::LZ, HW, BX>;   // v_z (and w_z) with the z-halo
+    using RX = Region<T::LZ, HW, BZ, 0, T::LX>;   // v_x (and w_x) with the x-halo
     __shared__ float svz[T::NL];
     __shared__ float svx[T::NL];
     __shared__ float swz[BORN ? T::NL : 1];
@@ -198,22 +244,37 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             lk[r] = S.dlnk[i];
         }
     }
-    auto ldz_ = [&](int lz, int lx, int c) {   // v_z (and w_z) with z-halo
-        const int gz = z0 + lz - HW, gx = x0 + lx - HW;
-        const bool in = (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx;
-        const long long i = gx * ldz + gz;
-        svz[c] = in ? S.v[0][i] : 0.f;
-        if (BORN) swz[c] = in ? S.w[0][i] : 0.f;
+    auto inside = [&](int lz, int lx) {
+        return (unsigned)(z0 + lz - HW) < (unsigned)nz && (unsigned)(x0 + lx - HW) < (unsigned)nx;
     };
-    auto ldx_ = [&](int lz, int lx, int c) {   // v_x (and w_x) with x-halo
-        const int gz = z0 + lz - HW, gx = x0 + lx - HW;
-        const bool in = (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx;
-        const long long i = gx * ldz + gz;
-        svx[c] = in ? S.v[1][i] : 0.f;
-        if (BORN) swx[c] = in ? S.w[1][i] : 0.f;
+    auto index = [&](int lz, int lx) -> long long {
+        return inside(lz, lx) ? (x0 + lx - HW) * ldz + (z0 + lz - HW) : 0;
     };
-    for_region<T::LZ>(0, T::LZ, HW, HW + BX, ldz_);
-    for_region<T::LZ>(HW, HW + BZ, 0, T::LX, ldx_);
+    auto ldz_ = [&](int lz, int lx, float* v) {
+        const long long i = index(lz, lx);
+        v[0] = S.v[0][i];
+        if (BORN) v[1] = S.w[0][i];
+    };
+    auto ldx_ = [&](int lz, int lx, float* v) {
+        const long long i = index(lz, lx);
+        v[0] = S.v[1][i];
+        if (BORN) v[1] = S.w[1][i];
+    };
+    auto stz_ = [&](int lz, int lx, int c, const float* v) {
+        const bool in = inside(lz, lx);
+        svz[c] = in ? v[0] : 0.f;
+        if (BORN) swz[c] = in ? v[1] : 0.f;
+    };
+    auto stx_ = [&](int lz, int lx, int c, const float* v) {
+        const bool in = inside(lz, lx);
+        svx[c] = in ? v[0] : 0.f;
+        if (BORN) swx[c] = in ? v[1] : 0.f;
+    };
+    float hz[RZ::IT][K], hx[RX::IT][K];
+    RZ::load(ldz_, hz);
+    RX::load(ldx_, hx);
+    RZ::store(stz_, hz);
+    RX::store(stx_, hx);
     __syncthreads();
     const gfloat* aciz = S.cpml[0] + 2 * nz;
     const gfloat* bciz = S.cpml[0] + 3 * nz;
@@ -281,16 +342,51 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
+    using RZ = Region<T::LZ, 0, 2 * HW, HW, BX, BZ, 0>;   // both z-halo strips
+    using RX = Region<T::LZ, HW, BZ, 0, 2 * HW, 0, BX>;   // both x-halo strips
     __shared__ float sez[T::NL];
     __shared__ float sex[T::NL];
     const int tix = xcd_remap(blockIdx.x, gridDim.x);
     const int4 tl = tiles[tix];
     const DSlot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
-    const int nz = S.n[0], nx = S.n[1];
+    const int nz = S.n[0], nx = S.n[1], npml = S.npml;
     const long long ldz = S.ldz;
     const gfloat* __restrict__ segq = S.seg + (long long)sstep * 3 * S.npts + 2 * S.npts;
-    float vz[R], vx[R], gk[R], qn[R], pt[R], kk[R];
+    const gfloat* aciz = S.cpml[0] + 2 * nz;
+    const gfloat* acix = S.cpml[1] + 2 * nx;
+    auto inside = [&](int lz, int lx) {
+        return (unsigned)(z0 + lz - HW) < (unsigned)nz && (unsigned)(x0 + lx - HW) < (unsigned)nx;
+    };
+    // loads of e~ at a cell: dt kappa, p~, then per wanted axis the CPML
+    // coefficient and phi~ (the latter only inside the strips)
+    auto lde = [&](int lz, int lx, float* v, bool wz, bool wx) {
+        const int gz = z0 + lz - HW, gx = x0 + lx - HW;
+        const bool in = inside(lz, lx);
+        const long long i = in ? gx * ldz + gz : 0;
+        v[0] = S.kdt[i];
+        v[1] = S.q[i];
+        if (wz) {
+            v[2] = aciz[in ? gz : 0];
+            v[3] = S.eta[0][in && in_pml(gz, nz, npml) ? i : 0];
+        }
+        if (wx) {
+            v[4] = acix[in ? gx : 0];
+            v[5] = S.eta[1][in && in_pml(gx, nx, npml) ? i : 0];
+        }
+    };
+    auto ete = [&](bool in, const float* v, bool wz, bool wx, float& ez, float& ex, float& qt) {
+        ez = ex = qt = 0.f;
+        if (in) {
+            qt = -v[0] * v[1];
+            ez = qt;
+            ex = qt;
+            if (wz && v[2] != 0.f) ez = qt + v[2] * (v[3] + qt);
+            if (wx && v[4] != 0.f) ex = qt + v[4] * (v[5] + qt);
+        }
+    };
+    // the tile's own nodes need both components; q~ is kept for the image
+    float vz[R], vx[R], gk[R], qn[R], ev[R][6];
     bool ok[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -303,38 +399,32 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         vx[r] = S.w[1][i];
         gk[r] = S.gk[i];
         qn[r] = segq[i];
-        pt[r] = S.q[i];
-        kk[r] = S.kdt[i];
+        lde(lz + HW, lx + HW, ev[r], true, true);
     }
-    const gfloat* aciz = S.cpml[0] + 2 * nz;
-    const gfloat* acix = S.cpml[1] + 2 * nx;
-    // interior: both e~_z and e~_x; z-halo rows: e~_z; x-halo columns: e~_x
-    auto ld = [&](int lz, int lx, int c, bool wz, bool wx) {
-        const int gz = z0 + lz - HW, gx = x0 + lx - HW;
-        const bool in = (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx;
-        float ez = 0.f, ex = 0.f;
-        if (in) {
-            const long long i = gx * ldz + gz;
-            const float qt = -S.kdt[i] * S.q[i];
-            ez = qt;
-            ex = qt;
-            if (wz) {
-                const float az = aciz[gz];
-                if (az != 0.f) ez = qt + az * (S.eta[0][i] + qt);
-            }
-            if (wx) {
-                const float ax = acix[gx];
-                if (ax != 0.f) ex = qt + ax * (S.eta[1][i] + qt);
-            }
-        }
-        if (wz) sez[c] = ez;
-        if (wx) sex[c] = ex;
-    };
-    for_region<T::LZ>(HW, HW + BZ, HW, HW + BX, [&](int a, int b, int c) { ld(a, b, c, true, true); });
-    for_region<T::LZ>(0, HW, HW, HW + BX, [&](int a, int b, int c) { ld(a, b, c, true, false); });
-    for_region<T::LZ>(HW + BZ, T::LZ, HW, HW + BX, [&](int a, int b, int c) { ld(a, b, c, true, false); });
-    for_region<T::LZ>(HW, HW + BZ, 0, HW, [&](int a, int b, int c) { ld(a, b, c, false, true); });
-    for_region<T::LZ>(HW, HW + BZ, HW + BX, T::LX, [&](int a, int b, int c) { ld(a, b, c, false, true); });
+    float hz[RZ::IT][6], hx[RX::IT][6];
+    RZ::load([&](int lz, int lx, float* v) { lde(lz, lx, v, true, false); }, hz);
+    RX::load([&](int lz, int lx, float* v) { lde(lz, lx, v, false, true); }, hx);
+    float qt[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int lz, lx;
+        node_of<BZ>(r, lz, lx);
+        float ez, ex;
+        ete(ok[r], ev[r], true, true, ez, ex, qt[r]);
+        const int c = (lx + HW) * T::LZ + lz + HW;
+        sez[c] = ez;
+        sex[c] = ex;
+    }
+    RZ::store([&](int lz, int lx, int c, const float* v) {
+        float ez, ex, q;
+        ete(inside(lz, lx), v, true, false, ez, ex, q);
+        sez[c] = ez;
+    }, hz);
+    RX::store([&](int lz, int lx, int c, const float* v) {
+        float ez, ex, q;
+        ete(inside(lz, lx), v, false, true, ez, ex, q);
+        sex[c] = ex;
+    }, hx);
     __syncthreads();
     const gfloat* achz = S.cpml[0];
     const gfloat* bchz = S.cpml[0] + nz;
@@ -349,11 +439,11 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const long long i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
         if (!flag) {
-            const float hz = achz[gz], hx = achx[gx];
-            if (hz != 0.f) S.xi[0][i] = bchz[gz] * (S.xi[0][i] + (-S.bdt[0][i] * vz[r]));
-            if (hx != 0.f) S.xi[1][i] = bchx[gx] * (S.xi[1][i] + (-S.bdt[1][i] * vx[r]));
+            const float hz_ = achz[gz], hx_ = achx[gx];
+            if (hz_ != 0.f) S.xi[0][i] = bchz[gz] * (S.xi[0][i] + (-S.bdt[0][i] * vz[r]));
+            if (hx_ != 0.f) S.xi[1][i] = bchx[gx] * (S.xi[1][i] + (-S.bdt[1][i] * vx[r]));
         }
-        S.gk[i] = gk[r] + qn[r] * (-kk[r] * pt[r]);
+        S.gk[i] = gk[r] + qn[r] * qt[r];
         S.w[0][i] = vz[r] - d_half(sez, c, 1, C.c[0]);
         S.w[1][i] = vx[r] - d_half(sex, c, T::LZ, C.c[1]);
     }
@@ -363,6 +453,8 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
 // Adjoint phase B (transpose of V): phi~_a <- bci_a (phi~_a + q~);
 // g_rho += avg^T(-dv_a v~_a);  h~_a = -dt b_a v~_a,
 // g~_a = h~_a + ach_a (chi_a + h~_a);  p~ -= sum_a D_a g~_a.
+// The products -dv_a v~_a are formed while staging (the transpose of the
+// half-node average needs them at the node and at its lower neighbour).
 // ---------------------------------------------------------------------------
 template <int BZ, int BX>
 __global__ void __launch_bounds__(NTHREADS)
@@ -370,17 +462,21 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
+    using RZ = Region<T::LZ, 0, T::LZ, HW, BX>;   // g~_z with the z-halo
+    using RX = Region<T::LZ, HW, BZ, 0, T::LX>;   // g~_x with the x-halo
     __shared__ float sgz[T::NL];
     __shared__ float sgx[T::NL];
+    __shared__ float sxz[T::NL];
+    __shared__ float sxx[T::NL];
     const int tix = xcd_remap(blockIdx.x, gridDim.x);
     const int4 tl = tiles[tix];
     const DSlot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
-    const int nz = S.n[0], nx = S.n[1];
+    const int nz = S.n[0], nx = S.n[1], npml = S.npml;
     const long long ldz = S.ldz;
     const gfloat* __restrict__ segz = S.seg + (long long)sstep * 3 * S.npts;
     const gfloat* __restrict__ segx = segz + S.npts;
-    float pt[R], gr[R], xz0[R], xz1[R], xx0[R], xx1[R];
+    float pt[R], gr[R];
     bool ok[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -391,38 +487,60 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const long long i = ok[r] ? gx * ldz + gz : 0;
         pt[r] = S.q[i];
         gr[r] = S.gr[i];
-        // lnrho imaging terms with the transpose of the half-node average
-        xz0[r] = -segz[i] * S.w[0][i];
-        xz1[r] = (ok[r] && gz > 0) ? -segz[i - 1] * S.w[0][i - 1] : 0.f;
-        xx0[r] = -segx[i] * S.w[1][i];
-        xx1[r] = (ok[r] && gx > 0) ? -segx[i - ldz] * S.w[1][i - ldz] : 0.f;
     }
     const gfloat* achz = S.cpml[0];
     const gfloat* achx = S.cpml[1];
-    auto ldz_ = [&](int lz, int lx, int c) {
+    auto inside = [&](int lz, int lx) {
+        return (unsigned)(z0 + lz - HW) < (unsigned)nz && (unsigned)(x0 + lx - HW) < (unsigned)nx;
+    };
+    // loads of g~_a and of the image product at a cell: v~_a, dt b_a, the
+    // CPML coefficient, chi_a (inside the strips only) and dv_a (on the rows
+    // or columns whose product is needed)
+    auto ldz_ = [&](int lz, int lx, float* v) {
         const int gz = z0 + lz - HW, gx = x0 + lx - HW;
-        float g = 0.f;
-        if ((unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx) {
-            const long long i = gx * ldz + gz;
-            const float h = -S.bdt[0][i] * S.w[0][i];
-            const float a = achz[gz];
-            g = a != 0.f ? h + a * (S.xi[0][i] + h) : h;
+        const bool in = inside(lz, lx);
+        const long long i = in ? gx * ldz + gz : 0;
+        v[0] = S.w[0][i];
+        v[1] = S.bdt[0][i];
+        v[2] = achz[in ? gz : 0];
+        v[3] = S.xi[0][in && in_pml(gz, nz, npml) ? i : 0];
+        v[4] = segz[in && lz >= HW - 1 && lz < HW + BZ ? i : 0];
+    };
+    auto ldx_ = [&](int lz, int lx, float* v) {
+        const int gz = z0 + lz - HW, gx = x0 + lx - HW;
+        const bool in = inside(lz, lx);
+        const long long i = in ? gx * ldz + gz : 0;
+        v[0] = S.w[1][i];
+        v[1] = S.bdt[1][i];
+        v[2] = achx[in ? gx : 0];
+        v[3] = S.xi[1][in && in_pml(gx, nx, npml) ? i : 0];
+        v[4] = segx[in && lx >= HW - 1 && lx < HW + BX ? i : 0];
+    };
+    auto stz_ = [&](int lz, int lx, int c, const float* v) {
+        float g = 0.f, x = 0.f;
+        if (inside(lz, lx)) {
+            const float h = -v[1] * v[0];
+            g = v[2] != 0.f ? h + v[2] * (v[3] + h) : h;
+            if (lz >= HW - 1 && lz < HW + BZ) x = -v[4] * v[0];
         }
         sgz[c] = g;
+        sxz[c] = x;
     };
-    auto ldx_ = [&](int lz, int lx, int c) {
-        const int gz = z0 + lz - HW, gx = x0 + lx - HW;
-        float g = 0.f;
-        if ((unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx) {
-            const long long i = gx * ldz + gz;
-            const float h = -S.bdt[1][i] * S.w[1][i];
-            const float a = achx[gx];
-            g = a != 0.f ? h + a * (S.xi[1][i] + h) : h;
+    auto stx_ = [&](int lz, int lx, int c, const float* v) {
+        float g = 0.f, x = 0.f;
+        if (inside(lz, lx)) {
+            const float h = -v[1] * v[0];
+            g = v[2] != 0.f ? h + v[2] * (v[3] + h) : h;
+            if (lx >= HW - 1 && lx < HW + BX) x = -v[4] * v[0];
         }
         sgx[c] = g;
+        sxx[c] = x;
     };
-    for_region<T::LZ>(0, T::LZ, HW, HW + BX, ldz_);
-    for_region<T::LZ>(HW, HW + BZ, 0, T::LX, ldx_);
+    float hz[RZ::IT][5], hx[RX::IT][5];
+    RZ::load(ldz_, hz);
+    RX::load(ldx_, hx);
+    RZ::store(stz_, hz);
+    RX::store(stx_, hx);
     __syncthreads();
     const gfloat* aciz = S.cpml[0] + 2 * nz;
     const gfloat* bciz = S.cpml[0] + 3 * nz;
@@ -442,7 +560,7 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             if (az != 0.f) S.eta[0][i] = bciz[gz] * (S.eta[0][i] + qt);
             if (ax != 0.f) S.eta[1][i] = bcix[gx] * (S.eta[1][i] + qt);
         }
-        S.gr[i] = gr[r] + (0.5f * (xz0[r] + xz1[r]) + 0.5f * (xx0[r] + xx1[r]));
+        S.gr[i] = gr[r] + (0.5f * (sxz[c] + sxz[c - 1]) + 0.5f * (sxx[c] + sxx[c - T::LZ]));
         const float dz = d_node(sgz, c, 1, C.c[0]);
         const float dx = d_node(sgx, c, T::LZ, C.c[1]);
         float pn = pt[r] - (dz + dx);

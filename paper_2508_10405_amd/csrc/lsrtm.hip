@@ -899,6 +899,7 @@ lsrtm_status plan(lsrtm_ctx* c) {
             S.npts = W.npts;
             S.src = sh.src_lin;
             S.shot = s;
+            S.npml = c->g.npml;
             S.src_amp = c->src_amp + (long long)s * nt;
             S.kdt = W.kdt;
             for (int a = 0; a < 3; ++a) {
