@@ -134,6 +134,48 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
     return base + k;
 }
 
+// A set of cells (tile-local row lz, column lx; negative = halo) that the
+// block stages: rows ZL + jz (jz < NZ) and columns XL + jx (jx < NX), where
+// an index jz >= ZW moves down by ZS rows and jx >= XW right by XS columns,
+// so that the two halo strips of one axis form one set.  Cell k of the set
+// goes to thread k % 256, pass k / 256.  load() issues every pass's loads
+// before store() combines them, so a thread's loads are all in flight at
+// once.
+template <int ZL, int NZ, int XL, int NX, int ZW = 0, int ZS = 0, int XW = 0, int XS = 0>
+struct Cells {
+    static constexpr int N = NZ * NX;
+    static constexpr int IT = (N + NTHREADS - 1) / NTHREADS;
+    __device__ static __forceinline__ void cell(int t, int& lz, int& lx) {
+        const int e = threadIdx.x + NTHREADS * t;
+        const int jz = e % NZ, jx = e / NZ;
+        lz = ZL + jz + ((ZS != 0 && jz >= ZW) ? ZS : 0);
+        lx = XL + jx + ((XS != 0 && jx >= XW) ? XS : 0);
+    }
+    // ld(lz, lx, vals) issues the K loads of a cell from addresses that are
+    // valid for any (lz, lx): passes past the end of the set load too but
+    // store nothing.
+    template <int K, typename LD>
+    __device__ static __forceinline__ void load(LD ld, float (&v)[IT][K]) {
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            int lz, lx;
+            cell(t, lz, lx);
+            ld(lz, lx, v[t]);
+        }
+    }
+    // st(lz, lx, vals) combines the values and writes the cell's LDS entry.
+    template <int K, typename ST>
+    __device__ static __forceinline__ void store(ST st, float (&v)[IT][K]) {
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            if (N % NTHREADS != 0 && threadIdx.x + NTHREADS * t >= N) continue;
+            int lz, lx;
+            cell(t, lz, lx);
+            st(lz, lx, v[t]);
+        }
+    }
+};
+
 // Whether the CPML coefficients of index g (node or half node) on an axis
 // of n nodes may be nonzero: the absorbing strips are the first npml and the
 // last npml + 1 indices (the half node just outside the last interior node

@@ -42,45 +42,6 @@ struct Tile2 {
     static_assert(NP % NTHREADS == 0, "tile must hold a multiple of 256 nodes");
 };
 
-// A set of LDS cells staged by the block: rows ZL + jz (jz < NZ) and columns
-// XL + jx (jx < NX) of the tile (halo included, LDS row length LZ), where an
-// index jz >= HW moves down by ZS rows and jx >= HW right by XS columns, so
-// that the two halo strips of one axis form one set.  Cell k of the set goes
-// to thread k % 256, pass k / 256.
-template <int LZ, int ZL, int NZ, int XL, int NX, int ZS = 0, int XS = 0>
-struct Region {
-    static constexpr int N = NZ * NX;
-    static constexpr int IT = (N + NTHREADS - 1) / NTHREADS;
-    __device__ static __forceinline__ void cell(int t, int& lz, int& lx) {
-        const int e = threadIdx.x + NTHREADS * t;
-        const int jz = e % NZ, jx = e / NZ;
-        lz = ZL + jz + (jz >= HW ? ZS : 0);
-        lx = XL + jx + (jx >= HW ? XS : 0);
-    }
-    // ld(lz, lx, vals) issues the K loads of a cell.  Passes past the end of
-    // the set load too (clamped addresses) but store nothing.
-    template <int K, typename LD>
-    __device__ static __forceinline__ void load(LD ld, float (&v)[IT][K]) {
-#pragma unroll
-        for (int t = 0; t < IT; ++t) {
-            int lz, lx;
-            cell(t, lz, lx);
-            ld(lz, lx, v[t]);
-        }
-    }
-    // st(lz, lx, c, vals) combines them and writes LDS cell c.
-    template <int K, typename ST>
-    __device__ static __forceinline__ void store(ST st, float (&v)[IT][K]) {
-#pragma unroll
-        for (int t = 0; t < IT; ++t) {
-            if (N % NTHREADS != 0 && threadIdx.x + NTHREADS * t >= N) continue;
-            int lz, lx;
-            cell(t, lz, lx);
-            st(lz, lx, lx * LZ + lz, v[t]);
-        }
-    }
-};
-
 // Node r of this thread in the tile.
 template <int BZ>
 __device__ __forceinline__ void node_of(int r, int& lz, int& lx) {
@@ -99,8 +60,8 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
     constexpr int K = BORN ? 2 : 1;
-    using RZ = Region<T::LZ, 0, T::LZ, HW, BX>;          // interior columns with the z-halo
-    using RX = Region<T::LZ, HW, BZ, 0, 2 * HW, 0, BX>;  // both x-halo strips
+    using RZ = Cells<0, T::LZ, HW, BX>;                    // interior columns with the z-halo
+    using RX = Cells<HW, BZ, 0, 2 * HW, 0, 0, HW, BX>;     // both x-halo strips
     __shared__ float sp[T::NL];
     __shared__ float sq[BORN ? T::NL : 1];
     const int tix = xcd_remap(blockIdx.x, gridDim.x);
@@ -140,7 +101,8 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         v[0] = S.p[i];
         if (BORN) v[1] = S.q[i];
     };
-    auto st = [&](int lz, int lx, int c, const float* v) {
+    auto st = [&](int lz, int lx, const float* v) {
+        const int c = lx * T::LZ + lz;
         const bool in = inside(lz, lx);
         sp[c] = in ? v[0] : 0.f;
         if (BORN) sq[c] = in ? v[1] : 0.f;
@@ -216,8 +178,8 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
     constexpr int K = BORN ? 2 : 1;
-    using RZ = Region<T::LZ, 0, T::LZ, HW, BX>;   // v_z (and w_z) with the z-halo
-    using RX = Region<T::LZ, HW, BZ, 0, T::LX>;   // v_x (and w_x) with the x-halo
+    using RZ = Cells<0, T::LZ, HW, BX>;   // v_z (and w_z) with the z-halo
+    using RX = Cells<HW, BZ, 0, T::LX>;   // v_x (and w_x) with the x-halo
     __shared__ float svz[T::NL];
     __shared__ float svx[T::NL];
     __shared__ float swz[BORN ? T::NL : 1];
@@ -260,12 +222,14 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         v[0] = S.v[1][i];
         if (BORN) v[1] = S.w[1][i];
     };
-    auto stz_ = [&](int lz, int lx, int c, const float* v) {
+    auto stz_ = [&](int lz, int lx, const float* v) {
+        const int c = lx * T::LZ + lz;
         const bool in = inside(lz, lx);
         svz[c] = in ? v[0] : 0.f;
         if (BORN) swz[c] = in ? v[1] : 0.f;
     };
-    auto stx_ = [&](int lz, int lx, int c, const float* v) {
+    auto stx_ = [&](int lz, int lx, const float* v) {
+        const int c = lx * T::LZ + lz;
         const bool in = inside(lz, lx);
         svx[c] = in ? v[0] : 0.f;
         if (BORN) swx[c] = in ? v[1] : 0.f;
@@ -342,8 +306,8 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
-    using RZ = Region<T::LZ, 0, 2 * HW, HW, BX, BZ, 0>;   // both z-halo strips
-    using RX = Region<T::LZ, HW, BZ, 0, 2 * HW, 0, BX>;   // both x-halo strips
+    using RZ = Cells<0, 2 * HW, HW, BX, HW, BZ>;          // both z-halo strips
+    using RX = Cells<HW, BZ, 0, 2 * HW, 0, 0, HW, BX>;    // both x-halo strips
     __shared__ float sez[T::NL];
     __shared__ float sex[T::NL];
     const int tix = xcd_remap(blockIdx.x, gridDim.x);
@@ -415,12 +379,14 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         sez[c] = ez;
         sex[c] = ex;
     }
-    RZ::store([&](int lz, int lx, int c, const float* v) {
+    RZ::store([&](int lz, int lx, const float* v) {
+        const int c = lx * T::LZ + lz;
         float ez, ex, q;
         ete(inside(lz, lx), v, true, false, ez, ex, q);
         sez[c] = ez;
     }, hz);
-    RX::store([&](int lz, int lx, int c, const float* v) {
+    RX::store([&](int lz, int lx, const float* v) {
+        const int c = lx * T::LZ + lz;
         float ez, ex, q;
         ete(inside(lz, lx), v, false, true, ez, ex, q);
         sex[c] = ex;
@@ -462,8 +428,8 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
-    using RZ = Region<T::LZ, 0, T::LZ, HW, BX>;   // g~_z with the z-halo
-    using RX = Region<T::LZ, HW, BZ, 0, T::LX>;   // g~_x with the x-halo
+    using RZ = Cells<0, T::LZ, HW, BX>;   // g~_z with the z-halo
+    using RX = Cells<HW, BZ, 0, T::LX>;   // g~_x with the x-halo
     __shared__ float sgz[T::NL];
     __shared__ float sgx[T::NL];
     __shared__ float sxz[T::NL];
@@ -516,7 +482,8 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         v[3] = S.xi[1][in && in_pml(gx, nx, npml) ? i : 0];
         v[4] = segx[in && lx >= HW - 1 && lx < HW + BX ? i : 0];
     };
-    auto stz_ = [&](int lz, int lx, int c, const float* v) {
+    auto stz_ = [&](int lz, int lx, const float* v) {
+        const int c = lx * T::LZ + lz;
         float g = 0.f, x = 0.f;
         if (inside(lz, lx)) {
             const float h = -v[1] * v[0];
@@ -526,7 +493,8 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         sgz[c] = g;
         sxz[c] = x;
     };
-    auto stx_ = [&](int lz, int lx, int c, const float* v) {
+    auto stx_ = [&](int lz, int lx, const float* v) {
+        const int c = lx * T::LZ + lz;
         float g = 0.f, x = 0.f;
         if (inside(lz, lx)) {
             const float h = -v[1] * v[0];

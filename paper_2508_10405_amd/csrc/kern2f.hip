@@ -33,13 +33,6 @@ struct F2 {
     static_assert(NP % NTHREADS == 0, "tile must hold a multiple of 256 nodes");
 };
 
-// Visit tile-local nodes (lz, lx) of rows [z0, z1) x cols [x0, x1).
-template <typename Fn>
-__device__ __forceinline__ void rect(int z0, int z1, int x0, int x1, Fn f) {
-    const int nzr = z1 - z0, n = nzr * (x1 - x0);
-    for (int e = threadIdx.x; e < n; e += NTHREADS) f(z0 + e % nzr, x0 + e / nzr);
-}
-
 // ---------------------------------------------------------------------------
 // Forward step: background (+ scattered for BORN, + replay store for SEG)
 // ---------------------------------------------------------------------------
@@ -49,6 +42,9 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
 {
     using T = F2<BZ, BX>;
     constexpr int R = T::R;
+    constexpr int K = BORN ? 2 : 1;
+    using CZ = Cells<-7, BZ + 14, 0, BX>;            // p on the tile columns, rows -7 .. BZ+6
+    using CX = Cells<0, BZ, -7, 14, 0, 0, 7, BX>;    // p on cols -7 .. -1 and BX .. BX+6
     __shared__ float sp[T::NPL];
     __shared__ float sq[BORN ? T::NPL : 1];
     __shared__ float svz[T::NVZ];
@@ -59,41 +55,53 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
     const int4 tl = tiles[tix];
     const DSlot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
-    const int nz = S.n[0], nx = S.n[1];
+    const int nz = S.n[0], nx = S.n[1], npml = S.npml;
     const long long ldz = S.ldz;
+    // Every global load before the first barrier, from addresses that are
+    // valid for any cell (element 0 where a cell is outside the grid or a
+    // CPML memory is not needed outside the strips).
     // pointwise loads of the pressure update
-    float kk[R], lk[R];
+    float kk[R], lk[R], ph0[R], ph1[R], et0[R], et1[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int e = threadIdx.x + NTHREADS * r;
         const int gz = z0 + e % BZ, gx = x0 + e / BZ;
-        const long long i = (gz < nz && gx < nx) ? gx * ldz + gz : 0;
+        const bool in = gz < nz && gx < nx;
+        const long long i = in ? gx * ldz + gz : 0;
+        const long long iz = in && in_pml(gz, nz, npml) ? i : 0;
+        const long long ix = in && in_pml(gx, nx, npml) ? i : 0;
         kk[r] = S.kdt[i];
-        if (BORN) lk[r] = S.dlnk[i];
+        ph0[r] = S.phi[0][iz];
+        ph1[r] = S.phi[1][ix];
+        if (BORN) {
+            lk[r] = S.dlnk[i];
+            et0[r] = S.eta[0][iz];
+            et1[r] = S.eta[1][ix];
+        }
     }
     // velocity regions: v_z on rows -4 .. BZ+2 of the tile columns, v_x on
-    // cols -4 .. BX+2 of the tile rows; their pointwise inputs are loaded now
+    // cols -4 .. BX+2 of the tile rows, with their pointwise inputs
     constexpr int NZR = BZ + 7, NXR = BZ;
     constexpr int RZ = (T::NVZ + NTHREADS - 1) / NTHREADS;
     constexpr int RX = (T::NVX + NTHREADS - 1) / NTHREADS;
-    float zv[RZ], zb[RZ], zw[RZ], zr0[RZ], zr1[RZ];
-    float xv[RX], xb[RX], xw[RX], xr0[RX], xr1[RX];
-    long long zi[RZ], xi_[RX];
-    bool zin[RZ], xin_[RX];
+    float zv[RZ], zb[RZ], zw[RZ], zr0[RZ], zr1[RZ], zps[RZ], zxs[RZ];
+    float xv[RX], xb[RX], xw[RX], xr0[RX], xr1[RX], xps[RX], xxs[RX];
 #pragma unroll
     for (int t = 0; t < RZ; ++t) {
         const int e = threadIdx.x + NTHREADS * t;
         const int lz = -4 + e % NZR, lx = e / NZR;
         const int gz = z0 + lz, gx = x0 + lx;
-        zin[t] = e < T::NVZ && (unsigned)gz < (unsigned)nz && gx < nx;
-        const long long i = zin[t] ? gx * ldz + gz : 0;
-        zi[t] = i;
+        const bool in = e < T::NVZ && (unsigned)gz < (unsigned)nz && gx < nx;
+        const long long i = in ? gx * ldz + gz : 0;
+        const long long im = in && in_pml(gz, nz, npml) ? i : 0;
         zv[t] = S.v[0][i];
         zb[t] = S.bdt[0][i];
+        zps[t] = S.psi[0][im];
         if (BORN) {
             zw[t] = S.w[0][i];
             zr0[t] = S.dlnr[i];
-            zr1[t] = S.dlnr[(zin[t] && gz + 1 < nz) ? i + 1 : i];
+            zr1[t] = S.dlnr[(in && gz + 1 < nz) ? i + 1 : i];
+            zxs[t] = S.xi[0][im];
         }
     }
 #pragma unroll
@@ -101,29 +109,39 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
         const int e = threadIdx.x + NTHREADS * t;
         const int lz = e % NXR, lx = -4 + e / NXR;
         const int gz = z0 + lz, gx = x0 + lx;
-        xin_[t] = e < T::NVX && gz < nz && (unsigned)gx < (unsigned)nx;
-        const long long i = xin_[t] ? gx * ldz + gz : 0;
-        xi_[t] = i;
+        const bool in = e < T::NVX && gz < nz && (unsigned)gx < (unsigned)nx;
+        const long long i = in ? gx * ldz + gz : 0;
+        const long long im = in && in_pml(gx, nx, npml) ? i : 0;
         xv[t] = S.v[1][i];
         xb[t] = S.bdt[1][i];
+        xps[t] = S.psi[1][im];
         if (BORN) {
             xw[t] = S.w[1][i];
             xr0[t] = S.dlnr[i];
-            xr1[t] = S.dlnr[(xin_[t] && gx + 1 < nx) ? i + ldz : i];
+            xr1[t] = S.dlnr[(in && gx + 1 < nx) ? i + ldz : i];
+            xxs[t] = S.xi[1][im];
         }
     }
-    // stage p (and dp) of the previous step on the cross
-    auto ldp = [&](int lz, int lx) {
-        const int gz = z0 + lz, gx = x0 + lx;
-        const bool in = (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx;
-        const long long i = gx * ldz + gz;
-        const int c = (lx + 7) * T::PZ + lz + 7;
-        sp[c] = in ? S.p[i] : 0.f;
-        if (BORN) sq[c] = in ? S.q[i] : 0.f;
+    // p (and dp) of the previous step on the cross
+    auto inside = [&](int lz, int lx) {
+        return (unsigned)(z0 + lz) < (unsigned)nz && (unsigned)(x0 + lx) < (unsigned)nx;
     };
-    rect(-7, BZ + 7, 0, BX, ldp);
-    rect(0, BZ, -7, 0, ldp);
-    rect(0, BZ, BX, BX + 7, ldp);
+    auto ldp = [&](int lz, int lx, float* v) {
+        const long long i = inside(lz, lx) ? (x0 + lx) * ldz + (z0 + lz) : 0;
+        v[0] = S.p[i];
+        if (BORN) v[1] = S.q[i];
+    };
+    auto stp = [&](int lz, int lx, const float* v) {
+        const bool in = inside(lz, lx);
+        const int c = (lx + 7) * T::PZ + lz + 7;
+        sp[c] = in ? v[0] : 0.f;
+        if (BORN) sq[c] = in ? v[1] : 0.f;
+    };
+    float hz[CZ::IT][K], hx[CX::IT][K];
+    CZ::load(ldp, hz);
+    CX::load(ldp, hx);
+    CZ::store(stp, hz);
+    CX::store(stp, hx);
     __syncthreads();
     const gfloat* achz = S.cpml[0];
     const gfloat* bchz = S.cpml[0] + nz;
@@ -135,21 +153,21 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
         const int e = threadIdx.x + NTHREADS * t;
         if (e >= T::NVZ) continue;
         const int lz = -4 + e % NZR, lx = e / NZR;
-        const int gz = z0 + lz;
+        const int gz = z0 + lz, gx = x0 + lx;
         const int cv = lx * T::VZ + lz + 4;
-        if (!zin[t]) {
+        if (!((unsigned)gz < (unsigned)nz && gx < nx)) {
             svz[cv] = 0.f;
             if (BORN) swz[cv] = 0.f;
             continue;
         }
         const bool own = lz >= 0 && lz < BZ;
-        const long long i = zi[t];
+        const long long i = gx * ldz + gz;
         const int c = (lx + 7) * T::PZ + lz + 7;
         const float az = achz[gz];
         const float bz = zb[t];
         float g = d_half(sp, c, 1, C.c[0]);
         if (az != 0.f) {
-            const float ps = fmaf(bchz[gz], S.psi[0][i], az * g);
+            const float ps = fmaf(bchz[gz], zps[t], az * g);
             if (own) S.psin[0][i] = ps;
             g = g + ps;
         }
@@ -163,7 +181,7 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
         if (BORN) {
             float gq = d_half(sq, c, 1, C.c[0]);
             if (az != 0.f) {
-                const float ps = fmaf(bchz[gz], S.xi[0][i], az * gq);
+                const float ps = fmaf(bchz[gz], zxs[t], az * gq);
                 if (own) S.xin[0][i] = ps;
                 gq = gq + ps;
             }
@@ -177,21 +195,21 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
         const int e = threadIdx.x + NTHREADS * t;
         if (e >= T::NVX) continue;
         const int lz = e % NXR, lx = -4 + e / NXR;
-        const int gx = x0 + lx;
+        const int gz = z0 + lz, gx = x0 + lx;
         const int cv = (lx + 4) * BZ + lz;
-        if (!xin_[t]) {
+        if (!(gz < nz && (unsigned)gx < (unsigned)nx)) {
             svx[cv] = 0.f;
             if (BORN) swx[cv] = 0.f;
             continue;
         }
         const bool own = lx >= 0 && lx < BX;
-        const long long i = xi_[t];
+        const long long i = gx * ldz + gz;
         const int c = (lx + 7) * T::PZ + lz + 7;
         const float ax = achx[gx];
         const float bx = xb[t];
         float g = d_half(sp, c, T::PZ, C.c[1]);
         if (ax != 0.f) {
-            const float ps = fmaf(bchx[gx], S.psi[1][i], ax * g);
+            const float ps = fmaf(bchx[gx], xps[t], ax * g);
             if (own) S.psin[1][i] = ps;
             g = g + ps;
         }
@@ -205,7 +223,7 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
         if (BORN) {
             float gq = d_half(sq, c, T::PZ, C.c[1]);
             if (ax != 0.f) {
-                const float ps = fmaf(bchx[gx], S.xi[1][i], ax * gq);
+                const float ps = fmaf(bchx[gx], xxs[t], ax * gq);
                 if (own) S.xin[1][i] = ps;
                 gq = gq + ps;
             }
@@ -235,12 +253,12 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
         float ez = d_node(svz, cz, 1, C.c[0]);
         float ex = d_node(svx, cx, BZ, C.c[1]);
         if (az != 0.f) {
-            const float ph = fmaf(bciz[gz], S.phi[0][i], az * ez);
+            const float ph = fmaf(bciz[gz], ph0[r], az * ez);
             S.phi[0][i] = ph;
             ez = ez + ph;
         }
         if (ax != 0.f) {
-            const float ph = fmaf(bcix[gx], S.phi[1][i], ax * ex);
+            const float ph = fmaf(bcix[gx], ph1[r], ax * ex);
             S.phi[1][i] = ph;
             ex = ex + ph;
         }
@@ -255,12 +273,12 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
             float fz = d_node(swz, cz, 1, C.c[0]);
             float fx = d_node(swx, cx, BZ, C.c[1]);
             if (az != 0.f) {
-                const float ph = fmaf(bciz[gz], S.eta[0][i], az * fz);
+                const float ph = fmaf(bciz[gz], et0[r], az * fz);
                 S.etan[0][i] = ph;
                 fz = fz + ph;
             }
             if (ax != 0.f) {
-                const float ph = fmaf(bcix[gx], S.eta[1][i], ax * fx);
+                const float ph = fmaf(bcix[gx], et1[r], ax * fx);
                 S.etan[1][i] = ph;
                 fx = fx + ph;
             }
@@ -283,8 +301,10 @@ k2f_adj(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
 {
     using T = F2<BZ, BX>;
     constexpr int R = T::R;
-    __shared__ float sez[(BZ + 14) * BX];     // e~_z rows -7 .. BZ+6
-    __shared__ float sex[BZ * (BX + 14)];     // e~_x cols -7 .. BX+6
+    using CZ = Cells<-7, BZ + 14, 0, BX>;      // e~_z rows -7 .. BZ+6 of the tile columns
+    using CX = Cells<0, BZ, -7, BX + 14>;      // e~_x cols -7 .. BX+6 of the tile rows
+    __shared__ float sez[(BZ + 14) * BX];
+    __shared__ float sex[BZ * (BX + 14)];
     __shared__ float sgz[T::NVZ];             // g~_z rows -4 .. BZ+2
     __shared__ float sgx[T::NVX];             // g~_x cols -4 .. BX+2
     __shared__ float sxz[T::NVZ];             // -dv_z v~_z (lnrho imaging)
@@ -293,80 +313,97 @@ k2f_adj(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
     const int4 tl = tiles[tix];
     const DSlot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
-    const int nz = S.n[0], nx = S.n[1];
+    const int nz = S.n[0], nx = S.n[1], npml = S.npml;
     const long long ldz = S.ldz;
     const gfloat* __restrict__ segz = S.seg + (long long)sstep * 3 * S.npts;
     const gfloat* __restrict__ segx = segz + S.npts;
     const gfloat* __restrict__ segq = segz + 2 * S.npts;
-    float pt[R], kk[R], gk[R], qn[R], gr[R];
+    // Every global load before the first barrier (clamped addresses, as in
+    // the forward step).
+    float pt[R], kk[R], gk[R], qn[R], gr[R], et0[R], et1[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int e = threadIdx.x + NTHREADS * r;
         const int gz = z0 + e % BZ, gx = x0 + e / BZ;
-        const long long i = (gz < nz && gx < nx) ? gx * ldz + gz : 0;
+        const bool in = gz < nz && gx < nx;
+        const long long i = in ? gx * ldz + gz : 0;
         pt[r] = S.q[i];
         kk[r] = S.kdt[i];
         gk[r] = S.gk[i];
         qn[r] = segq[i];
         gr[r] = S.gr[i];
+        et0[r] = S.eta[0][in && in_pml(gz, nz, npml) ? i : 0];
+        et1[r] = S.eta[1][in && in_pml(gx, nx, npml) ? i : 0];
     }
     const gfloat* aciz = S.cpml[0] + 2 * nz;
     const gfloat* bciz = S.cpml[0] + 3 * nz;
     const gfloat* acix = S.cpml[1] + 2 * nx;
     const gfloat* bcix = S.cpml[1] + 3 * nx;
-    // velocity regions (as in the forward step): pointwise inputs loaded now
+    // velocity regions (as in the forward step) with their pointwise inputs
     constexpr int NZR = BZ + 7, NXR = BZ;
     constexpr int RZ = (T::NVZ + NTHREADS - 1) / NTHREADS;
     constexpr int RX = (T::NVX + NTHREADS - 1) / NTHREADS;
-    float zv[RZ], zb[RZ], zs[RZ], xv[RX], xb[RX], xs[RX];
-    long long zi[RZ], xi_[RX];
-    bool zin[RZ], xin_[RX];
+    float zv[RZ], zb[RZ], zs[RZ], zc[RZ], xv[RX], xb[RX], xs[RX], xc[RX];
 #pragma unroll
     for (int t = 0; t < RZ; ++t) {
         const int e = threadIdx.x + NTHREADS * t;
         const int lz = -4 + e % NZR, lx = e / NZR;
         const int gz = z0 + lz, gx = x0 + lx;
-        zin[t] = e < T::NVZ && (unsigned)gz < (unsigned)nz && gx < nx;
-        const long long i = zin[t] ? gx * ldz + gz : 0;
-        zi[t] = i;
+        const bool in = e < T::NVZ && (unsigned)gz < (unsigned)nz && gx < nx;
+        const long long i = in ? gx * ldz + gz : 0;
         zv[t] = S.w[0][i];
         zb[t] = S.bdt[0][i];
         zs[t] = segz[i];
+        zc[t] = S.xi[0][in && in_pml(gz, nz, npml) ? i : 0];
     }
 #pragma unroll
     for (int t = 0; t < RX; ++t) {
         const int e = threadIdx.x + NTHREADS * t;
         const int lz = e % NXR, lx = -4 + e / NXR;
         const int gz = z0 + lz, gx = x0 + lx;
-        xin_[t] = e < T::NVX && gz < nz && (unsigned)gx < (unsigned)nx;
-        const long long i = xin_[t] ? gx * ldz + gz : 0;
-        xi_[t] = i;
+        const bool in = e < T::NVX && gz < nz && (unsigned)gx < (unsigned)nx;
+        const long long i = in ? gx * ldz + gz : 0;
         xv[t] = S.w[1][i];
         xb[t] = S.bdt[1][i];
         xs[t] = segx[i];
+        xc[t] = S.xi[1][in && in_pml(gx, nx, npml) ? i : 0];
     }
-    rect(-7, BZ + 7, 0, BX, [&](int lz, int lx) {
+    // e~_a on the crosses: dt kappa, p~, the CPML coefficient and phi~
+    auto inside = [&](int lz, int lx) {
+        return (unsigned)(z0 + lz) < (unsigned)nz && (unsigned)(x0 + lx) < (unsigned)nx;
+    };
+    auto lde_z = [&](int lz, int lx, float* v) {
         const int gz = z0 + lz, gx = x0 + lx;
-        float e = 0.f;
-        if ((unsigned)gz < (unsigned)nz && gx < nx) {
-            const long long i = gx * ldz + gz;
-            const float qt = -S.kdt[i] * S.q[i];
-            const float a = aciz[gz];
-            e = a != 0.f ? qt + a * (S.eta[0][i] + qt) : qt;
-        }
-        sez[lx * (BZ + 14) + lz + 7] = e;
-    });
-    rect(0, BZ, -7, BX + 7, [&](int lz, int lx) {
+        const bool in = inside(lz, lx);
+        const long long i = in ? gx * ldz + gz : 0;
+        v[0] = S.kdt[i];
+        v[1] = S.q[i];
+        v[2] = aciz[in ? gz : 0];
+        v[3] = S.eta[0][in && in_pml(gz, nz, npml) ? i : 0];
+    };
+    auto lde_x = [&](int lz, int lx, float* v) {
         const int gz = z0 + lz, gx = x0 + lx;
+        const bool in = inside(lz, lx);
+        const long long i = in ? gx * ldz + gz : 0;
+        v[0] = S.kdt[i];
+        v[1] = S.q[i];
+        v[2] = acix[in ? gx : 0];
+        v[3] = S.eta[1][in && in_pml(gx, nx, npml) ? i : 0];
+    };
+    auto ete = [&](bool in, const float* v) {
         float e = 0.f;
-        if (gz < nz && (unsigned)gx < (unsigned)nx) {
-            const long long i = gx * ldz + gz;
-            const float qt = -S.kdt[i] * S.q[i];
-            const float a = acix[gx];
-            e = a != 0.f ? qt + a * (S.eta[1][i] + qt) : qt;
+        if (in) {
+            const float qt = -v[0] * v[1];
+            const float a = v[2];
+            e = a != 0.f ? qt + a * (v[3] + qt) : qt;
         }
-        sex[(lx + 7) * BZ + lz] = e;
-    });
+        return e;
+    };
+    float hz[CZ::IT][4], hx[CX::IT][4];
+    CZ::load(lde_z, hz);
+    CX::load(lde_x, hx);
+    CZ::store([&](int lz, int lx, const float* v) { sez[lx * (BZ + 14) + lz + 7] = ete(inside(lz, lx), v); }, hz);
+    CX::store([&](int lz, int lx, const float* v) { sex[(lx + 7) * BZ + lz] = ete(inside(lz, lx), v); }, hx);
     __syncthreads();
     const gfloat* achz = S.cpml[0];
     const gfloat* bchz = S.cpml[0] + nz;
@@ -378,21 +415,21 @@ k2f_adj(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
         const int e = threadIdx.x + NTHREADS * t;
         if (e >= T::NVZ) continue;
         const int lz = -4 + e % NZR, lx = e / NZR;
-        const int gz = z0 + lz;
+        const int gz = z0 + lz, gx = x0 + lx;
         const int cv = lx * T::VZ + lz + 4;
-        if (!zin[t]) {
+        if (!((unsigned)gz < (unsigned)nz && gx < nx)) {
             sgz[cv] = 0.f;
             sxz[cv] = 0.f;
             continue;
         }
         const bool own = lz >= 0 && lz < BZ;
-        const long long i = zi[t];
+        const long long i = gx * ldz + gz;
         const float vo = zv[t];
         const float b = zb[t];
         const float a = achz[gz];
         float chi = 0.f;
         if (a != 0.f) {
-            chi = S.xi[0][i];
+            chi = zc[t];
             if (!flag) chi = bchz[gz] * (chi + (-b * vo));
             if (own) S.xin[0][i] = chi;
         }
@@ -407,21 +444,21 @@ k2f_adj(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
         const int e = threadIdx.x + NTHREADS * t;
         if (e >= T::NVX) continue;
         const int lz = e % NXR, lx = -4 + e / NXR;
-        const int gx = x0 + lx;
+        const int gz = z0 + lz, gx = x0 + lx;
         const int cv = (lx + 4) * BZ + lz;
-        if (!xin_[t]) {
+        if (!(gz < nz && (unsigned)gx < (unsigned)nx)) {
             sgx[cv] = 0.f;
             sxx[cv] = 0.f;
             continue;
         }
         const bool own = lx >= 0 && lx < BX;
-        const long long i = xi_[t];
+        const long long i = gx * ldz + gz;
         const float vo = xv[t];
         const float b = xb[t];
         const float a = achx[gx];
         float chi = 0.f;
         if (a != 0.f) {
-            chi = S.xi[1][i];
+            chi = xc[t];
             if (!flag) chi = bchx[gx] * (chi + (-b * vo));
             if (own) S.xin[1][i] = chi;
         }
@@ -445,8 +482,8 @@ k2f_adj(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
         const float az = aciz[gz], ax = acix[gx];
         if (az != 0.f || ax != 0.f) {
             const float qt = -kk[r] * pt[r];
-            if (az != 0.f) S.etan[0][i] = bciz[gz] * (S.eta[0][i] + qt);
-            if (ax != 0.f) S.etan[1][i] = bcix[gx] * (S.eta[1][i] + qt);
+            if (az != 0.f) S.etan[0][i] = bciz[gz] * (et0[r] + qt);
+            if (ax != 0.f) S.etan[1][i] = bcix[gx] * (et1[r] + qt);
         }
         S.gk[i] = gk[r] + qn[r] * (-kk[r] * pt[r]);
         const float xz1 = gz > 0 ? sxz[cz - 1] : 0.f;
