@@ -5,11 +5,15 @@
 // plane come from an LDS tile with the 4-node halo each derivative needs; the
 // y-derivative comes from a queue of the eight neighbouring planes kept in
 // registers, so every value of the staged field is read from memory once per
-// march.  Arrays read pointwise are loaded before the LDS barrier of each
-// plane.  The phases and the CPML bookkeeping are those of the 2D kernels
-// (section 2 of the paper for V/P, eq. scattereqln for the Born sources,
-// appendix A for the adjoint phases A/B); the replay buffer holds
-// dv_z, dv_x, dv_y, q per step.
+// march.  On every plane a thread issues all of its global loads at once --
+// the queue's new front, the arrays it reads pointwise, the CPML memories of
+// its nodes and its share of the halo -- from addresses that are always valid
+// (element 0 of the array, or of the plane, where a value lies outside the
+// grid or outside the absorbing strips), so no branch separates them; values
+// are combined and written to LDS only after that.  The phases and the CPML
+// bookkeeping are those of the 2D kernels (section 2 of the paper for V/P,
+// eq. scattereqln for the Born sources, appendix A for the adjoint phases
+// A/B); the replay buffer holds dv_z, dv_x, dv_y, q per step.
 #include "common.h"
 #include "kernels.h"
 
@@ -25,15 +29,6 @@ struct Tile3 {
     static_assert(NP % NTHREADS == 0, "tile must hold a multiple of 256 nodes");
 };
 
-template <int LZ, typename F>
-__device__ __forceinline__ void region3(int zl, int zh, int xl, int xh, F f) {
-    const int nzr = zh - zl, n = nzr * (xh - xl);
-    for (int e = threadIdx.x; e < n; e += NTHREADS) {
-        const int lz = zl + e % nzr, lx = xl + e / nzr;
-        f(lz, lx, lx * LZ + lz);
-    }
-}
-
 // y-derivative from a queue Q[m] = f(y + m - off): the staggered difference
 // sum_k c_k (Q[3+k] - Q[4-k]) is G_y (off = 3) or D_y (off = 4).
 __device__ __forceinline__ float d_queue(const float* Q, const float* ck) {
@@ -48,13 +43,13 @@ __device__ __forceinline__ float d_queue(const float* Q, const float* ck) {
     using T = Tile3<BZ, BX>;                                                  \
     constexpr int R = T::R;                                                   \
     const int4 tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];                  \
-    const DSlot& S = slots[tl.x];                                              \
+    const DSlot& S = slots[tl.x];                                             \
     const int z0 = tl.y, x0 = tl.z, y0 = tl.w;                                \
-    const int nz = S.n[0], nx = S.n[1], ny = S.n[2];                          \
+    const int nz = S.n[0], nx = S.n[1], ny = S.n[2], npml = S.npml;           \
     const long long sx = S.sx, sy = S.sy;                                     \
     const int y1 = y0 + BY < ny ? y0 + BY : ny;                               \
     int lzr[R], lxr[R];                                                       \
-    bool ok[R];                                                               \
+    bool ok[R], pz[R], px[R];                                                 \
     long long ib[R];                                                          \
     _Pragma("unroll") for (int r = 0; r < R; ++r) {                           \
         const int e = threadIdx.x + NTHREADS * r;                             \
@@ -62,7 +57,23 @@ __device__ __forceinline__ float d_queue(const float* Q, const float* ck) {
         lxr[r] = e / BZ;                                                      \
         ok[r] = z0 + lzr[r] < nz && x0 + lxr[r] < nx;                         \
         ib[r] = ok[r] ? (x0 + lxr[r]) * sx + (z0 + lzr[r]) : 0;               \
-    }
+        pz[r] = ok[r] && in_pml(z0 + lzr[r], nz, npml);                       \
+        px[r] = ok[r] && in_pml(x0 + lxr[r], nx, npml);                       \
+    }                                                                         \
+    auto inside = [&](int lz, int lx) {                                       \
+        return (unsigned)(z0 + lz - HW) < (unsigned)nz &&                     \
+               (unsigned)(x0 + lx - HW) < (unsigned)nx;                       \
+    };                                                                        \
+    /* index of LDS cell (lz, lx) on plane offset py, element py outside */   \
+    auto cidx = [&](int lz, int lx, long long py) -> long long {              \
+        return (inside(lz, lx) ? (x0 + lx - HW) * sx + (z0 + lz - HW) : 0) + py; \
+    };                                                                        \
+    /* value of f at node r of plane y, zero outside the grid */              \
+    auto at = [&](const gfloat* f, int r, int y) -> float {                   \
+        const bool v = ok[r] && (unsigned)y < (unsigned)ny;                   \
+        const float x = f[v ? ib[r] + y * sy : 0];                            \
+        return v ? x : 0.f;                                                   \
+    };
 
 // ---------------------------------------------------------------------------
 // V phase
@@ -72,12 +83,12 @@ __global__ void __launch_bounds__(NTHREADS)
 k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
 {
     TILE3_SETUP
+    constexpr int K = BORN ? 2 : 1;
+    using CZ = Cells<0, 2 * HW, HW, BX, HW, BZ>;        // both z-halo strips
+    using CX = Cells<HW, BZ, 0, 2 * HW, 0, 0, HW, BX>;  // both x-halo strips
     __shared__ float sp[T::NL];
     __shared__ float sq[BORN ? T::NL : 1];
     float Qp[R][8], Qq[R][8];
-    auto at = [&](const gfloat* f, int r, int y) -> float {
-        return (ok[r] && (unsigned)y < (unsigned)ny) ? f[ib[r] + y * sy] : 0.f;
-    };
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -94,7 +105,9 @@ k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     gfloat* __restrict__ seg = S.seg + (long long)sstep * 4 * S.npts;
     for (int y = y0; y < y1; ++y) {
         const long long py = y * sy;
+        const bool py_ = in_pml(y, ny, npml);
         float vz[R], vx[R], vy[R], bz[R], bx[R], by[R], wz[R], wx[R], wy[R], r0[R], r1z[R], r1x[R], r1y[R];
+        float m0[R], m1[R], m2[R], n0[R], n1[R], n2[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
 #pragma unroll
@@ -111,6 +124,9 @@ k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             bz[r] = S.bdt[0][i];
             bx[r] = S.bdt[1][i];
             by[r] = S.bdt[2][i];
+            m0[r] = S.psi[0][pz[r] ? i : 0];
+            m1[r] = S.psi[1][px[r] ? i : 0];
+            m2[r] = S.psi[2][ok[r] && py_ ? i : 0];
             if (BORN) {
                 const int gz = z0 + lzr[r], gx = x0 + lxr[r];
                 wz[r] = S.w[0][i];
@@ -120,8 +136,25 @@ k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
                 r1z[r] = S.dlnr[gz + 1 < nz ? i + 1 : i];
                 r1x[r] = S.dlnr[gx + 1 < nx ? i + sx : i];
                 r1y[r] = S.dlnr[y + 1 < ny ? i + sy : i];
+                n0[r] = S.xi[0][pz[r] ? i : 0];
+                n1[r] = S.xi[1][px[r] ? i : 0];
+                n2[r] = S.xi[2][ok[r] && py_ ? i : 0];
             }
         }
+        auto ld = [&](int lz, int lx, float* v) {
+            const long long i = cidx(lz, lx, py);
+            v[0] = S.p[i];
+            if (BORN) v[1] = S.q[i];
+        };
+        auto st = [&](int lz, int lx, const float* v) {
+            const int c = lx * T::LZ + lz;
+            const bool in = inside(lz, lx);
+            sp[c] = in ? v[0] : 0.f;
+            if (BORN) sq[c] = in ? v[1] : 0.f;
+        };
+        float hz[CZ::IT][K], hx[CX::IT][K];
+        CZ::load(ld, hz);
+        CX::load(ld, hx);
         __syncthreads();   // the previous plane's LDS tile is no longer read
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -129,17 +162,8 @@ k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             sp[c] = Qp[r][3];
             if (BORN) sq[c] = Qq[r][3];
         }
-        auto ld = [&](int lz, int lx, int c) {
-            const int gz = z0 + lz - HW, gx = x0 + lx - HW;
-            const bool in = (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx;
-            const long long i = gx * sx + gz + py;
-            sp[c] = in ? S.p[i] : 0.f;
-            if (BORN) sq[c] = in ? S.q[i] : 0.f;
-        };
-        region3<T::LZ>(0, HW, HW, HW + BX, ld);
-        region3<T::LZ>(HW + BZ, T::LZ, HW, HW + BX, ld);
-        region3<T::LZ>(HW, HW + BZ, 0, HW, ld);
-        region3<T::LZ>(HW, HW + BZ, HW + BX, T::LX, ld);
+        CZ::store(st, hz);
+        CX::store(st, hx);
         __syncthreads();
         const float ay = achy[y];
 #pragma unroll
@@ -153,17 +177,17 @@ k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             float gxp = d_half(sp, c, T::LZ, C.c[1]);
             float gyp = d_queue(Qp[r], C.c[2]);
             if (az != 0.f) {
-                const float ps = fmaf(bchz[gz], S.psi[0][i], az * gzp);
+                const float ps = fmaf(bchz[gz], m0[r], az * gzp);
                 S.psi[0][i] = ps;
                 gzp = gzp + ps;
             }
             if (ax != 0.f) {
-                const float ps = fmaf(bchx[gx], S.psi[1][i], ax * gxp);
+                const float ps = fmaf(bchx[gx], m1[r], ax * gxp);
                 S.psi[1][i] = ps;
                 gxp = gxp + ps;
             }
             if (ay != 0.f) {
-                const float ps = fmaf(bchy[y], S.psi[2][i], ay * gyp);
+                const float ps = fmaf(bchy[y], m2[r], ay * gyp);
                 S.psi[2][i] = ps;
                 gyp = gyp + ps;
             }
@@ -183,17 +207,17 @@ k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
                 float gxq = d_half(sq, c, T::LZ, C.c[1]);
                 float gyq = d_queue(Qq[r], C.c[2]);
                 if (az != 0.f) {
-                    const float ps = fmaf(bchz[gz], S.xi[0][i], az * gzq);
+                    const float ps = fmaf(bchz[gz], n0[r], az * gzq);
                     S.xi[0][i] = ps;
                     gzq = gzq + ps;
                 }
                 if (ax != 0.f) {
-                    const float ps = fmaf(bchx[gx], S.xi[1][i], ax * gxq);
+                    const float ps = fmaf(bchx[gx], n1[r], ax * gxq);
                     S.xi[1][i] = ps;
                     gxq = gxq + ps;
                 }
                 if (ay != 0.f) {
-                    const float ps = fmaf(bchy[y], S.xi[2][i], ay * gyq);
+                    const float ps = fmaf(bchy[y], n2[r], ay * gyq);
                     S.xi[2][i] = ps;
                     gyq = gyq + ps;
                 }
@@ -213,14 +237,14 @@ __global__ void __launch_bounds__(NTHREADS)
 k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
 {
     TILE3_SETUP
+    constexpr int K = BORN ? 2 : 1;
+    using CZ = Cells<0, T::LZ, HW, BX>;   // v_z (and w_z) with the z-halo
+    using CX = Cells<HW, BZ, 0, T::LX>;   // v_x (and w_x) with the x-halo
     __shared__ float svz[T::NL];
     __shared__ float svx[T::NL];
     __shared__ float swz[BORN ? T::NL : 1];
     __shared__ float swx[BORN ? T::NL : 1];
     float Qv[R][8], Qw[R][8];
-    auto at = [&](const gfloat* f, int r, int y) -> float {
-        return (ok[r] && (unsigned)y < (unsigned)ny) ? f[ib[r] + y * sy] : 0.f;
-    };
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -238,7 +262,8 @@ k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     gfloat* __restrict__ seg = S.seg + (long long)sstep * 4 * S.npts + 3 * S.npts;
     for (int y = y0; y < y1; ++y) {
         const long long py = y * sy;
-        float pp[R], kk[R], qq[R], lk[R];
+        const bool py_ = in_pml(y, ny, npml);
+        float pp[R], kk[R], qq[R], lk[R], m0[R], m1[R], m2[R], n0[R], n1[R], n2[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
 #pragma unroll
@@ -251,28 +276,41 @@ k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             const long long i = ib[r] + py;
             pp[r] = S.p[i];
             kk[r] = S.kdt[i];
+            m0[r] = S.phi[0][pz[r] ? i : 0];
+            m1[r] = S.phi[1][px[r] ? i : 0];
+            m2[r] = S.phi[2][ok[r] && py_ ? i : 0];
             if (BORN) {
                 qq[r] = S.q[i];
                 lk[r] = S.dlnk[i];
+                n0[r] = S.eta[0][pz[r] ? i : 0];
+                n1[r] = S.eta[1][px[r] ? i : 0];
+                n2[r] = S.eta[2][ok[r] && py_ ? i : 0];
             }
         }
+        float hz[CZ::IT][K], hx[CX::IT][K];
+        CZ::load([&](int lz, int lx, float* v) {
+            const long long i = cidx(lz, lx, py);
+            v[0] = S.v[0][i];
+            if (BORN) v[1] = S.w[0][i];
+        }, hz);
+        CX::load([&](int lz, int lx, float* v) {
+            const long long i = cidx(lz, lx, py);
+            v[0] = S.v[1][i];
+            if (BORN) v[1] = S.w[1][i];
+        }, hx);
         __syncthreads();
-        auto lz_ = [&](int lz, int lx, int c) {
-            const int gz = z0 + lz - HW, gx = x0 + lx - HW;
-            const bool in = (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx;
-            const long long i = gx * sx + gz + py;
-            svz[c] = in ? S.v[0][i] : 0.f;
-            if (BORN) swz[c] = in ? S.w[0][i] : 0.f;
-        };
-        auto lx_ = [&](int lz, int lx, int c) {
-            const int gz = z0 + lz - HW, gx = x0 + lx - HW;
-            const bool in = (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx;
-            const long long i = gx * sx + gz + py;
-            svx[c] = in ? S.v[1][i] : 0.f;
-            if (BORN) swx[c] = in ? S.w[1][i] : 0.f;
-        };
-        region3<T::LZ>(0, T::LZ, HW, HW + BX, lz_);
-        region3<T::LZ>(HW, HW + BZ, 0, T::LX, lx_);
+        CZ::store([&](int lz, int lx, const float* v) {
+            const int c = lx * T::LZ + lz;
+            const bool in = inside(lz, lx);
+            svz[c] = in ? v[0] : 0.f;
+            if (BORN) swz[c] = in ? v[1] : 0.f;
+        }, hz);
+        CX::store([&](int lz, int lx, const float* v) {
+            const int c = lx * T::LZ + lz;
+            const bool in = inside(lz, lx);
+            svx[c] = in ? v[0] : 0.f;
+            if (BORN) swx[c] = in ? v[1] : 0.f;
+        }, hx);
         __syncthreads();
         const float ay = aciy[y];
 #pragma unroll
@@ -286,17 +324,17 @@ k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             float ex = d_node(svx, c, T::LZ, C.c[1]);
             float ey = d_queue(Qv[r], C.c[2]);
             if (az != 0.f) {
-                const float ph = fmaf(bciz[gz], S.phi[0][i], az * ez);
+                const float ph = fmaf(bciz[gz], m0[r], az * ez);
                 S.phi[0][i] = ph;
                 ez = ez + ph;
             }
             if (ax != 0.f) {
-                const float ph = fmaf(bcix[gx], S.phi[1][i], ax * ex);
+                const float ph = fmaf(bcix[gx], m1[r], ax * ex);
                 S.phi[1][i] = ph;
                 ex = ex + ph;
             }
             if (ay != 0.f) {
-                const float ph = fmaf(bciy[y], S.phi[2][i], ay * ey);
+                const float ph = fmaf(bciy[y], m2[r], ay * ey);
                 S.phi[2][i] = ph;
                 ey = ey + ph;
             }
@@ -311,17 +349,17 @@ k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
                 float fx = d_node(swx, c, T::LZ, C.c[1]);
                 float fy = d_queue(Qw[r], C.c[2]);
                 if (az != 0.f) {
-                    const float ph = fmaf(bciz[gz], S.eta[0][i], az * fz);
+                    const float ph = fmaf(bciz[gz], n0[r], az * fz);
                     S.eta[0][i] = ph;
                     fz = fz + ph;
                 }
                 if (ax != 0.f) {
-                    const float ph = fmaf(bcix[gx], S.eta[1][i], ax * fx);
+                    const float ph = fmaf(bcix[gx], n1[r], ax * fx);
                     S.eta[1][i] = ph;
                     fx = fx + ph;
                 }
                 if (ay != 0.f) {
-                    const float ph = fmaf(bciy[y], S.eta[2][i], ay * fy);
+                    const float ph = fmaf(bciy[y], n2[r], ay * fy);
                     S.eta[2][i] = ph;
                     fy = fy + ph;
                 }
@@ -333,13 +371,15 @@ k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint phase A (transpose of P), see kern2d.hip
+// Adjoint phase A (transpose of P), as in the 2D kernels
 // ---------------------------------------------------------------------------
 template <int BZ, int BX, int BY>
 __global__ void __launch_bounds__(NTHREADS)
 k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
 {
     TILE3_SETUP
+    using CZ = Cells<0, 2 * HW, HW, BX, HW, BZ>;        // both z-halo strips
+    using CX = Cells<HW, BZ, 0, 2 * HW, 0, 0, HW, BX>;  // both x-halo strips
     __shared__ float sez[T::NL];
     __shared__ float sex[T::NL];
     const gfloat* aciz = S.cpml[0] + 2 * nz;
@@ -352,88 +392,117 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const gfloat* achy = S.cpml[2];
     const gfloat* bchy = S.cpml[2] + ny;
     const gfloat* __restrict__ segq = S.seg + (long long)sstep * 4 * S.npts + 3 * S.npts;
-    // E[m] = e~_y(y + m - 3);  QT[m] = q~(y + m), q~ = -dt kappa p~
+    // E[m] = e~_y(y + m - 3);  QT[m] = q~(y + m), q~ = -dt kappa p~.  The
+    // loads of plane y are kdt, p~ and (inside the y-strips) phi~_y.
     float E[R][8], QT[R][5];
-    auto qt_at = [&](int r, int y) -> float {
-        if (!ok[r] || (unsigned)y >= (unsigned)ny) return 0.f;
-        const long long i = ib[r] + y * sy;
-        return -S.kdt[i] * S.q[i];
+    auto front = [&](int r, int y, float& fk, float& fq, float& fe) {
+        const bool v = ok[r] && (unsigned)y < (unsigned)ny;
+        const long long i = v ? ib[r] + y * sy : 0;
+        fk = S.kdt[i];
+        fq = S.q[i];
+        fe = S.eta[2][v && in_pml(y, ny, npml) ? i : 0];
     };
-    auto ey_of = [&](int r, int y, float qt) -> float {
-        if (!ok[r] || (unsigned)y >= (unsigned)ny) return 0.f;
-        const float a = aciy[y];
-        return a != 0.f ? qt + a * (S.eta[2][ib[r] + y * sy] + qt) : qt;
+    auto combine = [&](int r, int y, float fk, float fq, float fe, float& qt, float& ey) {
+        const bool v = ok[r] && (unsigned)y < (unsigned)ny;
+        qt = 0.f;
+        ey = 0.f;
+        if (v) {
+            qt = -fk * fq;
+            const float a = aciy[y];
+            ey = a != 0.f ? qt + a * (fe + qt) : qt;
+        }
     };
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+    for (int r = 0; r < R; ++r) {
+        float fk[7], fq[7], fe[7];
+#pragma unroll
+        for (int m = 0; m < 7; ++m) front(r, y0 - 3 + m, fk[m], fq[m], fe[m]);
 #pragma unroll
         for (int m = 0; m < 7; ++m) {
-            const int yy = y0 - 3 + m;
-            const float qt = qt_at(r, yy);
-            E[r][m + 1] = ey_of(r, yy, qt);
+            float qt;
+            combine(r, y0 - 3 + m, fk[m], fq[m], fe[m], qt, E[r][m + 1]);
             if (m >= 3) QT[r][m - 2] = qt;
         }
+    }
+    // loads of e~ at a halo cell: dt kappa, p~, the CPML coefficient, phi~
+    auto ldz_ = [&](int lz, int lx, long long py, float* v) {
+        const int gz = z0 + lz - HW;
+        const long long i = cidx(lz, lx, py);
+        const bool in = inside(lz, lx);
+        v[0] = S.kdt[i];
+        v[1] = S.q[i];
+        v[2] = aciz[in ? gz : 0];
+        v[3] = S.eta[0][in && in_pml(gz, nz, npml) ? i : py];
+    };
+    auto ldx_ = [&](int lz, int lx, long long py, float* v) {
+        const int gx = x0 + lx - HW;
+        const long long i = cidx(lz, lx, py);
+        const bool in = inside(lz, lx);
+        v[0] = S.kdt[i];
+        v[1] = S.q[i];
+        v[2] = acix[in ? gx : 0];
+        v[3] = S.eta[1][in && in_pml(gx, nx, npml) ? i : py];
+    };
+    auto ete = [&](bool in, const float* v) {
+        float e = 0.f;
+        if (in) {
+            const float qt = -v[0] * v[1];
+            e = v[2] != 0.f ? qt + v[2] * (v[3] + qt) : qt;
+        }
+        return e;
+    };
     for (int y = y0; y < y1; ++y) {
         const long long py = y * sy;
-        float vz[R], vx[R], vy[R], gk[R], qn[R];
+        const bool py_ = in_pml(y, ny, npml);
+        float vz[R], vx[R], vy[R], gk[R], qn[R], e0[R], e1[R], fk[R], fq[R], fe[R];
+        float c0[R], c1[R], c2[R], b0[R], b1[R], b2[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-#pragma unroll
-            for (int m = 0; m < 7; ++m) E[r][m] = E[r][m + 1];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) QT[r][m] = QT[r][m + 1];
-            const float qt = qt_at(r, y + 4);
-            QT[r][4] = qt;
-            E[r][7] = ey_of(r, y + 4, qt);
+            front(r, y + 4, fk[r], fq[r], fe[r]);
             const long long i = ib[r] + py;
             vz[r] = S.w[0][i];
             vx[r] = S.w[1][i];
             vy[r] = S.w[2][i];
             gk[r] = S.gk[i];
             qn[r] = segq[i];
+            e0[r] = S.eta[0][pz[r] ? i : 0];
+            e1[r] = S.eta[1][px[r] ? i : 0];
+            if (!flag) {
+                const long long jz = pz[r] ? i : 0, jx = px[r] ? i : 0, jy = ok[r] && py_ ? i : 0;
+                c0[r] = S.xi[0][jz];
+                c1[r] = S.xi[1][jx];
+                c2[r] = S.xi[2][jy];
+                b0[r] = S.bdt[0][jz];
+                b1[r] = S.bdt[1][jx];
+                b2[r] = S.bdt[2][jy];
+            }
         }
+        float hz[CZ::IT][4], hx[CX::IT][4];
+        CZ::load([&](int lz, int lx, float* v) { ldz_(lz, lx, py, v); }, hz);
+        CX::load([&](int lz, int lx, float* v) { ldx_(lz, lx, py, v); }, hx);
         __syncthreads();
         // interior from the queue, halos from memory
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+#pragma unroll
+            for (int m = 0; m < 7; ++m) E[r][m] = E[r][m + 1];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) QT[r][m] = QT[r][m + 1];
+            combine(r, y + 4, fk[r], fq[r], fe[r], QT[r][4], E[r][7]);
             const int c = (lxr[r] + HW) * T::LZ + lzr[r] + HW;
             const float qt = QT[r][0];
             float ez = qt, ex = qt;
             if (ok[r]) {
                 const int gz = z0 + lzr[r], gx = x0 + lxr[r];
                 const float az = aciz[gz], ax = acix[gx];
-                if (az != 0.f) ez = qt + az * (S.eta[0][ib[r] + py] + qt);
-                if (ax != 0.f) ex = qt + ax * (S.eta[1][ib[r] + py] + qt);
+                if (az != 0.f) ez = qt + az * (e0[r] + qt);
+                if (ax != 0.f) ex = qt + ax * (e1[r] + qt);
             }
             sez[c] = ez;
             sex[c] = ex;
         }
-        auto hz = [&](int lz, int lx, int c) {
-            const int gz = z0 + lz - HW, gx = x0 + lx - HW;
-            float e = 0.f;
-            if ((unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx) {
-                const long long i = gx * sx + gz + py;
-                const float qt = -S.kdt[i] * S.q[i];
-                const float a = aciz[gz];
-                e = a != 0.f ? qt + a * (S.eta[0][i] + qt) : qt;
-            }
-            sez[c] = e;
-        };
-        auto hx = [&](int lz, int lx, int c) {
-            const int gz = z0 + lz - HW, gx = x0 + lx - HW;
-            float e = 0.f;
-            if ((unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx) {
-                const long long i = gx * sx + gz + py;
-                const float qt = -S.kdt[i] * S.q[i];
-                const float a = acix[gx];
-                e = a != 0.f ? qt + a * (S.eta[1][i] + qt) : qt;
-            }
-            sex[c] = e;
-        };
-        region3<T::LZ>(0, HW, HW, HW + BX, hz);
-        region3<T::LZ>(HW + BZ, T::LZ, HW, HW + BX, hz);
-        region3<T::LZ>(HW, HW + BZ, 0, HW, hx);
-        region3<T::LZ>(HW, HW + BZ, HW + BX, T::LX, hx);
+        CZ::store([&](int lz, int lx, const float* v) { sez[lx * T::LZ + lz] = ete(inside(lz, lx), v); }, hz);
+        CX::store([&](int lz, int lx, const float* v) { sex[lx * T::LZ + lz] = ete(inside(lz, lx), v); }, hx);
         __syncthreads();
         const float hyc = achy[y];
 #pragma unroll
@@ -444,9 +513,9 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             const int c = (lxr[r] + HW) * T::LZ + lzr[r] + HW;
             if (!flag) {
                 const float a = achz[gz], b = achx[gx];
-                if (a != 0.f) S.xi[0][i] = bchz[gz] * (S.xi[0][i] + (-S.bdt[0][i] * vz[r]));
-                if (b != 0.f) S.xi[1][i] = bchx[gx] * (S.xi[1][i] + (-S.bdt[1][i] * vx[r]));
-                if (hyc != 0.f) S.xi[2][i] = bchy[y] * (S.xi[2][i] + (-S.bdt[2][i] * vy[r]));
+                if (a != 0.f) S.xi[0][i] = bchz[gz] * (c0[r] + (-b0[r] * vz[r]));
+                if (b != 0.f) S.xi[1][i] = bchx[gx] * (c1[r] + (-b1[r] * vx[r]));
+                if (hyc != 0.f) S.xi[2][i] = bchy[y] * (c2[r] + (-b2[r] * vy[r]));
             }
             S.gk[i] = gk[r] + qn[r] * QT[r][0];
             S.w[0][i] = vz[r] - d_half(sez, c, 1, C.c[0]);
@@ -457,15 +526,21 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint phase B (transpose of V), see kern2d.hip
+// Adjoint phase B (transpose of V), as in the 2D kernels; the products
+// -dv_a v~_a of the lnrho image are formed while staging (z, x) or kept from
+// the previous plane (y).
 // ---------------------------------------------------------------------------
 template <int BZ, int BX, int BY>
 __global__ void __launch_bounds__(NTHREADS)
 k3_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
 {
     TILE3_SETUP
+    using CZ = Cells<0, T::LZ, HW, BX>;   // g~_z with the z-halo
+    using CX = Cells<HW, BZ, 0, T::LX>;   // g~_x with the x-halo
     __shared__ float sgz[T::NL];
     __shared__ float sgx[T::NL];
+    __shared__ float sxz[T::NL];
+    __shared__ float sxx[T::NL];
     const gfloat* achz = S.cpml[0];
     const gfloat* achx = S.cpml[1];
     const gfloat* achy = S.cpml[2];
@@ -478,85 +553,122 @@ k3_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const gfloat* __restrict__ segz = S.seg + (long long)sstep * 4 * S.npts;
     const gfloat* __restrict__ segx = segz + S.npts;
     const gfloat* __restrict__ segy = segz + 2 * S.npts;
-    // Gq[m] = g~_y(y + m - 4);  Xp = -dv_y v~_y on the previous plane
+    // Gq[m] = g~_y(y + m - 4) from dt b_y, v~_y and (inside the y-strips) chi_y;
+    // Xp = -dv_y v~_y on the previous plane
     float Gq[R][8], Xp[R];
-    auto gy_at = [&](int r, int y) -> float {
-        if (!ok[r] || (unsigned)y >= (unsigned)ny) return 0.f;
-        const long long i = ib[r] + y * sy;
-        const float h = -S.bdt[2][i] * S.w[2][i];
+    auto front = [&](int r, int y, float& fb, float& fw, float& fc) {
+        const bool v = ok[r] && (unsigned)y < (unsigned)ny;
+        const long long i = v ? ib[r] + y * sy : 0;
+        fb = S.bdt[2][i];
+        fw = S.w[2][i];
+        fc = S.xi[2][v && in_pml(y, ny, npml) ? i : 0];
+    };
+    auto gy_of = [&](int r, int y, float fb, float fw, float fc) -> float {
+        if (!(ok[r] && (unsigned)y < (unsigned)ny)) return 0.f;
+        const float h = -fb * fw;
         const float a = achy[y];
-        return a != 0.f ? h + a * (S.xi[2][i] + h) : h;
+        return a != 0.f ? h + a * (fc + h) : h;
     };
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+        float fb[7], fw[7], fc[7];
 #pragma unroll
-        for (int m = 0; m < 7; ++m) Gq[r][m + 1] = gy_at(r, y0 - 4 + m);
-        Xp[r] = 0.f;
-        if (ok[r] && y0 > 0) {
-            const long long i = ib[r] + (y0 - 1) * sy;
-            Xp[r] = -segy[i] * S.w[2][i];
-        }
+        for (int m = 0; m < 7; ++m) front(r, y0 - 4 + m, fb[m], fw[m], fc[m]);
+        const bool pv = ok[r] && y0 > 0;
+        const long long ip = pv ? ib[r] + (y0 - 1) * sy : 0;
+        const float s_ = segy[ip], w_ = S.w[2][ip];
+#pragma unroll
+        for (int m = 0; m < 7; ++m) Gq[r][m + 1] = gy_of(r, y0 - 4 + m, fb[m], fw[m], fc[m]);
+        Xp[r] = pv ? -s_ * w_ : 0.f;
     }
+    // loads of g~_a and of the image product at a cell: v~_a, dt b_a, the
+    // CPML coefficient, chi_a and dv_a (on the rows / columns whose product
+    // is needed)
+    auto ldz_ = [&](int lz, int lx, long long py, float* v) {
+        const int gz = z0 + lz - HW;
+        const bool in = inside(lz, lx);
+        const long long i = cidx(lz, lx, py);
+        v[0] = S.w[0][i];
+        v[1] = S.bdt[0][i];
+        v[2] = achz[in ? gz : 0];
+        v[3] = S.xi[0][in && in_pml(gz, nz, npml) ? i : py];
+        v[4] = segz[in && lz >= HW - 1 && lz < HW + BZ ? i : py];
+    };
+    auto ldx_ = [&](int lz, int lx, long long py, float* v) {
+        const int gx = x0 + lx - HW;
+        const bool in = inside(lz, lx);
+        const long long i = cidx(lz, lx, py);
+        v[0] = S.w[1][i];
+        v[1] = S.bdt[1][i];
+        v[2] = achx[in ? gx : 0];
+        v[3] = S.xi[1][in && in_pml(gx, nx, npml) ? i : py];
+        v[4] = segx[in && lx >= HW - 1 && lx < HW + BX ? i : py];
+    };
     for (int y = y0; y < y1; ++y) {
         const long long py = y * sy;
-        float pt[R], gr[R], xz0[R], xz1[R], xx0[R], xx1[R], xy0[R];
+        const bool py_ = in_pml(y, ny, npml);
+        float pt[R], gr[R], sy_[R], wy_[R], kk[R], e0[R], e1[R], e2[R], fb[R], fw[R], fc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-#pragma unroll
-            for (int m = 0; m < 7; ++m) Gq[r][m] = Gq[r][m + 1];
-            Gq[r][7] = gy_at(r, y + 3);
-            const int gz = z0 + lzr[r], gx = x0 + lxr[r];
+            front(r, y + 3, fb[r], fw[r], fc[r]);
             const long long i = ib[r] + py;
+            const bool any = pz[r] || px[r] || (ok[r] && py_);
             pt[r] = S.q[i];
             gr[r] = S.gr[i];
-            xz0[r] = -segz[i] * S.w[0][i];
-            xz1[r] = (ok[r] && gz > 0) ? -segz[i - 1] * S.w[0][i - 1] : 0.f;
-            xx0[r] = -segx[i] * S.w[1][i];
-            xx1[r] = (ok[r] && gx > 0) ? -segx[i - sx] * S.w[1][i - sx] : 0.f;
-            xy0[r] = -segy[i] * S.w[2][i];
+            sy_[r] = segy[i];
+            wy_[r] = S.w[2][i];
+            kk[r] = S.kdt[any ? i : 0];
+            e0[r] = S.eta[0][pz[r] ? i : 0];
+            e1[r] = S.eta[1][px[r] ? i : 0];
+            e2[r] = S.eta[2][ok[r] && py_ ? i : 0];
         }
+        float hz[CZ::IT][5], hx[CX::IT][5];
+        CZ::load([&](int lz, int lx, float* v) { ldz_(lz, lx, py, v); }, hz);
+        CX::load([&](int lz, int lx, float* v) { ldx_(lz, lx, py, v); }, hx);
         __syncthreads();
-        auto lz_ = [&](int lz, int lx, int c) {
-            const int gz = z0 + lz - HW, gx = x0 + lx - HW;
-            float g = 0.f;
-            if ((unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx) {
-                const long long i = gx * sx + gz + py;
-                const float h = -S.bdt[0][i] * S.w[0][i];
-                const float a = achz[gz];
-                g = a != 0.f ? h + a * (S.xi[0][i] + h) : h;
+        CZ::store([&](int lz, int lx, const float* v) {
+            const int c = lx * T::LZ + lz;
+            float g = 0.f, x = 0.f;
+            if (inside(lz, lx)) {
+                const float h = -v[1] * v[0];
+                g = v[2] != 0.f ? h + v[2] * (v[3] + h) : h;
+                if (lz >= HW - 1 && lz < HW + BZ) x = -v[4] * v[0];
             }
             sgz[c] = g;
-        };
-        auto lx_ = [&](int lz, int lx, int c) {
-            const int gz = z0 + lz - HW, gx = x0 + lx - HW;
-            float g = 0.f;
-            if ((unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx) {
-                const long long i = gx * sx + gz + py;
-                const float h = -S.bdt[1][i] * S.w[1][i];
-                const float a = achx[gx];
-                g = a != 0.f ? h + a * (S.xi[1][i] + h) : h;
+            sxz[c] = x;
+        }, hz);
+        CX::store([&](int lz, int lx, const float* v) {
+            const int c = lx * T::LZ + lz;
+            float g = 0.f, x = 0.f;
+            if (inside(lz, lx)) {
+                const float h = -v[1] * v[0];
+                g = v[2] != 0.f ? h + v[2] * (v[3] + h) : h;
+                if (lx >= HW - 1 && lx < HW + BX) x = -v[4] * v[0];
             }
             sgx[c] = g;
-        };
-        region3<T::LZ>(0, T::LZ, HW, HW + BX, lz_);
-        region3<T::LZ>(HW, HW + BZ, 0, T::LX, lx_);
+            sxx[c] = x;
+        }, hx);
         __syncthreads();
         const float ay = aciy[y];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+#pragma unroll
+            for (int m = 0; m < 7; ++m) Gq[r][m] = Gq[r][m + 1];
+            Gq[r][7] = gy_of(r, y + 3, fb[r], fw[r], fc[r]);
             if (!ok[r]) continue;
             const int gz = z0 + lzr[r], gx = x0 + lxr[r];
             const long long i = ib[r] + py;
             const int c = (lxr[r] + HW) * T::LZ + lzr[r] + HW;
             const float az = aciz[gz], ax = acix[gx];
             if (az != 0.f || ax != 0.f || ay != 0.f) {
-                const float qt = -S.kdt[i] * pt[r];
-                if (az != 0.f) S.eta[0][i] = bciz[gz] * (S.eta[0][i] + qt);
-                if (ax != 0.f) S.eta[1][i] = bcix[gx] * (S.eta[1][i] + qt);
-                if (ay != 0.f) S.eta[2][i] = bciy[y] * (S.eta[2][i] + qt);
+                const float qt = -kk[r] * pt[r];
+                if (az != 0.f) S.eta[0][i] = bciz[gz] * (e0[r] + qt);
+                if (ax != 0.f) S.eta[1][i] = bcix[gx] * (e1[r] + qt);
+                if (ay != 0.f) S.eta[2][i] = bciy[y] * (e2[r] + qt);
             }
-            S.gr[i] = gr[r] + ((0.5f * (xz0[r] + xz1[r]) + 0.5f * (xx0[r] + xx1[r])) + 0.5f * (xy0[r] + Xp[r]));
-            Xp[r] = xy0[r];
+            const float xy0 = -sy_[r] * wy_[r];
+            S.gr[i] = gr[r] + ((0.5f * (sxz[c] + sxz[c - 1]) + 0.5f * (sxx[c] + sxx[c - T::LZ])) + 0.5f * (xy0 + Xp[r]));
+            Xp[r] = xy0;
             const float dz = d_node(sgz, c, 1, C.c[0]);
             const float dx = d_node(sgx, c, T::LZ, C.c[1]);
             const float dy = d_queue(Gq[r], C.c[2]);
