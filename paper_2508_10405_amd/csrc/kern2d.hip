@@ -70,8 +70,14 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
     const long long ldz = S.ldz;
-    // pointwise loads
+    const int npml = S.npml;
+    const gfloat* achz = S.cpml[0];
+    const gfloat* bchz = S.cpml[0] + nz;
+    const gfloat* achx = S.cpml[1];
+    const gfloat* bchx = S.cpml[1] + nx;
+    // pointwise loads, CPML coefficients and (inside the strips) memories
     float vz[R], vx[R], bz[R], bx[R], wz[R], wx[R], r0[R], r1z[R], r1x[R];
+    float az[R], ax[R], cz[R], cx[R], m0[R], m1[R], n0[R], n1[R];
     bool ok[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -80,11 +86,21 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const int gz = z0 + lz, gx = x0 + lx;
         ok[r] = gz < nz && gx < nx;
         const long long i = ok[r] ? gx * ldz + gz : 0;
+        const long long iz = ok[r] && in_pml(gz, nz, npml) ? i : 0;
+        const long long ix = ok[r] && in_pml(gx, nx, npml) ? i : 0;
         vz[r] = S.v[0][i];
         vx[r] = S.v[1][i];
         bz[r] = S.bdt[0][i];
         bx[r] = S.bdt[1][i];
+        az[r] = achz[ok[r] ? gz : 0];
+        ax[r] = achx[ok[r] ? gx : 0];
+        cz[r] = bchz[ok[r] ? gz : 0];
+        cx[r] = bchx[ok[r] ? gx : 0];
+        m0[r] = S.psi[0][iz];
+        m1[r] = S.psi[1][ix];
         if (BORN) {
+            n0[r] = S.xi[0][iz];
+            n1[r] = S.xi[1][ix];
             wz[r] = S.w[0][i];
             wx[r] = S.w[1][i];
             r0[r] = S.dlnr[i];
@@ -113,10 +129,6 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     RZ::store(st, hz);
     RX::store(st, hx);
     __syncthreads();
-    const gfloat* achz = S.cpml[0];
-    const gfloat* bchz = S.cpml[0] + nz;
-    const gfloat* achx = S.cpml[1];
-    const gfloat* bchx = S.cpml[1] + nx;
     gfloat* __restrict__ seg = S.seg + (long long)sstep * 3 * S.npts;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -126,16 +138,15 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const int gz = z0 + lz, gx = x0 + lx;
         const long long i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
-        const float az = achz[gz], ax = achx[gx];
         float gzp = d_half(sp, c, 1, C.c[0]);
         float gxp = d_half(sp, c, T::LZ, C.c[1]);
-        if (az != 0.f) {
-            const float ps = fmaf(bchz[gz], S.psi[0][i], az * gzp);
+        if (az[r] != 0.f) {
+            const float ps = fmaf(cz[r], m0[r], az[r] * gzp);
             S.psi[0][i] = ps;
             gzp = gzp + ps;
         }
-        if (ax != 0.f) {
-            const float ps = fmaf(bchx[gx], S.psi[1][i], ax * gxp);
+        if (ax[r] != 0.f) {
+            const float ps = fmaf(cx[r], m1[r], ax[r] * gxp);
             S.psi[1][i] = ps;
             gxp = gxp + ps;
         }
@@ -150,13 +161,13 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         if (BORN) {
             float gzq = d_half(sq, c, 1, C.c[0]);
             float gxq = d_half(sq, c, T::LZ, C.c[1]);
-            if (az != 0.f) {
-                const float ps = fmaf(bchz[gz], S.xi[0][i], az * gzq);
+            if (az[r] != 0.f) {
+                const float ps = fmaf(cz[r], n0[r], az[r] * gzq);
                 S.xi[0][i] = ps;
                 gzq = gzq + ps;
             }
-            if (ax != 0.f) {
-                const float ps = fmaf(bchx[gx], S.xi[1][i], ax * gxq);
+            if (ax[r] != 0.f) {
+                const float ps = fmaf(cx[r], n1[r], ax[r] * gxq);
                 S.xi[1][i] = ps;
                 gxq = gxq + ps;
             }
@@ -190,7 +201,13 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
     const long long ldz = S.ldz;
-    float pp[R], kk[R], qq[R], lk[R];
+    const int npml = S.npml;
+    const gfloat* aciz = S.cpml[0] + 2 * nz;
+    const gfloat* bciz = S.cpml[0] + 3 * nz;
+    const gfloat* acix = S.cpml[1] + 2 * nx;
+    const gfloat* bcix = S.cpml[1] + 3 * nx;
+    // pointwise loads, CPML coefficients and (inside the strips) memories
+    float pp[R], kk[R], qq[R], lk[R], az[R], ax[R], cz[R], cx[R], m0[R], m1[R], n0[R], n1[R];
     bool ok[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -199,11 +216,21 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const int gz = z0 + lz, gx = x0 + lx;
         ok[r] = gz < nz && gx < nx;
         const long long i = ok[r] ? gx * ldz + gz : 0;
+        const long long iz = ok[r] && in_pml(gz, nz, npml) ? i : 0;
+        const long long ix = ok[r] && in_pml(gx, nx, npml) ? i : 0;
         pp[r] = S.p[i];
         kk[r] = S.kdt[i];
+        az[r] = aciz[ok[r] ? gz : 0];
+        ax[r] = acix[ok[r] ? gx : 0];
+        cz[r] = bciz[ok[r] ? gz : 0];
+        cx[r] = bcix[ok[r] ? gx : 0];
+        m0[r] = S.phi[0][iz];
+        m1[r] = S.phi[1][ix];
         if (BORN) {
             qq[r] = S.q[i];
             lk[r] = S.dlnk[i];
+            n0[r] = S.eta[0][iz];
+            n1[r] = S.eta[1][ix];
         }
     }
     auto inside = [&](int lz, int lx) {
@@ -239,12 +266,8 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     RX::load(ldx_, hx);
     RZ::store(stz_, hz);
     RX::store(stx_, hx);
-    __syncthreads();
-    const gfloat* aciz = S.cpml[0] + 2 * nz;
-    const gfloat* bciz = S.cpml[0] + 3 * nz;
-    const gfloat* acix = S.cpml[1] + 2 * nx;
-    const gfloat* bcix = S.cpml[1] + 3 * nx;
     const float amp = S.src >= 0 ? S.src_amp[n] : 0.f;
+    __syncthreads();
     gfloat* __restrict__ seg = S.seg + (long long)sstep * 3 * S.npts + 2 * S.npts;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -254,16 +277,15 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const int gz = z0 + lz, gx = x0 + lx;
         const long long i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
-        const float az = aciz[gz], ax = acix[gx];
         float ez = d_node(svz, c, 1, C.c[0]);
         float ex = d_node(svx, c, T::LZ, C.c[1]);
-        if (az != 0.f) {
-            const float ph = fmaf(bciz[gz], S.phi[0][i], az * ez);
+        if (az[r] != 0.f) {
+            const float ph = fmaf(cz[r], m0[r], az[r] * ez);
             S.phi[0][i] = ph;
             ez = ez + ph;
         }
-        if (ax != 0.f) {
-            const float ph = fmaf(bcix[gx], S.phi[1][i], ax * ex);
+        if (ax[r] != 0.f) {
+            const float ph = fmaf(cx[r], m1[r], ax[r] * ex);
             S.phi[1][i] = ph;
             ex = ex + ph;
         }
@@ -277,13 +299,13 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         if (BORN) {
             float fz = d_node(swz, c, 1, C.c[0]);
             float fx = d_node(swx, c, T::LZ, C.c[1]);
-            if (az != 0.f) {
-                const float ph = fmaf(bciz[gz], S.eta[0][i], az * fz);
+            if (az[r] != 0.f) {
+                const float ph = fmaf(cz[r], n0[r], az[r] * fz);
                 S.eta[0][i] = ph;
                 fz = fz + ph;
             }
-            if (ax != 0.f) {
-                const float ph = fmaf(bcix[gx], S.eta[1][i], ax * fx);
+            if (ax[r] != 0.f) {
+                const float ph = fmaf(cx[r], n1[r], ax[r] * fx);
                 S.eta[1][i] = ph;
                 fx = fx + ph;
             }
@@ -349,8 +371,15 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             if (wx && v[4] != 0.f) ex = qt + v[4] * (v[5] + qt);
         }
     };
-    // the tile's own nodes need both components; q~ is kept for the image
+    const gfloat* achz = S.cpml[0];
+    const gfloat* bchz = S.cpml[0] + nz;
+    const gfloat* achx = S.cpml[1];
+    const gfloat* bchx = S.cpml[1] + nx;
+    // the tile's own nodes need both components; q~ is kept for the image.
+    // Unless this is the first reverse step, the pending chi update needs
+    // the CPML coefficients, chi and dt b at the node (inside the strips).
     float vz[R], vx[R], gk[R], qn[R], ev[R][6];
+    float hz_[R], hx_[R], cz[R], cx[R], xz[R], xx[R], bz[R], bx[R];
     bool ok[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -364,6 +393,18 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         gk[r] = S.gk[i];
         qn[r] = segq[i];
         lde(lz + HW, lx + HW, ev[r], true, true);
+        if (!flag) {
+            const long long iz = ok[r] && in_pml(gz, nz, npml) ? i : 0;
+            const long long ix = ok[r] && in_pml(gx, nx, npml) ? i : 0;
+            hz_[r] = achz[ok[r] ? gz : 0];
+            hx_[r] = achx[ok[r] ? gx : 0];
+            cz[r] = bchz[ok[r] ? gz : 0];
+            cx[r] = bchx[ok[r] ? gx : 0];
+            xz[r] = S.xi[0][iz];
+            xx[r] = S.xi[1][ix];
+            bz[r] = S.bdt[0][iz];
+            bx[r] = S.bdt[1][ix];
+        }
     }
     float hz[RZ::IT][6], hx[RX::IT][6];
     RZ::load([&](int lz, int lx, float* v) { lde(lz, lx, v, true, false); }, hz);
@@ -392,10 +433,6 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         sex[c] = ex;
     }, hx);
     __syncthreads();
-    const gfloat* achz = S.cpml[0];
-    const gfloat* bchz = S.cpml[0] + nz;
-    const gfloat* achx = S.cpml[1];
-    const gfloat* bchx = S.cpml[1] + nx;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (!ok[r]) continue;
@@ -405,9 +442,8 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const long long i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
         if (!flag) {
-            const float hz_ = achz[gz], hx_ = achx[gx];
-            if (hz_ != 0.f) S.xi[0][i] = bchz[gz] * (S.xi[0][i] + (-S.bdt[0][i] * vz[r]));
-            if (hx_ != 0.f) S.xi[1][i] = bchx[gx] * (S.xi[1][i] + (-S.bdt[1][i] * vx[r]));
+            if (hz_[r] != 0.f) S.xi[0][i] = cz[r] * (xz[r] + (-bz[r] * vz[r]));
+            if (hx_[r] != 0.f) S.xi[1][i] = cx[r] * (xx[r] + (-bx[r] * vx[r]));
         }
         S.gk[i] = gk[r] + qn[r] * qt[r];
         S.w[0][i] = vz[r] - d_half(sez, c, 1, C.c[0]);
@@ -442,7 +478,13 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const long long ldz = S.ldz;
     const gfloat* __restrict__ segz = S.seg + (long long)sstep * 3 * S.npts;
     const gfloat* __restrict__ segx = segz + S.npts;
-    float pt[R], gr[R];
+    const gfloat* aciz = S.cpml[0] + 2 * nz;
+    const gfloat* bciz = S.cpml[0] + 3 * nz;
+    const gfloat* acix = S.cpml[1] + 2 * nx;
+    const gfloat* bcix = S.cpml[1] + 3 * nx;
+    // pointwise loads; the phi~ update needs the CPML coefficients, phi~ and
+    // dt kappa at the node (inside the strips)
+    float pt[R], gr[R], az[R], ax[R], cz[R], cx[R], ez[R], ex[R], kk[R];
     bool ok[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -451,8 +493,16 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const int gz = z0 + lz, gx = x0 + lx;
         ok[r] = gz < nz && gx < nx;
         const long long i = ok[r] ? gx * ldz + gz : 0;
+        const bool mz = ok[r] && in_pml(gz, nz, npml), mx = ok[r] && in_pml(gx, nx, npml);
         pt[r] = S.q[i];
         gr[r] = S.gr[i];
+        az[r] = aciz[ok[r] ? gz : 0];
+        ax[r] = acix[ok[r] ? gx : 0];
+        cz[r] = bciz[ok[r] ? gz : 0];
+        cx[r] = bcix[ok[r] ? gx : 0];
+        ez[r] = S.eta[0][mz ? i : 0];
+        ex[r] = S.eta[1][mx ? i : 0];
+        kk[r] = S.kdt[mz || mx ? i : 0];
     }
     const gfloat* achz = S.cpml[0];
     const gfloat* achx = S.cpml[1];
@@ -510,10 +560,6 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     RZ::store(stz_, hz);
     RX::store(stx_, hx);
     __syncthreads();
-    const gfloat* aciz = S.cpml[0] + 2 * nz;
-    const gfloat* bciz = S.cpml[0] + 3 * nz;
-    const gfloat* acix = S.cpml[1] + 2 * nx;
-    const gfloat* bcix = S.cpml[1] + 3 * nx;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (!ok[r]) continue;
@@ -522,11 +568,10 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const int gz = z0 + lz, gx = x0 + lx;
         const long long i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
-        const float az = aciz[gz], ax = acix[gx];
-        if (az != 0.f || ax != 0.f) {
-            const float qt = -S.kdt[i] * pt[r];
-            if (az != 0.f) S.eta[0][i] = bciz[gz] * (S.eta[0][i] + qt);
-            if (ax != 0.f) S.eta[1][i] = bcix[gx] * (S.eta[1][i] + qt);
+        if (az[r] != 0.f || ax[r] != 0.f) {
+            const float qt = -kk[r] * pt[r];
+            if (az[r] != 0.f) S.eta[0][i] = cz[r] * (ez[r] + qt);
+            if (ax[r] != 0.f) S.eta[1][i] = cx[r] * (ex[r] + qt);
         }
         S.gr[i] = gr[r] + (0.5f * (sxz[c] + sxz[c - 1]) + 0.5f * (sxx[c] + sxx[c - T::LZ]));
         const float dz = d_node(sgz, c, 1, C.c[0]);
