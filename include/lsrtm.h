@@ -95,9 +95,10 @@ enum {
                                        checkpoints of all shots do not fit)     */
     LSRTM_OPT_FUSED = 7             /* 2D: 1 = one kernel per time step (the
                                        velocity and pressure updates fused,
-                                       double-buffered fields; default), 0 = a
-                                       velocity and a pressure kernel per step.
-                                       Both give identical results.             */
+                                       double-buffered fields), 0 = a velocity
+                                       and a pressure kernel per step (default;
+                                       faster on gfx950).  Both give identical
+                                       results; lsrtm_autotune tries both.      */
 };
 
 /* Create a context for one grid on one HIP stream (hipStream_t, may be 0).

@@ -140,7 +140,7 @@ struct lsrtm_ctx {
     int opt_timing = 0;
     long long opt_budget_mb = 0;
     int opt_ckg = 0;
-    int opt_fused = 1;
+    int opt_fused = 0;
     // timing
     std::vector<EvPair> evpool;
     size_t evused = 0;

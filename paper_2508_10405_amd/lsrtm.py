@@ -111,7 +111,7 @@ class Context:
 
     def __init__(self, n, h, nt, dt, npml=20, pml_R=1e-4, pml_f0=10.0, ckpt_every=0,
                  ckpt_dtype="f32", stream=None, shots_per_launch=0, tile=-1, graph=True,
-                 timing=False, mem_budget_mb=0, ckpt_per_group=False, fused=True):
+                 timing=False, mem_budget_mb=0, ckpt_per_group=False, fused=False):
         import torch
         L = lib()
         self._torch = torch

@@ -19,6 +19,7 @@ CASES3 = [
     # n (nz, nx, ny), nt, npml, nshot, uneven
     ((14, 17, 11), 70, 4, 2, True),
     ((70, 9, 38), 60, 5, 1, False),
+    ((17, 19, 21), 60, 0, 1, False),   # no absorbing strips
 ]
 
 

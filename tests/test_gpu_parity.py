@@ -32,6 +32,9 @@ CASES = [
     ((37, 45), 160, 4, 1, False),
     ((70, 83), 220, 20, 3, True),
     ((129, 17), 150, 6, 2, True),
+    # no absorbing strips (zero outside the grid), and strips one node wide
+    ((33, 40), 120, 0, 2, True),
+    ((20, 26), 100, 1, 1, False),
 ]
 
 
