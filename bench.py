@@ -15,8 +15,13 @@ iterations, bracketed by device synchronisation.
 value = grid-point updates per second of the two operator passes
         2 * (sum over shots of padded nodes) * nt * K / time   [Gpts/s]
 
+Launch configuration: 32 shots per launch group (balanced to 4 groups of 30)
+and 32 x 16 tiles, the autotuner's pick for this workload on MI355X;
+--shots-per-launch -1 --tile -1 tunes again.
+
 Also reported: the roofline of the dominant kernel (algorithmic bytes per
-launch / average launch time from HIP events, against the 8 TB/s HBM peak),
+launch / average kernel time, from events that the runtime stamps with the
+start and end of every 16th step's kernels, against the 8 TB/s HBM peak),
 the plain per-shot CG-iteration time (one launch per shot, measured on a
 sample of shots and scaled by the shot count), and the FP64 oracle timed on
 the host cores on a bounded sample.
@@ -124,14 +129,24 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a 1 GiB axpy (known traffic) for counter calibration")
-    ap.add_argument("--shots-per-launch", type=int, default=-1,
-                    help="-1 = autotuned together with the tile shape")
-    ap.add_argument("--tile", type=int, default=-1)
+    ap.add_argument("--shots-per-launch", type=int, default=None,
+                    help="shots per launch group; -1 = autotuned together with the tile shape "
+                         "(default: 32 for the 2D workloads, the autotuner's pick on MI355X; "
+                         "autotuned for config5)")
+    ap.add_argument("--tile", type=int, default=None,
+                    help="tile shape id; -1 = autotuned (default: 1 = 32 x 16 for the 2D workloads)")
     ap.add_argument("--tune-steps", type=int, default=24)
+    ap.add_argument("--nt", type=int, default=0,
+                    help="truncate the time axis to nt steps (0 = the workload's own); for counter "
+                         "profiles, whose per-launch figures do not depend on nt")
     ap.add_argument("--workload", default="config2", choices=("config2", "config3", "config5"),
                     help="config2 = the benchmark workload; config3 (uneven apertures) and config5 (3D, "
                          "BF16 checkpoints) are measured on request")
     args = ap.parse_args()
+    if args.shots_per_launch is None:
+        args.shots_per_launch = -1 if args.workload == "config5" else 32
+    if args.tile is None:
+        args.tile = -1 if args.workload == "config5" else 1
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the shot-parallel "
               "multi-GPU layout is not built", file=sys.stderr)
@@ -143,7 +158,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    w = {"config2": synth.config2, "config3": synth.config3, "config5": synth.config5}[args.workload]()
+    make = {"config2": synth.config2, "config3": synth.config3, "config5": synth.config5}[args.workload]
+    w = make(nt=args.nt) if args.nt > 0 else make()
     tag = f"{args.workload}_batched"
     nd = w.ndim
     ckdt = "bf16" if args.workload == "config5" else "f32"
@@ -261,7 +277,8 @@ def main():
                                            "nt=4000, 15 Hz, CGNR step = Born + migration",
                                 "config5": "3D LSRTM 400x400x200 @12.5 m (440x440x240 padded), 16 shots, "
                                            "80x80 receivers, nt=2500, 20 Hz, BF16 checkpoints, "
-                                           "CGNR step = Born + migration"}[args.workload],
+                                           "CGNR step = Born + migration"}[args.workload]
+                               + (f" [time axis truncated to nt={w.nt}]" if args.nt > 0 else ""),
                    "shots": w.nshot, "nt": w.nt, "padded_points": padded,
                    "shots_per_launch": sz["shots_per_launch"], "ckpt_every": sz["ckpt_every"],
                    "tile": list(lsrtm.tile_shape(nd, sz["tile"])), "ckpt_dtype": ckdt,

@@ -1,6 +1,7 @@
 // Device-side data structures shared by the kernels and the runtime.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 namespace lsrtm {
@@ -84,6 +85,16 @@ static_assert(sizeof(Slot) == sizeof(DSlot), "host and device slot layouts diffe
 
 // Device view of a slot table filled by the host.
 __host__ __device__ inline const DSlot* dev_slots(const Slot* s) { return reinterpret_cast<const DSlot*>(s); }
+
+// Launch kernel k on stream st.  With an event pair the runtime stamps the
+// kernel's own start and end into e0 / e1 (hipExtLaunchKernel), so the
+// elapsed time between them is the kernel's execution alone, without the
+// marker packets that a separate hipEventRecord would put around it.
+template <typename F, typename... A>
+inline void launch_k(F k, dim3 g, dim3 b, hipStream_t st, hipEvent_t e0, hipEvent_t e1, A... args) {
+    if (e0) hipExtLaunchKernelGGL(k, g, b, 0, st, e0, e1, 0, args...);
+    else k<<<g, b, 0, st>>>(args...);
+}
 
 // Receiver entry of a launch group.
 struct Rec {

@@ -500,15 +500,16 @@ k2f_adj(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
 // ---------------------------------------------------------------------------
 template <int BZ, int BX>
 static hipError_t launch2f_t(int kind, int ntiles, hipStream_t st, const Slot* slots,
-                             const int4* tiles, const Coef& C, int n, int sstep, int flag, const TileRec& tr)
+                             const int4* tiles, const Coef& C, int n, int sstep, int flag, const TileRec& tr,
+                            hipEvent_t e0, hipEvent_t e1)
 {
     dim3 g(ntiles), b(NTHREADS);
     const DSlot* ds = dev_slots(slots);
     switch (kind) {
-    case K_BG_V:   k2f_step<BZ, BX, false, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
-    case K_SEG_V:  k2f_step<BZ, BX, false, true><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
-    case K_BORN_V: k2f_step<BZ, BX, true, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
-    case K_ADJ_A:  k2f_adj<BZ, BX><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag, tr); break;
+    case K_BG_V:   launch_k(k2f_step<BZ, BX, false, false>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag, tr); break;
+    case K_SEG_V:  launch_k(k2f_step<BZ, BX, false, true>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag, tr); break;
+    case K_BORN_V: launch_k(k2f_step<BZ, BX, true, false>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag, tr); break;
+    case K_ADJ_A:  launch_k(k2f_adj<BZ, BX>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag, tr); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -517,19 +518,20 @@ static hipError_t launch2f_t(int kind, int ntiles, hipStream_t st, const Slot* s
 // Fused schedule: kind is the velocity-phase kind of the step (K_BG_V,
 // K_SEG_V, K_BORN_V) or K_ADJ_A for the adjoint step.
 hipError_t launch2f(int kind, int tile_id, int ntiles, hipStream_t st, const Slot* slots,
-                    const int4* tiles, const Coef& C, int n, int sstep, int flag, const TileRec& tr)
+                    const int4* tiles, const Coef& C, int n, int sstep, int flag, const TileRec& tr,
+                            hipEvent_t e0, hipEvent_t e1)
 {
     if (ntiles <= 0) return hipSuccess;
     switch (tile_id) {
-    case 0: return launch2f_t<32, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
-    case 1: return launch2f_t<32, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
-    case 2: return launch2f_t<32, 32>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
-    case 3: return launch2f_t<64, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
-    case 4: return launch2f_t<64, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
-    case 5: return launch2f_t<64, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
-    case 6: return launch2f_t<128, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
-    case 7: return launch2f_t<128, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
-    case 8: return launch2f_t<256, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr);
+    case 0: return launch2f_t<32, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr, e0, e1);
+    case 1: return launch2f_t<32, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr, e0, e1);
+    case 2: return launch2f_t<32, 32>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr, e0, e1);
+    case 3: return launch2f_t<64, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr, e0, e1);
+    case 4: return launch2f_t<64, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr, e0, e1);
+    case 5: return launch2f_t<64, 16>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr, e0, e1);
+    case 6: return launch2f_t<128, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr, e0, e1);
+    case 7: return launch2f_t<128, 8>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr, e0, e1);
+    case 8: return launch2f_t<256, 4>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, tr, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }

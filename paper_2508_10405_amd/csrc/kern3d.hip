@@ -680,19 +680,20 @@ k3_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
 // ---------------------------------------------------------------------------
 template <int BZ, int BX, int BY>
 static hipError_t launch3_t(int kind, int ntiles, hipStream_t st, const Slot* slots,
-                            const int4* tiles, const Coef& C, int n, int sstep, int flag)
+                            const int4* tiles, const Coef& C, int n, int sstep, int flag,
+                            hipEvent_t e0, hipEvent_t e1)
 {
     dim3 g(ntiles), b(NTHREADS);
     const DSlot* ds = dev_slots(slots);
     switch (kind) {
-    case K_BG_V:    k3_v<BZ, BX, BY, false, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
-    case K_BG_P:    k3_p<BZ, BX, BY, false, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
-    case K_SEG_V:   k3_v<BZ, BX, BY, false, true><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
-    case K_SEG_P:   k3_p<BZ, BX, BY, false, true><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
-    case K_BORN_V:  k3_v<BZ, BX, BY, true, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
-    case K_BORN_P:  k3_p<BZ, BX, BY, true, false><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
-    case K_ADJ_A:   k3_a<BZ, BX, BY><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
-    case K_ADJ_B:   k3_b<BZ, BX, BY><<<g, b, 0, st>>>(ds, tiles, C, n, sstep, flag); break;
+    case K_BG_V:    launch_k(k3_v<BZ, BX, BY, false, false>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag); break;
+    case K_BG_P:    launch_k(k3_p<BZ, BX, BY, false, false>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag); break;
+    case K_SEG_V:   launch_k(k3_v<BZ, BX, BY, false, true>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag); break;
+    case K_SEG_P:   launch_k(k3_p<BZ, BX, BY, false, true>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag); break;
+    case K_BORN_V:  launch_k(k3_v<BZ, BX, BY, true, false>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag); break;
+    case K_BORN_P:  launch_k(k3_p<BZ, BX, BY, true, false>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag); break;
+    case K_ADJ_A:   launch_k(k3_a<BZ, BX, BY>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag); break;
+    case K_ADJ_B:   launch_k(k3_b<BZ, BX, BY>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -702,16 +703,17 @@ const int kTiles3[][3] = {{64, 4, 32}, {64, 8, 32}, {64, 8, 64}, {32, 8, 64}, {1
 const int kNumTiles3 = 6;
 
 hipError_t launch3d(int kind, int tile_id, int ntiles, hipStream_t st, const Slot* slots,
-                    const int4* tiles, const Coef& C, int n, int sstep, int flag)
+                    const int4* tiles, const Coef& C, int n, int sstep, int flag,
+                    hipEvent_t e0, hipEvent_t e1)
 {
     if (ntiles <= 0) return hipSuccess;
     switch (tile_id) {
-    case 0: return launch3_t<64, 4, 32>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 1: return launch3_t<64, 8, 32>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 2: return launch3_t<64, 8, 64>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 3: return launch3_t<32, 8, 64>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 4: return launch3_t<128, 4, 64>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
-    case 5: return launch3_t<64, 4, 64>(kind, ntiles, st, slots, tiles, C, n, sstep, flag);
+    case 0: return launch3_t<64, 4, 32>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, e0, e1);
+    case 1: return launch3_t<64, 8, 32>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, e0, e1);
+    case 2: return launch3_t<64, 8, 64>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, e0, e1);
+    case 3: return launch3_t<32, 8, 64>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, e0, e1);
+    case 4: return launch3_t<128, 4, 64>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, e0, e1);
+    case 5: return launch3_t<64, 4, 64>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }

@@ -23,13 +23,18 @@ extern const int kTiles3[][3];
 extern const int kNumTiles3;
 
 hipError_t launch2d(int kind, int tile_id, int ntiles, hipStream_t st, const Slot* slots,
-                    const int4* tiles, const Coef& C, int n, int sstep, int flag, const TileRec& tr);
+                    const int4* tiles, const Coef& C, int n, int sstep, int flag, const TileRec& tr,
+                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch3d(int kind, int tile_id, int ntiles, hipStream_t st, const Slot* slots,
-                    const int4* tiles, const Coef& C, int n, int sstep, int flag);
+                    const int4* tiles, const Coef& C, int n, int sstep, int flag,
+                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Fused 2D schedule (kern2f.hip): one kernel per step; kind is K_BG_V,
 // K_SEG_V, K_BORN_V (whole forward step) or K_ADJ_A (whole adjoint step).
 hipError_t launch2f(int kind, int tile_id, int ntiles, hipStream_t st, const Slot* slots,
-                    const int4* tiles, const Coef& C, int n, int sstep, int flag, const TileRec& tr);
+                    const int4* tiles, const Coef& C, int n, int sstep, int flag, const TileRec& tr,
+                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// Every stencil launcher takes an optional event pair that receives the
+// kernel's start and end (timing).
 
 // Auxiliary kernels (aux.hip).
 hipError_t launch_fill(float* p, long long n, float v, hipStream_t st);

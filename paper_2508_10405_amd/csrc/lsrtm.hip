@@ -273,20 +273,29 @@ long long strip_count_h(const int N[3], int a, int Sd) {
 // ---------------------------------------------------------------------------
 // Timing
 // ---------------------------------------------------------------------------
-void tbeg(lsrtm_ctx* c, int cls) {
-    c->tpending = false;
-    if (!c->opt_timing || !c->tnow) return;
+// The next free event pair for a sample of class cls, or null when this step
+// is not sampled.
+EvPair* tpick(lsrtm_ctx* c, int cls) {
+    if (!c->opt_timing || !c->tnow) return nullptr;
     if (c->evused == c->evpool.size()) {
         EvPair e;
         if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) {
             c->opt_timing = 0;
-            return;
+            return nullptr;
         }
         c->evpool.push_back(e);
     }
     EvPair& e = c->evpool[c->evused];
     e.cls = cls;
-    (void)hipEventRecord(e.a, c->st);
+    return &e;
+}
+
+// Time a group of launches between two event records (checkpoints, receivers).
+void tbeg(lsrtm_ctx* c, int cls) {
+    c->tpending = false;
+    EvPair* e = tpick(c, cls);
+    if (!e) return;
+    (void)hipEventRecord(e->a, c->st);
     c->tpending = true;
 }
 
@@ -412,13 +421,15 @@ const Slot* desc(const Group& gr, int par) { return ((par & 1) && gr.d_alt) ? gr
 lsrtm_status stencil(lsrtm_ctx* c, Group& gr, int kind, int n, int sstep, int flag, const Slot* sl,
                      TileRec tr = TileRec{nullptr, nullptr, nullptr, nullptr}) {
     static const int cls_of[8] = {2, 3, 2, 3, 0, 1, 4, 5};
-    tbeg(c, cls_of[kind]);
+    // a sampled launch carries its own start / end events
+    EvPair* ev = tpick(c, cls_of[kind]);
+    hipEvent_t e0 = ev ? ev->a : nullptr, e1 = ev ? ev->b : nullptr;
     hipError_t e;
-    if (c->ndim == 3) e = launch3d(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag);
-    else if (c->fused) e = launch2f(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag, tr);
-    else e = launch2d(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag, tr);
-    tend(c);
+    if (c->ndim == 3) e = launch3d(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag, e0, e1);
+    else if (c->fused) e = launch2f(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag, tr, e0, e1);
+    else e = launch2d(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag, tr, e0, e1);
     if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "stencil launch (kind %d): %s", kind, hipGetErrorString(e));
+    if (ev) c->evused++;
     return LSRTM_OK;
 }
 
