@@ -165,7 +165,7 @@ def main():
     ckdt = "bf16" if args.workload == "config5" else "f32"
     log(f"[bench] workload {w.name}: {w.nshot} shots, nt={w.nt}, padded points {w.padded_points()}")
     ctx = lsrtm.context_for(w, shots_per_launch=max(0, args.shots_per_launch), tile=args.tile, timing=True,
-                            ckpt_dtype=ckdt)
+                            ckpt_dtype=ckdt, progress=nd == 3)
     if args.tile < 0:
         t0 = time.perf_counter()
         tuned = ctx.autotune(nsteps=args.tune_steps, groups=args.shots_per_launch < 0)

@@ -93,12 +93,15 @@ enum {
                                        them before each group's migration (the
                                        planner picks this by itself when the
                                        checkpoints of all shots do not fit)     */
-    LSRTM_OPT_FUSED = 7             /* 2D: 1 = one kernel per time step (the
+    LSRTM_OPT_FUSED = 7,            /* 2D: 1 = one kernel per time step (the
                                        velocity and pressure updates fused,
                                        double-buffered fields), 0 = a velocity
                                        and a pressure kernel per step (default;
                                        faster on gfx950).  Both give identical
                                        results; lsrtm_autotune tries both.      */
+    LSRTM_OPT_PROGRESS = 8          /* 1 = wait for every launch group's pass
+                                       and print one line per group to stderr
+                                       (long 3D passes); default 0              */
 };
 
 /* Create a context for one grid on one HIP stream (hipStream_t, may be 0).

@@ -141,6 +141,7 @@ struct lsrtm_ctx {
     long long opt_budget_mb = 0;
     int opt_ckg = 0;
     int opt_fused = 0;
+    int opt_progress = 0;
     // timing
     std::vector<EvPair> evpool;
     size_t evused = 0;
@@ -570,7 +571,7 @@ bool use_graph(const lsrtm_ctx* c) {
     return c->opt_graph && !c->opt_timing && (long long)c->groups.size() * c->g.nt <= 400000;
 }
 
-lsrtm_status run_group(lsrtm_ctx* c, Group& gr, int gi, int pass, float* d, bool write_ck) {
+lsrtm_status run_group_impl(lsrtm_ctx* c, Group& gr, int gi, int pass, float* d, bool write_ck) {
     if (!use_graph(c)) return run_direct(c, gr, pass, d, write_ck);
     CHK(build_tiles(c, gr, c->tile));
     if (!c->gst) {
@@ -606,6 +607,19 @@ lsrtm_status run_group(lsrtm_ctx* c, Group& gr, int gi, int pass, float* d, bool
     HIPCHK(c, hipGraphLaunch(exec, c->gst));
     HIPCHK(c, hipEventRecord(c->gout, c->gst));
     HIPCHK(c, hipStreamWaitEvent(c->st, c->gout, 0));
+    return LSRTM_OK;
+}
+
+// One pass of one launch group; with the progress option the pass is waited
+// for and reported on stderr.
+lsrtm_status run_group(lsrtm_ctx* c, Group& gr, int gi, int pass, float* d, bool write_ck) {
+    CHK(run_group_impl(c, gr, gi, pass, d, write_ck));
+    if (c->opt_progress) {
+        static const char* name[4] = {"forward", "Born", "background", "migration"};
+        HIPCHK(c, hipStreamSynchronize(c->st));
+        fprintf(stderr, "[lsrtm] %s pass: group %d of %zu done\n", name[pass], gi + 1, c->groups.size());
+        fflush(stderr);
+    }
     return LSRTM_OK;
 }
 
@@ -1319,6 +1333,7 @@ lsrtm_status lsrtm_set_option(lsrtm_ctx* c, int key, long long v) {
         c->opt_fused = v != 0;
         if (c->have_acq) return plan(c);
         return LSRTM_OK;
+    case LSRTM_OPT_PROGRESS: c->opt_progress = v != 0; return LSRTM_OK;
     case LSRTM_OPT_CKPT_PER_GROUP:
         if (c->opt_ckg == (v != 0)) return LSRTM_OK;
         c->opt_ckg = v != 0;

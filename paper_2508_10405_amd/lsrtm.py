@@ -23,8 +23,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "lsrtm.h")
 
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
 CKPT = {"f32": 0, "f16": 1, "bf16": 2}
-OPT_SHOTS_PER_LAUNCH, OPT_TILE, OPT_GRAPH, OPT_TIMING, OPT_MEM_BUDGET_MB, OPT_CKPT_PER_GROUP, OPT_FUSED = \
-    1, 2, 3, 4, 5, 6, 7
+OPT_SHOTS_PER_LAUNCH, OPT_TILE, OPT_GRAPH, OPT_TIMING, OPT_MEM_BUDGET_MB, OPT_CKPT_PER_GROUP, OPT_FUSED, \
+    OPT_PROGRESS = 1, 2, 3, 4, 5, 6, 7, 8
 NKERNEL = 8
 KERNEL_NAMES = ("born_v", "born_p", "bg_v", "bg_p", "adj_a", "adj_b", "ckpt", "rec")
 
@@ -111,7 +111,7 @@ class Context:
 
     def __init__(self, n, h, nt, dt, npml=20, pml_R=1e-4, pml_f0=10.0, ckpt_every=0,
                  ckpt_dtype="f32", stream=None, shots_per_launch=0, tile=-1, graph=True,
-                 timing=False, mem_budget_mb=0, ckpt_per_group=False, fused=False):
+                 timing=False, mem_budget_mb=0, ckpt_per_group=False, fused=False, progress=False):
         import torch
         L = lib()
         self._torch = torch
@@ -140,6 +140,7 @@ class Context:
         self.set_option(OPT_MEM_BUDGET_MB, mem_budget_mb)
         self.set_option(OPT_CKPT_PER_GROUP, int(bool(ckpt_per_group)))
         self.set_option(OPT_FUSED, int(bool(fused)))
+        self.set_option(OPT_PROGRESS, int(bool(progress)))
         self.nrec: List[int] = []
         self._keep = []
 
