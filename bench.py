@@ -57,15 +57,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+# Sources of the stencil kernels a workload runs (a change to any of them
+# makes its committed counter profile stale).
+KERNEL_SOURCES = {2: ("common.h", "kernels.h", "kern2d.hip", "kern2f.hip"),
+                  3: ("common.h", "kernels.h", "kern3d.hip")}
+
+
+def kernel_source_hash(ndim=2):
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2508_10405_amd", "csrc"))):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(ROOT, "paper_2508_10405_amd", "csrc", f), "rb").read())
+    for f in KERNEL_SOURCES[ndim]:
+        h.update(open(os.path.join(ROOT, "paper_2508_10405_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload_tag, kernel, pts_per_launch):
+def read_traffic(workload_tag, kernel, pts_per_launch, ndim=2):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
     summary (calibrated bytes per padded node times the nodes of a launch),
     or None when it is missing or the kernels changed since."""
@@ -78,7 +83,7 @@ def read_traffic(workload_tag, kernel, pts_per_launch):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha") != kernel_source_hash():
+    if vals.get("kernel_source_sha") != kernel_source_hash(ndim):
         return None
     v = vals.get(f"traffic_bytes_per_point.{kernel}")
     return float(v) * pts_per_launch if v not in (None, "", "null") else None
@@ -207,7 +212,7 @@ def main():
     avg_ms = kms[dom] / max(1, kcnt[dom])
     bytes_launch = btab[dom] * pts_per_launch
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    traffic = read_traffic(tag + ("_fused" if (nd == 2 and sz["fused"]) else ""), dom, pts_per_launch)
+    traffic = read_traffic(tag + ("_fused" if (nd == 2 and sz["fused"]) else ""), dom, pts_per_launch, nd)
     kernels = {k: {"avg_ms": kms[k] / kcnt[k], "launches_timed": kcnt[k],
                    "GBs": (btab[k] * pts_per_launch / (kms[k] / kcnt[k] * 1e-3) / 1e9)
                    if k in btab else None}
