@@ -22,7 +22,8 @@ parametrization"):
   (lnVp, lnIp) by the gradient chain rule (section 3, the pair of equations
   after eq. normal).
 * CGNR on the normal equations L^H L dm = L^H dd (section 3, eq. normal and
-  the CGNR paragraph).
+  the CGNR paragraph), and its preconditioned form with the pseudo-Hessian
+  diagonal of appendix B.
 
 The paper gives the continuous equations only.  The discrete scheme below is
 one explicit reading of them (all readings are listed in the design notes of
@@ -569,5 +570,129 @@ def cgnr(L: Callable, Lt: Callable, d, niter: int, dot: Optional[Callable] = Non
         beta = zz_new / zz
         p = z + beta * p
         zz = zz_new
+        hist.append(dot(r, r) / r0)
+    return x, hist
+
+
+# ---------------------------------------------------------------------------
+# Pseudo-Hessian preconditioner (appendix B) and preconditioned CGNR
+# ---------------------------------------------------------------------------
+def _avg_sq_T(x: np.ndarray, a: int) -> np.ndarray:
+    """Transpose of the squared weights of avg_half: node i collects 1/4 of
+    the half-node values i - 1/2 and i + 1/2; the clamped last half node
+    averages the last node with itself (weight 1, squared 1)."""
+    ax = _nax(x.ndim, a)
+    n = x.shape[ax]
+    xs = np.moveaxis(x, ax, 0)
+    out = 0.25 * xs
+    out[1:] = out[1:] + 0.25 * xs[:-1]
+    out[n - 1] = out[n - 1] + 0.75 * xs[n - 1]
+    return np.moveaxis(out, 0, ax)
+
+
+def pseudo_hessian_shot(med: Medium, src_idx, wav: np.ndarray, nt: int):
+    """Pseudo-Hessian diagonal of one shot on its padded grid (appendix B).
+
+    The paper replaces diag(L^H L) by the time-integrated energy of the Born
+    secondary source that a unit perturbation creates in the incident field,
+    (dA/dm u0)^H (dA/dm u0): rho^2 int |dv/dt|^2 dt for lnrho and
+    kappa^2 int (div v)^2 dt for lnkappa.  Discrete reading: the sources are
+    the ones of the Born step (step_scattered) -- a unit dlnrho at node i adds
+    -avg_a(e_i) dv_a to the velocities, a unit dlnkappa adds -dt kappa q at
+    node i to the pressure -- and the time integral of a squared rate is the
+    sum over steps of the squared increment divided by dt, the velocity
+    source weighted by rho^2 as in the paper:
+
+      H_lnrho[i]   = rho_i^2 / dt * sum_n sum_a || avg_a(e_i) * dv_a^n ||^2
+      H_lnkappa[i] = 1 / dt * sum_n (dt kappa_i q_i^n)^2
+
+    Returns (H_lnrho / (rho^2 / dt), H_lnkappa) on the padded grid: the
+    density entry without its rho^2 / dt factor, which the caller applies
+    from the model."""
+    st = State.zeros(med.shape, med.ndim, np.result_type(med.kappa, np.float64))
+    s_v = [np.zeros(med.shape, dtype=st.p.dtype) for _ in range(med.ndim)]
+    s_q = np.zeros(med.shape, dtype=st.p.dtype)
+    for n in range(nt):
+        dv, q = step_background(st, med, src_idx, wav[n])
+        for a in range(med.ndim):
+            s_v[a] = s_v[a] + dv[a] * dv[a]
+        s_q = s_q + q * q
+    h_r = 0.0
+    for a in range(med.ndim):
+        h_r = h_r + _avg_sq_T(s_v[a], a)
+    h_k = (med.dt * med.kappa) ** 2 * s_q / med.dt
+    return h_r, h_k
+
+
+def pseudo_hessian(prob: Problem, lnvp, lnip) -> np.ndarray:
+    """Pseudo-Hessian diagonal for (lnVp, lnIp), summed over shots (appendix
+    B): the chain rule of section 3 makes both diagonal entries equal,
+    H_lnVp = H_lnIp = H_lnrho + H_lnkappa.  Returns one array of the physical
+    shape (the diagonal for either parameter)."""
+    ndim = prob.ndim
+    out = np.zeros(lnvp.shape, dtype=np.float64)
+    vmax = float(np.exp(np.max(np.real(lnvp))))
+    inner = tuple(slice(prob.npml, -prob.npml) if prob.npml > 0 else slice(None)
+                  for _ in range(ndim))
+    for s in range(prob.nshot):
+        med, si, _, sl = shot_setup(prob, lnvp, lnip, s, vmax)
+        h_r, h_k = pseudo_hessian_shot(med, si, prob.wavelet[s], prob.nt)
+        lnr, _ = log_params(pad_edge(lnvp[sl], prob.npml), pad_edge(lnip[sl], prob.npml))
+        rho2 = np.exp(2.0 * lnr)
+        out[sl] += (rho2 * h_r / med.dt + h_k)[inner]
+    return out
+
+
+def preconditioner(h: np.ndarray, eps_rel: float = 1e-3) -> np.ndarray:
+    """Diagonal inverse 1 / (H + eps) for both parameters, eps = eps_rel *
+    max H (the paper leaves the stabilisation unstated; this is the reading
+    used throughout).  Shape (2, *h.shape)."""
+    eps = eps_rel * float(np.max(h)) if h.size else 0.0
+    m = 1.0 / (h + eps)
+    return np.stack([m, m])
+
+
+def pcgnr(L: Callable, Lt: Callable, d, niter: int, minv, dot: Optional[Callable] = None):
+    """Preconditioned CGNR (section 3: CGNR with the pseudo-Hessian
+    preconditioner of appendix B): conjugate gradients on the normal
+    equations L^T L x = L^T d in which the normal residual s = L^T r is
+    preconditioned by the diagonal minv, x0 = 0.
+
+      s = L^T r, z = minv * s, p = z;  per iteration: w = L p,
+      alpha = <z, s> / <w, w>, x += alpha p, r -= alpha w, s = L^T r,
+      z = minv * s, beta = <z, s>_new / <z, s>_old, p = z + beta p.
+
+    With minv = 1 this is cgnr() operation for operation.  Returns x and the
+    normalised misfit history ||r_k||^2 / ||r_0||^2."""
+    if dot is None:
+        def dot(a, b):
+            if isinstance(a, (list, tuple)):
+                return float(sum(np.vdot(x, y).real for x, y in zip(a, b)))
+            return float(np.vdot(a, b).real)
+
+    def axpy(alpha, x, y):
+        if isinstance(x, (list, tuple)):
+            return [yy + alpha * xx for xx, yy in zip(x, y)]
+        return y + alpha * x
+
+    r = [x.copy() for x in d] if isinstance(d, (list, tuple)) else d.copy()
+    s_ = Lt(r)
+    z = minv * s_
+    p = z.copy()
+    x = np.zeros_like(z)
+    zs = dot(z, s_)
+    r0 = dot(r, r)
+    hist = [1.0]
+    for _ in range(niter):
+        w = L(p)
+        alpha = zs / dot(w, w)
+        x = x + alpha * p
+        r = axpy(-alpha, w, r)
+        s_ = Lt(r)
+        z = minv * s_
+        zs_new = dot(z, s_)
+        beta = zs_new / zs
+        p = z + beta * p
+        zs = zs_new
         hist.append(dot(r, r) / r0)
     return x, hist

@@ -1,0 +1,147 @@
+"""Pins of the oracle's pseudo-Hessian (appendix B of the paper) and of its
+preconditioned CGNR (section 3, CGNR with that preconditioner).
+
+The paper prints no values for either; the pins are mathematical:
+
+* the vectorised pseudo-Hessian equals, node by node, the energy of the Born
+  secondary source obtained by running the oracle's own Born step with a unit
+  perturbation at that node (brute force through a different code path);
+* it is quadratic in the source amplitude and additive over shots;
+* PCGNR with the identity preconditioner is CGNR operation for operation;
+* PCGNR with minv = D^2 is CGNR on the column-scaled operator L D (x = D y);
+* PCGNR reaches the least-squares solution after n steps on a dense full-rank
+  problem, with a non-increasing residual, and its k-th iterate minimises the
+  residual over the preconditioned Krylov space.
+"""
+import numpy as np
+import pytest
+
+from oracle import lsrtm_oracle as O
+from paper_2508_10405_amd import synth
+
+
+def _problem(w, wavelet=None):
+    return O.Problem(w.h, w.dt, w.nt, w.npml, w.pml_R, w.pml_freq, w.win, w.src, w.rec,
+                     (w.wavelet if wavelet is None else wavelet).astype(np.float64))
+
+
+def _f64(w):
+    return w.lnvp.astype(np.float64), w.lnip.astype(np.float64)
+
+
+def _unit(shape, idx):
+    e = np.zeros(shape)
+    e[idx] = 1.0
+    return e
+
+
+@pytest.mark.parametrize("n,npml", [((7, 9), 2), ((5, 6, 4), 1)])
+def test_pseudo_hessian_brute_force(n, npml):
+    """H_lnrho[i] and H_lnkappa[i] equal the time-summed squared Born sources
+    of a unit perturbation at node i, computed with step_scattered from a zero
+    scattered state (velocity part for lnrho, pressure part for lnkappa)."""
+    w = synth.small(n, nt=10, npml=npml, seed=21, nshot=1, uneven=False)
+    prob = _problem(w)
+    lnvp, lnip = _f64(w)
+    med, si, _, sl = O.shot_setup(prob, lnvp, lnip, 0)
+    h_r, h_k = O.pseudo_hessian_shot(med, si, prob.wavelet[0], prob.nt)
+    # background history
+    st = O.State.zeros(med.shape, med.ndim)
+    hist = [O.step_background(st, med, si, prob.wavelet[0][k]) for k in range(prob.nt)]
+    zero = np.zeros(med.shape)
+    bf_r = np.zeros(med.shape)
+    bf_k = np.zeros(med.shape)
+    for idx in np.ndindex(*med.shape):
+        e = _unit(med.shape, idx)
+        rbar = [O.avg_half(e, a) for a in range(med.ndim)]
+        rzero = [zero] * med.ndim
+        for dv, q in hist:
+            sc = O.State.zeros(med.shape, med.ndim)
+            O.step_scattered(sc, med, dv, q, rbar, zero)
+            bf_r[idx] += sum(float(np.sum(v * v)) for v in sc.v)
+            sc = O.State.zeros(med.shape, med.ndim)
+            O.step_scattered(sc, med, dv, q, rzero, e)
+            bf_k[idx] += float(np.sum(sc.p * sc.p))
+    bf_k /= med.dt
+    assert np.max(np.abs(h_r - bf_r)) <= 1e-12 * np.max(np.abs(bf_r))
+    assert np.max(np.abs(h_k - bf_k)) <= 1e-12 * np.max(np.abs(bf_k))
+    assert np.max(bf_r) > 0 and np.max(bf_k) > 0
+
+
+def test_pseudo_hessian_quadratic_and_additive():
+    """Doubling the wavelet multiplies H by 4; H >= 0; a two-shot problem is
+    the sum of its one-shot problems."""
+    w = synth.small((12, 14), nt=40, npml=3, seed=22, nshot=2, uneven=True)
+    lnvp, lnip = _f64(w)
+    prob = _problem(w)
+    h = O.pseudo_hessian(prob, lnvp, lnip)
+    h2 = O.pseudo_hessian(_problem(w, 2.0 * w.wavelet), lnvp, lnip)
+    assert np.all(h >= 0)
+    assert np.max(np.abs(h2 - 4 * h)) <= 1e-12 * np.max(h)
+    parts = 0
+    for s in range(2):
+        p1 = O.Problem(w.h, w.dt, w.nt, w.npml, w.pml_R, w.pml_freq, [w.win[s]], [w.src[s]],
+                       [w.rec[s]], w.wavelet[s:s + 1].astype(np.float64))
+        parts = parts + O.pseudo_hessian(p1, lnvp, lnip)
+    assert np.max(np.abs(parts - h)) <= 1e-12 * np.max(h)
+
+
+def test_preconditioner_reading():
+    """minv = 1 / (H + 1e-3 max H) for both parameters."""
+    h = np.array([[0.0, 1.0], [2.0, 4.0]])
+    m = O.preconditioner(h)
+    assert m.shape == (2, 2, 2)
+    assert np.allclose(m[0], 1.0 / (h + 4e-3)) and np.array_equal(m[0], m[1])
+
+
+def _dense(seed, m=36, n=12):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n)) @ np.diag(np.linspace(1, 6, n))
+    d = rng.standard_normal(m)
+    D = np.exp(rng.uniform(-1, 1, n))
+    return A, d, D
+
+
+def test_pcgnr_identity_is_cgnr():
+    A, d, _ = _dense(30)
+    x0, h0 = O.cgnr(lambda p: A @ p, lambda r: A.T @ r, d, 7)
+    x1, h1 = O.pcgnr(lambda p: A @ p, lambda r: A.T @ r, d, 7, np.ones(A.shape[1]))
+    assert np.array_equal(x0, x1) and h0 == h1
+
+
+def test_pcgnr_is_cgnr_on_scaled_operator():
+    """With minv = D^2, PCGNR on A equals D y where y is CGNR on A D, for
+    every iteration count (same residual history)."""
+    A, d, D = _dense(31)
+    for k in (1, 3, 6):
+        x, hx = O.pcgnr(lambda p: A @ p, lambda r: A.T @ r, d, k, D * D)
+        AD = A * D
+        y, hy = O.cgnr(lambda p: AD @ p, lambda r: AD.T @ r, d, k)
+        assert np.linalg.norm(x - D * y) <= 1e-10 * np.linalg.norm(x)
+        assert np.allclose(hx, hy, rtol=1e-10, atol=0)
+
+
+def test_pcgnr_least_squares_and_monotone():
+    A, d, D = _dense(32)
+    n = A.shape[1]
+    x, hist = O.pcgnr(lambda p: A @ p, lambda r: A.T @ r, d, n, D)
+    ref = np.linalg.lstsq(A, d, rcond=None)[0]
+    assert np.linalg.norm(x - ref) <= 1e-8 * np.linalg.norm(ref)
+    assert all(hist[i + 1] <= hist[i] + 1e-14 for i in range(len(hist) - 1))
+
+
+def test_pcgnr_krylov_optimal():
+    """After k steps the iterate minimises ||A x - d|| over the preconditioned
+    Krylov space span{M^-1 A^T d, (M^-1 A^T A) M^-1 A^T d, ...}."""
+    rng = np.random.default_rng(33)
+    A = rng.standard_normal((30, 20))
+    d = rng.standard_normal(30)
+    minv = np.exp(rng.uniform(-1, 1, 20))
+    k = 5
+    x, _ = O.pcgnr(lambda p: A @ p, lambda r: A.T @ r, d, k, minv)
+    K = [minv * (A.T @ d)]
+    for _ in range(k - 1):
+        K.append(minv * (A.T @ (A @ K[-1])))
+    Q, _ = np.linalg.qr(np.stack(K, axis=1))
+    c = np.linalg.lstsq(A @ Q, d, rcond=None)[0]
+    assert np.linalg.norm(x - Q @ c) <= 1e-8 * np.linalg.norm(x)
