@@ -164,6 +164,38 @@ lsrtm_status lsrtm_cgnr_begin(lsrtm_ctx* ctx, const float* d_obs, float* x);
 lsrtm_status lsrtm_cgnr_iterate(lsrtm_ctx* ctx, float* x, double* misfit);
 lsrtm_status lsrtm_cgnr_state(lsrtm_ctx* ctx, int get, float* r, float* z, float* p, double* scal);
 
+/* Pseudo-Hessian diagonal (appendix B): the diagonal of the Hessian is
+ * approximated by the time-integrated energy of the Born secondary source
+ * that a unit perturbation radiates in each shot's incident field, summed
+ * over shots.  With the Born step's sources (a unit dlnrho at node i adds
+ * -avg_a(e_i) dv_a to the velocities, a unit dlnkappa adds -dt kappa q at i):
+ *   h_i = sum_shots [ rho_i^2 / dt * sum_n sum_a ||avg_a(e_i) dv_a^n||^2
+ *                     + (dt kappa_i)^2 / dt * sum_n (q_i^n)^2 ],
+ * dv_a the background velocity increments and q the CPML-corrected
+ * divergence of step n.  By the chain rule of section 3 the diagonal is the
+ * same for lnVp and lnIp.
+ * h: DEVICE float [nz*nx*ny] (physical grid, z fastest), written.
+ * minv: DEVICE float [2][nz*nx*ny] or NULL; if given it receives
+ *   1 / (h + eps_rel * max h) for both parameters, the preconditioner of
+ *   lsrtm_set_preconditioner (the paper does not state the stabilisation).
+ * Runs one background pass (velocity and pressure kernels, plain launches)
+ * through the library's field buffers; stored checkpoints stay valid.
+ * Synchronises the stream when minv is given.  Errors: EINVAL (h NULL,
+ * eps_rel < 0, or minv requested for an all-zero h or eps_rel = 0), ESTATE
+ * (model or acquisition missing), ENONFINITE, EHIP. */
+lsrtm_status lsrtm_pseudo_hessian(lsrtm_ctx* ctx, float* h, float* minv, double eps_rel);
+
+/* Diagonal preconditioner of the CGNR solver (section 3: CGNR preconditioned
+ * with the pseudo-Hessian of appendix B).  The normal residual s = L^T r is
+ * replaced by z = minv * s; step length <z, s> / <L p, L p>, direction
+ * p = z + beta p with beta = <z, s>_new / <z, s>_old.  minv: DEVICE float
+ * [2][nz*nx*ny] (lnVp block, then lnIp), copied into a library buffer (the
+ * caller keeps ownership); NULL removes the preconditioner.  Takes effect at
+ * the next lsrtm_cgnr / lsrtm_cgnr_begin or state import; the exported state
+ * then holds z = minv * s and scal[0] = <z, s>.  Errors: EINVAL (ctx NULL),
+ * ENOMEM, EHIP. */
+lsrtm_status lsrtm_set_preconditioner(lsrtm_ctx* ctx, const float* minv);
+
 /* FP64-accumulated inner product of two DEVICE float vectors of length n;
  * *out is a HOST double.  Deterministic (fixed reduction tree). */
 lsrtm_status lsrtm_dot(lsrtm_ctx* ctx, const float* a, const float* b, long long n, double* out);

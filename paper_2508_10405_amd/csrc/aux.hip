@@ -195,6 +195,97 @@ hipError_t launch_image_store(const double* acc, float* img, long long n, int ac
 }
 
 // ---------------------------------------------------------------------------
+// Pseudo-Hessian (appendix B of the paper)
+// ---------------------------------------------------------------------------
+// Per physical node, in shot order: the slots' time sums of the squared
+// velocity increments (w_a, at half nodes) moved onto the node with the
+// squared weights of the half-node average -- 1/4 from each neighbouring
+// half node, weight 1 from a clamped last half node onto its own node -- into
+// acc[0], and the time sums of q^2 (g_kappa) into acc[1].
+__global__ void k_ph_reduce(ImgArgs a) {
+    const int ndim = a.ndim;
+    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < a.gpts;
+         g += (long long)gridDim.x * blockDim.x) {
+        const int z = (int)(g % a.gn[0]);
+        const long long r = g / a.gn[0];
+        const int x = (int)(r % a.gn[1]);
+        const int y = (int)(r / a.gn[1]);
+        double hv = a.acc[g], hq = a.acc[a.gpts + g];
+        for (int s = 0; s < a.nslot; ++s) {
+            const int* w = a.win + 6 * s;
+            if (z < w[0] || z >= w[1] || x < w[2] || x >= w[3]) continue;
+            if (ndim == 3 && (y < w[4] || y >= w[5])) continue;
+            const DSlot& S = dev_slots(a.slots)[s];
+            const int c[3] = {z - w[0] + a.npml, x - w[2] + a.npml, ndim == 3 ? y - w[4] + a.npml : 0};
+            const long long i = c[0] + S.sx * c[1] + S.sy * (long long)c[2];
+            for (int ax = 0; ax < ndim; ++ax) {
+                const long long stride = ax == 0 ? 1LL : (ax == 1 ? S.sx : S.sy);
+                const double v = S.w[ax][i];
+                double t = 0.25 * v;
+                if (c[ax] > 0) t += 0.25 * (double)S.w[ax][i - stride];
+                if (c[ax] == S.n[ax] - 1) t += 0.75 * v;
+                hv += t;
+            }
+            hq += S.gk[i];
+        }
+        a.acc[g] = hv;
+        a.acc[a.gpts + g] = hq;
+    }
+}
+
+hipError_t launch_ph_reduce(const ImgArgs& a, hipStream_t st) {
+    k_ph_reduce<<<nblocks(a.gpts), NTHREADS, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+// h = rho^2 / dt * acc[0] + (dt kappa)^2 / dt * acc[1], rho and kappa from
+// the physical model logs (lnrho = lnIp - lnVp, lnkappa = lnIp + lnVp).
+__global__ void k_ph_finish(const double* __restrict__ acc, const float* __restrict__ lnvp,
+                            const float* __restrict__ lnip, double dt, float* __restrict__ h, long long n) {
+    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < n;
+         g += (long long)gridDim.x * blockDim.x) {
+        const double lv = lnvp[g], li = lnip[g];
+        const double rho2 = exp(2.0 * (li - lv));
+        const double dk = dt * exp(li + lv);
+        h[g] = (float)((rho2 * acc[g] + dk * dk * acc[n + g]) / dt);
+    }
+}
+
+hipError_t launch_ph_finish(const double* acc, const float* lnvp, const float* lnip, double dt, float* h,
+                            long long n, hipStream_t st) {
+    k_ph_finish<<<nblocks(n), NTHREADS, 0, st>>>(acc, lnvp, lnip, dt, h, n);
+    return hipGetLastError();
+}
+
+// minv[0][g] = minv[1][g] = 1 / (h[g] + eps): the same diagonal for lnVp and lnIp.
+__global__ void k_ph_minv(const float* __restrict__ h, double eps, float* __restrict__ minv, long long n) {
+    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < n;
+         g += (long long)gridDim.x * blockDim.x) {
+        const float m = (float)(1.0 / ((double)h[g] + eps));
+        minv[g] = m;
+        minv[n + g] = m;
+    }
+}
+
+hipError_t launch_ph_minv(const float* h, double eps, float* minv, long long n, hipStream_t st) {
+    k_ph_minv<<<nblocks(n), NTHREADS, 0, st>>>(h, eps, minv, n);
+    return hipGetLastError();
+}
+
+// out = a * b elementwise (the diagonal preconditioner applied to a vector).
+__global__ void k_mul(const float* __restrict__ a, const float* __restrict__ b, float* __restrict__ out,
+                      long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        out[i] = a[i] * b[i];
+}
+
+hipError_t launch_mul(const float* a, const float* b, float* out, long long n, hipStream_t st) {
+    k_mul<<<nblocks(n), NTHREADS, 0, st>>>(a, b, out, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Reductions (fixed-shape trees, deterministic)
 // ---------------------------------------------------------------------------
 template <typename T, typename Op>

@@ -8,6 +8,11 @@ namespace lsrtm {
 
 constexpr int HW = 4;        // half width of the eighth-order staggered stencil
 constexpr int NTHREADS = 256;
+// Flag bit of the background (non-Born, non-replay) velocity and pressure
+// kernels: also accumulate the squared velocity increments into the slot's
+// w_a arrays and the squared divergence into g_kappa (pseudo-Hessian pass;
+// those arrays are free while only the background runs).
+constexpr int PH_ACCUMULATE = 2;
 
 // Stencil weights c_k / h_a for the three axes (z, x, y).
 struct Coef {

@@ -158,6 +158,10 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             seg[i] = dvz;
             seg[S.npts + i] = dvx;
         }
+        if (!BORN && !SEG && (flag & PH_ACCUMULATE)) {   // pseudo-Hessian: sum of dv_a^2
+            S.w[0][i] = S.w[0][i] + dvz * dvz;
+            S.w[1][i] = S.w[1][i] + dvx * dvx;
+        }
         if (BORN) {
             float gzq = d_half(sq, c, 1, C.c[0]);
             float gxq = d_half(sq, c, T::LZ, C.c[1]);
@@ -295,6 +299,7 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         if (i == S.src) pn = pn + amp;
         S.p[i] = pn;
         if (SEG) seg[i] = q;
+        if (!BORN && !SEG && (flag & PH_ACCUMULATE)) S.gk[i] = S.gk[i] + q * q;   // pseudo-Hessian: sum of q^2
         if (!BORN && tr.d) tile_gather(tr, tix, lz + BZ * lx, n, pn);
         if (BORN) {
             float fz = d_node(swz, c, 1, C.c[0]);

@@ -202,6 +202,11 @@ k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
                 seg[S.npts + i] = dvx;
                 seg[2 * S.npts + i] = dvy;
             }
+            if (!BORN && !SEG && (flag & PH_ACCUMULATE)) {   // pseudo-Hessian: sum of dv_a^2
+                S.w[0][i] = S.w[0][i] + dvz * dvz;
+                S.w[1][i] = S.w[1][i] + dvx * dvx;
+                S.w[2][i] = S.w[2][i] + dvy * dvy;
+            }
             if (BORN) {
                 float gzq = d_half(sq, c, 1, C.c[0]);
                 float gxq = d_half(sq, c, T::LZ, C.c[1]);
@@ -344,6 +349,7 @@ k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             if (i == S.src) pn = pn + amp;
             S.p[i] = pn;
             if (SEG) seg[i] = q;
+            if (!BORN && !SEG && (flag & PH_ACCUMULATE)) S.gk[i] = S.gk[i] + q * q;   // pseudo-Hessian
             if (BORN) {
                 float fz = d_node(swz, c, 1, C.c[0]);
                 float fx = d_node(swx, c, T::LZ, C.c[1]);

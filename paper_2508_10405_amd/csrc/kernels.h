@@ -95,6 +95,13 @@ struct ImgArgs {
 hipError_t launch_image_reduce(const ImgArgs& a, hipStream_t st);
 hipError_t launch_image_store(const double* acc, float* img, long long n, int accumulate,
                               hipStream_t st);
+// Pseudo-Hessian: slot sums -> acc[2][gpts] (shot order), then h and the
+// diagonal inverse 1 / (h + eps) for both parameters.
+hipError_t launch_ph_reduce(const ImgArgs& a, hipStream_t st);
+hipError_t launch_ph_finish(const double* acc, const float* lnvp, const float* lnip, double dt, float* h,
+                            long long n, hipStream_t st);
+hipError_t launch_ph_minv(const float* h, double eps, float* minv, long long n, hipStream_t st);
+hipError_t launch_mul(const float* a, const float* b, float* out, long long n, hipStream_t st);
 
 // Max |x| of a physical float array (finite check: non-finite -> +inf).
 hipError_t launch_maxabs(const float* x, long long n, float* partial, int nblk, hipStream_t st);

@@ -130,9 +130,14 @@ struct lsrtm_ctx {
     float* cg_w = nullptr;
     float* cg_z = nullptr;
     float* cg_p = nullptr;
-    double cg_zz = 0.0, cg_r0 = 0.0, cg_rr = 0.0;
+    double cg_zz = 0.0, cg_r0 = 0.0, cg_rr = 0.0;   // cg_zz = <z, s> (= <z, z> unpreconditioned)
     int cg_k = 0;
     bool cg_active = false;
+    // diagonal preconditioner M^-1 of the normal residual (pseudo-Hessian)
+    float* cg_minv = nullptr;      // [2][gpts], library copy
+    float* cg_s = nullptr;         // normal residual L^T r when preconditioned
+    bool precond = false;          // a preconditioner is set
+    bool cg_pre = false;           // the current CG run is preconditioned
     // options
     int opt_spl = 0;
     int opt_tile = -1;
@@ -553,6 +558,35 @@ lsrtm_status group_adjoint(lsrtm_ctx* c, Group& gr, const float* d) {
     ia.acc = c->acc64;
     ia.gpts = c->gpts;
     HIPCHK(c, launch_image_reduce(ia, c->st));
+    return LSRTM_OK;
+}
+
+// Pseudo-Hessian pass of one group (appendix B): the background of every
+// shot with the squared velocity increments and squared divergences summed
+// over time into the slots' w_a and g_kappa arrays, then added per physical
+// node into acc64 in shot order.  Always the two-phase kernels (the fused
+// 2D step has no accumulating variant); plain launches.
+lsrtm_status group_ph(lsrtm_ctx* c, Group& gr) {
+    CHK(build_tiles(c, gr, c->tile));
+    CHK(fill(c, c->pool, gr.bg_used));
+    CHK(fill(c, c->pool + c->bg_region, gr.sc_used));
+    CHK(fill(c, c->pool + c->bg_region + c->sc_region, gr.img_used));
+    const Slot* sl = desc(gr, 0);
+    for (int n = 0; n < c->g.nt; ++n) {
+        tstep(c, n);
+        CHK(stencil(c, gr, K_BG_V, n, 0, PH_ACCUMULATE, sl));
+        CHK(stencil(c, gr, K_BG_P, n, 0, PH_ACCUMULATE, sl));
+    }
+    ImgArgs ia;
+    ia.slots = gr.d_slots;
+    ia.win = gr.d_win;
+    ia.nslot = gr.ns;
+    ia.ndim = c->ndim;
+    for (int a = 0; a < 3; ++a) ia.gn[a] = c->g.n[a];
+    ia.npml = c->g.npml;
+    ia.acc = c->acc64;
+    ia.gpts = c->gpts;
+    HIPCHK(c, launch_ph_reduce(ia, c->st));
     return LSRTM_OK;
 }
 
@@ -1547,16 +1581,26 @@ lsrtm_status lsrtm_axpy(lsrtm_ctx* c, double alpha, const float* x, float* y, lo
     return LSRTM_OK;
 }
 
+// z = M^-1 L^T r (preconditioned run: s = L^T r kept), or z = L^T r.
+static lsrtm_status normal_residual(lsrtm_ctx* c) {
+    const long long nm = 2 * c->gpts;
+    if (!c->cg_pre) return adjoint_impl(c, c->cg_r, c->cg_z, 0);
+    CHK(adjoint_impl(c, c->cg_r, c->cg_s, 0));
+    HIPCHK(c, launch_mul(c->cg_minv, c->cg_s, c->cg_z, nm, c->st));
+    return LSRTM_OK;
+}
+
 lsrtm_status lsrtm_cgnr_begin(lsrtm_ctx* c, const float* d_obs, float* x) {
     CHK(check_ready(c));
     if (!x || (!d_obs && c->data_len > 0)) FAIL(c, LSRTM_EINVAL, "bad CGNR arguments");
     const long long nm = 2 * c->gpts, nd = c->data_len;
     CHK(pass_begin(c));
+    c->cg_pre = c->precond;
     HIPCHK(c, launch_copy(d_obs, c->cg_r, nd, c->st));
     HIPCHK(c, launch_fill(x, nm, 0.f, c->st));
-    CHK(adjoint_impl(c, c->cg_r, c->cg_z, 0));
+    CHK(normal_residual(c));
     HIPCHK(c, launch_copy(c->cg_z, c->cg_p, nm, c->st));
-    CHK(dot_impl(c, c->cg_z, c->cg_z, nm, &c->cg_zz));
+    CHK(dot_impl(c, c->cg_z, c->cg_pre ? c->cg_s : c->cg_z, nm, &c->cg_zz));
     CHK(dot_impl(c, c->cg_r, c->cg_r, nd, &c->cg_r0));
     c->cg_rr = c->cg_r0;
     c->cg_k = 0;
@@ -1579,9 +1623,9 @@ lsrtm_status lsrtm_cgnr_iterate(lsrtm_ctx* c, float* x, double* misfit) {
             const double alpha = c->cg_zz / ww;
             HIPCHK(c, launch_axpy(alpha, c->cg_p, x, nm, c->st));
             HIPCHK(c, launch_axpy(-alpha, c->cg_w, c->cg_r, nd, c->st));
-            CHK(adjoint_impl(c, c->cg_r, c->cg_z, 0));
+            CHK(normal_residual(c));
             double zz1;
-            CHK(dot_impl(c, c->cg_z, c->cg_z, nm, &zz1));
+            CHK(dot_impl(c, c->cg_z, c->cg_pre ? c->cg_s : c->cg_z, nm, &zz1));
             const double beta = zz1 / c->cg_zz;
             HIPCHK(c, launch_xpby(c->cg_z, beta, c->cg_p, nm, c->st));
             c->cg_zz = zz1;
@@ -1625,7 +1669,65 @@ lsrtm_status lsrtm_cgnr_state(lsrtm_ctx* c, int get, float* r, float* z, float* 
         c->cg_rr = scal[2];
         c->cg_k = (int)scal[3];
         c->cg_active = true;
+        c->cg_pre = c->precond;
     }
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_set_preconditioner(lsrtm_ctx* c, const float* minv) {
+    if (!c) return LSRTM_EINVAL;
+    if (!minv) {
+        c->precond = false;
+        return LSRTM_OK;
+    }
+    const long long nm = 2 * c->gpts;
+    if (!c->cg_minv) {
+        CHK(dalloc_t(c, &c->cg_minv, nm, false));
+        CHK(dalloc_t(c, &c->cg_s, nm, false));
+    }
+    HIPCHK(c, launch_copy(minv, c->cg_minv, nm, c->st));
+    c->precond = true;
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_pseudo_hessian(lsrtm_ctx* c, float* h, float* minv, double eps_rel) {
+    CHK(check_ready(c));
+    if (!h) FAIL(c, LSRTM_EINVAL, "h is NULL");
+    if (!(eps_rel >= 0.0)) FAIL(c, LSRTM_EINVAL, "eps_rel must be >= 0");
+    CHK(pass_begin(c));
+    HIPCHK(c, launch_fill_f64(c->acc64, 2 * c->gpts, c->st));
+    const bool fz = c->fused;
+    c->fused = false;              // the accumulating kernels are the two-phase ones
+    lsrtm_status s = LSRTM_OK;
+    for (size_t gi = 0; gi < c->groups.size() && s == LSRTM_OK; ++gi) {
+        s = group_ph(c, c->groups[gi]);
+        if (s == LSRTM_OK && c->opt_progress) {
+            const hipError_t e = hipStreamSynchronize(c->st);
+            if (e != hipSuccess) {
+                c->fused = fz;
+                FAIL(c, LSRTM_EHIP, "pseudo-Hessian pass: %s", hipGetErrorString(e));
+            }
+            fprintf(stderr, "[lsrtm] pseudo-Hessian pass: group %zu of %zu done\n", gi + 1, c->groups.size());
+            fflush(stderr);
+        }
+    }
+    c->fused = fz;
+    CHK(s);
+    HIPCHK(c, launch_ph_finish(c->acc64, c->lnvp, c->lnip, c->g.dt, h, c->gpts, c->st));
+    if (minv) {
+        const int nb = 256;
+        std::vector<float> part(nb);
+        HIPCHK(c, launch_maxval(h, c->gpts, c->partial, nb, c->st));
+        HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, nb * sizeof(float), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));
+        float mx = 0.f;
+        for (float x : part) mx = std::max(mx, x);
+        if (!std::isfinite(mx)) FAIL(c, LSRTM_ENONFINITE, "pseudo-Hessian holds NaN or Inf");
+        const double eps = eps_rel * (double)mx;
+        if (!(eps > 0.0)) FAIL(c, LSRTM_EINVAL, "zero pseudo-Hessian or eps_rel: preconditioner undefined");
+        HIPCHK(c, launch_ph_minv(h, eps, minv, c->gpts, c->st));
+    }
+    CHK(pass_end(c));
     return LSRTM_OK;
 }
 

@@ -57,6 +57,8 @@ SIGNATURES = {
     "lsrtm_cgnr_begin": (_c_int, [_vp, _vp, _vp]),
     "lsrtm_cgnr_iterate": (_c_int, [_vp, _vp, ctypes.POINTER(_c_double)]),
     "lsrtm_cgnr_state": (_c_int, [_vp, _c_int, _vp, _vp, _vp, ctypes.POINTER(_c_double)]),
+    "lsrtm_pseudo_hessian": (_c_int, [_vp, _vp, _vp, _c_double]),
+    "lsrtm_set_preconditioner": (_c_int, [_vp, _vp]),
     "lsrtm_dot": (_c_int, [_vp, _vp, _vp, _c_ll, ctypes.POINTER(_c_double)]),
     "lsrtm_axpy": (_c_int, [_vp, _c_double, _vp, _vp, _c_ll]),
     "lsrtm_set_option": (_c_int, [_vp, _c_int, _c_ll]),
@@ -305,6 +307,24 @@ class Context:
             _require_cuda(st[k], k)
         self._check(lib().lsrtm_cgnr_state(self._h, 0, _vp(_ptr(st["r"])), _vp(_ptr(st["z"])),
                                            _vp(_ptr(st["p"])), sc), "cgnr_state")
+
+    def pseudo_hessian(self, eps_rel=1e-3, preconditioner=True):
+        """Pseudo-Hessian diagonal h [shape] (lsrtm_pseudo_hessian) and, with
+        preconditioner=True, minv [2, *shape] = 1 / (h + eps_rel max h)."""
+        torch = self._torch
+        h = torch.empty(self.shape, dtype=torch.float32, device="cuda")
+        minv = torch.empty((2,) + self.shape, dtype=torch.float32, device="cuda") if preconditioner else None
+        self._check(lib().lsrtm_pseudo_hessian(self._h, _vp(_ptr(h)), _vp(_ptr(minv)), float(eps_rel)),
+                    "pseudo_hessian")
+        return h, minv
+
+    def set_preconditioner(self, minv):
+        """Diagonal preconditioner of the CGNR solver ([2, *shape]), or None."""
+        if minv is not None:
+            _require_cuda(minv, "minv")
+            if minv.numel() != 2 * int(np.prod(self.shape)):
+                raise ValueError("minv must hold 2 x grid points")
+        self._check(lib().lsrtm_set_preconditioner(self._h, _vp(_ptr(minv))), "set_preconditioner")
 
     def dot(self, a, b) -> float:
         _require_cuda(a, "a")
