@@ -59,8 +59,8 @@ def log(*a):
 
 # Sources of the stencil kernels a workload runs (a change to any of them
 # makes its committed counter profile stale).
-KERNEL_SOURCES = {2: ("common.h", "kernels.h", "kern2d.hip", "kern2f.hip"),
-                  3: ("common.h", "kernels.h", "kern3d.hip")}
+KERNEL_SOURCES = {2: ("common.h", "kern2d.hip", "kern2f.hip"),
+                  3: ("common.h", "kern3d.hip")}
 
 
 def kernel_source_hash(ndim=2):
@@ -141,6 +141,9 @@ def main():
     ap.add_argument("--tile", type=int, default=None,
                     help="tile shape id; -1 = autotuned (default: 1 = 32 x 16 for the 2D workloads)")
     ap.add_argument("--tune-steps", type=int, default=24)
+    ap.add_argument("--pcgnr", type=int, default=0,
+                    help="also run N CGNR and N pseudo-Hessian-preconditioned CGNR iterations from x = 0 "
+                         "and report both misfit curves (untimed for value)")
     ap.add_argument("--nt", type=int, default=0,
                     help="truncate the time axis to nt steps (0 = the workload's own); for counter "
                          "profiles, whose per-launch figures do not depend on nt")
@@ -213,10 +216,52 @@ def main():
     bytes_launch = btab[dom] * pts_per_launch
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     traffic = read_traffic(tag + ("_fused" if (nd == 2 and sz["fused"]) else ""), dom, pts_per_launch, nd)
-    kernels = {k: {"avg_ms": kms[k] / kcnt[k], "launches_timed": kcnt[k],
-                   "GBs": (btab[k] * pts_per_launch / (kms[k] / kcnt[k] * 1e-3) / 1e9)
-                   if k in btab else None}
-               for k in lsrtm.KERNEL_NAMES if kcnt[k] > 0}
+    kernels = {}
+    for k in lsrtm.KERNEL_NAMES:
+        if kcnt[k] == 0:
+            continue
+        t = kms[k] / kcnt[k] * 1e-3
+        tr = read_traffic(tag + ("_fused" if (nd == 2 and sz["fused"]) else ""), k, pts_per_launch, nd) \
+            if k in btab else None
+        kernels[k] = {"avg_ms": t * 1e3, "launches_timed": kcnt[k],
+                      "GBs": btab[k] * pts_per_launch / t / 1e9 if k in btab else None,
+                      "counter_GBs": tr / t / 1e9 if tr else None}
+
+    # per-pass rates (outside the timed region): one Born pass, one migration pass
+    torch.cuda.synchronize()
+    tb0 = time.perf_counter()
+    dtmp = ctx.born(x)
+    torch.cuda.synchronize()
+    tb1 = time.perf_counter()
+    ctx.adjoint(dtmp)
+    torch.cuda.synchronize()
+    tb2 = time.perf_counter()
+    del dtmp
+    passes = {"born_s": tb1 - tb0, "migration_s": tb2 - tb1,
+              "born_gpts": padded * w.nt / (tb1 - tb0) / 1e9,
+              "migration_gpts": padded * w.nt / (tb2 - tb1) / 1e9}
+    log(f"[bench] passes {passes}")
+
+    pcg = None
+    if args.pcgnr > 0:
+        tp0 = time.perf_counter()
+        _, minv = ctx.pseudo_hessian(eps_rel=1e-3)
+        torch.cuda.synchronize()
+        t_ph = time.perf_counter() - tp0
+        log(f"[bench] pseudo-Hessian pass {t_ph:.2f} s")
+        curves = {}
+        for name, pre in (("cgnr", None), ("pcgnr", minv)):
+            ctx.set_preconditioner(pre)
+            xx = ctx.cgnr_begin(d_obs)
+            mm = [1.0]
+            for i in range(args.pcgnr):
+                mm.append(ctx.cgnr_iterate(xx))
+                log(f"[bench] {name} iteration {i}: misfit {mm[-1]:.6f}")
+            curves[name] = mm
+            del xx
+        ctx.set_preconditioner(None)
+        pcg = {"iterations": args.pcgnr, "pseudo_hessian_s": t_ph, "eps_rel": 1e-3,
+               "cgnr_misfit": curves["cgnr"], "pcgnr_misfit": curves["pcgnr"]}
     ctx.close()
     del ctx, d_obs, x
     torch.cuda.empty_cache()
@@ -298,6 +343,8 @@ def main():
         "cg_iter_s_plain": plain,
         "speedup_batched_vs_plain": (plain["cg_iter_s"] / sec) if plain else None,
         "misfit": misfit,
+        "passes": passes,
+        "pcgnr": pcg,
         "kernels": kernels,
         "calibration": calib,
     }
