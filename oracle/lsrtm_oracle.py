@@ -24,6 +24,9 @@ parametrization"):
 * CGNR on the normal equations L^H L dm = L^H dd (section 3, eq. normal and
   the CGNR paragraph), and its preconditioned form with the pseudo-Hessian
   diagonal of appendix B.
+* Image-domain LSRTM with the point-spread-function Hessian (section 3,
+  eq. migdeconobj; appendix C, eq. trilinear): PSF images of a scatterer
+  lattice, the interpolated banded Hessian, mono- and multiparameter.
 
 The paper gives the continuous equations only.  The discrete scheme below is
 one explicit reading of them (all readings are listed in the design notes of
@@ -696,3 +699,112 @@ def pcgnr(L: Callable, Lt: Callable, d, niter: int, minv, dot: Optional[Callable
         zs = zs_new
         hist.append(dot(r, r) / r0)
     return x, hist
+
+
+# ---------------------------------------------------------------------------
+# Point-spread-function Hessian for image-domain LSRTM (appendix C)
+# ---------------------------------------------------------------------------
+def psf_halfwidth(spacing: int) -> int:
+    """Half-width W of the window kept around each scatterer: the windows of
+    neighbouring scatterers (spacing apart) do not overlap, 2W + 1 <= spacing."""
+    return (spacing - 1) // 2
+
+
+def psf_lattice(n_a: int, spacing: int) -> np.ndarray:
+    """Scatterer coordinates along one axis of n_a physical nodes: W, W + s,
+    W + 2s, ... (every s nodes, the first window inside the grid)."""
+    return np.arange(psf_halfwidth(spacing), n_a, spacing)
+
+
+def psf_scatterers(shape, spacing: int, q: int) -> np.ndarray:
+    """Model perturbation (2, *shape) with unit spikes in parameter q (0 =
+    lnVp, 1 = lnIp) on the scatterer lattice (appendix C: point scatterers
+    distributed evenly, all at once)."""
+    ndim = len(shape)
+    dm = np.zeros((2,) + tuple(shape))
+    lat = [psf_lattice(shape[ndim - 1 - a], spacing) for a in range(ndim)]
+    grids = np.meshgrid(*[lat[a] for a in reversed(range(ndim))], indexing="ij")
+    dm[(q,) + tuple(grids)] = 1.0
+    return dm
+
+
+def psf_images(prob: Problem, lnvp, lnip, spacing: int) -> np.ndarray:
+    """PSF images P[q] = L^T L (scatterers in parameter q) (appendix C: one
+    demigration and one migration of the scatterer image).  Shape
+    (2, 2, *physical shape): P[q][p] is the response in parameter p."""
+    out = []
+    for q in range(2):
+        dm = psf_scatterers(lnvp.shape, spacing, q)
+        d = born(prob, lnvp, lnip, dm)
+        out.append(adjoint(prob, lnvp, lnip, d))
+    return np.stack(out)
+
+
+def _psf_cell(j: np.ndarray, lat: np.ndarray):
+    """Lattice corners (c0, c1) and weight w of coordinate(s) j along one
+    axis: linear between neighbouring scatterers, w clamped to [0, 1]
+    outside the lattice (the nearest scatterer's window is used)."""
+    if len(lat) == 1:
+        c = np.full_like(j, lat[0])
+        return c, c, np.zeros(j.shape)
+    s_ = lat[1] - lat[0]
+    k = np.clip((j - lat[0]) // s_, 0, len(lat) - 2)
+    c0 = lat[k]
+    c1 = lat[k + 1]
+    w = np.clip((j - c0) / s_, 0.0, 1.0)
+    return c0, c1, w
+
+
+def psf_hessian(P: np.ndarray, spacing: int, mono: bool = False):
+    """Interpolated PSF Hessian (appendix C, eq. trilinear; bilinear in 2D)
+    as a sparse matrix acting on (dlnVp, dlnIp) flattened in numpy order.
+
+    Column j of block (p, q) is the window of the PSF images around the
+    lattice corners of j, shifted to j and weighted with the multilinear
+    weights: H_pq[j + o, j] = sum_c w_c(j) P[q][p][c + o] for every offset
+    |o_a| <= W with j + o and c + o inside the grid.  mono=True keeps the
+    lnIp block H_22 only (the monoparameter mode)."""
+    from scipy import sparse
+    shape = P.shape[2:]
+    ndim = len(shape)
+    N = int(np.prod(shape))
+    W = psf_halfwidth(spacing)
+    # coordinates (a-order) of every point j
+    idx = np.indices(shape).reshape(ndim, -1)          # numpy axes
+    J = [idx[ndim - 1 - a] for a in range(ndim)]        # axis a coordinate
+    n = [shape[ndim - 1 - a] for a in range(ndim)]
+    lat = [psf_lattice(n[a], spacing) for a in range(ndim)]
+    cells = [_psf_cell(J[a], lat[a]) for a in range(ndim)]
+    blocks = [(1, 1)] if mono else [(p, q) for p in range(2) for q in range(2)]
+    rows, cols, vals = [], [], []
+    offsets = np.array(np.meshgrid(*[np.arange(-W, W + 1)] * ndim, indexing="ij")).reshape(ndim, -1).T
+    for m in range(2 ** ndim):
+        C = []
+        wgt = np.ones(N)
+        for a in range(ndim):
+            c0, c1, w = cells[a]
+            bit = (m >> a) & 1
+            C.append(c1 if bit else c0)
+            wgt = wgt * (w if bit else 1.0 - w)
+        live = wgt != 0.0
+        for o in offsets:
+            R = [J[a] + o[a] for a in range(ndim)]
+            S = [C[a] + o[a] for a in range(ndim)]
+            ok = live.copy()
+            for a in range(ndim):
+                ok &= (R[a] >= 0) & (R[a] < n[a]) & (S[a] >= 0) & (S[a] < n[a])
+            if not ok.any():
+                continue
+            r_lin = np.ravel_multi_index(tuple(R[a][ok] for a in reversed(range(ndim))), shape)
+            s_idx = tuple(S[a][ok] for a in reversed(range(ndim)))
+            j_lin = np.flatnonzero(ok)
+            for bp, (p, q) in enumerate(blocks):
+                v = wgt[ok] * P[q][p][s_idx]
+                ro = 0 if mono else p * N
+                co = 0 if mono else q * N
+                rows.append(r_lin + ro)
+                cols.append(j_lin + co)
+                vals.append(v)
+    M = N if mono else 2 * N
+    return sparse.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                             shape=(M, M))
