@@ -196,6 +196,36 @@ lsrtm_status lsrtm_pseudo_hessian(lsrtm_ctx* ctx, float* h, float* minv, double 
  * ENOMEM, EHIP. */
 lsrtm_status lsrtm_set_preconditioner(lsrtm_ctx* ctx, const float* minv);
 
+/* Image-domain LSRTM with the point-spread-function Hessian (section 3,
+ * eq. migdeconobj; appendix C).  Scatterers sit on a lattice every `spacing`
+ * nodes of every axis, at W, W + spacing, ... with W = (spacing - 1) / 2 the
+ * half-width of the window kept around each scatterer (neighbouring windows
+ * do not overlap).  Errors of all three: EINVAL (NULL pointers, spacing < 1 or
+ * no scatterer on an axis), EHIP; lsrtm_psf_images also ESTATE.
+ *
+ * lsrtm_psf_images: PSF images P[q] = L^T L S_q, S_q the unit scatterers of
+ *   parameter q (0 = lnVp, 1 = lnIp): one Born and one migration pass per q.
+ *   psf: DEVICE float [2 (q)][2 (response p)][nz*nx*ny], written.
+ * lsrtm_psf_apply: y = H x (transpose = 0) or H^T x (transpose = 1) with the
+ *   interpolated Hessian of eq. trilinear (bilinear in 2D):
+ *     H_pq[j + o, j] = sum over the lattice corners c of j of
+ *                      w_c(j) P[q][p][c + o],  |o_a| <= W,
+ *   w_c the multilinear weights of j between its corners (clamped to the
+ *   nearest scatterer outside the lattice), entries with j + o or c + o
+ *   outside the grid dropped.  mono = 0: x, y DEVICE [2][n] (lnVp, lnIp),
+ *   the 2 x 2 block operator; mono = 1: the lnIp block H_22 on [n] vectors.
+ *   x and y must not alias.
+ * lsrtm_psf_cgnr: niter CGNR iterations on H^T H x = H^T m_rtm from x = 0 (the
+ *   paper solves the normal equations of the PSF Hessian because
+ *   interpolation breaks its symmetry).  m_rtm, x: DEVICE, [2][n] or (mono)
+ *   [n]; misfit: HOST double [niter + 1] or NULL, ||H x_k - m_rtm||^2 /
+ *   ||m_rtm||^2.  Needs lsrtm_set_model (FP64 inner products). */
+lsrtm_status lsrtm_psf_images(lsrtm_ctx* ctx, int spacing, float* psf);
+lsrtm_status lsrtm_psf_apply(lsrtm_ctx* ctx, const float* psf, int spacing, int mono, int transpose,
+                             const float* x, float* y);
+lsrtm_status lsrtm_psf_cgnr(lsrtm_ctx* ctx, const float* psf, int spacing, int mono, const float* m_rtm,
+                            int niter, float* x, double* misfit);
+
 /* FP64-accumulated inner product of two DEVICE float vectors of length n;
  * *out is a HOST double.  Deterministic (fixed reduction tree). */
 lsrtm_status lsrtm_dot(lsrtm_ctx* ctx, const float* a, const float* b, long long n, double* out);

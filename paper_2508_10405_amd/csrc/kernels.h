@@ -103,6 +103,20 @@ hipError_t launch_ph_finish(const double* acc, const float* lnvp, const float* l
 hipError_t launch_ph_minv(const float* h, double eps, float* minv, long long n, hipStream_t st);
 hipError_t launch_mul(const float* a, const float* b, float* out, long long n, hipStream_t st);
 
+// Interpolated PSF Hessian (psf.hip).
+struct PsfArgs {
+    int n[3];              // physical sizes (z, x, y); n[2] = 1 in 2D
+    int ndim;
+    int W;                 // window half-width
+    int mono;              // 1 = the lnIp block only
+    long long N;           // n[0] * n[1] * n[2]
+    const int* tab;        // per coordinate of each axis: corner c0, corner c1, weight (float bits)
+    int off[3];            // first coordinate of axis a in tab
+    const float* psf;      // PSF images [2 (scatterer parameter q)][2 (response p)][N]
+};
+hipError_t launch_psf_apply(const PsfArgs& a, const float* x, float* y, int transpose, hipStream_t st);
+hipError_t launch_psf_spikes(const PsfArgs& a, int q, float* dm, hipStream_t st);
+
 // Max |x| of a physical float array (finite check: non-finite -> +inf).
 hipError_t launch_maxabs(const float* x, long long n, float* partial, int nblk, hipStream_t st);
 // Per-block maximum of x (non-finite -> +inf); partial[nblk].

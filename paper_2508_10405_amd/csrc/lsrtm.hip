@@ -138,6 +138,12 @@ struct lsrtm_ctx {
     float* cg_s = nullptr;         // normal residual L^T r when preconditioned
     bool precond = false;          // a preconditioner is set
     bool cg_pre = false;           // the current CG run is preconditioned
+    // PSF Hessian (image domain)
+    int* psf_tab = nullptr;        // corner/weight tables of psf_spacing
+    int psf_spacing = 0;
+    float* psf_dm = nullptr;       // [2][gpts] scatterer model
+    float* psf_d = nullptr;        // data of the scatterer model
+    float* psf_v[4] = {nullptr, nullptr, nullptr, nullptr};   // image-domain CG: r, z, p, w
     // options
     int opt_spl = 0;
     int opt_tile = -1;
@@ -232,6 +238,7 @@ void free_acq(lsrtm_ctx* c) {
     c->ckpart = nullptr;
     c->acc64 = nullptr;
     c->cg_r = c->cg_w = c->cg_z = c->cg_p = nullptr;
+    c->psf_d = nullptr;
     c->cg_active = false;
     c->src_amp = nullptr;
 }
@@ -1670,6 +1677,130 @@ lsrtm_status lsrtm_cgnr_state(lsrtm_ctx* c, int get, float* r, float* z, float* 
         c->cg_k = (int)scal[3];
         c->cg_active = true;
         c->cg_pre = c->precond;
+    }
+    return LSRTM_OK;
+}
+
+// Corner/weight tables of the interpolated PSF Hessian for a lattice spacing
+// (appendix C): scatterers at W, W + s, ... on every axis, W = (s - 1) / 2;
+// coordinate j lies between corners c0 <= c1 with weight (j - c0) / s,
+// clamped to [0, 1] outside the lattice.
+static lsrtm_status psf_setup(lsrtm_ctx* c, const float* psf, int spacing, int mono, PsfArgs* a) {
+    if (spacing < 1) FAIL(c, LSRTM_EINVAL, "PSF spacing must be >= 1");
+    const int W = (spacing - 1) / 2;
+    a->ndim = c->ndim;
+    a->W = W;
+    a->mono = mono ? 1 : 0;
+    a->N = c->gpts;
+    a->psf = psf;
+    long long tot = 0;
+    for (int ax = 0; ax < 3; ++ax) {
+        a->n[ax] = ax < c->ndim ? c->g.n[ax] : 1;
+        a->off[ax] = (int)tot;
+        tot += a->n[ax];
+    }
+    if (!c->psf_tab) CHK(dalloc_t(c, &c->psf_tab, 3 * (size_t)tot, false));
+    a->tab = c->psf_tab;
+    if (c->psf_spacing == spacing) return LSRTM_OK;
+    std::vector<int> tab(3 * tot, 0);
+    for (int ax = 0; ax < c->ndim; ++ax) {
+        const int n = a->n[ax];
+        std::vector<int> lat;
+        for (int v = W; v < n; v += spacing) lat.push_back(v);
+        if (lat.empty()) FAIL(c, LSRTM_EINVAL, "PSF spacing %d leaves no scatterer on axis %d (%d nodes)", spacing, ax, n);
+        for (int j = 0; j < n; ++j) {
+            int c0, c1;
+            double w;
+            if (lat.size() == 1) {
+                c0 = c1 = lat[0];
+                w = 0.0;
+            } else {
+                long long k = (long long)std::floor((double)(j - lat[0]) / spacing);
+                k = std::min<long long>(std::max<long long>(k, 0), (long long)lat.size() - 2);
+                c0 = lat[k];
+                c1 = lat[k + 1];
+                w = std::min(1.0, std::max(0.0, (double)(j - c0) / spacing));
+            }
+            const float wf = (float)w;
+            int* t = &tab[3 * (a->off[ax] + j)];
+            t[0] = c0;
+            t[1] = c1;
+            memcpy(&t[2], &wf, sizeof(float));
+        }
+    }
+    HIPCHK(c, hipMemcpy(c->psf_tab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice));
+    c->psf_spacing = spacing;
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_psf_images(lsrtm_ctx* c, int spacing, float* psf) {
+    CHK(check_ready(c));
+    if (!psf) FAIL(c, LSRTM_EINVAL, "psf is NULL");
+    PsfArgs a;
+    CHK(psf_setup(c, psf, spacing, 0, &a));
+    const long long nm = 2 * c->gpts;
+    if (!c->psf_dm) CHK(dalloc_t(c, &c->psf_dm, nm, false));
+    if (!c->psf_d) CHK(dalloc_t(c, &c->psf_d, std::max(1LL, c->data_len), true));
+    CHK(pass_begin(c));
+    for (int q = 0; q < 2; ++q) {
+        HIPCHK(c, launch_psf_spikes(a, q, c->psf_dm, c->st));
+        CHK(born_impl(c, c->psf_dm, c->psf_d));
+        CHK(adjoint_impl(c, c->psf_d, psf + (long long)q * nm, 0));
+    }
+    CHK(pass_end(c));
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_psf_apply(lsrtm_ctx* c, const float* psf, int spacing, int mono, int transpose,
+                             const float* x, float* y) {
+    if (!c || !psf || !x || !y) return LSRTM_EINVAL;
+    if (x == y) FAIL(c, LSRTM_EINVAL, "x and y must not alias");
+    PsfArgs a;
+    CHK(psf_setup(c, psf, spacing, mono, &a));
+    HIPCHK(c, launch_psf_apply(a, x, y, transpose, c->st));
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_psf_cgnr(lsrtm_ctx* c, const float* psf, int spacing, int mono, const float* m_rtm, int niter,
+                            float* x, double* misfit) {
+    if (!c || !psf || !m_rtm || !x) return LSRTM_EINVAL;
+    if (niter < 0) FAIL(c, LSRTM_EINVAL, "niter < 0");
+    if (!c->dpart) FAIL(c, LSRTM_ESTATE, "set_model must precede lsrtm_psf_cgnr");
+    PsfArgs a;
+    CHK(psf_setup(c, psf, spacing, mono, &a));
+    const long long M = (mono ? 1 : 2) * c->gpts;
+    for (int k = 0; k < 4; ++k)
+        if (!c->psf_v[k]) CHK(dalloc_t(c, &c->psf_v[k], 2 * c->gpts, false));
+    float *r = c->psf_v[0], *z = c->psf_v[1], *p = c->psf_v[2], *w = c->psf_v[3];
+    // CGNR on H^T H x = H^T m_rtm (section 3, eq. migdeconobj), x0 = 0
+    HIPCHK(c, launch_copy(m_rtm, r, M, c->st));
+    HIPCHK(c, launch_fill(x, M, 0.f, c->st));
+    HIPCHK(c, launch_psf_apply(a, r, z, 1, c->st));
+    HIPCHK(c, launch_copy(z, p, M, c->st));
+    double zz, r0;
+    CHK(dot_impl(c, z, z, M, &zz));
+    CHK(dot_impl(c, r, r, M, &r0));
+    double rr = r0;
+    if (misfit) misfit[0] = 1.0;
+    for (int it = 0; it < niter; ++it) {
+        if (zz > 0.0 && r0 > 0.0) {
+            HIPCHK(c, launch_psf_apply(a, p, w, 0, c->st));
+            double ww;
+            CHK(dot_impl(c, w, w, M, &ww));
+            if (ww > 0.0) {
+                const double alpha = zz / ww;
+                HIPCHK(c, launch_axpy(alpha, p, x, M, c->st));
+                HIPCHK(c, launch_axpy(-alpha, w, r, M, c->st));
+                HIPCHK(c, launch_psf_apply(a, r, z, 1, c->st));
+                double zz1;
+                CHK(dot_impl(c, z, z, M, &zz1));
+                const double beta = zz1 / zz;
+                HIPCHK(c, launch_xpby(z, beta, p, M, c->st));
+                zz = zz1;
+            }
+            CHK(dot_impl(c, r, r, M, &rr));
+        }
+        if (misfit) misfit[it + 1] = r0 > 0.0 ? rr / r0 : 0.0;
     }
     return LSRTM_OK;
 }

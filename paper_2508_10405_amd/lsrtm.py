@@ -59,6 +59,9 @@ SIGNATURES = {
     "lsrtm_cgnr_state": (_c_int, [_vp, _c_int, _vp, _vp, _vp, ctypes.POINTER(_c_double)]),
     "lsrtm_pseudo_hessian": (_c_int, [_vp, _vp, _vp, _c_double]),
     "lsrtm_set_preconditioner": (_c_int, [_vp, _vp]),
+    "lsrtm_psf_images": (_c_int, [_vp, _c_int, _vp]),
+    "lsrtm_psf_apply": (_c_int, [_vp, _vp, _c_int, _c_int, _c_int, _vp, _vp]),
+    "lsrtm_psf_cgnr": (_c_int, [_vp, _vp, _c_int, _c_int, _vp, _c_int, _vp, ctypes.POINTER(_c_double)]),
     "lsrtm_dot": (_c_int, [_vp, _vp, _vp, _c_ll, ctypes.POINTER(_c_double)]),
     "lsrtm_axpy": (_c_int, [_vp, _c_double, _vp, _vp, _c_ll]),
     "lsrtm_set_option": (_c_int, [_vp, _c_int, _c_ll]),
@@ -325,6 +328,40 @@ class Context:
             if minv.numel() != 2 * int(np.prod(self.shape)):
                 raise ValueError("minv must hold 2 x grid points")
         self._check(lib().lsrtm_set_preconditioner(self._h, _vp(_ptr(minv))), "set_preconditioner")
+
+    def psf_images(self, spacing):
+        """PSF images [2 (scatterer parameter), 2 (response), *shape]
+        (lsrtm_psf_images)."""
+        torch = self._torch
+        psf = torch.empty((2, 2) + self.shape, dtype=torch.float32, device="cuda")
+        self._check(lib().lsrtm_psf_images(self._h, int(spacing), _vp(_ptr(psf))), "psf_images")
+        return psf
+
+    def _psf_vec(self, v, mono, name):
+        _require_cuda(v, name)
+        want = (1 if mono else 2) * int(np.prod(self.shape))
+        if v.numel() != want:
+            raise ValueError(f"{name} must hold {want} values")
+
+    def psf_apply(self, psf, spacing, x, transpose=False, mono=False):
+        """y = H x or H^T x with the interpolated PSF Hessian (lsrtm_psf_apply)."""
+        _require_cuda(psf, "psf")
+        self._psf_vec(x, mono, "x")
+        y = self._torch.empty_like(x)
+        self._check(lib().lsrtm_psf_apply(self._h, _vp(_ptr(psf)), int(spacing), int(bool(mono)),
+                                          int(bool(transpose)), _vp(_ptr(x)), _vp(_ptr(y))), "psf_apply")
+        return y
+
+    def psf_cgnr(self, psf, spacing, m_rtm, niter, mono=False):
+        """Image-domain CGNR with the PSF Hessian; returns x and the misfit
+        history (lsrtm_psf_cgnr)."""
+        _require_cuda(psf, "psf")
+        self._psf_vec(m_rtm, mono, "m_rtm")
+        x = self._torch.empty_like(m_rtm)
+        mis = (_c_double * (niter + 1))()
+        self._check(lib().lsrtm_psf_cgnr(self._h, _vp(_ptr(psf)), int(spacing), int(bool(mono)),
+                                         _vp(_ptr(m_rtm)), int(niter), _vp(_ptr(x)), mis), "psf_cgnr")
+        return x, [float(v) for v in mis]
 
     def dot(self, a, b) -> float:
         _require_cuda(a, "a")

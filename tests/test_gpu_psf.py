@@ -1,0 +1,119 @@
+"""Image-domain LSRTM with the PSF Hessian (appendix C) on the GPU, through
+the C ABI, against the FP64 oracle.
+
+PSF images go through one Born and one migration pass, so they carry the
+bar of the operators (1e-4 relative L2).  The interpolated Hessian products
+sum (2W + 1)^ndim x 2^ndim FP32 terms per point and are held to 1e-5; the
+image-domain CGNR to the bar of the data-domain CGNR test (x within 1e-3,
+misfit within 1e-4).
+"""
+import numpy as np
+import pytest
+
+from oracle import lsrtm_oracle as O
+from paper_2508_10405_amd import synth
+from gpu_common import f64, oracle_problem, rel, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def test_psf_images_vs_oracle(torch):
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((30, 36), nt=110, npml=5, seed=51, nshot=2, uneven=True)
+    print("[case] PSF images 30x36 spacing 6", flush=True)
+    prob = oracle_problem(w)
+    ref = O.psf_images(prob, f64(w.lnvp), f64(w.lnip), 6)
+    ctx = lsrtm.context_for(w)
+    psf = ctx.psf_images(6).cpu().numpy()
+    for q in range(2):
+        for p in range(2):
+            e = rel(psf[q][p], ref[q][p])
+            print("psf", q, p, e, flush=True)
+            assert e <= 1e-4
+    ctx.close()
+
+
+CASES = [((37, 45), 7), ((20, 26), 4), ((17, 19), 1), ((23, 16), 30), ((11, 13, 9), 4)]   # spacing 30: one scatterer per axis
+
+
+@pytest.mark.parametrize("n,spacing", CASES)
+def test_psf_apply_vs_oracle(torch, n, spacing):
+    """H x and H^T x, multi- and monoparameter, against the oracle's sparse
+    Hessian built from the same PSF images (random images, so every entry of
+    every block is exercised)."""
+    from paper_2508_10405_amd import lsrtm
+    print(f"[case] PSF apply {n} spacing {spacing}", flush=True)
+    shape = tuple(reversed(n))
+    ctx = lsrtm.Context(n, (10.0,) * len(n), 10, 1e-3)
+    rng = np.random.default_rng(sum(n) + spacing)
+    P = rng.standard_normal((2, 2) + shape).astype(np.float32)
+    psf = to_dev(torch, P)
+    for mono in (False, True):
+        H = O.psf_hessian(P.astype(np.float64), spacing, mono=mono)
+        x = rng.standard_normal(((1,) if mono else (2,)) + shape).astype(np.float32)
+        xd = to_dev(torch, x)
+        for tr in (False, True):
+            y = ctx.psf_apply(psf, spacing, xd, transpose=tr, mono=mono).cpu().numpy().reshape(-1)
+            ref = (H.T if tr else H) @ x.astype(np.float64).reshape(-1)
+            e = rel(y, ref)
+            print("mono", mono, "transpose", tr, "rel", e, flush=True)
+            assert e <= 1e-5
+    ctx.close()
+
+
+def test_psf_apply_adjoint(torch):
+    from paper_2508_10405_amd import lsrtm
+    n, spacing = (64, 75), 9
+    shape = tuple(reversed(n))
+    ctx = lsrtm.Context(n, (10.0, 10.0), 10, 1e-3)
+    rng = np.random.default_rng(3)
+    psf = to_dev(torch, rng.standard_normal((2, 2) + shape))
+    x = to_dev(torch, rng.standard_normal((2,) + shape))
+    y = to_dev(torch, rng.standard_normal((2,) + shape))
+    hx = ctx.psf_apply(psf, spacing, x)
+    hty = ctx.psf_apply(psf, spacing, y, transpose=True)
+    a = float((hx.double() * y.double()).sum())
+    b = float((x.double() * hty.double()).sum())
+    print("psf dot", a, b, abs(a - b) / abs(a), flush=True)
+    assert abs(a - b) <= 1e-5 * abs(a)
+    ctx.close()
+
+
+@pytest.mark.parametrize("mono", [False, True])
+def test_psf_cgnr_vs_oracle(torch, mono):
+    """Image-domain inversion of an RTM image: five CGNR iterations on the
+    PSF Hessian against the oracle's CGNR on the same sparse operator."""
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((36, 44), nt=120, npml=6, seed=52, nshot=3, uneven=True)
+    ctx = lsrtm.context_for(w)
+    spacing = 7
+    psf = ctx.psf_images(spacing)
+    m_rtm = ctx.adjoint(ctx.born(to_dev(torch, w.dm)))
+    rhs = m_rtm[1].contiguous() if mono else m_rtm
+    x, hist = ctx.psf_cgnr(psf, spacing, rhs, 5, mono=mono)
+    H = O.psf_hessian(psf.cpu().numpy().astype(np.float64), spacing, mono=mono)
+    b = rhs.cpu().numpy().astype(np.float64).reshape(-1)
+    x_ref, hist_ref = O.cgnr(lambda v: H @ v, lambda v: H.T @ v, b, 5)
+    e = rel(x.cpu().numpy().reshape(-1), x_ref)
+    print("psf cgnr mono", mono, "x rel", e, hist, hist_ref, flush=True)
+    assert e <= 1e-3
+    assert np.allclose(hist, hist_ref, atol=1e-4)
+    assert all(hist[i + 1] <= hist[i] + 1e-6 for i in range(5))
+    ctx.close()
+
+
+def test_psf_errors(torch):
+    from paper_2508_10405_amd import lsrtm
+    ctx = lsrtm.Context((12, 10), (10.0, 10.0), 10, 1e-3)
+    psf = torch.zeros((2, 2, 10, 12), device="cuda")
+    x = torch.zeros((2, 10, 12), device="cuda")
+    with pytest.raises(lsrtm.LsrtmError):
+        ctx.psf_apply(psf, 40, x)              # W = 19: no scatterer inside 12 nodes
+    with pytest.raises(lsrtm.LsrtmError):
+        ctx.psf_apply(psf, 0, x)
+    ctx.close()
