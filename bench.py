@@ -144,6 +144,9 @@ def main():
     ap.add_argument("--pcgnr", type=int, default=0,
                     help="also run N CGNR and N pseudo-Hessian-preconditioned CGNR iterations from x = 0 "
                          "and report both misfit curves (untimed for value)")
+    ap.add_argument("--psf", type=int, default=0,
+                    help="also run image-domain LSRTM with the PSF Hessian: scatterers every N nodes, "
+                         "10 multi- and 10 monoparameter CGNR iterations on the RTM image (untimed for value)")
     ap.add_argument("--nt", type=int, default=0,
                     help="truncate the time axis to nt steps (0 = the workload's own); for counter "
                          "profiles, whose per-launch figures do not depend on nt")
@@ -262,6 +265,34 @@ def main():
         ctx.set_preconditioner(None)
         pcg = {"iterations": args.pcgnr, "pseudo_hessian_s": t_ph, "eps_rel": 1e-3,
                "cgnr_misfit": curves["cgnr"], "pcgnr_misfit": curves["pcgnr"]}
+
+    psf_out = None
+    if args.psf > 0:
+        sp = args.psf
+        torch.cuda.synchronize()
+        ts0 = time.perf_counter()
+        psf = ctx.psf_images(sp)
+        torch.cuda.synchronize()
+        t_img = time.perf_counter() - ts0
+        m_rtm = ctx.adjoint(d_obs)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ctx.psf_apply(psf, sp, m_rtm)                     # warm-up
+        e0.record()
+        for _ in range(5):
+            ctx.psf_apply(psf, sp, m_rtm)
+        e1.record()
+        torch.cuda.synchronize()
+        t_mv = e0.elapsed_time(e1) / 5
+        res = {}
+        for mono in (False, True):
+            rhs = m_rtm[1].contiguous() if mono else m_rtm
+            tc0 = time.perf_counter()
+            _, hist = ctx.psf_cgnr(psf, sp, rhs, 10, mono=mono)
+            torch.cuda.synchronize()
+            res["mono" if mono else "multi"] = {"misfit": hist, "s": time.perf_counter() - tc0}
+        psf_out = {"spacing": sp, "window": 2 * ((sp - 1) // 2) + 1, "psf_images_s": t_img,
+                   "matvec_ms": t_mv, "cgnr_multi": res["multi"], "cgnr_mono": res["mono"]}
+        log(f"[bench] psf {psf_out}")
     ctx.close()
     del ctx, d_obs, x
     torch.cuda.empty_cache()
@@ -345,6 +376,7 @@ def main():
         "misfit": misfit,
         "passes": passes,
         "pcgnr": pcg,
+        "psf": psf_out,
         "kernels": kernels,
         "calibration": calib,
     }
