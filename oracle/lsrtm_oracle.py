@@ -27,6 +27,9 @@ parametrization"):
 * Image-domain LSRTM with the point-spread-function Hessian (section 3,
   eq. migdeconobj; appendix C, eq. trilinear): PSF images of a scatterer
   lattice, the interpolated banded Hessian, mono- and multiparameter.
+* Nonstationary Wiener deblurring (appendix D, eq. sol and the regularised
+  least-squares estimate of the inverse eigenvalues): local blocks, Fourier
+  transforms, overlap-add with valences.
 
 The paper gives the continuous equations only.  The discrete scheme below is
 one explicit reading of them (all readings are listed in the design notes of
@@ -808,3 +811,60 @@ def psf_hessian(P: np.ndarray, spacing: int, mono: bool = False):
     M = N if mono else 2 * N
     return sparse.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                              shape=(M, M))
+
+
+# ---------------------------------------------------------------------------
+# Nonstationary Wiener deblurring (appendix D)
+# ---------------------------------------------------------------------------
+def wiener_starts(n_a: int, block: int) -> np.ndarray:
+    """Window origins along one axis: every block/2 nodes from -block/2, so
+    that every node lies in exactly two windows."""
+    h = block // 2
+    return np.arange((n_a - 1) // h + 2) * h - h
+
+
+def wiener_taper(block: int) -> np.ndarray:
+    """sin^2 taper of one axis; shifted by block/2 the tapers of the two
+    windows over a node add up to one."""
+    u = np.arange(block)
+    return np.sin(np.pi * (u + 0.5) / block) ** 2
+
+
+def wiener_deblur(m_ref: np.ndarray, m_blur: np.ndarray, m_in: np.ndarray,
+                  block: int, eps_rel: float) -> np.ndarray:
+    """Nonstationary Wiener filter of appendix D on one image.
+
+    The Hessian is taken as locally translation invariant, hence diagonal in
+    the Fourier basis of each local block: with F the block's Fourier
+    transform, the inverse eigenvalues minimise
+    ||F m_ref - Lambda^-1 F m_blur||^2 + eps ||Lambda^-1||^2, i.e.
+    Lambda^-1 = conj(F m_blur) F m_ref / (|F m_blur|^2 + eps), and the block's
+    estimate is F^-1 [Lambda^-1 F m_in] (eq. sol).  Blocks are tapered
+    (wiener_taper in every axis), eps = eps_rel * max |F m_blur|^2 of the
+    block, and the estimates are merged with their valences:
+    dm = sum_w dm_w / sum_w t_w, t_w the block's taper at the node."""
+    shape = m_ref.shape
+    nd = m_ref.ndim
+    T = 1.0
+    for _ in range(nd):
+        T = np.multiply.outer(T, wiener_taper(block)) if np.ndim(T) else wiener_taper(block)
+    out = np.zeros(shape)
+    wsum = np.zeros(shape)
+    starts = [wiener_starts(shape[k], block) for k in range(nd)]
+    for origin in np.array(np.meshgrid(*starts, indexing="ij")).reshape(nd, -1).T:
+        src = tuple(slice(max(o, 0), min(o + block, shape[k])) for k, o in enumerate(origin))
+        dst = tuple(slice(max(o, 0) - o, min(o + block, shape[k]) - o) for k, o in enumerate(origin))
+        blk = []
+        for img in (m_ref, m_blur, m_in):
+            b = np.zeros((block,) * nd)
+            b[dst] = img[src]
+            blk.append(np.fft.fftn(T * b))
+        A, B, C = blk
+        pw = (B * np.conj(B)).real
+        mx = pw.max()
+        if mx > 0:
+            G = np.conj(B) * A / (pw + eps_rel * mx)
+            d = np.fft.ifftn(G * C).real
+            out[src] += d[dst]
+        wsum[src] += T[dst]
+    return out / wsum
