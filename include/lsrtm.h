@@ -226,6 +226,23 @@ lsrtm_status lsrtm_psf_apply(lsrtm_ctx* ctx, const float* psf, int spacing, int 
 lsrtm_status lsrtm_psf_cgnr(lsrtm_ctx* ctx, const float* psf, int spacing, int mono, const float* m_rtm,
                             int niter, float* x, double* misfit);
 
+/* Nonstationary Wiener deblurring (appendix D).  The Hessian is taken as
+ * locally translation invariant, hence diagonal in the Fourier basis of each
+ * local block; per block (F its Fourier transform) the regularised inverse
+ * eigenvalues are Lambda^-1 = conj(F m_blur) F m_ref / (|F m_blur|^2 + eps),
+ * eps = eps_rel * max |F m_blur|^2 of the block, and the block estimate is
+ * F^-1[Lambda^-1 F m_in] (eq. sol).  Blocks of `block` nodes per axis (even)
+ * start every block/2 nodes from -block/2 (zero outside the image), tapered by
+ * sin^2(pi (u + 1/2) / block) per axis; the estimates are merged with these
+ * valences, out = sum_w dm_w / sum_w t_w.  The paper's use: m_ref = m_in =
+ * the RTM image, m_blur = its remigration L^T L m_rtm.
+ * m_ref, m_blur, m_in, out: DEVICE float [nimg][nz*nx*ny] (each image
+ * filtered on its own; out may alias an input).  FFT plans and a work buffer
+ * of 3 * blocks * block^ndim complex values are kept in the context.
+ * Errors: EINVAL (NULL, nimg < 1, odd or < 2 block, eps_rel < 0), EHIP. */
+lsrtm_status lsrtm_wiener(lsrtm_ctx* ctx, const float* m_ref, const float* m_blur, const float* m_in,
+                          int nimg, int block, double eps_rel, float* out);
+
 /* FP64-accumulated inner product of two DEVICE float vectors of length n;
  * *out is a HOST double.  Deterministic (fixed reduction tree). */
 lsrtm_status lsrtm_dot(lsrtm_ctx* ctx, const float* a, const float* b, long long n, double* out);

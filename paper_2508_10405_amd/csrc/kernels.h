@@ -117,6 +117,14 @@ struct PsfArgs {
 hipError_t launch_psf_apply(const PsfArgs& a, const float* x, float* y, int transpose, hipStream_t st);
 hipError_t launch_psf_spikes(const PsfArgs& a, int q, float* dm, hipStream_t st);
 
+// Nonstationary Wiener deblurring (wiener.hip): FFT plans and buffers kept
+// between calls; returns nullptr or an error message.
+struct WienerWork;
+const char* wiener_apply(WienerWork** work, int ndim, const int n[3], int block, double eps_rel,
+                         const float* ref, const float* blur, const float* in, int nimg, float* out,
+                         hipStream_t st);
+void wiener_free(WienerWork* w);
+
 // Max |x| of a physical float array (finite check: non-finite -> +inf).
 hipError_t launch_maxabs(const float* x, long long n, float* partial, int nblk, hipStream_t st);
 // Per-block maximum of x (non-finite -> +inf); partial[nblk].

@@ -144,6 +144,7 @@ struct lsrtm_ctx {
     float* psf_dm = nullptr;       // [2][gpts] scatterer model
     float* psf_d = nullptr;        // data of the scatterer model
     float* psf_v[4] = {nullptr, nullptr, nullptr, nullptr};   // image-domain CG: r, z, p, w
+    WienerWork* wiener = nullptr;  // FFT plans and buffers of the Wiener filter
     // options
     int opt_spl = 0;
     int opt_tile = -1;
@@ -1342,6 +1343,7 @@ void lsrtm_destroy(lsrtm_ctx* c) {
     }
     if (c->pa) (void)hipEventDestroy(c->pa);
     if (c->pb) (void)hipEventDestroy(c->pb);
+    wiener_free(c->wiener);
     delete c;
 }
 
@@ -1802,6 +1804,16 @@ lsrtm_status lsrtm_psf_cgnr(lsrtm_ctx* c, const float* psf, int spacing, int mon
         }
         if (misfit) misfit[it + 1] = r0 > 0.0 ? rr / r0 : 0.0;
     }
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_wiener(lsrtm_ctx* c, const float* m_ref, const float* m_blur, const float* m_in, int nimg,
+                          int block, double eps_rel, float* out) {
+    if (!c || !m_ref || !m_blur || !m_in || !out || nimg < 1) return LSRTM_EINVAL;
+    int n[3];
+    for (int a = 0; a < 3; ++a) n[a] = a < c->ndim ? c->g.n[a] : 1;
+    const char* err = wiener_apply(&c->wiener, c->ndim, n, block, eps_rel, m_ref, m_blur, m_in, nimg, out, c->st);
+    if (err) FAIL(c, strstr(err, "must") ? LSRTM_EINVAL : LSRTM_EHIP, "wiener: %s", err);
     return LSRTM_OK;
 }
 

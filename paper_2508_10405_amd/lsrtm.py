@@ -60,6 +60,7 @@ SIGNATURES = {
     "lsrtm_pseudo_hessian": (_c_int, [_vp, _vp, _vp, _c_double]),
     "lsrtm_set_preconditioner": (_c_int, [_vp, _vp]),
     "lsrtm_psf_images": (_c_int, [_vp, _c_int, _vp]),
+    "lsrtm_wiener": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _c_int, _c_double, _vp]),
     "lsrtm_psf_apply": (_c_int, [_vp, _vp, _c_int, _c_int, _c_int, _vp, _vp]),
     "lsrtm_psf_cgnr": (_c_int, [_vp, _vp, _c_int, _c_int, _vp, _c_int, _vp, ctypes.POINTER(_c_double)]),
     "lsrtm_dot": (_c_int, [_vp, _vp, _vp, _c_ll, ctypes.POINTER(_c_double)]),
@@ -362,6 +363,21 @@ class Context:
         self._check(lib().lsrtm_psf_cgnr(self._h, _vp(_ptr(psf)), int(spacing), int(bool(mono)),
                                          _vp(_ptr(m_rtm)), int(niter), _vp(_ptr(x)), mis), "psf_cgnr")
         return x, [float(v) for v in mis]
+
+    def wiener(self, m_ref, m_blur, m_in=None, block=64, eps_rel=1e-3):
+        """Nonstationary Wiener deblurring (lsrtm_wiener) of one image or a
+        stack [k, *shape]; m_in defaults to m_ref."""
+        m_in = m_ref if m_in is None else m_in
+        n = int(np.prod(self.shape))
+        for t, name in ((m_ref, "m_ref"), (m_blur, "m_blur"), (m_in, "m_in")):
+            _require_cuda(t, name)
+            if t.numel() % n or t.numel() != m_ref.numel():
+                raise ValueError(f"{name} must hold a whole number of images")
+        out = self._torch.empty_like(m_ref)
+        self._check(lib().lsrtm_wiener(self._h, _vp(_ptr(m_ref)), _vp(_ptr(m_blur)), _vp(_ptr(m_in)),
+                                       m_ref.numel() // n, int(block), float(eps_rel), _vp(_ptr(out))),
+                    "wiener")
+        return out
 
     def dot(self, a, b) -> float:
         _require_cuda(a, "a")
