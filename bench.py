@@ -147,6 +147,9 @@ def main():
     ap.add_argument("--psf", type=int, default=0,
                     help="also run image-domain LSRTM with the PSF Hessian: scatterers every N nodes, "
                          "10 multi- and 10 monoparameter CGNR iterations on the RTM image (untimed for value)")
+    ap.add_argument("--wiener", type=int, default=0,
+                    help="also run the nonstationary Wiener deblurring of the RTM image with blocks of N "
+                         "nodes (untimed for value)")
     ap.add_argument("--nt", type=int, default=0,
                     help="truncate the time axis to nt steps (0 = the workload's own); for counter "
                          "profiles, whose per-launch figures do not depend on nt")
@@ -293,6 +296,27 @@ def main():
         psf_out = {"spacing": sp, "window": 2 * ((sp - 1) // 2) + 1, "psf_images_s": t_img,
                    "matvec_ms": t_mv, "cgnr_multi": res["multi"], "cgnr_mono": res["mono"]}
         log(f"[bench] psf {psf_out}")
+
+    wiener_out = None
+    if args.wiener > 0:
+        m_rtm = ctx.adjoint(d_obs)
+        torch.cuda.synchronize()
+        tw0 = time.perf_counter()
+        m_rem = ctx.adjoint(ctx.born(m_rtm))
+        torch.cuda.synchronize()
+        tw1 = time.perf_counter()
+        ctx.wiener(m_rtm, m_rem, block=args.wiener)        # plans and buffers
+        torch.cuda.synchronize()
+        tw2 = time.perf_counter()
+        out = ctx.wiener(m_rtm, m_rem, block=args.wiener)
+        torch.cuda.synchronize()
+        tw3 = time.perf_counter()
+        dmt = torch.from_numpy(w.dm).to(dev)
+        corr = [float((out[k] * dmt[k]).sum() / (out[k].norm() * dmt[k].norm() + 1e-30)) for k in range(2)]
+        corr_rtm = [float((m_rtm[k] * dmt[k]).sum() / (m_rtm[k].norm() * dmt[k].norm() + 1e-30)) for k in range(2)]
+        wiener_out = {"block": args.wiener, "remigration_s": tw1 - tw0, "first_call_s": tw2 - tw1,
+                      "filter_s": tw3 - tw2, "corr_with_true_dm": corr, "corr_rtm_with_true_dm": corr_rtm}
+        log(f"[bench] wiener {wiener_out}")
     ctx.close()
     del ctx, d_obs, x
     torch.cuda.empty_cache()
@@ -377,6 +401,7 @@ def main():
         "passes": passes,
         "pcgnr": pcg,
         "psf": psf_out,
+        "wiener": wiener_out,
         "kernels": kernels,
         "calibration": calib,
     }
