@@ -30,6 +30,8 @@ parametrization"):
 * Nonstationary Wiener deblurring (appendix D, eq. sol and the regularised
   least-squares estimate of the inverse eigenvalues): local blocks, Fourier
   transforms, overlap-add with valences.
+* The nonlinear-residual data preparation (section 4.1): a top mute of the
+  direct arrival on observed-minus-background data.
 
 The paper gives the continuous equations only.  The discrete scheme below is
 one explicit reading of them (all readings are listed in the design notes of
@@ -868,3 +870,31 @@ def wiener_deblur(m_ref: np.ndarray, m_blur: np.ndarray, m_in: np.ndarray,
             out[src] += d[dst]
         wsum[src] += T[dst]
     return out / wsum
+
+
+# ---------------------------------------------------------------------------
+# Data preparation: top mute (section 4.1)
+# ---------------------------------------------------------------------------
+def mute_weights(prob: Problem, s: int, v_mute: float, t0: float, ntaper: int) -> np.ndarray:
+    """Weights (nt, nrec_s) of the top mute of shot s (the paper mutes the
+    direct arrival of its nonlinear residual data without stating how):
+    with D the source-receiver distance, tc = t0 + D / v_mute; a sample
+    recorded at t = (n + 1) dt before tc gets 0, the next ntaper samples
+    0.5 (1 - cos(pi (t - tc) / (ntaper dt))), the rest 1."""
+    rec = np.asarray(prob.rec[s], dtype=np.float64).reshape(-1, prob.ndim)
+    src = np.asarray(prob.src[s], dtype=np.float64)
+    dist = np.sqrt(np.sum(((rec - src) * np.asarray(prob.h)) ** 2, axis=1))
+    tc = t0 + dist / v_mute
+    t = (np.arange(prob.nt) + 1.0)[:, None] * prob.dt
+    w = np.ones((prob.nt, len(tc)))
+    w[t < tc] = 0.0
+    if ntaper > 0:
+        ramp = (t >= tc) & (t < tc + ntaper * prob.dt)
+        w = np.where(ramp, 0.5 * (1.0 - np.cos(np.pi * (t - tc) / (ntaper * prob.dt))), w)
+    return w
+
+
+def mute(prob: Problem, ds: Sequence[np.ndarray], v_mute: float, t0: float = 0.0,
+         ntaper: int = 0) -> List[np.ndarray]:
+    """Top mute of every shot's data (nt, nrec_s)."""
+    return [d * mute_weights(prob, s, v_mute, t0, ntaper) for s, d in enumerate(ds)]
