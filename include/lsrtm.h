@@ -226,6 +226,17 @@ lsrtm_status lsrtm_psf_apply(lsrtm_ctx* ctx, const float* psf, int spacing, int 
 lsrtm_status lsrtm_psf_cgnr(lsrtm_ctx* ctx, const float* psf, int spacing, int mono, const float* m_rtm,
                             int niter, float* x, double* misfit);
 
+/* Top mute of recorded data, in place (the nonlinear-residual data
+ * preparation of section 4.1: observed minus background data with the direct
+ * arrival muted; the paper does not state the mute).  For shot s and receiver
+ * r at distance D (metres, physical node coordinates times h), samples
+ * recorded before tc = t0 + D / v_mute are zeroed and the next ntaper samples
+ * ramp up with 0.5 (1 - cos(pi (t - tc) / (ntaper dt))); sample n is recorded
+ * at time (n + 1) dt.  d: DEVICE float [data length] in the layout of
+ * lsrtm_forward.  Synchronises the stream.  Errors: EINVAL (v_mute <= 0,
+ * ntaper < 0, NULL d), ESTATE (no acquisition), EHIP. */
+lsrtm_status lsrtm_mute(lsrtm_ctx* ctx, float* d, double v_mute, double t0, int ntaper);
+
 /* Nonstationary Wiener deblurring (appendix D).  The Hessian is taken as
  * locally translation invariant, hence diagonal in the Fourier basis of each
  * local block; per block (F its Fourier transform) the regularised inverse

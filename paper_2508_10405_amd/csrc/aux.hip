@@ -286,6 +286,37 @@ hipError_t launch_mul(const float* a, const float* b, float* out, long long n, h
 }
 
 // ---------------------------------------------------------------------------
+// Top mute of recorded data (the nonlinear-residual data preparation)
+// ---------------------------------------------------------------------------
+// Receiver j's trace starts at d + off[j] with stride stride[j]; sample n is
+// recorded at time (n + 1) dt.  Samples before tc[j] are zeroed, the next
+// ntaper samples ramp up with 0.5 (1 - cos(pi (t - tc) / (ntaper dt))).
+__global__ void k_mute(float* __restrict__ d, const long long* __restrict__ off, const int* __restrict__ stride,
+                       const double* __restrict__ tc, int nrec, int nt, double dt, int ntaper) {
+    const long long total = (long long)nrec * nt;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int j = (int)(e % nrec);
+        const int n = (int)(e / nrec);
+        const double t = (n + 1) * dt;
+        double wgt = 1.0;
+        if (t < tc[j]) wgt = 0.0;
+        else if (ntaper > 0 && t < tc[j] + ntaper * dt) wgt = 0.5 * (1.0 - cos(M_PI * (t - tc[j]) / (ntaper * dt)));
+        if (wgt != 1.0) {
+            float* p = d + off[j] + (long long)n * stride[j];
+            *p = (float)(wgt * (double)*p);
+        }
+    }
+}
+
+hipError_t launch_mute(float* d, const long long* off, const int* stride, const double* tc, int nrec, int nt,
+                       double dt, int ntaper, hipStream_t st) {
+    if (nrec <= 0 || nt <= 0) return hipSuccess;
+    k_mute<<<nblocks((long long)nrec * nt), NTHREADS, 0, st>>>(d, off, stride, tc, nrec, nt, dt, ntaper);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Reductions (fixed-shape trees, deterministic)
 // ---------------------------------------------------------------------------
 template <typename T, typename Op>

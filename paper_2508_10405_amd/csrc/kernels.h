@@ -103,6 +103,10 @@ hipError_t launch_ph_finish(const double* acc, const float* lnvp, const float* l
 hipError_t launch_ph_minv(const float* h, double eps, float* minv, long long n, hipStream_t st);
 hipError_t launch_mul(const float* a, const float* b, float* out, long long n, hipStream_t st);
 
+// Top mute of recorded data, in place (aux.hip).
+hipError_t launch_mute(float* d, const long long* off, const int* stride, const double* tc, int nrec, int nt,
+                       double dt, int ntaper, hipStream_t st);
+
 // Interpolated PSF Hessian (psf.hip).
 struct PsfArgs {
     int n[3];              // physical sizes (z, x, y); n[2] = 1 in 2D

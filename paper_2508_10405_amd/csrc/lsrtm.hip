@@ -1807,6 +1807,48 @@ lsrtm_status lsrtm_psf_cgnr(lsrtm_ctx* c, const float* psf, int spacing, int mon
     return LSRTM_OK;
 }
 
+lsrtm_status lsrtm_mute(lsrtm_ctx* c, float* d, double v_mute, double t0, int ntaper) {
+    if (!c) return LSRTM_EINVAL;
+    if (!c->have_acq) FAIL(c, LSRTM_ESTATE, "set_acquisition must precede lsrtm_mute");
+    if (!(v_mute > 0.0) || ntaper < 0 || !std::isfinite(t0)) FAIL(c, LSRTM_EINVAL, "bad mute parameters");
+    if (!d && c->data_len > 0) FAIL(c, LSRTM_EINVAL, "d is NULL");
+    const int nd = c->ndim;
+    const int total = c->a_recptr[c->nshot];
+    if (total == 0) return LSRTM_OK;
+    std::vector<long long> off(total);
+    std::vector<int> stride(total);
+    std::vector<double> tc(total);
+    for (int s = 0; s < c->nshot; ++s) {
+        const int r0 = c->a_recptr[s], nr = c->a_recptr[s + 1] - r0;
+        for (int r = 0; r < nr; ++r) {
+            double d2 = 0.0;
+            for (int a = 0; a < nd; ++a) {
+                const double x = (c->a_rec[(size_t)(r0 + r) * nd + a] - c->a_src[(size_t)s * nd + a]) * c->g.h[a];
+                d2 += x * x;
+            }
+            off[r0 + r] = (long long)c->g.nt * r0 + r;
+            stride[r0 + r] = nr;
+            tc[r0 + r] = t0 + std::sqrt(d2) / v_mute;
+        }
+    }
+    long long* d_off = nullptr;
+    int* d_stride = nullptr;
+    double* d_tc = nullptr;
+    HIPCHK(c, hipMalloc(&d_off, total * sizeof(long long)));
+    hipError_t e = hipMalloc(&d_stride, total * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&d_tc, total * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(d_off, off.data(), total * sizeof(long long), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_stride, stride.data(), total * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_tc, tc.data(), total * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_mute(d, d_off, d_stride, d_tc, total, c->g.nt, c->g.dt, ntaper, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    (void)hipFree(d_off);
+    (void)hipFree(d_stride);
+    (void)hipFree(d_tc);
+    if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "mute: %s", hipGetErrorString(e));
+    return LSRTM_OK;
+}
+
 lsrtm_status lsrtm_wiener(lsrtm_ctx* c, const float* m_ref, const float* m_blur, const float* m_in, int nimg,
                           int block, double eps_rel, float* out) {
     if (!c || !m_ref || !m_blur || !m_in || !out || nimg < 1) return LSRTM_EINVAL;

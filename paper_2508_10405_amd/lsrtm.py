@@ -61,6 +61,7 @@ SIGNATURES = {
     "lsrtm_set_preconditioner": (_c_int, [_vp, _vp]),
     "lsrtm_psf_images": (_c_int, [_vp, _c_int, _vp]),
     "lsrtm_wiener": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _c_int, _c_double, _vp]),
+    "lsrtm_mute": (_c_int, [_vp, _vp, _c_double, _c_double, _c_int]),
     "lsrtm_psf_apply": (_c_int, [_vp, _vp, _c_int, _c_int, _c_int, _vp, _vp]),
     "lsrtm_psf_cgnr": (_c_int, [_vp, _vp, _c_int, _c_int, _vp, _c_int, _vp, ctypes.POINTER(_c_double)]),
     "lsrtm_dot": (_c_int, [_vp, _vp, _vp, _c_ll, ctypes.POINTER(_c_double)]),
@@ -363,6 +364,14 @@ class Context:
         self._check(lib().lsrtm_psf_cgnr(self._h, _vp(_ptr(psf)), int(spacing), int(bool(mono)),
                                          _vp(_ptr(m_rtm)), int(niter), _vp(_ptr(x)), mis), "psf_cgnr")
         return x, [float(v) for v in mis]
+
+    def mute(self, d, v_mute, t0=0.0, ntaper=0):
+        """Top mute of a data vector in place (lsrtm_mute); returns d."""
+        _require_cuda(d, "d")
+        if d.numel() != self.data_len:
+            raise ValueError("d must hold the data length")
+        self._check(lib().lsrtm_mute(self._h, _vp(_ptr(d)), float(v_mute), float(t0), int(ntaper)), "mute")
+        return d
 
     def wiener(self, m_ref, m_blur, m_in=None, block=64, eps_rel=1e-3):
         """Nonstationary Wiener deblurring (lsrtm_wiener) of one image or a
