@@ -50,6 +50,15 @@ __device__ __forceinline__ void node_of(int r, int& lz, int& lx) {
     lx = e / BZ;
 }
 
+// Whether a tile (with the halo its staging reads) reaches a CPML strip; the
+// tiles that do not (most of them) skip every CPML coefficient and memory
+// load -- the coefficients are zero there.  Uniform over the workgroup.
+template <int BZ, int BX>
+__device__ __forceinline__ bool tile_in_pml(int z0, int x0, int nz, int nx, int npml) {
+    return z0 - HW - 1 < npml || z0 + BZ + HW >= nz - npml - 1 ||
+           x0 - HW - 1 < npml || x0 + BX + HW >= nx - npml - 1;
+}
+
 // ---------------------------------------------------------------------------
 // V phase
 // ---------------------------------------------------------------------------
@@ -75,6 +84,7 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const gfloat* bchz = S.cpml[0] + nz;
     const gfloat* achx = S.cpml[1];
     const gfloat* bchx = S.cpml[1] + nx;
+    const bool pml = tile_in_pml<BZ, BX>(z0, x0, nz, nx, npml);
     // pointwise loads, CPML coefficients and (inside the strips) memories
     float vz[R], vx[R], bz[R], bx[R], wz[R], wx[R], r0[R], r1z[R], r1x[R];
     float az[R], ax[R], cz[R], cx[R], m0[R], m1[R], n0[R], n1[R];
@@ -92,15 +102,15 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         vx[r] = S.v[1][i];
         bz[r] = S.bdt[0][i];
         bx[r] = S.bdt[1][i];
-        az[r] = achz[ok[r] ? gz : 0];
-        ax[r] = achx[ok[r] ? gx : 0];
-        cz[r] = bchz[ok[r] ? gz : 0];
-        cx[r] = bchx[ok[r] ? gx : 0];
-        m0[r] = S.psi[0][iz];
-        m1[r] = S.psi[1][ix];
+        az[r] = pml ? achz[ok[r] ? gz : 0] : 0.f;
+        ax[r] = pml ? achx[ok[r] ? gx : 0] : 0.f;
+        cz[r] = pml ? bchz[ok[r] ? gz : 0] : 0.f;
+        cx[r] = pml ? bchx[ok[r] ? gx : 0] : 0.f;
+        m0[r] = pml ? S.psi[0][iz] : 0.f;
+        m1[r] = pml ? S.psi[1][ix] : 0.f;
         if (BORN) {
-            n0[r] = S.xi[0][iz];
-            n1[r] = S.xi[1][ix];
+            n0[r] = pml ? S.xi[0][iz] : 0.f;
+            n1[r] = pml ? S.xi[1][ix] : 0.f;
             wz[r] = S.w[0][i];
             wx[r] = S.w[1][i];
             r0[r] = S.dlnr[i];
@@ -155,8 +165,9 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         S.v[0][i] = vz[r] + dvz;
         S.v[1][i] = vx[r] + dvx;
         if (SEG) {
-            seg[i] = dvz;
-            seg[S.npts + i] = dvx;
+            // the replay buffer is read back only k steps later: streaming stores
+            __builtin_nontemporal_store(dvz, &seg[i]);
+            __builtin_nontemporal_store(dvx, &seg[S.npts + i]);
         }
         if (!BORN && !SEG && (flag & PH_ACCUMULATE)) {   // pseudo-Hessian: sum of dv_a^2
             S.w[0][i] = S.w[0][i] + dvz * dvz;
@@ -210,6 +221,7 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const gfloat* bciz = S.cpml[0] + 3 * nz;
     const gfloat* acix = S.cpml[1] + 2 * nx;
     const gfloat* bcix = S.cpml[1] + 3 * nx;
+    const bool pml = tile_in_pml<BZ, BX>(z0, x0, nz, nx, npml);
     // pointwise loads, CPML coefficients and (inside the strips) memories
     float pp[R], kk[R], qq[R], lk[R], az[R], ax[R], cz[R], cx[R], m0[R], m1[R], n0[R], n1[R];
     bool ok[R];
@@ -224,17 +236,17 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const long long ix = ok[r] && in_pml(gx, nx, npml) ? i : 0;
         pp[r] = S.p[i];
         kk[r] = S.kdt[i];
-        az[r] = aciz[ok[r] ? gz : 0];
-        ax[r] = acix[ok[r] ? gx : 0];
-        cz[r] = bciz[ok[r] ? gz : 0];
-        cx[r] = bcix[ok[r] ? gx : 0];
-        m0[r] = S.phi[0][iz];
-        m1[r] = S.phi[1][ix];
+        az[r] = pml ? aciz[ok[r] ? gz : 0] : 0.f;
+        ax[r] = pml ? acix[ok[r] ? gx : 0] : 0.f;
+        cz[r] = pml ? bciz[ok[r] ? gz : 0] : 0.f;
+        cx[r] = pml ? bcix[ok[r] ? gx : 0] : 0.f;
+        m0[r] = pml ? S.phi[0][iz] : 0.f;
+        m1[r] = pml ? S.phi[1][ix] : 0.f;
         if (BORN) {
             qq[r] = S.q[i];
             lk[r] = S.dlnk[i];
-            n0[r] = S.eta[0][iz];
-            n1[r] = S.eta[1][ix];
+            n0[r] = pml ? S.eta[0][iz] : 0.f;
+            n1[r] = pml ? S.eta[1][ix] : 0.f;
         }
     }
     auto inside = [&](int lz, int lx) {
@@ -298,7 +310,7 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         float pn = pp[r] - k * q;
         if (i == S.src) pn = pn + amp;
         S.p[i] = pn;
-        if (SEG) seg[i] = q;
+        if (SEG) __builtin_nontemporal_store(q, &seg[i]);
         if (!BORN && !SEG && (flag & PH_ACCUMULATE)) S.gk[i] = S.gk[i] + q * q;   // pseudo-Hessian: sum of q^2
         if (!BORN && tr.d) tile_gather(tr, tix, lz + BZ * lx, n, pn);
         if (BORN) {
@@ -346,6 +358,7 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const gfloat* __restrict__ segq = S.seg + (long long)sstep * 3 * S.npts + 2 * S.npts;
     const gfloat* aciz = S.cpml[0] + 2 * nz;
     const gfloat* acix = S.cpml[1] + 2 * nx;
+    const bool pml = tile_in_pml<BZ, BX>(z0, x0, nz, nx, npml);
     auto inside = [&](int lz, int lx) {
         return (unsigned)(z0 + lz - HW) < (unsigned)nz && (unsigned)(x0 + lx - HW) < (unsigned)nx;
     };
@@ -358,12 +371,12 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         v[0] = S.kdt[i];
         v[1] = S.q[i];
         if (wz) {
-            v[2] = aciz[in ? gz : 0];
-            v[3] = S.eta[0][in && in_pml(gz, nz, npml) ? i : 0];
+            v[2] = pml ? aciz[in ? gz : 0] : 0.f;
+            v[3] = pml ? S.eta[0][in && in_pml(gz, nz, npml) ? i : 0] : 0.f;
         }
         if (wx) {
-            v[4] = acix[in ? gx : 0];
-            v[5] = S.eta[1][in && in_pml(gx, nx, npml) ? i : 0];
+            v[4] = pml ? acix[in ? gx : 0] : 0.f;
+            v[5] = pml ? S.eta[1][in && in_pml(gx, nx, npml) ? i : 0] : 0.f;
         }
     };
     auto ete = [&](bool in, const float* v, bool wz, bool wx, float& ez, float& ex, float& qt) {
@@ -396,9 +409,9 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         vz[r] = S.w[0][i];
         vx[r] = S.w[1][i];
         gk[r] = S.gk[i];
-        qn[r] = segq[i];
+        qn[r] = __builtin_nontemporal_load(&segq[i]);
         lde(lz + HW, lx + HW, ev[r], true, true);
-        if (!flag) {
+        if (!flag && pml) {
             const long long iz = ok[r] && in_pml(gz, nz, npml) ? i : 0;
             const long long ix = ok[r] && in_pml(gx, nx, npml) ? i : 0;
             hz_[r] = achz[ok[r] ? gz : 0];
@@ -409,6 +422,8 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             xx[r] = S.xi[1][ix];
             bz[r] = S.bdt[0][iz];
             bx[r] = S.bdt[1][ix];
+        } else {
+            hz_[r] = hx_[r] = cz[r] = cx[r] = xz[r] = xx[r] = bz[r] = bx[r] = 0.f;
         }
     }
     float hz[RZ::IT][6], hx[RX::IT][6];
@@ -487,6 +502,7 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const gfloat* bciz = S.cpml[0] + 3 * nz;
     const gfloat* acix = S.cpml[1] + 2 * nx;
     const gfloat* bcix = S.cpml[1] + 3 * nx;
+    const bool pml = tile_in_pml<BZ, BX>(z0, x0, nz, nx, npml);
     // pointwise loads; the phi~ update needs the CPML coefficients, phi~ and
     // dt kappa at the node (inside the strips)
     float pt[R], gr[R], az[R], ax[R], cz[R], cx[R], ez[R], ex[R], kk[R];
@@ -501,13 +517,13 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const bool mz = ok[r] && in_pml(gz, nz, npml), mx = ok[r] && in_pml(gx, nx, npml);
         pt[r] = S.q[i];
         gr[r] = S.gr[i];
-        az[r] = aciz[ok[r] ? gz : 0];
-        ax[r] = acix[ok[r] ? gx : 0];
-        cz[r] = bciz[ok[r] ? gz : 0];
-        cx[r] = bcix[ok[r] ? gx : 0];
-        ez[r] = S.eta[0][mz ? i : 0];
-        ex[r] = S.eta[1][mx ? i : 0];
-        kk[r] = S.kdt[mz || mx ? i : 0];
+        az[r] = pml ? aciz[ok[r] ? gz : 0] : 0.f;
+        ax[r] = pml ? acix[ok[r] ? gx : 0] : 0.f;
+        cz[r] = pml ? bciz[ok[r] ? gz : 0] : 0.f;
+        cx[r] = pml ? bcix[ok[r] ? gx : 0] : 0.f;
+        ez[r] = pml ? S.eta[0][mz ? i : 0] : 0.f;
+        ex[r] = pml ? S.eta[1][mx ? i : 0] : 0.f;
+        kk[r] = pml ? S.kdt[mz || mx ? i : 0] : 0.f;
     }
     const gfloat* achz = S.cpml[0];
     const gfloat* achx = S.cpml[1];
@@ -523,8 +539,8 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const long long i = in ? gx * ldz + gz : 0;
         v[0] = S.w[0][i];
         v[1] = S.bdt[0][i];
-        v[2] = achz[in ? gz : 0];
-        v[3] = S.xi[0][in && in_pml(gz, nz, npml) ? i : 0];
+        v[2] = pml ? achz[in ? gz : 0] : 0.f;
+        v[3] = pml ? S.xi[0][in && in_pml(gz, nz, npml) ? i : 0] : 0.f;
         v[4] = segz[in && lz >= HW - 1 && lz < HW + BZ ? i : 0];
     };
     auto ldx_ = [&](int lz, int lx, float* v) {
@@ -533,8 +549,8 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const long long i = in ? gx * ldz + gz : 0;
         v[0] = S.w[1][i];
         v[1] = S.bdt[1][i];
-        v[2] = achx[in ? gx : 0];
-        v[3] = S.xi[1][in && in_pml(gx, nx, npml) ? i : 0];
+        v[2] = pml ? achx[in ? gx : 0] : 0.f;
+        v[3] = pml ? S.xi[1][in && in_pml(gx, nx, npml) ? i : 0] : 0.f;
         v[4] = segx[in && lx >= HW - 1 && lx < HW + BX ? i : 0];
     };
     auto stz_ = [&](int lz, int lx, const float* v) {

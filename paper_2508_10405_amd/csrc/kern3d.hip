@@ -197,10 +197,10 @@ k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             S.v[0][i] = vz[r] + dvz;
             S.v[1][i] = vx[r] + dvx;
             S.v[2][i] = vy[r] + dvy;
-            if (SEG) {
-                seg[i] = dvz;
-                seg[S.npts + i] = dvx;
-                seg[2 * S.npts + i] = dvy;
+            if (SEG) {   // read back only k steps later: streaming stores
+                __builtin_nontemporal_store(dvz, &seg[i]);
+                __builtin_nontemporal_store(dvx, &seg[S.npts + i]);
+                __builtin_nontemporal_store(dvy, &seg[2 * S.npts + i]);
             }
             if (!BORN && !SEG && (flag & PH_ACCUMULATE)) {   // pseudo-Hessian: sum of dv_a^2
                 S.w[0][i] = S.w[0][i] + dvz * dvz;
@@ -348,7 +348,7 @@ k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             float pn = pp[r] - k * q;
             if (i == S.src) pn = pn + amp;
             S.p[i] = pn;
-            if (SEG) seg[i] = q;
+            if (SEG) __builtin_nontemporal_store(q, &seg[i]);
             if (!BORN && !SEG && (flag & PH_ACCUMULATE)) S.gk[i] = S.gk[i] + q * q;   // pseudo-Hessian
             if (BORN) {
                 float fz = d_node(swz, c, 1, C.c[0]);
@@ -470,7 +470,7 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             vx[r] = S.w[1][i];
             vy[r] = S.w[2][i];
             gk[r] = S.gk[i];
-            qn[r] = segq[i];
+            qn[r] = __builtin_nontemporal_load(&segq[i]);
             e0[r] = S.eta[0][pz[r] ? i : 0];
             e1[r] = S.eta[1][px[r] ? i : 0];
             if (!flag) {
