@@ -10,7 +10,8 @@
 // its nodes and its share of the halo -- from addresses that are always valid
 // (element 0 of the array, or of the plane, where a value lies outside the
 // grid or outside the absorbing strips), so no branch separates them; values
-// are combined and written to LDS only after that.  The phases and the CPML
+// are combined and written to LDS only after that.  The z and x CPML
+// coefficients of a thread's nodes are read once, before the march.  The phases and the CPML
 // bookkeeping are those of the 2D kernels (section 2 of the paper for V/P,
 // eq. scattereqln for the Born sources, appendix A for the adjoint phases
 // A/B); the replay buffer holds dv_z, dv_x, dv_y, q per step.
@@ -28,6 +29,23 @@ struct Tile3 {
     static constexpr int R = NP / NTHREADS;
     static_assert(NP % NTHREADS == 0, "tile must hold a multiple of 256 nodes");
 };
+
+// Whether a tile, with the halo planes and cells its queues and staging
+// read, reaches a CPML strip.  The tiles that do not skip every CPML
+// coefficient and memory load (the coefficients are zero there); each kernel
+// branches once, on entry, between two instantiations of its tile body, so
+// neither holds a branch between its loads.
+template <int BZ, int BX, int BY>
+__device__ __forceinline__ bool tile3_pml(const DSlot* __restrict__ slots, const int4* __restrict__ tiles) {
+    const int4 tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const DSlot& S = slots[tl.x];
+    const int z0 = tl.y, x0 = tl.z, y0 = tl.w;
+    const int nz = S.n[0], nx = S.n[1], ny = S.n[2], npml = S.npml;
+    const int y1 = y0 + BY < ny ? y0 + BY : ny;
+    return z0 - HW - 1 < npml || z0 + BZ + HW >= nz - npml - 1 ||
+           x0 - HW - 1 < npml || x0 + BX + HW >= nx - npml - 1 ||
+           y0 - HW - 1 < npml || y1 + HW >= ny - npml - 1;
+}
 
 // y-derivative from a queue Q[m] = f(y + m - off): the staggered difference
 // sum_k c_k (Q[3+k] - Q[4-k]) is G_y (off = 3) or D_y (off = 4).
@@ -57,9 +75,13 @@ __device__ __forceinline__ float d_queue(const float* Q, const float* ck) {
         lxr[r] = e / BZ;                                                      \
         ok[r] = z0 + lzr[r] < nz && x0 + lxr[r] < nx;                         \
         ib[r] = ok[r] ? (x0 + lxr[r]) * sx + (z0 + lzr[r]) : 0;               \
-        pz[r] = ok[r] && in_pml(z0 + lzr[r], nz, npml);                       \
-        px[r] = ok[r] && in_pml(x0 + lxr[r], nx, npml);                       \
+        pz[r] = PML && ok[r] && in_pml(z0 + lzr[r], nz, npml);                \
+        px[r] = PML && ok[r] && in_pml(x0 + lxr[r], nx, npml);                \
     }                                                                         \
+    /* CPML coefficient or memory: zero on tiles away from the strips */      \
+    auto cp = [&](const gfloat* a, long long j) -> float {                    \
+        return PML ? a[j] : 0.f;                                              \
+    };                                                                        \
     auto inside = [&](int lz, int lx) {                                       \
         return (unsigned)(z0 + lz - HW) < (unsigned)nz &&                     \
                (unsigned)(x0 + lx - HW) < (unsigned)nx;                       \
@@ -78,16 +100,15 @@ __device__ __forceinline__ float d_queue(const float* Q, const float* ck) {
 // ---------------------------------------------------------------------------
 // V phase
 // ---------------------------------------------------------------------------
-template <int BZ, int BX, int BY, bool BORN, bool SEG>
-__global__ void __launch_bounds__(NTHREADS)
-k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+template <int BZ, int BX, int BY, bool BORN, bool SEG, bool PML>
+__device__ __forceinline__ void
+v3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const Coef& C, int n, int sstep, int flag,
+        float* __restrict__ sp, float* __restrict__ sq)
 {
     TILE3_SETUP
     constexpr int K = BORN ? 2 : 1;
     using CZ = Cells<0, 2 * HW, HW, BX, HW, BZ>;        // both z-halo strips
     using CX = Cells<HW, BZ, 0, 2 * HW, 0, 0, HW, BX>;  // both x-halo strips
-    __shared__ float sp[T::NL];
-    __shared__ float sq[BORN ? T::NL : 1];
     float Qp[R][8], Qq[R][8];
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -102,10 +123,20 @@ k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const gfloat* bchx = S.cpml[1] + nx;
     const gfloat* achy = S.cpml[2];
     const gfloat* bchy = S.cpml[2] + ny;
+    // the z and x CPML coefficients of a node are the same on every plane
+    float achz_[R], bchz_[R], achx_[R], bchx_[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int gz = ok[r] ? z0 + lzr[r] : 0, gx = ok[r] ? x0 + lxr[r] : 0;
+        achz_[r] = cp(achz, gz);
+        bchz_[r] = cp(bchz, gz);
+        achx_[r] = cp(achx, gx);
+        bchx_[r] = cp(bchx, gx);
+    }
     gfloat* __restrict__ seg = S.seg + (long long)sstep * 4 * S.npts;
     for (int y = y0; y < y1; ++y) {
         const long long py = y * sy;
-        const bool py_ = in_pml(y, ny, npml);
+        const bool py_ = PML && in_pml(y, ny, npml);
         float vz[R], vx[R], vy[R], bz[R], bx[R], by[R], wz[R], wx[R], wy[R], r0[R], r1z[R], r1x[R], r1y[R];
         float m0[R], m1[R], m2[R], n0[R], n1[R], n2[R];
 #pragma unroll
@@ -124,9 +155,9 @@ k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             bz[r] = S.bdt[0][i];
             bx[r] = S.bdt[1][i];
             by[r] = S.bdt[2][i];
-            m0[r] = S.psi[0][pz[r] ? i : 0];
-            m1[r] = S.psi[1][px[r] ? i : 0];
-            m2[r] = S.psi[2][ok[r] && py_ ? i : 0];
+            m0[r] = cp(S.psi[0], pz[r] ? i : 0);
+            m1[r] = cp(S.psi[1], px[r] ? i : 0);
+            m2[r] = cp(S.psi[2], ok[r] && py_ ? i : 0);
             if (BORN) {
                 const int gz = z0 + lzr[r], gx = x0 + lxr[r];
                 wz[r] = S.w[0][i];
@@ -136,9 +167,9 @@ k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
                 r1z[r] = S.dlnr[gz + 1 < nz ? i + 1 : i];
                 r1x[r] = S.dlnr[gx + 1 < nx ? i + sx : i];
                 r1y[r] = S.dlnr[y + 1 < ny ? i + sy : i];
-                n0[r] = S.xi[0][pz[r] ? i : 0];
-                n1[r] = S.xi[1][px[r] ? i : 0];
-                n2[r] = S.xi[2][ok[r] && py_ ? i : 0];
+                n0[r] = cp(S.xi[0], pz[r] ? i : 0);
+                n1[r] = cp(S.xi[1], px[r] ? i : 0);
+                n2[r] = cp(S.xi[2], ok[r] && py_ ? i : 0);
             }
         }
         auto ld = [&](int lz, int lx, float* v) {
@@ -165,24 +196,24 @@ k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         CZ::store(st, hz);
         CX::store(st, hx);
         __syncthreads();
-        const float ay = achy[y];
+        const float ay = cp(achy, y);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (!ok[r]) continue;
             const int gz = z0 + lzr[r], gx = x0 + lxr[r];
             const long long i = ib[r] + py;
             const int c = (lxr[r] + HW) * T::LZ + lzr[r] + HW;
-            const float az = achz[gz], ax = achx[gx];
+            const float az = achz_[r], ax = achx_[r];
             float gzp = d_half(sp, c, 1, C.c[0]);
             float gxp = d_half(sp, c, T::LZ, C.c[1]);
             float gyp = d_queue(Qp[r], C.c[2]);
             if (az != 0.f) {
-                const float ps = fmaf(bchz[gz], m0[r], az * gzp);
+                const float ps = fmaf(bchz_[r], m0[r], az * gzp);
                 S.psi[0][i] = ps;
                 gzp = gzp + ps;
             }
             if (ax != 0.f) {
-                const float ps = fmaf(bchx[gx], m1[r], ax * gxp);
+                const float ps = fmaf(bchx_[r], m1[r], ax * gxp);
                 S.psi[1][i] = ps;
                 gxp = gxp + ps;
             }
@@ -212,12 +243,12 @@ k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
                 float gxq = d_half(sq, c, T::LZ, C.c[1]);
                 float gyq = d_queue(Qq[r], C.c[2]);
                 if (az != 0.f) {
-                    const float ps = fmaf(bchz[gz], n0[r], az * gzq);
+                    const float ps = fmaf(bchz_[r], n0[r], az * gzq);
                     S.xi[0][i] = ps;
                     gzq = gzq + ps;
                 }
                 if (ax != 0.f) {
-                    const float ps = fmaf(bchx[gx], n1[r], ax * gxq);
+                    const float ps = fmaf(bchx_[r], n1[r], ax * gxq);
                     S.xi[1][i] = ps;
                     gxq = gxq + ps;
                 }
@@ -234,21 +265,31 @@ k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     }
 }
 
+template <int BZ, int BX, int BY, bool BORN, bool SEG>
+__global__ void __launch_bounds__(NTHREADS)
+k3_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+{
+    using T = Tile3<BZ, BX>;
+    __shared__ float sp[T::NL];
+    __shared__ float sq[BORN ? T::NL : 1];
+    if (tile3_pml<BZ, BX, BY>(slots, tiles))
+        v3_tile<BZ, BX, BY, BORN, SEG, true>(slots, tiles, C, n, sstep, flag, sp, sq);
+    else
+        v3_tile<BZ, BX, BY, BORN, SEG, false>(slots, tiles, C, n, sstep, flag, sp, sq);
+}
+
 // ---------------------------------------------------------------------------
 // P phase
 // ---------------------------------------------------------------------------
-template <int BZ, int BX, int BY, bool BORN, bool SEG>
-__global__ void __launch_bounds__(NTHREADS)
-k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+template <int BZ, int BX, int BY, bool BORN, bool SEG, bool PML>
+__device__ __forceinline__ void
+p3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const Coef& C, int n, int sstep, int flag,
+        float* __restrict__ svz, float* __restrict__ svx, float* __restrict__ swz, float* __restrict__ swx)
 {
     TILE3_SETUP
     constexpr int K = BORN ? 2 : 1;
     using CZ = Cells<0, T::LZ, HW, BX>;   // v_z (and w_z) with the z-halo
     using CX = Cells<HW, BZ, 0, T::LX>;   // v_x (and w_x) with the x-halo
-    __shared__ float svz[T::NL];
-    __shared__ float svx[T::NL];
-    __shared__ float swz[BORN ? T::NL : 1];
-    __shared__ float swx[BORN ? T::NL : 1];
     float Qv[R][8], Qw[R][8];
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -263,11 +304,21 @@ k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const gfloat* bcix = S.cpml[1] + 3 * nx;
     const gfloat* aciy = S.cpml[2] + 2 * ny;
     const gfloat* bciy = S.cpml[2] + 3 * ny;
+    // the z and x CPML coefficients of a node are the same on every plane
+    float aciz_[R], bciz_[R], acix_[R], bcix_[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int gz = ok[r] ? z0 + lzr[r] : 0, gx = ok[r] ? x0 + lxr[r] : 0;
+        aciz_[r] = cp(aciz, gz);
+        bciz_[r] = cp(bciz, gz);
+        acix_[r] = cp(acix, gx);
+        bcix_[r] = cp(bcix, gx);
+    }
     const float amp = S.src >= 0 ? S.src_amp[n] : 0.f;
     gfloat* __restrict__ seg = S.seg + (long long)sstep * 4 * S.npts + 3 * S.npts;
     for (int y = y0; y < y1; ++y) {
         const long long py = y * sy;
-        const bool py_ = in_pml(y, ny, npml);
+        const bool py_ = PML && in_pml(y, ny, npml);
         float pp[R], kk[R], qq[R], lk[R], m0[R], m1[R], m2[R], n0[R], n1[R], n2[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -281,15 +332,15 @@ k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             const long long i = ib[r] + py;
             pp[r] = S.p[i];
             kk[r] = S.kdt[i];
-            m0[r] = S.phi[0][pz[r] ? i : 0];
-            m1[r] = S.phi[1][px[r] ? i : 0];
-            m2[r] = S.phi[2][ok[r] && py_ ? i : 0];
+            m0[r] = cp(S.phi[0], pz[r] ? i : 0);
+            m1[r] = cp(S.phi[1], px[r] ? i : 0);
+            m2[r] = cp(S.phi[2], ok[r] && py_ ? i : 0);
             if (BORN) {
                 qq[r] = S.q[i];
                 lk[r] = S.dlnk[i];
-                n0[r] = S.eta[0][pz[r] ? i : 0];
-                n1[r] = S.eta[1][px[r] ? i : 0];
-                n2[r] = S.eta[2][ok[r] && py_ ? i : 0];
+                n0[r] = cp(S.eta[0], pz[r] ? i : 0);
+                n1[r] = cp(S.eta[1], px[r] ? i : 0);
+                n2[r] = cp(S.eta[2], ok[r] && py_ ? i : 0);
             }
         }
         float hz[CZ::IT][K], hx[CX::IT][K];
@@ -317,24 +368,24 @@ k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             if (BORN) swx[c] = in ? v[1] : 0.f;
         }, hx);
         __syncthreads();
-        const float ay = aciy[y];
+        const float ay = cp(aciy, y);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (!ok[r]) continue;
             const int gz = z0 + lzr[r], gx = x0 + lxr[r];
             const long long i = ib[r] + py;
             const int c = (lxr[r] + HW) * T::LZ + lzr[r] + HW;
-            const float az = aciz[gz], ax = acix[gx];
+            const float az = aciz_[r], ax = acix_[r];
             float ez = d_node(svz, c, 1, C.c[0]);
             float ex = d_node(svx, c, T::LZ, C.c[1]);
             float ey = d_queue(Qv[r], C.c[2]);
             if (az != 0.f) {
-                const float ph = fmaf(bciz[gz], m0[r], az * ez);
+                const float ph = fmaf(bciz_[r], m0[r], az * ez);
                 S.phi[0][i] = ph;
                 ez = ez + ph;
             }
             if (ax != 0.f) {
-                const float ph = fmaf(bcix[gx], m1[r], ax * ex);
+                const float ph = fmaf(bcix_[r], m1[r], ax * ex);
                 S.phi[1][i] = ph;
                 ex = ex + ph;
             }
@@ -355,12 +406,12 @@ k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
                 float fx = d_node(swx, c, T::LZ, C.c[1]);
                 float fy = d_queue(Qw[r], C.c[2]);
                 if (az != 0.f) {
-                    const float ph = fmaf(bciz[gz], n0[r], az * fz);
+                    const float ph = fmaf(bciz_[r], n0[r], az * fz);
                     S.eta[0][i] = ph;
                     fz = fz + ph;
                 }
                 if (ax != 0.f) {
-                    const float ph = fmaf(bcix[gx], n1[r], ax * fx);
+                    const float ph = fmaf(bcix_[r], n1[r], ax * fx);
                     S.eta[1][i] = ph;
                     fx = fx + ph;
                 }
@@ -376,18 +427,32 @@ k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     }
 }
 
+template <int BZ, int BX, int BY, bool BORN, bool SEG>
+__global__ void __launch_bounds__(NTHREADS)
+k3_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+{
+    using T = Tile3<BZ, BX>;
+    __shared__ float svz[T::NL];
+    __shared__ float svx[T::NL];
+    __shared__ float swz[BORN ? T::NL : 1];
+    __shared__ float swx[BORN ? T::NL : 1];
+    if (tile3_pml<BZ, BX, BY>(slots, tiles))
+        p3_tile<BZ, BX, BY, BORN, SEG, true>(slots, tiles, C, n, sstep, flag, svz, svx, swz, swx);
+    else
+        p3_tile<BZ, BX, BY, BORN, SEG, false>(slots, tiles, C, n, sstep, flag, svz, svx, swz, swx);
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint phase A (transpose of P), as in the 2D kernels
 // ---------------------------------------------------------------------------
-template <int BZ, int BX, int BY>
-__global__ void __launch_bounds__(NTHREADS)
-k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+template <int BZ, int BX, int BY, bool PML>
+__device__ __forceinline__ void
+a3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const Coef& C, int n, int sstep, int flag,
+        float* __restrict__ sez, float* __restrict__ sex)
 {
     TILE3_SETUP
     using CZ = Cells<0, 2 * HW, HW, BX, HW, BZ>;        // both z-halo strips
     using CX = Cells<HW, BZ, 0, 2 * HW, 0, 0, HW, BX>;  // both x-halo strips
-    __shared__ float sez[T::NL];
-    __shared__ float sex[T::NL];
     const gfloat* aciz = S.cpml[0] + 2 * nz;
     const gfloat* acix = S.cpml[1] + 2 * nx;
     const gfloat* aciy = S.cpml[2] + 2 * ny;
@@ -397,6 +462,18 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const gfloat* bchx = S.cpml[1] + nx;
     const gfloat* achy = S.cpml[2];
     const gfloat* bchy = S.cpml[2] + ny;
+    // the z and x CPML coefficients of a node are the same on every plane
+    float aciz_[R], acix_[R], achz_[R], bchz_[R], achx_[R], bchx_[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int gz = ok[r] ? z0 + lzr[r] : 0, gx = ok[r] ? x0 + lxr[r] : 0;
+        aciz_[r] = cp(aciz, gz);
+        acix_[r] = cp(acix, gx);
+        achz_[r] = cp(achz, gz);
+        bchz_[r] = cp(bchz, gz);
+        achx_[r] = cp(achx, gx);
+        bchx_[r] = cp(bchx, gx);
+    }
     const gfloat* __restrict__ segq = S.seg + (long long)sstep * 4 * S.npts + 3 * S.npts;
     // E[m] = e~_y(y + m - 3);  QT[m] = q~(y + m), q~ = -dt kappa p~.  The
     // loads of plane y are kdt, p~ and (inside the y-strips) phi~_y.
@@ -406,7 +483,7 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const long long i = v ? ib[r] + y * sy : 0;
         fk = S.kdt[i];
         fq = S.q[i];
-        fe = S.eta[2][v && in_pml(y, ny, npml) ? i : 0];
+        fe = cp(S.eta[2], v && in_pml(y, ny, npml) ? i : 0);
     };
     auto combine = [&](int r, int y, float fk, float fq, float fe, float& qt, float& ey) {
         const bool v = ok[r] && (unsigned)y < (unsigned)ny;
@@ -414,7 +491,7 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         ey = 0.f;
         if (v) {
             qt = -fk * fq;
-            const float a = aciy[y];
+            const float a = cp(aciy, y);
             ey = a != 0.f ? qt + a * (fe + qt) : qt;
         }
     };
@@ -437,8 +514,8 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const bool in = inside(lz, lx);
         v[0] = S.kdt[i];
         v[1] = S.q[i];
-        v[2] = aciz[in ? gz : 0];
-        v[3] = S.eta[0][in && in_pml(gz, nz, npml) ? i : py];
+        v[2] = cp(aciz, in ? gz : 0);
+        v[3] = cp(S.eta[0], in && in_pml(gz, nz, npml) ? i : py);
     };
     auto ldx_ = [&](int lz, int lx, long long py, float* v) {
         const int gx = x0 + lx - HW;
@@ -446,8 +523,8 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const bool in = inside(lz, lx);
         v[0] = S.kdt[i];
         v[1] = S.q[i];
-        v[2] = acix[in ? gx : 0];
-        v[3] = S.eta[1][in && in_pml(gx, nx, npml) ? i : py];
+        v[2] = cp(acix, in ? gx : 0);
+        v[3] = cp(S.eta[1], in && in_pml(gx, nx, npml) ? i : py);
     };
     auto ete = [&](bool in, const float* v) {
         float e = 0.f;
@@ -459,7 +536,7 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     };
     for (int y = y0; y < y1; ++y) {
         const long long py = y * sy;
-        const bool py_ = in_pml(y, ny, npml);
+        const bool py_ = PML && in_pml(y, ny, npml);
         float vz[R], vx[R], vy[R], gk[R], qn[R], e0[R], e1[R], fk[R], fq[R], fe[R];
         float c0[R], c1[R], c2[R], b0[R], b1[R], b2[R];
 #pragma unroll
@@ -471,16 +548,16 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             vy[r] = S.w[2][i];
             gk[r] = S.gk[i];
             qn[r] = __builtin_nontemporal_load(&segq[i]);
-            e0[r] = S.eta[0][pz[r] ? i : 0];
-            e1[r] = S.eta[1][px[r] ? i : 0];
+            e0[r] = cp(S.eta[0], pz[r] ? i : 0);
+            e1[r] = cp(S.eta[1], px[r] ? i : 0);
             if (!flag) {
                 const long long jz = pz[r] ? i : 0, jx = px[r] ? i : 0, jy = ok[r] && py_ ? i : 0;
-                c0[r] = S.xi[0][jz];
-                c1[r] = S.xi[1][jx];
-                c2[r] = S.xi[2][jy];
-                b0[r] = S.bdt[0][jz];
-                b1[r] = S.bdt[1][jx];
-                b2[r] = S.bdt[2][jy];
+                c0[r] = cp(S.xi[0], jz);
+                c1[r] = cp(S.xi[1], jx);
+                c2[r] = cp(S.xi[2], jy);
+                b0[r] = cp(S.bdt[0], jz);
+                b1[r] = cp(S.bdt[1], jx);
+                b2[r] = cp(S.bdt[2], jy);
             }
         }
         float hz[CZ::IT][4], hx[CX::IT][4];
@@ -500,7 +577,7 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             float ez = qt, ex = qt;
             if (ok[r]) {
                 const int gz = z0 + lzr[r], gx = x0 + lxr[r];
-                const float az = aciz[gz], ax = acix[gx];
+                const float az = aciz_[r], ax = acix_[r];
                 if (az != 0.f) ez = qt + az * (e0[r] + qt);
                 if (ax != 0.f) ex = qt + ax * (e1[r] + qt);
             }
@@ -510,7 +587,7 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         CZ::store([&](int lz, int lx, const float* v) { sez[lx * T::LZ + lz] = ete(inside(lz, lx), v); }, hz);
         CX::store([&](int lz, int lx, const float* v) { sex[lx * T::LZ + lz] = ete(inside(lz, lx), v); }, hx);
         __syncthreads();
-        const float hyc = achy[y];
+        const float hyc = cp(achy, y);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (!ok[r]) continue;
@@ -518,9 +595,9 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             const long long i = ib[r] + py;
             const int c = (lxr[r] + HW) * T::LZ + lzr[r] + HW;
             if (!flag) {
-                const float a = achz[gz], b = achx[gx];
-                if (a != 0.f) S.xi[0][i] = bchz[gz] * (c0[r] + (-b0[r] * vz[r]));
-                if (b != 0.f) S.xi[1][i] = bchx[gx] * (c1[r] + (-b1[r] * vx[r]));
+                const float a = achz_[r], b = achx_[r];
+                if (a != 0.f) S.xi[0][i] = bchz_[r] * (c0[r] + (-b0[r] * vz[r]));
+                if (b != 0.f) S.xi[1][i] = bchx_[r] * (c1[r] + (-b1[r] * vx[r]));
                 if (hyc != 0.f) S.xi[2][i] = bchy[y] * (c2[r] + (-b2[r] * vy[r]));
             }
             S.gk[i] = gk[r] + qn[r] * QT[r][0];
@@ -531,22 +608,32 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     }
 }
 
+template <int BZ, int BX, int BY>
+__global__ void __launch_bounds__(NTHREADS)
+k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+{
+    using T = Tile3<BZ, BX>;
+    __shared__ float sez[T::NL];
+    __shared__ float sex[T::NL];
+    if (tile3_pml<BZ, BX, BY>(slots, tiles))
+        a3_tile<BZ, BX, BY, true>(slots, tiles, C, n, sstep, flag, sez, sex);
+    else
+        a3_tile<BZ, BX, BY, false>(slots, tiles, C, n, sstep, flag, sez, sex);
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint phase B (transpose of V), as in the 2D kernels; the products
 // -dv_a v~_a of the lnrho image are formed while staging (z, x) or kept from
 // the previous plane (y).
 // ---------------------------------------------------------------------------
-template <int BZ, int BX, int BY>
-__global__ void __launch_bounds__(NTHREADS)
-k3_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+template <int BZ, int BX, int BY, bool PML>
+__device__ __forceinline__ void
+b3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const Coef& C, int n, int sstep, int flag,
+        float* __restrict__ sgz, float* __restrict__ sgx, float* __restrict__ sxz, float* __restrict__ sxx)
 {
     TILE3_SETUP
     using CZ = Cells<0, T::LZ, HW, BX>;   // g~_z with the z-halo
     using CX = Cells<HW, BZ, 0, T::LX>;   // g~_x with the x-halo
-    __shared__ float sgz[T::NL];
-    __shared__ float sgx[T::NL];
-    __shared__ float sxz[T::NL];
-    __shared__ float sxx[T::NL];
     const gfloat* achz = S.cpml[0];
     const gfloat* achx = S.cpml[1];
     const gfloat* achy = S.cpml[2];
@@ -556,6 +643,16 @@ k3_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const gfloat* bcix = S.cpml[1] + 3 * nx;
     const gfloat* aciy = S.cpml[2] + 2 * ny;
     const gfloat* bciy = S.cpml[2] + 3 * ny;
+    // the z and x CPML coefficients of a node are the same on every plane
+    float aciz_[R], bciz_[R], acix_[R], bcix_[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int gz = ok[r] ? z0 + lzr[r] : 0, gx = ok[r] ? x0 + lxr[r] : 0;
+        aciz_[r] = cp(aciz, gz);
+        bciz_[r] = cp(bciz, gz);
+        acix_[r] = cp(acix, gx);
+        bcix_[r] = cp(bcix, gx);
+    }
     const gfloat* __restrict__ segz = S.seg + (long long)sstep * 4 * S.npts;
     const gfloat* __restrict__ segx = segz + S.npts;
     const gfloat* __restrict__ segy = segz + 2 * S.npts;
@@ -567,12 +664,12 @@ k3_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const long long i = v ? ib[r] + y * sy : 0;
         fb = S.bdt[2][i];
         fw = S.w[2][i];
-        fc = S.xi[2][v && in_pml(y, ny, npml) ? i : 0];
+        fc = cp(S.xi[2], v && in_pml(y, ny, npml) ? i : 0);
     };
     auto gy_of = [&](int r, int y, float fb, float fw, float fc) -> float {
         if (!(ok[r] && (unsigned)y < (unsigned)ny)) return 0.f;
         const float h = -fb * fw;
-        const float a = achy[y];
+        const float a = cp(achy, y);
         return a != 0.f ? h + a * (fc + h) : h;
     };
 #pragma unroll
@@ -596,8 +693,8 @@ k3_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const long long i = cidx(lz, lx, py);
         v[0] = S.w[0][i];
         v[1] = S.bdt[0][i];
-        v[2] = achz[in ? gz : 0];
-        v[3] = S.xi[0][in && in_pml(gz, nz, npml) ? i : py];
+        v[2] = cp(achz, in ? gz : 0);
+        v[3] = cp(S.xi[0], in && in_pml(gz, nz, npml) ? i : py);
         v[4] = segz[in && lz >= HW - 1 && lz < HW + BZ ? i : py];
     };
     auto ldx_ = [&](int lz, int lx, long long py, float* v) {
@@ -606,13 +703,13 @@ k3_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const long long i = cidx(lz, lx, py);
         v[0] = S.w[1][i];
         v[1] = S.bdt[1][i];
-        v[2] = achx[in ? gx : 0];
-        v[3] = S.xi[1][in && in_pml(gx, nx, npml) ? i : py];
+        v[2] = cp(achx, in ? gx : 0);
+        v[3] = cp(S.xi[1], in && in_pml(gx, nx, npml) ? i : py);
         v[4] = segx[in && lx >= HW - 1 && lx < HW + BX ? i : py];
     };
     for (int y = y0; y < y1; ++y) {
         const long long py = y * sy;
-        const bool py_ = in_pml(y, ny, npml);
+        const bool py_ = PML && in_pml(y, ny, npml);
         float pt[R], gr[R], sy_[R], wy_[R], kk[R], e0[R], e1[R], e2[R], fb[R], fw[R], fc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -623,10 +720,10 @@ k3_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             gr[r] = S.gr[i];
             sy_[r] = segy[i];
             wy_[r] = S.w[2][i];
-            kk[r] = S.kdt[any ? i : 0];
-            e0[r] = S.eta[0][pz[r] ? i : 0];
-            e1[r] = S.eta[1][px[r] ? i : 0];
-            e2[r] = S.eta[2][ok[r] && py_ ? i : 0];
+            kk[r] = cp(S.kdt, any ? i : 0);
+            e0[r] = cp(S.eta[0], pz[r] ? i : 0);
+            e1[r] = cp(S.eta[1], px[r] ? i : 0);
+            e2[r] = cp(S.eta[2], ok[r] && py_ ? i : 0);
         }
         float hz[CZ::IT][5], hx[CX::IT][5];
         CZ::load([&](int lz, int lx, float* v) { ldz_(lz, lx, py, v); }, hz);
@@ -655,7 +752,7 @@ k3_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             sxx[c] = x;
         }, hx);
         __syncthreads();
-        const float ay = aciy[y];
+        const float ay = cp(aciy, y);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
 #pragma unroll
@@ -665,11 +762,11 @@ k3_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             const int gz = z0 + lzr[r], gx = x0 + lxr[r];
             const long long i = ib[r] + py;
             const int c = (lxr[r] + HW) * T::LZ + lzr[r] + HW;
-            const float az = aciz[gz], ax = acix[gx];
+            const float az = aciz_[r], ax = acix_[r];
             if (az != 0.f || ax != 0.f || ay != 0.f) {
                 const float qt = -kk[r] * pt[r];
-                if (az != 0.f) S.eta[0][i] = bciz[gz] * (e0[r] + qt);
-                if (ax != 0.f) S.eta[1][i] = bcix[gx] * (e1[r] + qt);
+                if (az != 0.f) S.eta[0][i] = bciz_[r] * (e0[r] + qt);
+                if (ax != 0.f) S.eta[1][i] = bcix_[r] * (e1[r] + qt);
                 if (ay != 0.f) S.eta[2][i] = bciy[y] * (e2[r] + qt);
             }
             const float xy0 = -sy_[r] * wy_[r];
@@ -681,6 +778,21 @@ k3_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             S.q[i] = pt[r] - ((dz + dx) + dy);
         }
     }
+}
+
+template <int BZ, int BX, int BY>
+__global__ void __launch_bounds__(NTHREADS)
+k3_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, int n, int sstep, int flag)
+{
+    using T = Tile3<BZ, BX>;
+    __shared__ float sgz[T::NL];
+    __shared__ float sgx[T::NL];
+    __shared__ float sxz[T::NL];
+    __shared__ float sxx[T::NL];
+    if (tile3_pml<BZ, BX, BY>(slots, tiles))
+        b3_tile<BZ, BX, BY, true>(slots, tiles, C, n, sstep, flag, sgz, sgx, sxz, sxx);
+    else
+        b3_tile<BZ, BX, BY, false>(slots, tiles, C, n, sstep, flag, sgz, sgx, sxz, sxx);
 }
 
 // ---------------------------------------------------------------------------
