@@ -47,6 +47,10 @@ __device__ __forceinline__ double lnrho_at(const PrepArgs& a, int pz, int px, in
     return (double)a.lnip[g] - (double)a.lnvp[g];
 }
 
+// sqrt(dt) * exp(-lnrho / 2), rounded to FP32 (the one rounding every user of
+// sb and bdt shares)
+__device__ __forceinline__ float sb_of(double dt, double lr) { return (float)(sqrt(dt) * exp(-0.5 * lr)); }
+
 __global__ void k_model_prep(PrepArgs a) {
     const long long tot = (long long)a.N[0] * a.N[1] * a.N[2];
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
@@ -63,12 +67,14 @@ __global__ void k_model_prep(PrepArgs a) {
         const double lk = (double)a.lnvp[g] + (double)a.lnip[g];
         a.kdt[i] = (float)(a.dt * exp(lk));
         const double lr = (double)a.lnip[g] - (double)a.lnvp[g];
+        const float s0 = sb_of(a.dt, lr);
+        a.sb[i] = s0;
+        // dt b_a at the half node: the FP32 product the velocity kernels form
         const int pn[3] = {pz, px, py};
         for (int ax = 0; ax < a.ndim; ++ax) {
             int q[3] = {pn[0], pn[1], pn[2]};
             q[ax] = q[ax] + 1 < a.N[ax] ? q[ax] + 1 : q[ax];
-            const double lr1 = lnrho_at(a, q[0], q[1], q[2]);
-            a.bdt[ax][i] = (float)(a.dt * exp(-0.5 * (lr + lr1)));
+            a.bdt[ax][i] = s0 * sb_of(a.dt, lnrho_at(a, q[0], q[1], q[2]));
         }
     }
 }

@@ -56,7 +56,9 @@ struct SlotT {
     int pad_;
     const F* src_amp;        // [nt] dt * w / cell
     const F* kdt;            // dt * kappa at nodes
-    const F* bdt[3];         // dt * b_a at half nodes
+    const F* sb;             // sqrt(dt b) at nodes: dt b_a at the half node i + 1/2
+                             // is sb[i] * sb[i + e_a] (sb[i]^2 on an axis' last node)
+    const F* bdt[3];         // the same products, stored (read by the adjoint kernels)
     const F* dlnr;           // dlnrho at nodes (zero in the PML)
     const F* dlnk;           // dlnkappa at nodes (zero in the PML)
     const F* cpml[3];        // per axis: [ach | bch | aci | bci], n_a each

@@ -86,7 +86,7 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const gfloat* bchx = S.cpml[1] + nx;
     const bool pml = tile_in_pml<BZ, BX>(z0, x0, nz, nx, npml);
     // pointwise loads, CPML coefficients and (inside the strips) memories
-    float vz[R], vx[R], bz[R], bx[R], wz[R], wx[R], r0[R], r1z[R], r1x[R];
+    float vz[R], vx[R], s0[R], s1z[R], s1x[R], wz[R], wx[R], r0[R], r1z[R], r1x[R];
     float az[R], ax[R], cz[R], cx[R], m0[R], m1[R], n0[R], n1[R];
     bool ok[R];
 #pragma unroll
@@ -100,8 +100,9 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const long long ix = ok[r] && in_pml(gx, nx, npml) ? i : 0;
         vz[r] = S.v[0][i];
         vx[r] = S.v[1][i];
-        bz[r] = S.bdt[0][i];
-        bx[r] = S.bdt[1][i];
+        s0[r] = S.sb[i];   // dt b_a = sb at the node times sb at its upper neighbour
+        s1z[r] = S.sb[gz + 1 < nz ? i + 1 : i];
+        s1x[r] = S.sb[gx + 1 < nx ? i + ldz : i];
         az[r] = pml ? achz[ok[r] ? gz : 0] : 0.f;
         ax[r] = pml ? achx[ok[r] ? gx : 0] : 0.f;
         cz[r] = pml ? bchz[ok[r] ? gz : 0] : 0.f;
@@ -160,8 +161,9 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             S.psi[1][i] = ps;
             gxp = gxp + ps;
         }
-        const float dvz = -bz[r] * gzp;
-        const float dvx = -bx[r] * gxp;
+        const float bz = s0[r] * s1z[r], bx = s0[r] * s1x[r];
+        const float dvz = -bz * gzp;
+        const float dvx = -bx * gxp;
         S.v[0][i] = vz[r] + dvz;
         S.v[1][i] = vx[r] + dvx;
         if (SEG) {
@@ -188,8 +190,8 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             }
             const float rz = 0.5f * (r0[r] + r1z[r]);
             const float rx = 0.5f * (r0[r] + r1x[r]);
-            S.w[0][i] = (wz[r] - bz[r] * gzq) - rz * dvz;
-            S.w[1][i] = (wx[r] - bx[r] * gxq) - rx * dvx;
+            S.w[0][i] = (wz[r] - bz * gzq) - rz * dvz;
+            S.w[1][i] = (wx[r] - bx * gxq) - rx * dvx;
         }
     }
 }

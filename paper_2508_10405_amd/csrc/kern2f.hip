@@ -84,8 +84,8 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
     constexpr int NZR = BZ + 7, NXR = BZ;
     constexpr int RZ = (T::NVZ + NTHREADS - 1) / NTHREADS;
     constexpr int RX = (T::NVX + NTHREADS - 1) / NTHREADS;
-    float zv[RZ], zb[RZ], zw[RZ], zr0[RZ], zr1[RZ], zps[RZ], zxs[RZ];
-    float xv[RX], xb[RX], xw[RX], xr0[RX], xr1[RX], xps[RX], xxs[RX];
+    float zv[RZ], zb[RZ], zb1[RZ], zw[RZ], zr0[RZ], zr1[RZ], zps[RZ], zxs[RZ];
+    float xv[RX], xb[RX], xb1[RX], xw[RX], xr0[RX], xr1[RX], xps[RX], xxs[RX];
 #pragma unroll
     for (int t = 0; t < RZ; ++t) {
         const int e = threadIdx.x + NTHREADS * t;
@@ -95,7 +95,8 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
         const long long i = in ? gx * ldz + gz : 0;
         const long long im = in && in_pml(gz, nz, npml) ? i : 0;
         zv[t] = S.v[0][i];
-        zb[t] = S.bdt[0][i];
+        zb[t] = S.sb[i];   // dt b_z = sb here times sb at the upper z-neighbour
+        zb1[t] = S.sb[(in && gz + 1 < nz) ? i + 1 : i];
         zps[t] = S.psi[0][im];
         if (BORN) {
             zw[t] = S.w[0][i];
@@ -113,7 +114,8 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
         const long long i = in ? gx * ldz + gz : 0;
         const long long im = in && in_pml(gx, nx, npml) ? i : 0;
         xv[t] = S.v[1][i];
-        xb[t] = S.bdt[1][i];
+        xb[t] = S.sb[i];
+        xb1[t] = S.sb[(in && gx + 1 < nx) ? i + ldz : i];
         xps[t] = S.psi[1][im];
         if (BORN) {
             xw[t] = S.w[1][i];
@@ -164,7 +166,7 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
         const long long i = gx * ldz + gz;
         const int c = (lx + 7) * T::PZ + lz + 7;
         const float az = achz[gz];
-        const float bz = zb[t];
+        const float bz = zb[t] * zb1[t];
         float g = d_half(sp, c, 1, C.c[0]);
         if (az != 0.f) {
             const float ps = fmaf(bchz[gz], zps[t], az * g);
@@ -206,7 +208,7 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
         const long long i = gx * ldz + gz;
         const int c = (lx + 7) * T::PZ + lz + 7;
         const float ax = achx[gx];
-        const float bx = xb[t];
+        const float bx = xb[t] * xb1[t];
         float g = d_half(sp, c, T::PZ, C.c[1]);
         if (ax != 0.f) {
             const float ps = fmaf(bchx[gx], xps[t], ax * g);

@@ -134,10 +134,15 @@ v3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
         bchx_[r] = cp(bchx, gx);
     }
     gfloat* __restrict__ seg = S.seg + (long long)sstep * 4 * S.npts;
+    // dt b_a = sb at the node times sb at its upper neighbour along a; sb of
+    // the next plane is kept for the next plane's own value
+    float sbq[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) sbq[r] = S.sb[ib[r] + y0 * sy];
     for (int y = y0; y < y1; ++y) {
         const long long py = y * sy;
         const bool py_ = PML && in_pml(y, ny, npml);
-        float vz[R], vx[R], vy[R], bz[R], bx[R], by[R], wz[R], wx[R], wy[R], r0[R], r1z[R], r1x[R], r1y[R];
+        float vz[R], vx[R], vy[R], s0[R], s1z[R], s1x[R], wz[R], wx[R], wy[R], r0[R], r1z[R], r1x[R], r1y[R];
         float m0[R], m1[R], m2[R], n0[R], n1[R], n2[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -152,9 +157,10 @@ v3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
             vz[r] = S.v[0][i];
             vx[r] = S.v[1][i];
             vy[r] = S.v[2][i];
-            bz[r] = S.bdt[0][i];
-            bx[r] = S.bdt[1][i];
-            by[r] = S.bdt[2][i];
+            s0[r] = sbq[r];
+            s1z[r] = S.sb[ok[r] && z0 + lzr[r] + 1 < nz ? i + 1 : i];
+            s1x[r] = S.sb[ok[r] && x0 + lxr[r] + 1 < nx ? i + sx : i];
+            sbq[r] = S.sb[y + 1 < ny ? i + sy : i];
             m0[r] = cp(S.psi[0], pz[r] ? i : 0);
             m1[r] = cp(S.psi[1], px[r] ? i : 0);
             m2[r] = cp(S.psi[2], ok[r] && py_ ? i : 0);
@@ -222,9 +228,10 @@ v3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
                 S.psi[2][i] = ps;
                 gyp = gyp + ps;
             }
-            const float dvz = -bz[r] * gzp;
-            const float dvx = -bx[r] * gxp;
-            const float dvy = -by[r] * gyp;
+            const float bz = s0[r] * s1z[r], bx = s0[r] * s1x[r], by = s0[r] * sbq[r];
+            const float dvz = -bz * gzp;
+            const float dvx = -bx * gxp;
+            const float dvy = -by * gyp;
             S.v[0][i] = vz[r] + dvz;
             S.v[1][i] = vx[r] + dvx;
             S.v[2][i] = vy[r] + dvy;
@@ -257,9 +264,9 @@ v3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
                     S.xi[2][i] = ps;
                     gyq = gyq + ps;
                 }
-                S.w[0][i] = (wz[r] - bz[r] * gzq) - 0.5f * (r0[r] + r1z[r]) * dvz;
-                S.w[1][i] = (wx[r] - bx[r] * gxq) - 0.5f * (r0[r] + r1x[r]) * dvx;
-                S.w[2][i] = (wy[r] - by[r] * gyq) - 0.5f * (r0[r] + r1y[r]) * dvy;
+                S.w[0][i] = (wz[r] - bz * gzq) - 0.5f * (r0[r] + r1z[r]) * dvz;
+                S.w[1][i] = (wx[r] - bx * gxq) - 0.5f * (r0[r] + r1x[r]) * dvx;
+                S.w[2][i] = (wy[r] - by * gyq) - 0.5f * (r0[r] + r1y[r]) * dvy;
             }
         }
     }
@@ -659,29 +666,30 @@ b3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
     // Gq[m] = g~_y(y + m - 4) from dt b_y, v~_y and (inside the y-strips) chi_y;
     // Xp = -dv_y v~_y on the previous plane
     float Gq[R][8], Xp[R];
-    auto front = [&](int r, int y, float& fb, float& fw, float& fc) {
+    auto front = [&](int r, int y, float* f) {
         const bool v = ok[r] && (unsigned)y < (unsigned)ny;
         const long long i = v ? ib[r] + y * sy : 0;
-        fb = S.bdt[2][i];
-        fw = S.w[2][i];
-        fc = cp(S.xi[2], v && in_pml(y, ny, npml) ? i : 0);
+        f[0] = S.bdt[2][i];
+        f[1] = S.w[2][i];
+        f[2] = cp(S.xi[2], v && in_pml(y, ny, npml) ? i : 0);
     };
-    auto gy_of = [&](int r, int y, float fb, float fw, float fc) -> float {
+    auto gy_of = [&](int r, int y, const float* f) -> float {
         if (!(ok[r] && (unsigned)y < (unsigned)ny)) return 0.f;
-        const float h = -fb * fw;
+        const float h = -f[0] * f[1];
+        const float fc = f[2];
         const float a = cp(achy, y);
         return a != 0.f ? h + a * (fc + h) : h;
     };
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        float fb[7], fw[7], fc[7];
+        float f[7][3];
 #pragma unroll
-        for (int m = 0; m < 7; ++m) front(r, y0 - 4 + m, fb[m], fw[m], fc[m]);
+        for (int m = 0; m < 7; ++m) front(r, y0 - 4 + m, f[m]);
         const bool pv = ok[r] && y0 > 0;
         const long long ip = pv ? ib[r] + (y0 - 1) * sy : 0;
         const float s_ = segy[ip], w_ = S.w[2][ip];
 #pragma unroll
-        for (int m = 0; m < 7; ++m) Gq[r][m + 1] = gy_of(r, y0 - 4 + m, fb[m], fw[m], fc[m]);
+        for (int m = 0; m < 7; ++m) Gq[r][m + 1] = gy_of(r, y0 - 4 + m, f[m]);
         Xp[r] = pv ? -s_ * w_ : 0.f;
     }
     // loads of g~_a and of the image product at a cell: v~_a, dt b_a, the
@@ -710,10 +718,10 @@ b3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
     for (int y = y0; y < y1; ++y) {
         const long long py = y * sy;
         const bool py_ = PML && in_pml(y, ny, npml);
-        float pt[R], gr[R], sy_[R], wy_[R], kk[R], e0[R], e1[R], e2[R], fb[R], fw[R], fc[R];
+        float pt[R], gr[R], sy_[R], wy_[R], kk[R], e0[R], e1[R], e2[R], fr[R][3];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            front(r, y + 3, fb[r], fw[r], fc[r]);
+            front(r, y + 3, fr[r]);
             const long long i = ib[r] + py;
             const bool any = pz[r] || px[r] || (ok[r] && py_);
             pt[r] = S.q[i];
@@ -757,7 +765,7 @@ b3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
         for (int r = 0; r < R; ++r) {
 #pragma unroll
             for (int m = 0; m < 7; ++m) Gq[r][m] = Gq[r][m + 1];
-            Gq[r][7] = gy_of(r, y + 3, fb[r], fw[r], fc[r]);
+            Gq[r][7] = gy_of(r, y + 3, fr[r]);
             if (!ok[r]) continue;
             const int gz = z0 + lzr[r], gx = x0 + lxr[r];
             const long long i = ib[r] + py;

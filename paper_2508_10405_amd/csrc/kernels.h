@@ -41,7 +41,11 @@ hipError_t launch_fill(float* p, long long n, float v, hipStream_t st);
 hipError_t launch_fill_f64(double* p, long long n, hipStream_t st);
 
 // Model on a shot's padded grid from the global physical logs (edge-replicated
-// into the PML): kdt = dt*exp(lnvp+lnip); bdt_a = dt*exp(-(lnrho_i+lnrho_i+1)/2).
+// into the PML): kdt = dt*exp(lnvp+lnip); sb = sqrt(dt)*exp(-lnrho/2), so that
+// dt*b_a = dt*exp(-(lnrho_i + lnrho_i+1)/2) at the half node i + 1/2 is the
+// FP32 product sb_i * sb_i+1.  The velocity kernels form that product from sb
+// (one array instead of ndim); bdt_a holds the same products for the adjoint
+// kernels, which read dt b_a at halo cells.
 struct PrepArgs {
     const float* lnvp; const float* lnip;   // global physical arrays
     int gn[3];                              // global physical sizes (z, x, y)
@@ -51,7 +55,7 @@ struct PrepArgs {
     long long sx, sy;                       // strides
     double dt;
     int ndim;
-    float* kdt; float* bdt[3];
+    float* kdt; float* sb; float* bdt[3];
 };
 hipError_t launch_model_prep(const PrepArgs& a, hipStream_t st);
 

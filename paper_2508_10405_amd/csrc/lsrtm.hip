@@ -39,6 +39,7 @@ struct Window {
     int ldz;
     long long sx, sy, npts;
     float* kdt = nullptr;
+    float* sb = nullptr;
     float* bdt[3] = {nullptr, nullptr, nullptr};
     float* dlnr = nullptr;
     float* dlnk = nullptr;
@@ -702,7 +703,6 @@ lsrtm_status prep_model_windows(lsrtm_ctx* c) {
             a.lo[i] = w.lo[i];
             a.wn[i] = w.hi[i] - w.lo[i];
             a.N[i] = w.N[i];
-            a.bdt[i] = w.bdt[i];
         }
         a.npml = c->g.npml;
         a.sx = w.sx;
@@ -710,6 +710,8 @@ lsrtm_status prep_model_windows(lsrtm_ctx* c) {
         a.dt = c->g.dt;
         a.ndim = c->ndim;
         a.kdt = w.kdt;
+        a.sb = w.sb;
+        for (int i = 0; i < 3; ++i) a.bdt[i] = w.bdt[i];
         HIPCHK(c, launch_model_prep(a, c->st));
         // CPML tables
         for (int ax = 0; ax < c->ndim; ++ax) {
@@ -822,7 +824,7 @@ lsrtm_status plan(lsrtm_ctx* c) {
     const int nsc = 1 + 3 * nd + (c->fused ? 1 + 3 * nd : 0);   // q, w, xi, eta [, q', w', xi', eta']
     const int nt = c->g.nt;
     long long model_bytes = 0;
-    for (auto& W : c->wins) model_bytes += (long long)(nd + 3) * W.npts * 4 + 4LL * nd * 4 * std::max(W.N[0], std::max(W.N[1], W.N[2]));
+    for (auto& W : c->wins) model_bytes += (long long)(4 + nd) * W.npts * 4 + 4LL * nd * 4 * std::max(W.N[0], std::max(W.N[1], W.N[2]));
     long long ck_per_shot_sum = 0;
     for (auto& sh : c->shots) ck_per_shot_sum += sh.ckbytes;
     const long long fixed = model_bytes + 2LL * c->gpts * 8 + (long long)nshot * nt * 4 + 2 * c->data_len * 4 +
@@ -881,9 +883,10 @@ lsrtm_status plan(lsrtm_ctx* c) {
     // ---- model windows -------------------------------------------------------
     for (auto& W : c->wins) {
         CHK(dalloc_t(c, &W.kdt, W.npts, true));
+        CHK(dalloc_t(c, &W.sb, W.npts, true));
         for (int a = 0; a < 3; ++a) {
             if (a < nd) CHK(dalloc_t(c, &W.bdt[a], W.npts, true));
-            else W.bdt[a] = W.kdt;
+            else W.bdt[a] = W.sb;
             if (a < nd) CHK(dalloc_t(c, &W.cpml[a], 4 * W.N[a], true));
             else W.cpml[a] = nullptr;
         }
@@ -892,6 +895,7 @@ lsrtm_status plan(lsrtm_ctx* c) {
         HIPCHK(c, launch_fill(W.kdt, W.npts, 0.f, c->st));
         HIPCHK(c, launch_fill(W.dlnr, W.npts, 0.f, c->st));
         HIPCHK(c, launch_fill(W.dlnk, W.npts, 0.f, c->st));
+        HIPCHK(c, launch_fill(W.sb, W.npts, 0.f, c->st));
         for (int a = 0; a < nd; ++a) HIPCHK(c, launch_fill(W.bdt[a], W.npts, 0.f, c->st));
     }
     // ---- groups ----------------------------------------------------------------
@@ -969,6 +973,7 @@ lsrtm_status plan(lsrtm_ctx* c) {
             S.npml = c->g.npml;
             S.src_amp = c->src_amp + (long long)s * nt;
             S.kdt = W.kdt;
+            S.sb = W.sb;
             for (int a = 0; a < 3; ++a) {
                 S.bdt[a] = W.bdt[a];
                 S.cpml[a] = W.cpml[a];
