@@ -73,6 +73,13 @@ struct Group {
     int* d_win = nullptr;
     int* d_trp = nullptr;          // 2D: receivers per tile (CSR over the tile table)
     Rec* d_trec = nullptr;
+    // 2D: tables of other tile shapes for the phases without receivers
+    struct AltTiles {
+        int tile;
+        int4* d;
+        int n;
+    };
+    std::vector<AltTiles> alt;
     std::vector<Rec> h_rec;        // receivers of the group (host copy)
     long long max_npts = 0;
     long long bg_used = 0, sc_used = 0, img_used = 0;   // floats
@@ -155,6 +162,8 @@ struct lsrtm_ctx {
     int opt_ckg = 0;
     int opt_fused = 0;
     int opt_progress = 0;
+    int opt_tile_v = -1;           // 2D two-phase: tile of the velocity phases (-1: tile)
+    int opt_tile_a = -1;           // 2D two-phase: tile of the adjoint A phase (-1: tile)
     // timing
     std::vector<EvPair> evpool;
     size_t evused = 0;
@@ -370,17 +379,44 @@ void tile_shape(int ndim, int id, int* bz, int* bx, int* by) {
     }
 }
 
-lsrtm_status build_tiles(lsrtm_ctx* c, Group& gr, int tile) {
-    if (gr.tiles_for == tile) return LSRTM_OK;
+// Tile table of a group: (slot, z0, x0, y0) of every tile of every slot.
+void tile_list(const lsrtm_ctx* c, const Group& gr, int tile, std::vector<int4>& t) {
     int bz, bx, by;
     tile_shape(c->ndim, tile, &bz, &bx, &by);
-    std::vector<int4> t;
+    t.clear();
     for (int s = 0; s < gr.ns; ++s) {
         const Slot& S = gr.h_slots[s];
         for (int y0 = 0; y0 < S.n[2]; y0 += by)
             for (int x0 = 0; x0 < S.n[1]; x0 += bx)
                 for (int z0 = 0; z0 < S.n[0]; z0 += bz) t.push_back(make_int4(s, z0, x0, y0));
     }
+}
+
+// Tables of the receiver-free phases' own tile shapes (2D two-phase only).
+lsrtm_status build_alt_tiles(lsrtm_ctx* c, Group& gr) {
+    if (c->ndim != 2 || c->fused) return LSRTM_OK;
+    for (int tile : {c->opt_tile_v, c->opt_tile_a}) {
+        if (tile < 0) continue;
+        bool have = false;
+        for (const auto& a : gr.alt) have = have || a.tile == tile;
+        if (have) continue;
+        std::vector<int4> t;
+        tile_list(c, gr, tile, t);
+        Group::AltTiles a{tile, nullptr, (int)t.size()};
+        CHK(dalloc_t(c, &a.d, t.size(), true));
+        HIPCHK(c, hipMemcpy(a.d, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
+        gr.alt.push_back(a);
+    }
+    return LSRTM_OK;
+}
+
+lsrtm_status build_tiles(lsrtm_ctx* c, Group& gr, int tile) {
+    CHK(build_alt_tiles(c, gr));
+    if (gr.tiles_for == tile) return LSRTM_OK;
+    int bz, bx, by;
+    tile_shape(c->ndim, tile, &bz, &bx, &by);
+    std::vector<int4> t;
+    tile_list(c, gr, tile, t);
     if (gr.d_tiles) {
         (void)hipFree(gr.d_tiles);
         auto it = std::find(c->acq_allocs.begin(), c->acq_allocs.end(), (void*)gr.d_tiles);
@@ -442,7 +478,24 @@ lsrtm_status stencil(lsrtm_ctx* c, Group& gr, int kind, int n, int sstep, int fl
     hipError_t e;
     if (c->ndim == 3) e = launch3d(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag, e0, e1);
     else if (c->fused) e = launch2f(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag, tr, e0, e1);
-    else e = launch2d(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag, tr, e0, e1);
+    else {
+        // the velocity phases and the adjoint A phase touch no receivers and
+        // may walk a table of their own tile shape
+        const bool vph = kind == K_BG_V || kind == K_SEG_V || kind == K_BORN_V;
+        const int want = vph ? c->opt_tile_v : kind == K_ADJ_A ? c->opt_tile_a : -1;
+        int tile = c->tile, nt = gr.ntiles;
+        const int4* tab = gr.d_tiles;
+        if (want >= 0 && want != c->tile) {
+            for (const auto& a : gr.alt)
+                if (a.tile == want) {
+                    tile = a.tile;
+                    nt = a.n;
+                    tab = a.d;
+                }
+            if (tab == gr.d_tiles) FAIL(c, LSRTM_ESTATE, "tile table %d of phase %d was not built", want, kind);
+        }
+        e = launch2d(kind, tile, nt, c->st, sl, tab, c->C, n, sstep, flag, tr, e0, e1);
+    }
     if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "stencil launch (kind %d): %s", kind, hipGetErrorString(e));
     if (ev) c->evused++;
     return LSRTM_OK;
@@ -1382,6 +1435,14 @@ lsrtm_status lsrtm_set_option(lsrtm_ctx* c, int key, long long v) {
         if (c->have_acq) return plan(c);
         return LSRTM_OK;
     case LSRTM_OPT_PROGRESS: c->opt_progress = v != 0; return LSRTM_OK;
+    case LSRTM_OPT_TILE_V:
+    case LSRTM_OPT_TILE_ADJ_A: {
+        if (c->ndim != 2) FAIL(c, LSRTM_EINVAL, "per-phase tiles are a 2D option");
+        if (v < -1 || v >= kNumTiles2) FAIL(c, LSRTM_EINVAL, "tile id %lld out of range", v);
+        (key == LSRTM_OPT_TILE_V ? c->opt_tile_v : c->opt_tile_a) = (int)v;
+        clear_graphs(c);
+        return LSRTM_OK;
+    }
     case LSRTM_OPT_CKPT_PER_GROUP:
         if (c->opt_ckg == (v != 0)) return LSRTM_OK;
         c->opt_ckg = v != 0;

@@ -24,7 +24,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "lsrtm.h")
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
 CKPT = {"f32": 0, "f16": 1, "bf16": 2}
 OPT_SHOTS_PER_LAUNCH, OPT_TILE, OPT_GRAPH, OPT_TIMING, OPT_MEM_BUDGET_MB, OPT_CKPT_PER_GROUP, OPT_FUSED, \
-    OPT_PROGRESS = 1, 2, 3, 4, 5, 6, 7, 8
+    OPT_PROGRESS, OPT_TILE_V, OPT_TILE_ADJ_A = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
 NKERNEL = 8
 KERNEL_NAMES = ("born_v", "born_p", "bg_v", "bg_p", "adj_a", "adj_b", "ckpt", "rec")
 
@@ -113,12 +113,15 @@ class Context:
     Parameters follow lsrtm_grid: n = (nz, nx[, ny]) physical sizes,
     h = (dz, dx[, dy]), npml CPML cells, nt steps of dt seconds, CPML
     parameters pml_R and pml_f0, checkpoint interval (0 = planner) and
-    checkpoint storage ("f32", "f16", "bf16").
+    checkpoint storage ("f32", "f16", "bf16").  In 2D, tile_v and tile_adj_a
+    give the velocity phases and the adjoint A phase tile shapes of their own
+    (-1 = the stencil tile); results do not depend on them.
     """
 
     def __init__(self, n, h, nt, dt, npml=20, pml_R=1e-4, pml_f0=10.0, ckpt_every=0,
                  ckpt_dtype="f32", stream=None, shots_per_launch=0, tile=-1, graph=True,
-                 timing=False, mem_budget_mb=0, ckpt_per_group=False, fused=False, progress=False):
+                 timing=False, mem_budget_mb=0, ckpt_per_group=False, fused=False, progress=False,
+                 tile_v=-1, tile_adj_a=-1):
         import torch
         L = lib()
         self._torch = torch
@@ -148,6 +151,9 @@ class Context:
         self.set_option(OPT_CKPT_PER_GROUP, int(bool(ckpt_per_group)))
         self.set_option(OPT_FUSED, int(bool(fused)))
         self.set_option(OPT_PROGRESS, int(bool(progress)))
+        if ndim == 2:
+            self.set_option(OPT_TILE_V, tile_v)
+            self.set_option(OPT_TILE_ADJ_A, tile_adj_a)
         self.nrec: List[int] = []
         self._keep = []
 

@@ -121,6 +121,27 @@ def test_batched_equals_per_shot_and_tiles(torch):
                 assert np.array_equal(im, ref[1]), (spl, tile, fused)
 
 
+def test_per_phase_tiles_bitwise(torch):
+    """The velocity phases and the adjoint A phase may walk tables of their
+    own tile shapes (they record and inject nothing): Born data and images are
+    bitwise those of one tile shape for every phase."""
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((50, 90), nt=120, npml=6, seed=9, nshot=4, uneven=True)
+    dm = to_dev(torch, w.dm)
+    y = to_dev(torch, np.random.default_rng(4).standard_normal(sum(w.nt * len(r) for r in w.rec)))
+    ctx = lsrtm.context_for(w, shots_per_launch=2, tile=1)
+    ref = (ctx.born(dm).cpu().numpy(), ctx.adjoint(y).cpu().numpy())
+    ctx.close()
+    for tile, tv, ta in ((1, 4, 2), (0, 8, 6), (1, -1, 2), (3, 1, -1)):
+        print(f"[case] tile {tile} tile_v {tv} tile_adj_a {ta}", flush=True)
+        ctx = lsrtm.context_for(w, shots_per_launch=2, tile=tile, tile_v=tv, tile_adj_a=ta)
+        assert np.array_equal(ctx.born(dm).cpu().numpy(), ref[0])
+        assert np.array_equal(ctx.adjoint(y).cpu().numpy(), ref[1])
+        ctx.close()
+    with pytest.raises(lsrtm.LsrtmError):
+        lsrtm.context_for(w, tile_v=9)
+
+
 def test_run_twice_deterministic(torch):
     w = synth.small((40, 60), nt=90, npml=5, seed=12, nshot=3, uneven=True)
     ctx = _ctx(torch, w)
