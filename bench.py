@@ -140,11 +140,13 @@ def main():
                          "autotuned for config5)")
     ap.add_argument("--tile", type=int, default=None,
                     help="tile shape id; -1 = autotuned (default: 1 = 32 x 16 for the 2D workloads)")
-    ap.add_argument("--tile-v", type=int, default=-1,
-                    help="2D: tile shape id of the velocity phases (-1 = the stencil tile)")
+    ap.add_argument("--tile-v", type=int, default=None,
+                    help="tile shape id of the velocity phases (-1 = the stencil tile; default: -1 for "
+                         "the 2D workloads, 1 = 64 x 8 x 32 for config5)")
     ap.add_argument("--tile-adj-a", type=int, default=None,
-                    help="2D: tile shape id of the adjoint A phase (-1 = the stencil tile; default: 2 = "
-                         "32 x 32 for the 2D workloads, the fastest shape for that phase on MI355X)")
+                    help="tile shape id of the adjoint A phase (-1 = the stencil tile; default: 2 = "
+                         "32 x 32 for the 2D workloads, 1 = 64 x 8 x 32 for config5: the fastest shapes "
+                         "for those phases on MI355X)")
     ap.add_argument("--tune-steps", type=int, default=24)
     ap.add_argument("--pcgnr", type=int, default=0,
                     help="also run N CGNR and N pseudo-Hessian-preconditioned CGNR iterations from x = 0 "
@@ -166,8 +168,10 @@ def main():
         args.shots_per_launch = -1 if args.workload == "config5" else 32
     if args.tile is None:
         args.tile = -1 if args.workload == "config5" else 1
+    if args.tile_v is None:
+        args.tile_v = 1 if args.workload == "config5" else -1
     if args.tile_adj_a is None:
-        args.tile_adj_a = -1 if args.workload == "config5" else 2
+        args.tile_adj_a = 1 if args.workload == "config5" else 2
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the shot-parallel "
               "multi-GPU layout is not built", file=sys.stderr)
@@ -185,8 +189,8 @@ def main():
     nd = w.ndim
     ckdt = "bf16" if args.workload == "config5" else "f32"
     log(f"[bench] workload {w.name}: {w.nshot} shots, nt={w.nt}, padded points {w.padded_points()}")
-    tiles2 = dict(tile_v=args.tile_v, tile_adj_a=args.tile_adj_a) if w.ndim == 2 else {}
-    ctx = lsrtm.context_for(w, shots_per_launch=max(0, args.shots_per_launch), tile=args.tile, timing=True, **tiles2,
+    ctx = lsrtm.context_for(w, shots_per_launch=max(0, args.shots_per_launch), tile=args.tile, timing=True,
+                            tile_v=args.tile_v, tile_adj_a=args.tile_adj_a,
                             ckpt_dtype=ckdt, progress=nd == 3)
     if args.tile < 0:
         t0 = time.perf_counter()
@@ -395,9 +399,8 @@ def main():
                    "shots": w.nshot, "nt": w.nt, "padded_points": padded,
                    "shots_per_launch": sz["shots_per_launch"], "ckpt_every": sz["ckpt_every"],
                    "tile": list(lsrtm.tile_shape(nd, sz["tile"])),
-                   **({"tile_v": list(lsrtm.tile_shape(nd, args.tile_v)) if args.tile_v >= 0 else None,
-                       "tile_adj_a": list(lsrtm.tile_shape(nd, args.tile_adj_a)) if args.tile_adj_a >= 0 else None}
-                      if nd == 2 else {}),
+                   "tile_v": list(lsrtm.tile_shape(nd, args.tile_v)) if args.tile_v >= 0 else None,
+                   "tile_adj_a": list(lsrtm.tile_shape(nd, args.tile_adj_a)) if args.tile_adj_a >= 0 else None,
                    "ckpt_dtype": ckdt,
                    "ckpt_per_group": bool(sz["ckpt_per_group"]),
                    "schedule": "fused step" if sz["fused"] else "two-phase step",

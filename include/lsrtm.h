@@ -102,14 +102,14 @@ enum {
     LSRTM_OPT_PROGRESS = 8,         /* 1 = wait for every launch group's pass
                                        and print one line per group to stderr
                                        (long 3D passes); default 0              */
-    LSRTM_OPT_TILE_V = 9,           /* 2D two-phase schedule: tile id of the
-                                       velocity phases (Born, background and
-                                       replay), which record and inject
-                                       nothing; -1 = LSRTM_OPT_TILE (default).
-                                       Results do not depend on it.             */
-    LSRTM_OPT_TILE_ADJ_A = 10       /* 2D two-phase schedule: tile id of the
-                                       adjoint pressure phase (A), likewise;
-                                       -1 = LSRTM_OPT_TILE (default)            */
+    LSRTM_OPT_TILE_V = 9,           /* two-phase steps (2D default, 3D): tile
+                                       id of the velocity phases (Born,
+                                       background and replay), which record
+                                       and inject nothing; -1 = LSRTM_OPT_TILE
+                                       (default).  Results do not depend on it;
+                                       ignored by the fused 2D schedule.        */
+    LSRTM_OPT_TILE_ADJ_A = 10       /* likewise for the adjoint pressure phase
+                                       (A); -1 = LSRTM_OPT_TILE (default)       */
 };
 
 /* Create a context for one grid on one HIP stream (hipStream_t, may be 0).

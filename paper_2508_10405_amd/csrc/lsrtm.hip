@@ -73,7 +73,7 @@ struct Group {
     int* d_win = nullptr;
     int* d_trp = nullptr;          // 2D: receivers per tile (CSR over the tile table)
     Rec* d_trec = nullptr;
-    // 2D: tables of other tile shapes for the phases without receivers
+    // tables of other tile shapes for the phases without receivers
     struct AltTiles {
         int tile;
         int4* d;
@@ -162,8 +162,8 @@ struct lsrtm_ctx {
     int opt_ckg = 0;
     int opt_fused = 0;
     int opt_progress = 0;
-    int opt_tile_v = -1;           // 2D two-phase: tile of the velocity phases (-1: tile)
-    int opt_tile_a = -1;           // 2D two-phase: tile of the adjoint A phase (-1: tile)
+    int opt_tile_v = -1;           // two-phase steps: tile of the velocity phases (-1: tile)
+    int opt_tile_a = -1;           // two-phase steps: tile of the adjoint A phase (-1: tile)
     // timing
     std::vector<EvPair> evpool;
     size_t evused = 0;
@@ -392,9 +392,9 @@ void tile_list(const lsrtm_ctx* c, const Group& gr, int tile, std::vector<int4>&
     }
 }
 
-// Tables of the receiver-free phases' own tile shapes (2D two-phase only).
+// Tables of the receiver-free phases' own tile shapes (two-phase steps).
 lsrtm_status build_alt_tiles(lsrtm_ctx* c, Group& gr) {
-    if (c->ndim != 2 || c->fused) return LSRTM_OK;
+    if (c->fused) return LSRTM_OK;
     for (int tile : {c->opt_tile_v, c->opt_tile_a}) {
         if (tile < 0) continue;
         bool have = false;
@@ -476,11 +476,11 @@ lsrtm_status stencil(lsrtm_ctx* c, Group& gr, int kind, int n, int sstep, int fl
     EvPair* ev = tpick(c, cls_of[kind]);
     hipEvent_t e0 = ev ? ev->a : nullptr, e1 = ev ? ev->b : nullptr;
     hipError_t e;
-    if (c->ndim == 3) e = launch3d(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag, e0, e1);
-    else if (c->fused) e = launch2f(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag, tr, e0, e1);
+    if (c->fused) e = launch2f(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag, tr, e0, e1);
     else {
-        // the velocity phases and the adjoint A phase touch no receivers and
-        // may walk a table of their own tile shape
+        // the velocity phases and the adjoint A phase touch no receivers (in
+        // 3D none of the phases does; the 2D P and B phases use the stencil
+        // tile's receiver lists) and may walk a table of their own tile shape
         const bool vph = kind == K_BG_V || kind == K_SEG_V || kind == K_BORN_V;
         const int want = vph ? c->opt_tile_v : kind == K_ADJ_A ? c->opt_tile_a : -1;
         int tile = c->tile, nt = gr.ntiles;
@@ -494,7 +494,8 @@ lsrtm_status stencil(lsrtm_ctx* c, Group& gr, int kind, int n, int sstep, int fl
                 }
             if (tab == gr.d_tiles) FAIL(c, LSRTM_ESTATE, "tile table %d of phase %d was not built", want, kind);
         }
-        e = launch2d(kind, tile, nt, c->st, sl, tab, c->C, n, sstep, flag, tr, e0, e1);
+        if (c->ndim == 3) e = launch3d(kind, tile, nt, c->st, sl, tab, c->C, n, sstep, flag, e0, e1);
+        else e = launch2d(kind, tile, nt, c->st, sl, tab, c->C, n, sstep, flag, tr, e0, e1);
     }
     if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "stencil launch (kind %d): %s", kind, hipGetErrorString(e));
     if (ev) c->evused++;
@@ -1437,8 +1438,8 @@ lsrtm_status lsrtm_set_option(lsrtm_ctx* c, int key, long long v) {
     case LSRTM_OPT_PROGRESS: c->opt_progress = v != 0; return LSRTM_OK;
     case LSRTM_OPT_TILE_V:
     case LSRTM_OPT_TILE_ADJ_A: {
-        if (c->ndim != 2) FAIL(c, LSRTM_EINVAL, "per-phase tiles are a 2D option");
-        if (v < -1 || v >= kNumTiles2) FAIL(c, LSRTM_EINVAL, "tile id %lld out of range", v);
+        const int nt = c->ndim == 2 ? kNumTiles2 : kNumTiles3;
+        if (v < -1 || v >= nt) FAIL(c, LSRTM_EINVAL, "tile id %lld out of range", v);
         (key == LSRTM_OPT_TILE_V ? c->opt_tile_v : c->opt_tile_a) = (int)v;
         clear_graphs(c);
         return LSRTM_OK;

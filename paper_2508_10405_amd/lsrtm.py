@@ -113,8 +113,8 @@ class Context:
     Parameters follow lsrtm_grid: n = (nz, nx[, ny]) physical sizes,
     h = (dz, dx[, dy]), npml CPML cells, nt steps of dt seconds, CPML
     parameters pml_R and pml_f0, checkpoint interval (0 = planner) and
-    checkpoint storage ("f32", "f16", "bf16").  In 2D, tile_v and tile_adj_a
-    give the velocity phases and the adjoint A phase tile shapes of their own
+    checkpoint storage ("f32", "f16", "bf16").  tile_v and tile_adj_a give
+    the velocity phases and the adjoint A phase tile shapes of their own
     (-1 = the stencil tile); results do not depend on them.
     """
 
@@ -151,9 +151,8 @@ class Context:
         self.set_option(OPT_CKPT_PER_GROUP, int(bool(ckpt_per_group)))
         self.set_option(OPT_FUSED, int(bool(fused)))
         self.set_option(OPT_PROGRESS, int(bool(progress)))
-        if ndim == 2:
-            self.set_option(OPT_TILE_V, tile_v)
-            self.set_option(OPT_TILE_ADJ_A, tile_adj_a)
+        self.set_option(OPT_TILE_V, tile_v)
+        self.set_option(OPT_TILE_ADJ_A, tile_adj_a)
         self.nrec: List[int] = []
         self._keep = []
 

@@ -50,8 +50,8 @@ def test_3d_vs_oracle(torch, n, nt, npml, nshot, uneven):
 
 
 def test_3d_invariances(torch):
-    """Tiles, batching, replay interval and per-group checkpoints do not
-    change a single bit of the 3D results."""
+    """Tiles (also per phase), batching, replay interval and per-group
+    checkpoints do not change a single bit of the 3D results."""
     from paper_2508_10405_amd import lsrtm
     w = synth.small((20, 18, 70), nt=50, npml=4, seed=5, nshot=3, uneven=True, h=12.5)
     dm = to_dev(torch, w.dm)
@@ -59,7 +59,8 @@ def test_3d_invariances(torch):
     ref = None
     for opts in ({"tile": 0}, {"tile": 1, "shots_per_launch": 1}, {"tile": 2, "ckpt_every": 7},
                  {"tile": 3, "ckpt_every": 50}, {"tile": 4, "ckpt_per_group": True, "shots_per_launch": 2},
-                 {"tile": 5, "graph": False}):
+                 {"tile": 5, "graph": False}, {"tile": 0, "tile_v": 1, "tile_adj_a": 2},
+                 {"tile": 3, "tile_v": 5, "tile_adj_a": 0, "ckpt_per_group": True}):
         ctx = lsrtm.context_for(w, **opts)
         out = (ctx.born(dm).cpu().numpy(), ctx.adjoint(y).cpu().numpy())
         ctx.close()
