@@ -276,10 +276,14 @@ lsrtm_status lsrtm_set_option(lsrtm_ctx* ctx, int key, long long value);
 /* Autotuner: times the stencil kernels of a Born, replay and adjoint step
  * over nsteps time steps on the actual launch groups for every tile shape,
  * and with tune_groups = 1 also for several shot-per-launch sizes and (2D)
- * both step schedules (rebuilding the memory plan), then keeps the fastest.  out (HOST double[3], may be NULL) = (tile id, shots per
- * launch, ms per time step).  With LSRTM_TUNE_CACHE naming a file, results
- * are read from and appended to it.  Invalidates stored checkpoints.  When
- * no tile is set, a tile-only tuning runs on the first pass by itself. */
+ * both step schedules (rebuilding the memory plan), then keeps the fastest.
+ * For two-phase steps it then tries every other shape for the velocity
+ * phases and for the adjoint A phase (LSRTM_OPT_TILE_V / _TILE_ADJ_A, set to
+ * the picks or -1).  out (HOST double[5], may be NULL) = (tile id, shots per
+ * launch, ms per time step, velocity-phase tile, adjoint-A tile).  With
+ * LSRTM_TUNE_CACHE naming a file, results are read from and appended to it.
+ * Invalidates stored checkpoints.  When no tile is set, the same tile tuning
+ * (without group sizes and schedules) runs on the first pass by itself. */
 lsrtm_status lsrtm_autotune(lsrtm_ctx* ctx, int nsteps, int tune_groups, double* out);
 
 /* Sizes: out[0] = data length, out[1] = physical grid points (one image),

@@ -1163,7 +1163,7 @@ std::string tune_key(const lsrtm_ctx* c) {
     return b;
 }
 
-bool tune_cache_get(const lsrtm_ctx* c, int* tile, int* spl, int* fused) {
+bool tune_cache_get(const lsrtm_ctx* c, int* tile, int* spl, int* fused, int* tile_v, int* tile_a) {
     const char* f = getenv("LSRTM_TUNE_CACHE");
     if (!f) return false;
     FILE* fp = fopen(f, "r");
@@ -1175,11 +1175,13 @@ bool tune_cache_get(const lsrtm_ctx* c, int* tile, int* spl, int* fused) {
         std::string l(line);
         const size_t bar = l.find('|');
         if (bar == std::string::npos || l.substr(0, bar) != key) continue;
-        int t, g, f;
-        if (sscanf(l.c_str() + bar + 1, "%d %d %d", &t, &g, &f) == 3) {
+        int t, g, f, tv = -1, ta = -1;
+        if (sscanf(l.c_str() + bar + 1, "%d %d %d %d %d", &t, &g, &f, &tv, &ta) >= 3) {
             *tile = t;
             *spl = g;
             *fused = f;
+            *tile_v = tv;
+            *tile_a = ta;
             found = true;
         }
     }
@@ -1192,7 +1194,7 @@ void tune_cache_put(const lsrtm_ctx* c, int tile, int spl, int fused) {
     if (!f) return;
     FILE* fp = fopen(f, "a");
     if (!fp) return;
-    fprintf(fp, "%s|%d %d %d\n", tune_key(c).c_str(), tile, spl, fused);
+    fprintf(fp, "%s|%d %d %d %d %d\n", tune_key(c).c_str(), tile, spl, fused, c->opt_tile_v, c->opt_tile_a);
     fclose(fp);
 }
 
@@ -1246,6 +1248,8 @@ lsrtm_status tune_tiles(lsrtm_ctx* c, int nsteps, int* best, double* best_ms) {
         CHK(fill(c, c->pool + c->bg_region + c->sc_region, gr.img_used));
     }
     double ms;
+    // one shape for every phase first
+    c->opt_tile_v = c->opt_tile_a = -1;
     CHK(time_tile(c, 0, 1, &ms));   // warm-up
     *best = 0;
     *best_ms = 1e30;
@@ -1257,29 +1261,51 @@ lsrtm_status tune_tiles(lsrtm_ctx* c, int nsteps, int* best, double* best_ms) {
         }
     }
     c->tile = *best;
+    // then, for two-phase steps, the phases without receivers may keep
+    // shapes of their own: the velocity phases, then the adjoint A phase
+    if (!c->fused) {
+        for (int* opt : {&c->opt_tile_v, &c->opt_tile_a}) {
+            int pick = -1;
+            for (int t = 0; t < ntile; ++t) {
+                if (t == *best) continue;
+                *opt = t;
+                CHK(time_tile(c, *best, nsteps, &ms));
+                if (ms < *best_ms) {
+                    *best_ms = ms;
+                    pick = t;
+                }
+            }
+            *opt = pick;
+        }
+    }
     clear_graphs(c);
     return LSRTM_OK;
 }
 
 lsrtm_status autotune(lsrtm_ctx* c, int nsteps, bool groups, double* out) {
-    int tile = -1, spl = c->opt_spl, fused = c->opt_fused;
-    if (tune_cache_get(c, &tile, &spl, &fused)) {
+    int tile = -1, spl = c->opt_spl, fused = c->opt_fused, tile_v = -1, tile_a = -1;
+    if (tune_cache_get(c, &tile, &spl, &fused, &tile_v, &tile_a)) {
         if (groups && (spl != c->opt_spl || fused != c->opt_fused)) {
             c->opt_spl = spl;
             c->opt_fused = fused;
             CHK(plan(c));
         }
         c->tile = tile;
+        c->opt_tile_v = tile_v;
+        c->opt_tile_a = tile_a;
         c->tuned = true;
+        clear_graphs(c);
         if (out) {
             out[0] = tile;
             out[1] = c->G;
             out[2] = -1.0;
+            out[3] = tile_v;
+            out[4] = tile_a;
         }
         return LSRTM_OK;
     }
     double best_ms = 1e30;
-    int best_tile = 0, best_spl = c->opt_spl, best_fused = c->opt_fused;
+    int best_tile = 0, best_spl = c->opt_spl, best_fused = c->opt_fused, best_tv = -1, best_ta = -1;
     std::vector<int> cands;
     if (groups) {
         cands.push_back(0);
@@ -1307,6 +1333,8 @@ lsrtm_status autotune(lsrtm_ctx* c, int nsteps, bool groups, double* out) {
                 best_tile = t;
                 best_spl = g;
                 best_fused = f;
+                best_tv = c->opt_tile_v;
+                best_ta = c->opt_tile_a;
             }
         }
     }
@@ -1316,6 +1344,8 @@ lsrtm_status autotune(lsrtm_ctx* c, int nsteps, bool groups, double* out) {
         CHK(plan(c));
     }
     c->tile = best_tile;
+    c->opt_tile_v = best_tv;
+    c->opt_tile_a = best_ta;
     c->tuned = true;
     clear_graphs(c);
     tune_cache_put(c, best_tile, best_spl, best_fused);
@@ -1323,6 +1353,8 @@ lsrtm_status autotune(lsrtm_ctx* c, int nsteps, bool groups, double* out) {
         out[0] = best_tile;
         out[1] = c->G;
         out[2] = best_ms;
+        out[3] = best_tv;
+        out[4] = best_ta;
     }
     return LSRTM_OK;
 }

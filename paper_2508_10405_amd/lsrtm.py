@@ -209,9 +209,10 @@ class Context:
 
     # -- sizes --------------------------------------------------------------
     def autotune(self, nsteps=8, groups=False):
-        out = (_c_double * 3)()
+        out = (_c_double * 5)()
         self._check(lib().lsrtm_autotune(self._h, int(nsteps), int(bool(groups)), out), "autotune")
-        return {"tile": int(out[0]), "shots_per_launch": int(out[1]), "ms_per_step": out[2]}
+        return {"tile": int(out[0]), "shots_per_launch": int(out[1]), "ms_per_step": out[2],
+                "tile_v": int(out[3]), "tile_adj_a": int(out[4])}
 
     def sizes(self):
         out = (_c_ll * 10)()

@@ -285,8 +285,12 @@ def test_autotune_keeps_results_and_caches(torch, tmp_path, monkeypatch):
     ctx2 = lsrtm.context_for(w)
     res2 = ctx2.autotune(nsteps=2, groups=True)
     assert res2["tile"] == res["tile"] and ctx2.sizes()["shots_per_launch"] == ctx.sizes()["shots_per_launch"]
+    assert (res2["tile_v"], res2["tile_adj_a"]) == (res["tile_v"], res["tile_adj_a"])
     assert cache.read_text().count("|") == 1   # served from the cache
     assert np.array_equal(ctx2.born(dm).cpu().numpy(), ref)
+    y = to_dev(torch, np.random.default_rng(5).standard_normal(ctx2.data_len))
+    plain = lsrtm.context_for(w, tile=0, shots_per_launch=1)
+    assert np.array_equal(ctx2.adjoint(y).cpu().numpy(), plain.adjoint(y).cpu().numpy())
 
 
 def test_cgnr_resume_from_saved_state(torch):
