@@ -24,6 +24,9 @@ from gpu_common import f64, rel, require_gpu, to_dev
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
 M = 300   # sampled time steps
+# the launch configuration bench.py times for the 2D workloads: 32 shots per
+# launch (balanced groups), 32 x 16 tiles, 32 x 32 tiles for the adjoint A phase
+BENCH_2D = dict(shots_per_launch=32, tile=1, tile_adj_a=2)
 
 
 @pytest.fixture(scope="module")
@@ -75,9 +78,54 @@ def _check_sampled(torch, w, shots, **opts):
 
 
 def test_config2_full_size_sampled(torch):
-    _check_sampled(torch, synth.config2(), [0, 77])
+    _check_sampled(torch, synth.config2(), [0, 77], **BENCH_2D)
 
 
 def test_config3_full_size_sampled(torch):
     w = synth.config3()
-    _check_sampled(torch, w, [5])
+    _check_sampled(torch, w, [5], **BENCH_2D)
+
+
+def test_config5_full_size_dot(torch):
+    """The 3D workload at its full grid (400 x 400 x 200, 440 x 440 x 240
+    padded, 16 shots) in the launch configuration bench.py times for it (one
+    shot per launch, 64 x 4 x 32 tiles, the velocity and adjoint A phases on
+    64 x 8 x 32), on a truncated time axis.  The oracle cannot run this grid,
+    so: the Born operator and the migration with FP32 checkpoints are checked
+    against each other (dot-product test over the whole problem); the
+    migration with the BF16 checkpoints the benchmark uses stays within the
+    BF16 bound (2e-2) of the FP32 one; and the data agree bit for bit with a
+    run on a shorter time axis (causality)."""
+    from paper_2508_10405_amd import lsrtm
+    w = synth.config5(nt=160)
+    print(f"[case] {w.name} full grid, nt {w.nt}", flush=True)
+    cfg = dict(shots_per_launch=1, tile=0, tile_v=1, tile_adj_a=1)
+    rng = np.random.default_rng(11)
+    x = to_dev(torch, 0.01 * rng.standard_normal((2,) + w.shape))
+    ctx = lsrtm.context_for(w, ckpt_dtype="f32", **cfg)
+    print("plan", ctx.sizes(), flush=True)
+    d = ctx.born(x)
+    yv = to_dev(torch, rng.standard_normal(ctx.data_len))
+    img32 = ctx.adjoint(yv)
+    a = ctx.dot(d, yv)
+    b = ctx.dot(x.view(-1), img32.view(-1))
+    print("3D full-size dot", a, b, abs(a - b) / abs(a), flush=True)
+    assert abs(a - b) <= TOL * abs(a)
+    parts = [p.cpu().numpy() for p in ctx.split(d)]
+    img32 = img32.cpu().numpy()
+    ctx.close()
+    ctx = lsrtm.context_for(w, ckpt_dtype="bf16", **cfg)
+    assert np.array_equal(ctx.born(x).cpu().numpy(), d.cpu().numpy())
+    img16 = ctx.adjoint(yv).cpu().numpy()
+    ctx.close()
+    for k in range(2):
+        e = rel(img16[k], img32[k])
+        print(f"BF16 vs FP32 checkpoints, image {k}: rel {e:.2e}", flush=True)
+        assert e <= 2e-2
+    short = synth.Workload(w.name, w.h, w.dt, 100, w.npml, w.f0, w.lnvp, w.lnip, w.dm, w.win, w.src, w.rec,
+                           np.ascontiguousarray(w.wavelet[:, :100]), pml_R=w.pml_R, pml_f0=w.pml_f0)
+    ctx = lsrtm.context_for(short, ckpt_dtype="bf16", **cfg)
+    ds = [p.cpu().numpy() for p in ctx.split(ctx.born(x))]
+    ctx.close()
+    for s in (0, 15):
+        assert np.array_equal(parts[s][:100], ds[s]), s
