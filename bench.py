@@ -43,7 +43,7 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic HBM bytes per padded node and launch (FP32, interior node,
 # every array read once and written once; CPML strips excluded).
 BYTES_PER_PT = {
-    2: {"born_v": 48, "born_p": 40, "bg_v": 32, "bg_p": 24, "adj_a": 36, "adj_b": 40},
+    2: {"born_v": 48, "born_p": 40, "bg_v": 32, "bg_p": 24, "adj_a": 36, "adj_b": 36},
     3: {"born_v": 64, "born_p": 48, "bg_v": 44, "bg_p": 28, "adj_a": 44, "adj_b": 52},
     # fused 2D schedule: one kernel per step, reported under the velocity-phase class
     "2f": {"born_v": 64, "bg_v": 44, "adj_a": 64},

@@ -18,7 +18,8 @@
 // appendix A for the adjoint):
 //   V : v_a <- v_a - dt b_a (G_a p + psi_a), with the CPML memory psi_a
 //       advanced in the strips.  BORN adds the scattered velocity with the
-//       density source -avg(dlnrho) dv_a; SEG stores dv_a for migration.
+//       density source -avg(dlnrho) dv_a; SEG stores G_a p + psi_a (the
+//       gradient behind dv_a) for migration.
 //   P : p <- p - dt kappa q, q = sum_a (D_a v_a + phi_a), plus the source.
 //       BORN adds the scattered pressure with the bulk-modulus source
 //       dlnkappa (-dt kappa q); SEG stores q for migration.
@@ -168,8 +169,8 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         S.v[1][i] = vx[r] + dvx;
         if (SEG) {
             // the replay buffer is read back only k steps later: streaming stores
-            __builtin_nontemporal_store(dvz, &seg[i]);
-            __builtin_nontemporal_store(dvx, &seg[S.npts + i]);
+            __builtin_nontemporal_store(gzp, &seg[i]);
+            __builtin_nontemporal_store(gxp, &seg[S.npts + i]);
         }
         if (!BORN && !SEG && (flag & PH_ACCUMULATE)) {   // pseudo-Hessian: sum of dv_a^2
             S.w[0][i] = S.w[0][i] + dvz * dvz;
@@ -337,8 +338,15 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint phase A (transpose of P): g_kappa += (-dt kappa q^n) p~;
-// e~_a = q~ + aci_a (phi~_a + q~) with q~ = -dt kappa p~;  v~_a -= G_a e~_a.
+// The adjoint state is kept scaled: Q = q~ = -dt kappa p~ in place of p~ and
+// U_a = -dt b_a v~_a in place of v~_a (the same fields, one FP32 rounding
+// apart), so that neither adjoint phase reads dt kappa or dt b_a at halo
+// cells.  The replay buffer holds the CPML-corrected gradient G_a p + psi_a,
+// so the lnrho image product -dv_a v~_a is -(G_a p + psi_a) U_a.
+//
+// Adjoint phase A (transpose of P): g_kappa += q^n Q;
+// e~_a = Q + aci_a (phi~_a + Q);  v~_a -= G_a e~_a, i.e. U_a += dt b_a G_a e~_a;
+// the pending chi update uses U_a before that.
 // flag = 1 on the first reverse step (no pending chi update).
 // ---------------------------------------------------------------------------
 template <int BZ, int BX>
@@ -364,42 +372,42 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     auto inside = [&](int lz, int lx) {
         return (unsigned)(z0 + lz - HW) < (unsigned)nz && (unsigned)(x0 + lx - HW) < (unsigned)nx;
     };
-    // loads of e~ at a cell: dt kappa, p~, then per wanted axis the CPML
-    // coefficient and phi~ (the latter only inside the strips)
+    // loads of e~ at a cell: Q, then per wanted axis the CPML coefficient and
+    // phi~ (the latter only inside the strips)
     auto lde = [&](int lz, int lx, float* v, bool wz, bool wx) {
         const int gz = z0 + lz - HW, gx = x0 + lx - HW;
         const bool in = inside(lz, lx);
         const long long i = in ? gx * ldz + gz : 0;
-        v[0] = S.kdt[i];
-        v[1] = S.q[i];
+        v[0] = S.q[i];
         if (wz) {
-            v[2] = pml ? aciz[in ? gz : 0] : 0.f;
-            v[3] = pml ? S.eta[0][in && in_pml(gz, nz, npml) ? i : 0] : 0.f;
+            v[1] = pml ? aciz[in ? gz : 0] : 0.f;
+            v[2] = pml ? S.eta[0][in && in_pml(gz, nz, npml) ? i : 0] : 0.f;
         }
         if (wx) {
-            v[4] = pml ? acix[in ? gx : 0] : 0.f;
-            v[5] = pml ? S.eta[1][in && in_pml(gx, nx, npml) ? i : 0] : 0.f;
+            v[3] = pml ? acix[in ? gx : 0] : 0.f;
+            v[4] = pml ? S.eta[1][in && in_pml(gx, nx, npml) ? i : 0] : 0.f;
         }
     };
     auto ete = [&](bool in, const float* v, bool wz, bool wx, float& ez, float& ex, float& qt) {
         ez = ex = qt = 0.f;
         if (in) {
-            qt = -v[0] * v[1];
+            qt = v[0];
             ez = qt;
             ex = qt;
-            if (wz && v[2] != 0.f) ez = qt + v[2] * (v[3] + qt);
-            if (wx && v[4] != 0.f) ex = qt + v[4] * (v[5] + qt);
+            if (wz && v[1] != 0.f) ez = qt + v[1] * (v[2] + qt);
+            if (wx && v[3] != 0.f) ex = qt + v[3] * (v[4] + qt);
         }
     };
     const gfloat* achz = S.cpml[0];
     const gfloat* bchz = S.cpml[0] + nz;
     const gfloat* achx = S.cpml[1];
     const gfloat* bchx = S.cpml[1] + nx;
-    // the tile's own nodes need both components; q~ is kept for the image.
-    // Unless this is the first reverse step, the pending chi update needs
-    // the CPML coefficients, chi and dt b at the node (inside the strips).
-    float vz[R], vx[R], gk[R], qn[R], ev[R][6];
-    float hz_[R], hx_[R], cz[R], cx[R], xz[R], xx[R], bz[R], bx[R];
+    // the tile's own nodes need both components; Q is kept for the image and
+    // sb at the node and its upper neighbours for dt b_a.  Unless this is the
+    // first reverse step, the pending chi update needs the CPML coefficients
+    // and chi at the node (inside the strips).
+    float vz[R], vx[R], gk[R], qn[R], ev[R][5], s0[R], s1z[R], s1x[R];
+    float hz_[R], hx_[R], cz[R], cx[R], xz[R], xx[R];
     bool ok[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -412,6 +420,9 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         vx[r] = S.w[1][i];
         gk[r] = S.gk[i];
         qn[r] = __builtin_nontemporal_load(&segq[i]);
+        s0[r] = S.sb[i];
+        s1z[r] = S.sb[gz + 1 < nz ? i + 1 : i];
+        s1x[r] = S.sb[gx + 1 < nx ? i + ldz : i];
         lde(lz + HW, lx + HW, ev[r], true, true);
         if (!flag && pml) {
             const long long iz = ok[r] && in_pml(gz, nz, npml) ? i : 0;
@@ -422,13 +433,11 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             cx[r] = bchx[ok[r] ? gx : 0];
             xz[r] = S.xi[0][iz];
             xx[r] = S.xi[1][ix];
-            bz[r] = S.bdt[0][iz];
-            bx[r] = S.bdt[1][ix];
         } else {
-            hz_[r] = hx_[r] = cz[r] = cx[r] = xz[r] = xx[r] = bz[r] = bx[r] = 0.f;
+            hz_[r] = hx_[r] = cz[r] = cx[r] = xz[r] = xx[r] = 0.f;
         }
     }
-    float hz[RZ::IT][6], hx[RX::IT][6];
+    float hz[RZ::IT][5], hx[RX::IT][5];
     RZ::load([&](int lz, int lx, float* v) { lde(lz, lx, v, true, false); }, hz);
     RX::load([&](int lz, int lx, float* v) { lde(lz, lx, v, false, true); }, hx);
     float qt[R];
@@ -464,20 +473,22 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const long long i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
         if (!flag) {
-            if (hz_[r] != 0.f) S.xi[0][i] = cz[r] * (xz[r] + (-bz[r] * vz[r]));
-            if (hx_[r] != 0.f) S.xi[1][i] = cx[r] * (xx[r] + (-bx[r] * vx[r]));
+            if (hz_[r] != 0.f) S.xi[0][i] = cz[r] * (xz[r] + vz[r]);
+            if (hx_[r] != 0.f) S.xi[1][i] = cx[r] * (xx[r] + vx[r]);
         }
         S.gk[i] = gk[r] + qn[r] * qt[r];
-        S.w[0][i] = vz[r] - d_half(sez, c, 1, C.c[0]);
-        S.w[1][i] = vx[r] - d_half(sex, c, T::LZ, C.c[1]);
+        const float bz = s0[r] * s1z[r], bx = s0[r] * s1x[r];
+        S.w[0][i] = vz[r] + bz * d_half(sez, c, 1, C.c[0]);
+        S.w[1][i] = vx[r] + bx * d_half(sex, c, T::LZ, C.c[1]);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint phase B (transpose of V): phi~_a <- bci_a (phi~_a + q~);
-// g_rho += avg^T(-dv_a v~_a);  h~_a = -dt b_a v~_a,
-// g~_a = h~_a + ach_a (chi_a + h~_a);  p~ -= sum_a D_a g~_a.
-// The products -dv_a v~_a are formed while staging (the transpose of the
+// Adjoint phase B (transpose of V): phi~_a <- bci_a (phi~_a + Q);
+// g_rho += avg^T(-dv_a v~_a) = avg^T(-(G_a p + psi_a) U_a);  h~_a = U_a,
+// g~_a = h~_a + ach_a (chi_a + h~_a);  p~ -= sum_a D_a g~_a (and the adjoint
+// source is added to p~), i.e. Q += dt kappa (sum_a D_a g~_a - source).
+// The image products are formed while staging (the transpose of the
 // half-node average needs them at the node and at its lower neighbour).
 // ---------------------------------------------------------------------------
 template <int BZ, int BX>
@@ -505,8 +516,8 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const gfloat* acix = S.cpml[1] + 2 * nx;
     const gfloat* bcix = S.cpml[1] + 3 * nx;
     const bool pml = tile_in_pml<BZ, BX>(z0, x0, nz, nx, npml);
-    // pointwise loads; the phi~ update needs the CPML coefficients, phi~ and
-    // dt kappa at the node (inside the strips)
+    // pointwise loads: Q, g_rho and dt kappa; the phi~ update needs the CPML
+    // coefficients and phi~ at the node (inside the strips)
     float pt[R], gr[R], az[R], ax[R], cz[R], cx[R], ez[R], ex[R], kk[R];
     bool ok[R];
 #pragma unroll
@@ -525,43 +536,43 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         cx[r] = pml ? bcix[ok[r] ? gx : 0] : 0.f;
         ez[r] = pml ? S.eta[0][mz ? i : 0] : 0.f;
         ex[r] = pml ? S.eta[1][mx ? i : 0] : 0.f;
-        kk[r] = pml ? S.kdt[mz || mx ? i : 0] : 0.f;
+        kk[r] = S.kdt[i];
     }
     const gfloat* achz = S.cpml[0];
     const gfloat* achx = S.cpml[1];
     auto inside = [&](int lz, int lx) {
         return (unsigned)(z0 + lz - HW) < (unsigned)nz && (unsigned)(x0 + lx - HW) < (unsigned)nx;
     };
-    // loads of g~_a and of the image product at a cell: v~_a, dt b_a, the
-    // CPML coefficient, chi_a (inside the strips only) and dv_a (on the rows
-    // or columns whose product is needed)
+    // loads of g~_a and of the image product at a cell: the CPML coefficient,
+    // chi_a (inside the strips only), U_a and G_a p + psi_a (on the rows or
+    // columns whose product is needed).  This order keeps the compiler's
+    // schedule of the staging loads in one batch (54 VGPRs; other orders
+    // split it into dependent groups at 66-67 VGPRs).
     auto ldz_ = [&](int lz, int lx, float* v) {
         const int gz = z0 + lz - HW, gx = x0 + lx - HW;
         const bool in = inside(lz, lx);
         const long long i = in ? gx * ldz + gz : 0;
-        v[0] = S.w[0][i];
-        v[1] = S.bdt[0][i];
-        v[2] = pml ? achz[in ? gz : 0] : 0.f;
-        v[3] = pml ? S.xi[0][in && in_pml(gz, nz, npml) ? i : 0] : 0.f;
-        v[4] = segz[in && lz >= HW - 1 && lz < HW + BZ ? i : 0];
+        v[0] = pml ? achz[in ? gz : 0] : 0.f;
+        v[1] = pml ? S.xi[0][in && in_pml(gz, nz, npml) ? i : 0] : 0.f;
+        v[2] = S.w[0][i];
+        v[3] = segz[in && lz >= HW - 1 && lz < HW + BZ ? i : 0];
     };
     auto ldx_ = [&](int lz, int lx, float* v) {
         const int gz = z0 + lz - HW, gx = x0 + lx - HW;
         const bool in = inside(lz, lx);
         const long long i = in ? gx * ldz + gz : 0;
-        v[0] = S.w[1][i];
-        v[1] = S.bdt[1][i];
-        v[2] = pml ? achx[in ? gx : 0] : 0.f;
-        v[3] = pml ? S.xi[1][in && in_pml(gx, nx, npml) ? i : 0] : 0.f;
-        v[4] = segx[in && lx >= HW - 1 && lx < HW + BX ? i : 0];
+        v[0] = pml ? achx[in ? gx : 0] : 0.f;
+        v[1] = pml ? S.xi[1][in && in_pml(gx, nx, npml) ? i : 0] : 0.f;
+        v[2] = S.w[1][i];
+        v[3] = segx[in && lx >= HW - 1 && lx < HW + BX ? i : 0];
     };
     auto stz_ = [&](int lz, int lx, const float* v) {
         const int c = lx * T::LZ + lz;
         float g = 0.f, x = 0.f;
         if (inside(lz, lx)) {
-            const float h = -v[1] * v[0];
-            g = v[2] != 0.f ? h + v[2] * (v[3] + h) : h;
-            if (lz >= HW - 1 && lz < HW + BZ) x = -v[4] * v[0];
+            const float h = v[2];
+            g = v[0] != 0.f ? h + v[0] * (v[1] + h) : h;
+            if (lz >= HW - 1 && lz < HW + BZ) x = -v[3] * v[2];
         }
         sgz[c] = g;
         sxz[c] = x;
@@ -570,14 +581,14 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const int c = lx * T::LZ + lz;
         float g = 0.f, x = 0.f;
         if (inside(lz, lx)) {
-            const float h = -v[1] * v[0];
-            g = v[2] != 0.f ? h + v[2] * (v[3] + h) : h;
-            if (lx >= HW - 1 && lx < HW + BX) x = -v[4] * v[0];
+            const float h = v[2];
+            g = v[0] != 0.f ? h + v[0] * (v[1] + h) : h;
+            if (lx >= HW - 1 && lx < HW + BX) x = -v[3] * v[2];
         }
         sgx[c] = g;
         sxx[c] = x;
     };
-    float hz[RZ::IT][5], hx[RX::IT][5];
+    float hz[RZ::IT][4], hx[RX::IT][4];
     RZ::load(ldz_, hz);
     RX::load(ldx_, hx);
     RZ::store(stz_, hz);
@@ -591,17 +602,14 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const int gz = z0 + lz, gx = x0 + lx;
         const long long i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
-        if (az[r] != 0.f || ax[r] != 0.f) {
-            const float qt = -kk[r] * pt[r];
-            if (az[r] != 0.f) S.eta[0][i] = cz[r] * (ez[r] + qt);
-            if (ax[r] != 0.f) S.eta[1][i] = cx[r] * (ex[r] + qt);
-        }
+        if (az[r] != 0.f) S.eta[0][i] = cz[r] * (ez[r] + pt[r]);
+        if (ax[r] != 0.f) S.eta[1][i] = cx[r] * (ex[r] + pt[r]);
         S.gr[i] = gr[r] + (0.5f * (sxz[c] + sxz[c - 1]) + 0.5f * (sxx[c] + sxx[c - T::LZ]));
         const float dz = d_node(sgz, c, 1, C.c[0]);
         const float dx = d_node(sgx, c, T::LZ, C.c[1]);
-        float pn = pt[r] - (dz + dx);
-        if (tr.y && n > 0) pn = pn + tile_inject(tr, tix, lz + BZ * lx, n - 1);
-        S.q[i] = pn;
+        float qn = pt[r] + kk[r] * (dz + dx);
+        if (tr.y && n > 0) qn = qn - kk[r] * tile_inject(tr, tix, lz + BZ * lx, n - 1);
+        S.q[i] = qn;
     }
 }
 

@@ -11,9 +11,10 @@
 // updated in place, the scattered/adjoint phi is double-buffered like the
 // rest because the adjoint reads it at halo nodes.
 // Each expression is the one of the two-phase kernels (kern2d.hip) with the
-// same operation order, so both schedules give identical bits.  Per-shot HBM
-// traffic per node and step: 48 B (Born, was 72), 36 B (replay, was 48), 52 B
-// (adjoint, was 64).
+// same operation order (the adjoint on the same scaled state Q = -dt kappa p~,
+// U_a = -dt b_a v~_a), so both schedules give identical bits.  Algorithmic
+// HBM traffic per node and step: 64 B (Born; two-phase 88), 44 B (replay;
+// 56), 64 B (adjoint; 72).
 #include "common.h"
 #include "kernels.h"
 
@@ -178,7 +179,7 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
         svz[cv] = vn;
         if (own) {
             S.vn[0][i] = vn;
-            if (SEG) seg[i] = dv;
+            if (SEG) seg[i] = g;   // the gradient behind dv, for migration
         }
         if (BORN) {
             float gq = d_half(sq, c, 1, C.c[0]);
@@ -220,7 +221,7 @@ k2f_step(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C
         svx[cv] = vn;
         if (own) {
             S.vn[1][i] = vn;
-            if (SEG) seg[S.npts + i] = dv;
+            if (SEG) seg[S.npts + i] = g;
         }
         if (BORN) {
             float gq = d_half(sq, c, T::PZ, C.c[1]);
@@ -329,7 +330,7 @@ k2f_adj(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
         const int gz = z0 + e % BZ, gx = x0 + e / BZ;
         const bool in = gz < nz && gx < nx;
         const long long i = in ? gx * ldz + gz : 0;
-        pt[r] = S.q[i];
+        pt[r] = S.q[i];   // Q = -dt kappa p~
         kk[r] = S.kdt[i];
         gk[r] = S.gk[i];
         qn[r] = segq[i];
@@ -370,7 +371,7 @@ k2f_adj(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
         xs[t] = segx[i];
         xc[t] = S.xi[1][in && in_pml(gx, nx, npml) ? i : 0];
     }
-    // e~_a on the crosses: dt kappa, p~, the CPML coefficient and phi~
+    // e~_a on the crosses: Q, the CPML coefficient and phi~
     auto inside = [&](int lz, int lx) {
         return (unsigned)(z0 + lz) < (unsigned)nz && (unsigned)(x0 + lx) < (unsigned)nx;
     };
@@ -378,30 +379,28 @@ k2f_adj(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
         const int gz = z0 + lz, gx = x0 + lx;
         const bool in = inside(lz, lx);
         const long long i = in ? gx * ldz + gz : 0;
-        v[0] = S.kdt[i];
-        v[1] = S.q[i];
-        v[2] = aciz[in ? gz : 0];
-        v[3] = S.eta[0][in && in_pml(gz, nz, npml) ? i : 0];
+        v[0] = S.q[i];
+        v[1] = aciz[in ? gz : 0];
+        v[2] = S.eta[0][in && in_pml(gz, nz, npml) ? i : 0];
     };
     auto lde_x = [&](int lz, int lx, float* v) {
         const int gz = z0 + lz, gx = x0 + lx;
         const bool in = inside(lz, lx);
         const long long i = in ? gx * ldz + gz : 0;
-        v[0] = S.kdt[i];
-        v[1] = S.q[i];
-        v[2] = acix[in ? gx : 0];
-        v[3] = S.eta[1][in && in_pml(gx, nx, npml) ? i : 0];
+        v[0] = S.q[i];
+        v[1] = acix[in ? gx : 0];
+        v[2] = S.eta[1][in && in_pml(gx, nx, npml) ? i : 0];
     };
     auto ete = [&](bool in, const float* v) {
         float e = 0.f;
         if (in) {
-            const float qt = -v[0] * v[1];
-            const float a = v[2];
-            e = a != 0.f ? qt + a * (v[3] + qt) : qt;
+            const float qt = v[0];
+            const float a = v[1];
+            e = a != 0.f ? qt + a * (v[2] + qt) : qt;
         }
         return e;
     };
-    float hz[CZ::IT][4], hx[CX::IT][4];
+    float hz[CZ::IT][3], hx[CX::IT][3];
     CZ::load(lde_z, hz);
     CX::load(lde_x, hx);
     CZ::store([&](int lz, int lx, const float* v) { sez[lx * (BZ + 14) + lz + 7] = ete(inside(lz, lx), v); }, hz);
@@ -432,12 +431,12 @@ k2f_adj(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
         float chi = 0.f;
         if (a != 0.f) {
             chi = zc[t];
-            if (!flag) chi = bchz[gz] * (chi + (-b * vo));
+            if (!flag) chi = bchz[gz] * (chi + vo);
             if (own) S.xin[0][i] = chi;
         }
-        const float vn = vo - d_half(sez, lx * (BZ + 14) + lz + 7, 1, C.c[0]);
+        const float vn = vo + b * d_half(sez, lx * (BZ + 14) + lz + 7, 1, C.c[0]);
         if (own) S.wn[0][i] = vn;
-        const float h = -b * vn;
+        const float h = vn;
         sgz[cv] = a != 0.f ? h + a * (chi + h) : h;
         sxz[cv] = -zs[t] * vn;
     }
@@ -461,12 +460,12 @@ k2f_adj(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
         float chi = 0.f;
         if (a != 0.f) {
             chi = xc[t];
-            if (!flag) chi = bchx[gx] * (chi + (-b * vo));
+            if (!flag) chi = bchx[gx] * (chi + vo);
             if (own) S.xin[1][i] = chi;
         }
-        const float vn = vo - d_half(sex, (lx + 7) * BZ + lz, BZ, C.c[1]);
+        const float vn = vo + b * d_half(sex, (lx + 7) * BZ + lz, BZ, C.c[1]);
         if (own) S.wn[1][i] = vn;
-        const float h = -b * vn;
+        const float h = vn;
         sgx[cv] = a != 0.f ? h + a * (chi + h) : h;
         sxx[cv] = -xs[t] * vn;
     }
@@ -482,20 +481,17 @@ k2f_adj(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
         const int cz = lx * T::VZ + lz + 4;
         const int cx = (lx + 4) * BZ + lz;
         const float az = aciz[gz], ax = acix[gx];
-        if (az != 0.f || ax != 0.f) {
-            const float qt = -kk[r] * pt[r];
-            if (az != 0.f) S.etan[0][i] = bciz[gz] * (et0[r] + qt);
-            if (ax != 0.f) S.etan[1][i] = bcix[gx] * (et1[r] + qt);
-        }
-        S.gk[i] = gk[r] + qn[r] * (-kk[r] * pt[r]);
+        if (az != 0.f) S.etan[0][i] = bciz[gz] * (et0[r] + pt[r]);
+        if (ax != 0.f) S.etan[1][i] = bcix[gx] * (et1[r] + pt[r]);
+        S.gk[i] = gk[r] + qn[r] * pt[r];
         const float xz1 = gz > 0 ? sxz[cz - 1] : 0.f;
         const float xx1 = gx > 0 ? sxx[cx - BZ] : 0.f;
         S.gr[i] = gr[r] + (0.5f * (sxz[cz] + xz1) + 0.5f * (sxx[cx] + xx1));
         const float dz = d_node(sgz, cz, 1, C.c[0]);
         const float dx = d_node(sgx, cx, BZ, C.c[1]);
-        float pn = pt[r] - (dz + dx);
-        if (tr.y && n > 0) pn = pn + tile_inject(tr, tix, e, n - 1);
-        S.qn[i] = pn;
+        float qn_ = pt[r] + kk[r] * (dz + dx);
+        if (tr.y && n > 0) qn_ = qn_ - kk[r] * tile_inject(tr, tix, e, n - 1);
+        S.qn[i] = qn_;
     }
 }
 
