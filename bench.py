@@ -44,7 +44,7 @@ HBM_PEAK_GBS = 8000.0
 # every array read once and written once; CPML strips excluded).
 BYTES_PER_PT = {
     2: {"born_v": 48, "born_p": 40, "bg_v": 32, "bg_p": 24, "adj_a": 36, "adj_b": 36},
-    3: {"born_v": 64, "born_p": 48, "bg_v": 44, "bg_p": 28, "adj_a": 44, "adj_b": 52},
+    3: {"born_v": 64, "born_p": 48, "bg_v": 44, "bg_p": 28, "adj_a": 44, "adj_b": 44},
     # fused 2D schedule: one kernel per step, reported under the velocity-phase class
     "2f": {"born_v": 64, "bg_v": 44, "adj_a": 64},
 }
@@ -145,8 +145,8 @@ def main():
                          "the 2D workloads, 1 = 64 x 8 x 32 for config5)")
     ap.add_argument("--tile-adj-a", type=int, default=None,
                     help="tile shape id of the adjoint A phase (-1 = the stencil tile; default: 2 = "
-                         "32 x 32 for the 2D workloads, 1 = 64 x 8 x 32 for config5: the fastest shapes "
-                         "for those phases on MI355X)")
+                         "32 x 32 for the 2D workloads, the fastest shape for that phase on MI355X, and "
+                         "-1 for config5)")
     ap.add_argument("--tune-steps", type=int, default=24)
     ap.add_argument("--pcgnr", type=int, default=0,
                     help="also run N CGNR and N pseudo-Hessian-preconditioned CGNR iterations from x = 0 "
@@ -171,7 +171,7 @@ def main():
     if args.tile_v is None:
         args.tile_v = 1 if args.workload == "config5" else -1
     if args.tile_adj_a is None:
-        args.tile_adj_a = 1 if args.workload == "config5" else 2
+        args.tile_adj_a = -1 if args.workload == "config5" else 2
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the shot-parallel "
               "multi-GPU layout is not built", file=sys.stderr)

@@ -137,8 +137,7 @@ hipError_t launch_gather(const Slot* slots, const Rec* rec, int nrec, int n, int
 
 __global__ void k_inject(const Slot* __restrict__ slots, const int* __restrict__ node_slot,
                          const int* __restrict__ node_idx, const int* __restrict__ node_ptr,
-                         const Rec* __restrict__ rec, int nnode, int n, const float* __restrict__ d,
-                         int scaled) {
+                         const Rec* __restrict__ rec, int nnode, int n, const float* __restrict__ d) {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= nnode) return;
     float s = 0.f;
@@ -146,17 +145,17 @@ __global__ void k_inject(const Slot* __restrict__ slots, const int* __restrict__
     const DSlot& S = dev_slots(slots)[node_slot[u]];
     gfloat* q = S.q;
     const int i = node_idx[u];
-    // scaled: the field holds Q = -dt kappa p~ (2D adjoint), so the source
-    // added to p~ enters as -dt kappa s
-    q[i] = scaled ? q[i] - S.kdt[i] * s : q[i] + s;
+    // the field holds Q = -dt kappa p~, so the source added to p~ enters as
+    // -dt kappa s
+    q[i] = q[i] - S.kdt[i] * s;
 }
 
 hipError_t launch_inject(const Slot* slots, const int* node_slot, const int* node_idx,
                          const int* node_ptr, const Rec* rec, int nnode, int n, const float* d,
-                         int scaled, hipStream_t st) {
+                         hipStream_t st) {
     if (nnode <= 0) return hipSuccess;
     k_inject<<<(nnode + NTHREADS - 1) / NTHREADS, NTHREADS, 0, st>>>(slots, node_slot, node_idx, node_ptr,
-                                                                     rec, nnode, n, d, scaled);
+                                                                     rec, nnode, n, d);
     return hipGetLastError();
 }
 

@@ -11,10 +11,12 @@
 // (element 0 of the array, or of the plane, where a value lies outside the
 // grid or outside the absorbing strips), so no branch separates them; values
 // are combined and written to LDS only after that.  The z and x CPML
-// coefficients of a thread's nodes are read once, before the march.  The phases and the CPML
-// bookkeeping are those of the 2D kernels (section 2 of the paper for V/P,
-// eq. scattereqln for the Born sources, appendix A for the adjoint phases
-// A/B); the replay buffer holds dv_z, dv_x, dv_y, q per step.
+// coefficients of a thread's nodes are read once, before the march.  The
+// phases and the CPML bookkeeping are those of the 2D kernels (section 2 of
+// the paper for V/P, eq. scattereqln for the Born sources, appendix A for the
+// adjoint phases A/B), the adjoint state scaled as there (Q = -dt kappa p~,
+// U_a = -dt b_a v~_a); the replay buffer holds G_a p + psi_a for the three
+// axes and q per step.
 #include "common.h"
 #include "kernels.h"
 
@@ -236,9 +238,9 @@ v3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
             S.v[1][i] = vx[r] + dvx;
             S.v[2][i] = vy[r] + dvy;
             if (SEG) {   // read back only k steps later: streaming stores
-                __builtin_nontemporal_store(dvz, &seg[i]);
-                __builtin_nontemporal_store(dvx, &seg[S.npts + i]);
-                __builtin_nontemporal_store(dvy, &seg[2 * S.npts + i]);
+                __builtin_nontemporal_store(gzp, &seg[i]);
+                __builtin_nontemporal_store(gxp, &seg[S.npts + i]);
+                __builtin_nontemporal_store(gyp, &seg[2 * S.npts + i]);
             }
             if (!BORN && !SEG && (flag & PH_ACCUMULATE)) {   // pseudo-Hessian: sum of dv_a^2
                 S.w[0][i] = S.w[0][i] + dvz * dvz;
@@ -482,79 +484,85 @@ a3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
         bchx_[r] = cp(bchx, gx);
     }
     const gfloat* __restrict__ segq = S.seg + (long long)sstep * 4 * S.npts + 3 * S.npts;
-    // E[m] = e~_y(y + m - 3);  QT[m] = q~(y + m), q~ = -dt kappa p~.  The
-    // loads of plane y are kdt, p~ and (inside the y-strips) phi~_y.
+    // E[m] = e~_y(y + m - 3);  QT[m] = Q(y + m).  The loads of plane y are Q
+    // and (inside the y-strips) phi~_y.
     float E[R][8], QT[R][5];
-    auto front = [&](int r, int y, float& fk, float& fq, float& fe) {
+    auto front = [&](int r, int y, float& fq, float& fe) {
         const bool v = ok[r] && (unsigned)y < (unsigned)ny;
         const long long i = v ? ib[r] + y * sy : 0;
-        fk = S.kdt[i];
         fq = S.q[i];
         fe = cp(S.eta[2], v && in_pml(y, ny, npml) ? i : 0);
     };
-    auto combine = [&](int r, int y, float fk, float fq, float fe, float& qt, float& ey) {
+    auto combine = [&](int r, int y, float fq, float fe, float& qt, float& ey) {
         const bool v = ok[r] && (unsigned)y < (unsigned)ny;
         qt = 0.f;
         ey = 0.f;
         if (v) {
-            qt = -fk * fq;
+            qt = fq;
             const float a = cp(aciy, y);
             ey = a != 0.f ? qt + a * (fe + qt) : qt;
         }
     };
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        float fk[7], fq[7], fe[7];
+        float fq[7], fe[7];
 #pragma unroll
-        for (int m = 0; m < 7; ++m) front(r, y0 - 3 + m, fk[m], fq[m], fe[m]);
+        for (int m = 0; m < 7; ++m) front(r, y0 - 3 + m, fq[m], fe[m]);
 #pragma unroll
         for (int m = 0; m < 7; ++m) {
             float qt;
-            combine(r, y0 - 3 + m, fk[m], fq[m], fe[m], qt, E[r][m + 1]);
+            combine(r, y0 - 3 + m, fq[m], fe[m], qt, E[r][m + 1]);
             if (m >= 3) QT[r][m - 2] = qt;
         }
     }
-    // loads of e~ at a halo cell: dt kappa, p~, the CPML coefficient, phi~
+    // dt b_a of a node = sb there times sb at its upper neighbour; sb of the
+    // next plane is kept for the next plane's own value
+    float sbq[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) sbq[r] = S.sb[ib[r] + y0 * sy];
+    // loads of e~ at a halo cell: the CPML coefficient, phi~, Q
     auto ldz_ = [&](int lz, int lx, long long py, float* v) {
         const int gz = z0 + lz - HW;
         const long long i = cidx(lz, lx, py);
         const bool in = inside(lz, lx);
-        v[0] = S.kdt[i];
-        v[1] = S.q[i];
-        v[2] = cp(aciz, in ? gz : 0);
-        v[3] = cp(S.eta[0], in && in_pml(gz, nz, npml) ? i : py);
+        v[0] = cp(aciz, in ? gz : 0);
+        v[1] = cp(S.eta[0], in && in_pml(gz, nz, npml) ? i : py);
+        v[2] = S.q[i];
     };
     auto ldx_ = [&](int lz, int lx, long long py, float* v) {
         const int gx = x0 + lx - HW;
         const long long i = cidx(lz, lx, py);
         const bool in = inside(lz, lx);
-        v[0] = S.kdt[i];
-        v[1] = S.q[i];
-        v[2] = cp(acix, in ? gx : 0);
-        v[3] = cp(S.eta[1], in && in_pml(gx, nx, npml) ? i : py);
+        v[0] = cp(acix, in ? gx : 0);
+        v[1] = cp(S.eta[1], in && in_pml(gx, nx, npml) ? i : py);
+        v[2] = S.q[i];
     };
     auto ete = [&](bool in, const float* v) {
         float e = 0.f;
         if (in) {
-            const float qt = -v[0] * v[1];
-            e = v[2] != 0.f ? qt + v[2] * (v[3] + qt) : qt;
+            const float qt = v[2];
+            e = v[0] != 0.f ? qt + v[0] * (v[1] + qt) : qt;
         }
         return e;
     };
     for (int y = y0; y < y1; ++y) {
         const long long py = y * sy;
         const bool py_ = PML && in_pml(y, ny, npml);
-        float vz[R], vx[R], vy[R], gk[R], qn[R], e0[R], e1[R], fk[R], fq[R], fe[R];
-        float c0[R], c1[R], c2[R], b0[R], b1[R], b2[R];
+        float vz[R], vx[R], vy[R], gk[R], qn[R], e0[R], e1[R], fq[R], fe[R];
+        float c0[R], c1[R], c2[R], s0[R], s1z[R], s1x[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            front(r, y + 4, fk[r], fq[r], fe[r]);
+            front(r, y + 4, fq[r], fe[r]);
             const long long i = ib[r] + py;
             vz[r] = S.w[0][i];
             vx[r] = S.w[1][i];
             vy[r] = S.w[2][i];
             gk[r] = S.gk[i];
             qn[r] = __builtin_nontemporal_load(&segq[i]);
+            s0[r] = sbq[r];
+            s1z[r] = S.sb[ok[r] && z0 + lzr[r] + 1 < nz ? i + 1 : i];
+            s1x[r] = S.sb[ok[r] && x0 + lxr[r] + 1 < nx ? i + sx : i];
+            sbq[r] = S.sb[y + 1 < ny ? i + sy : i];
             e0[r] = cp(S.eta[0], pz[r] ? i : 0);
             e1[r] = cp(S.eta[1], px[r] ? i : 0);
             if (!flag) {
@@ -562,12 +570,9 @@ a3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
                 c0[r] = cp(S.xi[0], jz);
                 c1[r] = cp(S.xi[1], jx);
                 c2[r] = cp(S.xi[2], jy);
-                b0[r] = cp(S.bdt[0], jz);
-                b1[r] = cp(S.bdt[1], jx);
-                b2[r] = cp(S.bdt[2], jy);
             }
         }
-        float hz[CZ::IT][4], hx[CX::IT][4];
+        float hz[CZ::IT][3], hx[CX::IT][3];
         CZ::load([&](int lz, int lx, float* v) { ldz_(lz, lx, py, v); }, hz);
         CX::load([&](int lz, int lx, float* v) { ldx_(lz, lx, py, v); }, hx);
         __syncthreads();
@@ -578,7 +583,7 @@ a3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
             for (int m = 0; m < 7; ++m) E[r][m] = E[r][m + 1];
 #pragma unroll
             for (int m = 0; m < 4; ++m) QT[r][m] = QT[r][m + 1];
-            combine(r, y + 4, fk[r], fq[r], fe[r], QT[r][4], E[r][7]);
+            combine(r, y + 4, fq[r], fe[r], QT[r][4], E[r][7]);
             const int c = (lxr[r] + HW) * T::LZ + lzr[r] + HW;
             const float qt = QT[r][0];
             float ez = qt, ex = qt;
@@ -603,14 +608,15 @@ a3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
             const int c = (lxr[r] + HW) * T::LZ + lzr[r] + HW;
             if (!flag) {
                 const float a = achz_[r], b = achx_[r];
-                if (a != 0.f) S.xi[0][i] = bchz_[r] * (c0[r] + (-b0[r] * vz[r]));
-                if (b != 0.f) S.xi[1][i] = bchx_[r] * (c1[r] + (-b1[r] * vx[r]));
-                if (hyc != 0.f) S.xi[2][i] = bchy[y] * (c2[r] + (-b2[r] * vy[r]));
+                if (a != 0.f) S.xi[0][i] = bchz_[r] * (c0[r] + vz[r]);
+                if (b != 0.f) S.xi[1][i] = bchx_[r] * (c1[r] + vx[r]);
+                if (hyc != 0.f) S.xi[2][i] = bchy[y] * (c2[r] + vy[r]);
             }
             S.gk[i] = gk[r] + qn[r] * QT[r][0];
-            S.w[0][i] = vz[r] - d_half(sez, c, 1, C.c[0]);
-            S.w[1][i] = vx[r] - d_half(sex, c, T::LZ, C.c[1]);
-            S.w[2][i] = vy[r] - d_queue(E[r], C.c[2]);
+            const float bz = s0[r] * s1z[r], bx = s0[r] * s1x[r], by = s0[r] * sbq[r];
+            S.w[0][i] = vz[r] + bz * d_half(sez, c, 1, C.c[0]);
+            S.w[1][i] = vx[r] + bx * d_half(sex, c, T::LZ, C.c[1]);
+            S.w[2][i] = vy[r] + by * d_queue(E[r], C.c[2]);
         }
     }
 }
@@ -630,8 +636,8 @@ k3_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
 
 // ---------------------------------------------------------------------------
 // Adjoint phase B (transpose of V), as in the 2D kernels; the products
-// -dv_a v~_a of the lnrho image are formed while staging (z, x) or kept from
-// the previous plane (y).
+// -(G_a p + psi_a) U_a of the lnrho image are formed while staging (z, x) or
+// kept from the previous plane (y).
 // ---------------------------------------------------------------------------
 template <int BZ, int BX, int BY, bool PML>
 __device__ __forceinline__ void
@@ -663,26 +669,25 @@ b3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
     const gfloat* __restrict__ segz = S.seg + (long long)sstep * 4 * S.npts;
     const gfloat* __restrict__ segx = segz + S.npts;
     const gfloat* __restrict__ segy = segz + 2 * S.npts;
-    // Gq[m] = g~_y(y + m - 4) from dt b_y, v~_y and (inside the y-strips) chi_y;
-    // Xp = -dv_y v~_y on the previous plane
+    // Gq[m] = g~_y(y + m - 4) from U_y and (inside the y-strips) chi_y;
+    // Xp = -(G_y p + psi_y) U_y on the previous plane
     float Gq[R][8], Xp[R];
     auto front = [&](int r, int y, float* f) {
         const bool v = ok[r] && (unsigned)y < (unsigned)ny;
         const long long i = v ? ib[r] + y * sy : 0;
-        f[0] = S.bdt[2][i];
-        f[1] = S.w[2][i];
-        f[2] = cp(S.xi[2], v && in_pml(y, ny, npml) ? i : 0);
+        f[0] = S.w[2][i];
+        f[1] = cp(S.xi[2], v && in_pml(y, ny, npml) ? i : 0);
     };
     auto gy_of = [&](int r, int y, const float* f) -> float {
         if (!(ok[r] && (unsigned)y < (unsigned)ny)) return 0.f;
-        const float h = -f[0] * f[1];
-        const float fc = f[2];
+        const float h = f[0];
+        const float fc = f[1];
         const float a = cp(achy, y);
         return a != 0.f ? h + a * (fc + h) : h;
     };
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        float f[7][3];
+        float f[7][2];
 #pragma unroll
         for (int m = 0; m < 7; ++m) front(r, y0 - 4 + m, f[m]);
         const bool pv = ok[r] && y0 > 0;
@@ -692,48 +697,45 @@ b3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
         for (int m = 0; m < 7; ++m) Gq[r][m + 1] = gy_of(r, y0 - 4 + m, f[m]);
         Xp[r] = pv ? -s_ * w_ : 0.f;
     }
-    // loads of g~_a and of the image product at a cell: v~_a, dt b_a, the
-    // CPML coefficient, chi_a and dv_a (on the rows / columns whose product
-    // is needed)
+    // loads of g~_a and of the image product at a cell: the CPML coefficient,
+    // chi_a, U_a and G_a p + psi_a (on the rows / columns whose product is
+    // needed)
     auto ldz_ = [&](int lz, int lx, long long py, float* v) {
         const int gz = z0 + lz - HW;
         const bool in = inside(lz, lx);
         const long long i = cidx(lz, lx, py);
-        v[0] = S.w[0][i];
-        v[1] = S.bdt[0][i];
-        v[2] = cp(achz, in ? gz : 0);
-        v[3] = cp(S.xi[0], in && in_pml(gz, nz, npml) ? i : py);
-        v[4] = segz[in && lz >= HW - 1 && lz < HW + BZ ? i : py];
+        v[0] = cp(achz, in ? gz : 0);
+        v[1] = cp(S.xi[0], in && in_pml(gz, nz, npml) ? i : py);
+        v[2] = S.w[0][i];
+        v[3] = segz[in && lz >= HW - 1 && lz < HW + BZ ? i : py];
     };
     auto ldx_ = [&](int lz, int lx, long long py, float* v) {
         const int gx = x0 + lx - HW;
         const bool in = inside(lz, lx);
         const long long i = cidx(lz, lx, py);
-        v[0] = S.w[1][i];
-        v[1] = S.bdt[1][i];
-        v[2] = cp(achx, in ? gx : 0);
-        v[3] = cp(S.xi[1], in && in_pml(gx, nx, npml) ? i : py);
-        v[4] = segx[in && lx >= HW - 1 && lx < HW + BX ? i : py];
+        v[0] = cp(achx, in ? gx : 0);
+        v[1] = cp(S.xi[1], in && in_pml(gx, nx, npml) ? i : py);
+        v[2] = S.w[1][i];
+        v[3] = segx[in && lx >= HW - 1 && lx < HW + BX ? i : py];
     };
     for (int y = y0; y < y1; ++y) {
         const long long py = y * sy;
         const bool py_ = PML && in_pml(y, ny, npml);
-        float pt[R], gr[R], sy_[R], wy_[R], kk[R], e0[R], e1[R], e2[R], fr[R][3];
+        float pt[R], gr[R], sy_[R], wy_[R], kk[R], e0[R], e1[R], e2[R], fr[R][2];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             front(r, y + 3, fr[r]);
             const long long i = ib[r] + py;
-            const bool any = pz[r] || px[r] || (ok[r] && py_);
             pt[r] = S.q[i];
             gr[r] = S.gr[i];
             sy_[r] = segy[i];
             wy_[r] = S.w[2][i];
-            kk[r] = cp(S.kdt, any ? i : 0);
+            kk[r] = S.kdt[i];
             e0[r] = cp(S.eta[0], pz[r] ? i : 0);
             e1[r] = cp(S.eta[1], px[r] ? i : 0);
             e2[r] = cp(S.eta[2], ok[r] && py_ ? i : 0);
         }
-        float hz[CZ::IT][5], hx[CX::IT][5];
+        float hz[CZ::IT][4], hx[CX::IT][4];
         CZ::load([&](int lz, int lx, float* v) { ldz_(lz, lx, py, v); }, hz);
         CX::load([&](int lz, int lx, float* v) { ldx_(lz, lx, py, v); }, hx);
         __syncthreads();
@@ -741,9 +743,9 @@ b3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
             const int c = lx * T::LZ + lz;
             float g = 0.f, x = 0.f;
             if (inside(lz, lx)) {
-                const float h = -v[1] * v[0];
-                g = v[2] != 0.f ? h + v[2] * (v[3] + h) : h;
-                if (lz >= HW - 1 && lz < HW + BZ) x = -v[4] * v[0];
+                const float h = v[2];
+                g = v[0] != 0.f ? h + v[0] * (v[1] + h) : h;
+                if (lz >= HW - 1 && lz < HW + BZ) x = -v[3] * v[2];
             }
             sgz[c] = g;
             sxz[c] = x;
@@ -752,9 +754,9 @@ b3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
             const int c = lx * T::LZ + lz;
             float g = 0.f, x = 0.f;
             if (inside(lz, lx)) {
-                const float h = -v[1] * v[0];
-                g = v[2] != 0.f ? h + v[2] * (v[3] + h) : h;
-                if (lx >= HW - 1 && lx < HW + BX) x = -v[4] * v[0];
+                const float h = v[2];
+                g = v[0] != 0.f ? h + v[0] * (v[1] + h) : h;
+                if (lx >= HW - 1 && lx < HW + BX) x = -v[3] * v[2];
             }
             sgx[c] = g;
             sxx[c] = x;
@@ -771,19 +773,16 @@ b3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
             const long long i = ib[r] + py;
             const int c = (lxr[r] + HW) * T::LZ + lzr[r] + HW;
             const float az = aciz_[r], ax = acix_[r];
-            if (az != 0.f || ax != 0.f || ay != 0.f) {
-                const float qt = -kk[r] * pt[r];
-                if (az != 0.f) S.eta[0][i] = bciz_[r] * (e0[r] + qt);
-                if (ax != 0.f) S.eta[1][i] = bcix_[r] * (e1[r] + qt);
-                if (ay != 0.f) S.eta[2][i] = bciy[y] * (e2[r] + qt);
-            }
+            if (az != 0.f) S.eta[0][i] = bciz_[r] * (e0[r] + pt[r]);
+            if (ax != 0.f) S.eta[1][i] = bcix_[r] * (e1[r] + pt[r]);
+            if (ay != 0.f) S.eta[2][i] = bciy[y] * (e2[r] + pt[r]);
             const float xy0 = -sy_[r] * wy_[r];
             S.gr[i] = gr[r] + ((0.5f * (sxz[c] + sxz[c - 1]) + 0.5f * (sxx[c] + sxx[c - T::LZ])) + 0.5f * (xy0 + Xp[r]));
             Xp[r] = xy0;
             const float dz = d_node(sgz, c, 1, C.c[0]);
             const float dx = d_node(sgx, c, T::LZ, C.c[1]);
             const float dy = d_queue(Gq[r], C.c[2]);
-            S.q[i] = pt[r] - ((dz + dx) + dy);
+            S.q[i] = pt[r] + kk[r] * ((dz + dx) + dy);
         }
     }
 }

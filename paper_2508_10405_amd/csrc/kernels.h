@@ -78,12 +78,11 @@ hipError_t launch_dm_prep(const DmArgs& a, hipStream_t st);
 hipError_t launch_gather(const Slot* slots, const Rec* rec, int nrec, int n, int from_scattered,
                          float* d, hipStream_t st);
 // Injection of d[it = n] into the adjoint pressure: one thread per distinct
-// receiver node, summing its receivers in a fixed order.  scaled = 1 when the
-// field holds Q = -dt kappa p~ (the 2D adjoint state): the sum s enters as
-// -dt kappa s.
+// receiver node, summing its receivers in a fixed order.  The adjoint state
+// holds Q = -dt kappa p~, so the sum s enters as -dt kappa s.
 hipError_t launch_inject(const Slot* slots, const int* node_slot, const int* node_idx,
                          const int* node_ptr, const Rec* rec, int nnode, int n, const float* d,
-                         int scaled, hipStream_t st);
+                         hipStream_t st);
 
 // Images of a launch group added into the FP64 global accumulator
 // acc[2][gpts] (lnVp, lnIp): img_lnVp = -g_lnrho + g_lnkappa,

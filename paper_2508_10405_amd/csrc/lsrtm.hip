@@ -581,7 +581,7 @@ lsrtm_status group_adjoint(lsrtm_ctx* c, Group& gr, const float* d) {
     auto inject = [&](int n) -> lsrtm_status {
         tbeg(c, 7);
         hipError_t e = launch_inject(desc(gr, apar(n)), gr.d_node_slot, gr.d_node_idx, gr.d_node_ptr,
-                                     gr.d_node_rec, gr.nnode, n, d, c->ndim == 2, c->st);
+                                     gr.d_node_rec, gr.nnode, n, d, c->st);
         tend(c);
         if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "inject: %s", hipGetErrorString(e));
         return LSRTM_OK;

@@ -89,8 +89,8 @@ def test_config3_full_size_sampled(torch):
 def test_config5_full_size_dot(torch):
     """The 3D workload at its full grid (400 x 400 x 200, 440 x 440 x 240
     padded, 16 shots) in the launch configuration bench.py times for it (one
-    shot per launch, 64 x 4 x 32 tiles, the velocity and adjoint A phases on
-    64 x 8 x 32), on a truncated time axis.  The oracle cannot run this grid,
+    shot per launch, 64 x 4 x 32 tiles, the velocity phases on 64 x 8 x 32),
+    on a truncated time axis.  The oracle cannot run this grid,
     so: the Born operator and the migration with FP32 checkpoints are checked
     against each other (dot-product test over the whole problem); the
     migration with the BF16 checkpoints the benchmark uses stays within the
@@ -99,7 +99,7 @@ def test_config5_full_size_dot(torch):
     from paper_2508_10405_amd import lsrtm
     w = synth.config5(nt=160)
     print(f"[case] {w.name} full grid, nt {w.nt}", flush=True)
-    cfg = dict(shots_per_launch=1, tile=0, tile_v=1, tile_adj_a=1)
+    cfg = dict(shots_per_launch=1, tile=0, tile_v=1)
     rng = np.random.default_rng(11)
     x = to_dev(torch, 0.01 * rng.standard_normal((2,) + w.shape))
     ctx = lsrtm.context_for(w, ckpt_dtype="f32", **cfg)
