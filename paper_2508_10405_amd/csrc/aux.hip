@@ -71,7 +71,7 @@ __global__ void k_model_prep(PrepArgs a) {
         a.sb[i] = s0;
         // dt b_a at the half node: the FP32 product the velocity kernels form
         const int pn[3] = {pz, px, py};
-        for (int ax = 0; ax < a.ndim; ++ax) {
+        for (int ax = 0; ax < a.ndim && a.bdt[0]; ++ax) {
             int q[3] = {pn[0], pn[1], pn[2]};
             q[ax] = q[ax] + 1 < a.N[ax] ? q[ax] + 1 : q[ax];
             a.bdt[ax][i] = s0 * sb_of(a.dt, lnrho_at(a, q[0], q[1], q[2]));

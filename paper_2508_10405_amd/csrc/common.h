@@ -58,7 +58,7 @@ struct SlotT {
     const F* kdt;            // dt * kappa at nodes
     const F* sb;             // sqrt(dt b) at nodes: dt b_a at the half node i + 1/2
                              // is sb[i] * sb[i + e_a] (sb[i]^2 on an axis' last node)
-    const F* bdt[3];         // the same products, stored (read by the adjoint kernels)
+    const F* bdt[3];         // the same products, stored (fused 2D schedule only; else null)
     const F* dlnr;           // dlnrho at nodes (zero in the PML)
     const F* dlnk;           // dlnkappa at nodes (zero in the PML)
     const F* cpml[3];        // per axis: [ach | bch | aci | bci], n_a each

@@ -43,9 +43,9 @@ hipError_t launch_fill_f64(double* p, long long n, hipStream_t st);
 // Model on a shot's padded grid from the global physical logs (edge-replicated
 // into the PML): kdt = dt*exp(lnvp+lnip); sb = sqrt(dt)*exp(-lnrho/2), so that
 // dt*b_a = dt*exp(-(lnrho_i + lnrho_i+1)/2) at the half node i + 1/2 is the
-// FP32 product sb_i * sb_i+1.  The velocity kernels form that product from sb
-// (one array instead of ndim); bdt_a holds the same products for the adjoint
-// kernels, which read dt b_a at halo cells.
+// FP32 product sb_i * sb_i+1.  The kernels form that product from sb (one
+// array instead of ndim); bdt_a, when not null, holds the same products for
+// the fused 2D adjoint, which reads dt b_a on its velocity halo.
 struct PrepArgs {
     const float* lnvp; const float* lnip;   // global physical arrays
     int gn[3];                              // global physical sizes (z, x, y)

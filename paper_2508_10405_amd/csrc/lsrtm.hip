@@ -878,7 +878,7 @@ lsrtm_status plan(lsrtm_ctx* c) {
     const int nsc = 1 + 3 * nd + (c->fused ? 1 + 3 * nd : 0);   // q, w, xi, eta [, q', w', xi', eta']
     const int nt = c->g.nt;
     long long model_bytes = 0;
-    for (auto& W : c->wins) model_bytes += (long long)(4 + nd) * W.npts * 4 + 4LL * nd * 4 * std::max(W.N[0], std::max(W.N[1], W.N[2]));
+    for (auto& W : c->wins) model_bytes += (long long)(4 + (c->fused ? nd : 0)) * W.npts * 4 + 4LL * nd * 4 * std::max(W.N[0], std::max(W.N[1], W.N[2]));
     long long ck_per_shot_sum = 0;
     for (auto& sh : c->shots) ck_per_shot_sum += sh.ckbytes;
     const long long fixed = model_bytes + 2LL * c->gpts * 8 + (long long)nshot * nt * 4 + 2 * c->data_len * 4 +
@@ -938,9 +938,10 @@ lsrtm_status plan(lsrtm_ctx* c) {
     for (auto& W : c->wins) {
         CHK(dalloc_t(c, &W.kdt, W.npts, true));
         CHK(dalloc_t(c, &W.sb, W.npts, true));
+        // the stored dt b_a products serve only the fused 2D adjoint
         for (int a = 0; a < 3; ++a) {
-            if (a < nd) CHK(dalloc_t(c, &W.bdt[a], W.npts, true));
-            else W.bdt[a] = W.sb;
+            if (a < nd && c->fused) CHK(dalloc_t(c, &W.bdt[a], W.npts, true));
+            else W.bdt[a] = nullptr;
             if (a < nd) CHK(dalloc_t(c, &W.cpml[a], 4 * W.N[a], true));
             else W.cpml[a] = nullptr;
         }
@@ -950,7 +951,8 @@ lsrtm_status plan(lsrtm_ctx* c) {
         HIPCHK(c, launch_fill(W.dlnr, W.npts, 0.f, c->st));
         HIPCHK(c, launch_fill(W.dlnk, W.npts, 0.f, c->st));
         HIPCHK(c, launch_fill(W.sb, W.npts, 0.f, c->st));
-        for (int a = 0; a < nd; ++a) HIPCHK(c, launch_fill(W.bdt[a], W.npts, 0.f, c->st));
+        for (int a = 0; a < nd; ++a)
+            if (W.bdt[a]) HIPCHK(c, launch_fill(W.bdt[a], W.npts, 0.f, c->st));
     }
     // ---- groups ----------------------------------------------------------------
     int s0 = 0;
