@@ -66,8 +66,8 @@ struct SlotT {
     F* v[3];                 // background particle velocities
     F* psi[3];               // background CPML memory of G_a p
     F* phi[3];               // background CPML memory of D_a v_a
-    F* q;                    // scattered pressure  | adjoint p~
-    F* w[3];                 // scattered velocity  | adjoint v~
+    F* q;                    // scattered pressure  | adjoint Q = -dt kappa p~
+    F* w[3];                 // scattered velocity  | adjoint U_a = -dt b_a v~_a
     F* xi[3];                // scattered psi       | adjoint of psi (chi)
     F* eta[3];               // scattered phi       | adjoint of phi
     F* gk;                   // image of lnkappa
@@ -82,7 +82,7 @@ struct SlotT {
     F* wn[3];
     F* xin[3];
     F* etan[3];
-    F* seg;                  // replay buffer [k][ndim + 1][npts]: dv_a, q
+    F* seg;                  // replay buffer [k][ndim + 1][npts]: G_a p + psi_a, q
     C* ck;                   // checkpoint 1 of this shot; checkpoint j >= 1 at ck + (j-1) * ckbytes
     long long ckbytes;
 };

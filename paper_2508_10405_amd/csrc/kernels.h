@@ -9,7 +9,7 @@ namespace lsrtm {
 enum Kind {
     K_BG_V = 0,    // background velocity phase
     K_BG_P = 1,    // background pressure phase
-    K_SEG_V = 2,   // background velocity phase, stores dv_a (replay)
+    K_SEG_V = 2,   // background velocity phase, stores G_a p + psi_a (replay)
     K_SEG_P = 3,   // background pressure phase, stores q (replay)
     K_BORN_V = 4,  // background + scattered velocity phase
     K_BORN_P = 5,  // background + scattered pressure phase

@@ -7,8 +7,10 @@
 //   born    : background + scattered steps (section 2, eq. scattereqln),
 //             scattered pressure recorded (section 3, L dm := R du).
 //   adjoint : for each checkpoint segment, last first: restore the background
-//             state, replay k steps storing dv_a and q, then run the k adjoint
-//             steps backwards with the imaging conditions (appendix A,
+//             state, replay k steps storing G_a p + psi_a (the gradient behind
+//             dv_a) and q, then run the k adjoint steps backwards, on the
+//             scaled state Q = -dt kappa p~, U_a = -dt b_a v~_a, with the
+//             imaging conditions (appendix A,
 //             eqs. gradlsm, gradrho, gradkappa).  The images of every shot
 //             are added in shot order into an FP64 accumulator and mapped to
 //             (lnVp, lnIp) by the chain rule of section 3.
