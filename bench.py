@@ -399,8 +399,8 @@ def main():
                    "shots": w.nshot, "nt": w.nt, "padded_points": padded,
                    "shots_per_launch": sz["shots_per_launch"], "ckpt_every": sz["ckpt_every"],
                    "tile": list(lsrtm.tile_shape(nd, sz["tile"])),
-                   "tile_v": list(lsrtm.tile_shape(nd, args.tile_v)) if args.tile_v >= 0 else None,
-                   "tile_adj_a": list(lsrtm.tile_shape(nd, args.tile_adj_a)) if args.tile_adj_a >= 0 else None,
+                   "tile_v": list(lsrtm.tile_shape(nd, sz["tile_v"])) if sz["tile_v"] >= 0 else None,
+                   "tile_adj_a": list(lsrtm.tile_shape(nd, sz["tile_adj_a"])) if sz["tile_adj_a"] >= 0 else None,
                    "ckpt_dtype": ckdt,
                    "ckpt_per_group": bool(sz["ckpt_per_group"]),
                    "schedule": "fused step" if sz["fused"] else "two-phase step",

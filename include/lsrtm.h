@@ -290,8 +290,9 @@ lsrtm_status lsrtm_autotune(lsrtm_ctx* ctx, int nsteps, int tune_groups, double*
  * out[2] = shots per launch, out[3] = checkpoint interval, out[4] = number of
  * launch groups, out[5] = padded points summed over shots, out[6] = device
  * bytes planned, out[7] = tile id in use, out[8] = 1 if checkpoints are held
- * per launch group, out[9] = 1 for the fused 2D schedule.  HOST long long
- * [nout]. */
+ * per launch group, out[9] = 1 for the fused 2D schedule, out[10] / out[11] =
+ * tile id of the velocity phases / of the adjoint A phase (-1 = out[7]).
+ * HOST long long [nout]; the first min(nout, 12) entries are written. */
 lsrtm_status lsrtm_sizes(lsrtm_ctx* ctx, long long* out, int nout);
 
 /* Timing statistics of the last pass (HOST double [nout]); see

@@ -1579,9 +1579,9 @@ lsrtm_status lsrtm_autotune(lsrtm_ctx* c, int nsteps, int tune_groups, double* o
 
 lsrtm_status lsrtm_sizes(lsrtm_ctx* c, long long* out, int nout) {
     if (!c || !out) return LSRTM_EINVAL;
-    long long v[10] = {c->data_len, c->gpts, c->G, c->k, (long long)c->groups.size(), c->padded_total, c->plan_bytes,
-                       c->tile, c->ck_group ? 1 : 0, c->fused ? 1 : 0};
-    for (int i = 0; i < nout && i < 10; ++i) out[i] = v[i];
+    long long v[12] = {c->data_len, c->gpts, c->G, c->k, (long long)c->groups.size(), c->padded_total, c->plan_bytes,
+                       c->tile, c->ck_group ? 1 : 0, c->fused ? 1 : 0, c->opt_tile_v, c->opt_tile_a};
+    for (int i = 0; i < nout && i < 12; ++i) out[i] = v[i];
     return LSRTM_OK;
 }
 

@@ -215,10 +215,10 @@ class Context:
                 "tile_v": int(out[3]), "tile_adj_a": int(out[4])}
 
     def sizes(self):
-        out = (_c_ll * 10)()
-        self._check(lib().lsrtm_sizes(self._h, out, 10), "sizes")
+        out = (_c_ll * 12)()
+        self._check(lib().lsrtm_sizes(self._h, out, 12), "sizes")
         keys = ("data_len", "grid_points", "shots_per_launch", "ckpt_every", "groups",
-                "padded_points", "plan_bytes", "tile", "ckpt_per_group", "fused")
+                "padded_points", "plan_bytes", "tile", "ckpt_per_group", "fused", "tile_v", "tile_adj_a")
         return dict(zip(keys, [int(x) for x in out]))
 
     @property
