@@ -604,7 +604,12 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const int c = (lx + HW) * T::LZ + lz + HW;
         if (az[r] != 0.f) S.eta[0][i] = cz[r] * (ez[r] + pt[r]);
         if (ax[r] != 0.f) S.eta[1][i] = cx[r] * (ex[r] + pt[r]);
-        S.gr[i] = gr[r] + (0.5f * (sxz[c] + sxz[c - 1]) + 0.5f * (sxx[c] + sxx[c - T::LZ]));
+        // transpose of the half-node average: the last node of an axis also
+        // takes the other half of its own product (the forward average there
+        // clamps the upper neighbour to the node itself)
+        const float tz = 0.5f * (sxz[c] + sxz[c - 1]) + (gz + 1 == nz ? 0.5f * sxz[c] : 0.f);
+        const float tx = 0.5f * (sxx[c] + sxx[c - T::LZ]) + (gx + 1 == nx ? 0.5f * sxx[c] : 0.f);
+        S.gr[i] = gr[r] + (tz + tx);
         const float dz = d_node(sgz, c, 1, C.c[0]);
         const float dx = d_node(sgx, c, T::LZ, C.c[1]);
         float qn = pt[r] + kk[r] * (dz + dx);

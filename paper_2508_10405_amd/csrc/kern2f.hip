@@ -486,7 +486,11 @@ k2f_adj(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C,
         S.gk[i] = gk[r] + qn[r] * pt[r];
         const float xz1 = gz > 0 ? sxz[cz - 1] : 0.f;
         const float xx1 = gx > 0 ? sxx[cx - BZ] : 0.f;
-        S.gr[i] = gr[r] + (0.5f * (sxz[cz] + xz1) + 0.5f * (sxx[cx] + xx1));
+        // the last node of an axis also takes the other half of its own
+        // product (transpose of the clamped forward average)
+        const float tz = 0.5f * (sxz[cz] + xz1) + (gz + 1 == nz ? 0.5f * sxz[cz] : 0.f);
+        const float tx = 0.5f * (sxx[cx] + xx1) + (gx + 1 == nx ? 0.5f * sxx[cx] : 0.f);
+        S.gr[i] = gr[r] + (tz + tx);
         const float dz = d_node(sgz, cz, 1, C.c[0]);
         const float dx = d_node(sgx, cx, BZ, C.c[1]);
         float qn_ = pt[r] + kk[r] * (dz + dx);

@@ -777,7 +777,12 @@ b3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
             if (ax != 0.f) S.eta[1][i] = bcix_[r] * (e1[r] + pt[r]);
             if (ay != 0.f) S.eta[2][i] = bciy[y] * (e2[r] + pt[r]);
             const float xy0 = -sy_[r] * wy_[r];
-            S.gr[i] = gr[r] + ((0.5f * (sxz[c] + sxz[c - 1]) + 0.5f * (sxx[c] + sxx[c - T::LZ])) + 0.5f * (xy0 + Xp[r]));
+            // the last node of an axis also takes the other half of its own
+            // product (transpose of the clamped forward average)
+            const float tz = 0.5f * (sxz[c] + sxz[c - 1]) + (gz + 1 == nz ? 0.5f * sxz[c] : 0.f);
+            const float tx = 0.5f * (sxx[c] + sxx[c - T::LZ]) + (gx + 1 == nx ? 0.5f * sxx[c] : 0.f);
+            const float ty = 0.5f * (xy0 + Xp[r]) + (y + 1 == ny ? 0.5f * xy0 : 0.f);
+            S.gr[i] = gr[r] + ((tz + tx) + ty);
             Xp[r] = xy0;
             const float dz = d_node(sgz, c, 1, C.c[0]);
             const float dx = d_node(sgx, c, T::LZ, C.c[1]);

@@ -1,0 +1,115 @@
+"""Degenerate acquisitions and sizes on the GPU, through the C ABI, against the
+FP64 oracle (relative L2 1e-4, or exactly zero where the oracle is zero):
+
+* the shortest time axes (1, 2 and 3 steps: the first reverse step is also
+  the last, the checkpoint interval exceeds nt);
+* a shot without receivers between shots with receivers (empty receiver and
+  injection lists, zero-length data block);
+* receivers duplicated on one node and a receiver on the source node
+  (injection sums every receiver of a node);
+* a grid smaller than one tile, with and without absorbing strips, in both
+  2D schedules.
+"""
+import numpy as np
+import pytest
+
+from oracle import lsrtm_oracle as O
+from paper_2508_10405_amd import synth
+from gpu_common import concat, f64, oracle_problem, rel, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _close(a, b):
+    b = np.asarray(b, dtype=np.float64).ravel()
+    if np.linalg.norm(b) == 0.0:
+        return np.all(np.asarray(a) == 0.0)
+    return rel(a, b) <= TOL
+
+
+def _check(torch, w, **opts):
+    from paper_2508_10405_amd import lsrtm
+    print(f"[case] {w.name} nt={w.nt} npml={w.npml} nrec={[len(r) for r in w.rec]} opts={opts}", flush=True)
+    prob = oracle_problem(w)
+    lnvp, lnip = f64(w.lnvp), f64(w.lnip)
+    ctx = lsrtm.context_for(w, **opts)
+    assert ctx.data_len == sum(w.nt * len(r) for r in w.rec)
+    assert _close(ctx.forward().cpu().numpy(), concat(O.forward(prob, lnvp, lnip)))
+    refd = O.born(prob, lnvp, lnip, f64(w.dm))
+    assert _close(ctx.born(to_dev(torch, w.dm)).cpu().numpy(), concat(refd))
+    rng = np.random.default_rng(w.nt + len(w.rec))
+    ys = [rng.standard_normal((w.nt, len(r))) for r in w.rec]
+    img = ctx.adjoint(to_dev(torch, concat(ys))).cpu().numpy()
+    refi = O.adjoint(prob, lnvp, lnip, ys)
+    for k in range(2):
+        assert _close(img[k], refi[k]), k
+    ctx.close()
+
+
+def _near_source(w):
+    # receivers on the source node and its neighbours, so that even one or
+    # two steps record (and inject) something
+    for s in range(len(w.rec)):
+        z, x = w.src[s]
+        near = [(z, x), (z + 1, x), (z, x + 1), (z, x - 1), (z + 2, x)]
+        lo, hi = w.win[s][1]
+        near = [(a, b) for a, b in near if 0 <= a < w.lnvp.shape[1] and lo <= b < hi]
+        w.rec[s] = np.concatenate([w.rec[s], np.array(near, dtype=w.rec[s].dtype)])
+    return w
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3])
+def test_shortest_time_axes(torch, nt):
+    w = _near_source(synth.small((20, 24), nt=nt, npml=3, seed=31, nshot=2, uneven=True))
+    _check(torch, w)
+    _check(torch, w, fused=True, shots_per_launch=1)
+
+
+def test_shot_without_receivers(torch):
+    w = synth.small((30, 36), nt=90, npml=4, seed=32, nshot=3, uneven=True)
+    w.rec[1] = np.zeros((0, 2), dtype=w.rec[0].dtype)
+    _check(torch, w)
+    _check(torch, w, shots_per_launch=1)
+
+
+def test_duplicate_receivers_and_receiver_on_source(torch):
+    w = synth.small((28, 34), nt=100, npml=4, seed=33, nshot=2, uneven=True)
+    for s in range(2):
+        r = w.rec[s]
+        extra = np.array([r[0], r[0], list(w.src[s])], dtype=r.dtype)
+        w.rec[s] = np.concatenate([r, extra])
+    _check(torch, w)
+    _check(torch, w, fused=True)
+
+
+@pytest.mark.parametrize("npml", [0, 2])
+def test_grid_smaller_than_a_tile(torch, npml):
+    w = synth.small((6, 9), nt=60, npml=npml, seed=34, nshot=2, uneven=True)
+    for tile in (1, 8):
+        _check(torch, w, tile=tile)
+        _check(torch, w, tile=tile, fused=True)
+
+
+@pytest.mark.parametrize("n", [(20, 20), (10, 11, 12)])
+def test_sources_and_receivers_on_the_last_nodes(torch, n):
+    """Without absorbing strips the wavefield reaches the last node of each
+    axis, where the forward half-node average of dlnrho clamps its upper
+    neighbour to the node itself; the migration must take the transpose of
+    that clamp (regression: the last row and column of the lnrho image)."""
+    w = synth.small(n, nt=50, npml=0, seed=35, nshot=2, uneven=False)
+    last = [k - 1 for k in n]
+    w.src = [tuple(last), tuple(k // 2 for k in n)]
+    recs = []
+    for a in range(len(n)):
+        r = [k // 2 for k in n]
+        r[a] = last[a]
+        recs.append(r)
+    recs.append(last)
+    w.rec = [np.array(recs, dtype=np.int64), np.array(recs[::-1], dtype=np.int64)]
+    _check(torch, w)
