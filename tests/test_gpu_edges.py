@@ -113,3 +113,31 @@ def test_sources_and_receivers_on_the_last_nodes(torch, n):
     recs.append(last)
     w.rec = [np.array(recs, dtype=np.int64), np.array(recs[::-1], dtype=np.int64)]
     _check(torch, w)
+
+
+def _near_source_3d(w):
+    for s in range(len(w.rec)):
+        z, x, y = w.src[s]
+        near = [(z, x, y), (z + 1, x, y), (z, x + 1, y), (z, x, y + 1), (z, x, y - 1)]
+        (zl, zh), (xl, xh), (yl, yh) = w.win[s]
+        near = [(a, b, c) for a, b, c in near if zl <= a < zh and xl <= b < xh and yl <= c < yh]
+        w.rec[s] = np.concatenate([w.rec[s], np.array(near, dtype=w.rec[s].dtype)])
+    return w
+
+
+@pytest.mark.parametrize("case", ["tiny-npml0", "thin-y", "no-receivers", "nt1", "nt2"])
+def test_3d_degenerate(torch, case):
+    """3D: a grid smaller than every tile shape without strips, a y extent far
+    below the march length, a shot without receivers, and 1-2 step time axes."""
+    if case == "tiny-npml0":
+        w = synth.small((5, 6, 7), nt=30, npml=0, seed=41, nshot=2, uneven=True)
+    elif case == "thin-y":
+        w = synth.small((12, 10, 3), nt=40, npml=2, seed=42, nshot=2, uneven=True)
+    elif case == "no-receivers":
+        w = synth.small((10, 12, 9), nt=40, npml=2, seed=43, nshot=3, uneven=True)
+        w.rec[1] = np.zeros((0, 3), dtype=w.rec[0].dtype)
+    else:
+        nt = 1 if case == "nt1" else 2
+        w = _near_source_3d(synth.small((10, 12, 9), nt=nt, npml=2, seed=44, nshot=2, uneven=True))
+    _check(torch, w)
+    _check(torch, w, tile=4, shots_per_launch=1)
