@@ -102,6 +102,10 @@ def test_sources_and_receivers_on_the_last_nodes(torch, n):
     axis, where the forward half-node average of dlnrho clamps its upper
     neighbour to the node itself; the migration must take the transpose of
     that clamp (regression: the last row and column of the lnrho image)."""
+    _check(torch, _last_node_geometry(n))
+
+
+def _last_node_geometry(n):
     w = synth.small(n, nt=50, npml=0, seed=35, nshot=2, uneven=False)
     last = [k - 1 for k in n]
     w.src = [tuple(last), tuple(k // 2 for k in n)]
@@ -112,7 +116,20 @@ def test_sources_and_receivers_on_the_last_nodes(torch, n):
         recs.append(r)
     recs.append(last)
     w.rec = [np.array(recs, dtype=np.int64), np.array(recs[::-1], dtype=np.int64)]
-    _check(torch, w)
+    return w
+
+
+@pytest.mark.parametrize("n", [(20, 20), (10, 11, 12)])
+def test_pseudo_hessian_on_the_last_nodes(torch, n):
+    """The pseudo-Hessian's squared half-node averages, on the same geometry
+    (the clamped last half node carries weight 1 there)."""
+    from paper_2508_10405_amd import lsrtm
+    w = _last_node_geometry(n)
+    ref = O.pseudo_hessian(oracle_problem(w), f64(w.lnvp), f64(w.lnip))
+    ctx = lsrtm.context_for(w)
+    h, _ = ctx.pseudo_hessian(eps_rel=1e-3)
+    assert rel(h.cpu().numpy(), ref) <= TOL
+    ctx.close()
 
 
 def _near_source_3d(w):
