@@ -158,3 +158,27 @@ def test_3d_degenerate(torch, case):
         w = _near_source_3d(synth.small((10, 12, 9), nt=nt, npml=2, seed=44, nshot=2, uneven=True))
     _check(torch, w)
     _check(torch, w, tile=4, shots_per_launch=1)
+
+
+def test_zero_and_one_iterations(torch):
+    """Zero CGNR iterations return x = 0 and the misfit history [1]; one
+    iteration matches the oracle's first CGNR step (data domain); zero
+    image-domain iterations likewise return x = 0."""
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((24, 30), nt=80, npml=4, seed=50, nshot=2, uneven=True)
+    prob = oracle_problem(w)
+    lnvp, lnip = f64(w.lnvp), f64(w.lnip)
+    dobs = O.born(prob, lnvp, lnip, f64(w.dm))
+    ctx = lsrtm.context_for(w)
+    d = to_dev(torch, concat(dobs))
+    x, hist = ctx.cgnr(d, 0)
+    assert float(x.abs().max()) == 0.0 and list(hist) == [1.0]
+    x_ref, hist_ref = O.cgnr(lambda m: O.born(prob, lnvp, lnip, m),
+                             lambda y: O.adjoint(prob, lnvp, lnip, y), dobs, 1)
+    x1, hist1 = ctx.cgnr(d, 1)
+    assert rel(x1.cpu().numpy(), x_ref) <= 1e-3
+    assert abs(hist1[1] - hist_ref[1]) <= 1e-4
+    psf = ctx.psf_images(5)
+    x, hist = ctx.psf_cgnr(psf, 5, ctx.adjoint(d), 0)
+    assert float(x.abs().max()) == 0.0 and list(hist) == [1.0]
+    ctx.close()

@@ -20,7 +20,9 @@ def torch():
     return require_gpu()
 
 
-CASES = [((37, 45), 16, 1e-3), ((64, 75), 32, 1e-2), ((240, 100), 64, 1e-3), ((12, 14, 10), 8, 1e-3)]
+CASES = [((37, 45), 16, 1e-3), ((64, 75), 32, 1e-2), ((240, 100), 64, 1e-3), ((12, 14, 10), 8, 1e-3),
+         # blocks larger than the image along every axis
+         ((20, 24), 64, 1e-3), ((5, 6, 4), 8, 1e-3)]
 
 
 @pytest.mark.parametrize("n,block,eps", CASES)
