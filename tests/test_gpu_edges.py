@@ -182,3 +182,21 @@ def test_zero_and_one_iterations(torch):
     x, hist = ctx.psf_cgnr(psf, 5, ctx.adjoint(d), 0)
     assert float(x.abs().max()) == 0.0 and list(hist) == [1.0]
     ctx.close()
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_windows_offset_along_every_axis(torch, ndim):
+    """Shot windows that start away from the model origin along z (and y),
+    overlapping differently, with receivers on window corners."""
+    if ndim == 2:
+        w = synth.small((14, 16), nt=50, npml=3, seed=60, nshot=2, uneven=False)
+        w.win = [((2, 14), (3, 16)), ((0, 11), (0, 12))]
+        w.src = [(4, 8), (3, 5)]
+        w.rec = [np.array([(2, 3), (13, 15), (7, 9)]), np.array([(0, 0), (10, 11), (5, 6)])]
+    else:
+        w = synth.small((12, 14, 10), nt=50, npml=3, seed=60, nshot=2, uneven=False)
+        w.win = [((2, 12), (3, 14), (1, 9)), ((0, 9), (0, 10), (2, 10))]
+        w.src = [(4, 8, 4), (3, 5, 6)]
+        w.rec = [np.array([(2, 3, 1), (11, 13, 8), (7, 9, 5)]), np.array([(0, 0, 2), (8, 9, 9), (5, 6, 6)])]
+    _check(torch, w)
+    _check(torch, w, shots_per_launch=1)
