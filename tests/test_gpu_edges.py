@@ -200,3 +200,39 @@ def test_windows_offset_along_every_axis(torch, ndim):
         w.rec = [np.array([(2, 3, 1), (11, 13, 8), (7, 9, 5)]), np.array([(0, 0, 2), (8, 9, 9), (5, 6, 6)])]
     _check(torch, w)
     _check(torch, w, shots_per_launch=1)
+
+
+def test_planner_budgets_and_per_group_checkpoints(torch):
+    """2D: a tighter memory budget gives smaller launch groups, checkpoints
+    held per launch group (each migration re-runs its group's background
+    first) and both schedules, all with bitwise the same data, images and CGNR
+    iterates; a budget below the fixed needs is refused with an error."""
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((40, 60), nt=300, npml=6, seed=70, nshot=6, uneven=True)
+    dm = to_dev(torch, w.dm)
+    ref_ctx = lsrtm.context_for(w, tile=1)
+    full = ref_ctx.sizes()
+    d_ref = ref_ctx.born(dm)
+    y = to_dev(torch, np.random.default_rng(8).standard_normal(ref_ctx.data_len))
+    img_ref = ref_ctx.adjoint(y).cpu().numpy()
+    x_ref, h_ref = ref_ctx.cgnr(d_ref, 2)
+    x_ref = x_ref.cpu().numpy()
+    d_ref = d_ref.cpu().numpy()
+    ref_ctx.close()
+    budget = int(0.96 * full["plan_bytes"]) >> 20
+    for opts in ({"mem_budget_mb": budget}, {"ckpt_per_group": True, "shots_per_launch": 2},
+                 {"ckpt_per_group": True, "fused": True}):
+        print(f"[case] planner {opts}", flush=True)
+        ctx = lsrtm.context_for(w, tile=1, **opts)
+        sz = ctx.sizes()
+        if "mem_budget_mb" in opts:
+            assert sz["groups"] > full["groups"] and sz["plan_bytes"] <= budget << 20
+        else:
+            assert sz["ckpt_per_group"] == 1
+        assert np.array_equal(ctx.born(dm).cpu().numpy(), d_ref)
+        assert np.array_equal(ctx.adjoint(y).cpu().numpy(), img_ref)
+        x, h = ctx.cgnr(to_dev(torch, d_ref), 2)
+        assert np.array_equal(x.cpu().numpy(), x_ref) and list(h) == list(h_ref)
+        ctx.close()
+    with pytest.raises(lsrtm.LsrtmError):
+        lsrtm.context_for(w, mem_budget_mb=1)
