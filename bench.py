@@ -16,8 +16,9 @@ value = grid-point updates per second of the two operator passes
         2 * (sum over shots of padded nodes) * nt * K / time   [Gpts/s]
 
 Launch configuration: 32 shots per launch group (balanced to 4 groups of 30)
-and 32 x 16 tiles, the autotuner's pick for this workload on MI355X;
---shots-per-launch -1 --tile -1 tunes again.
+and 32 x 16 tiles, the autotuner's pick for this workload on MI355X, with
+32 x 32 tiles for the adjoint A phase (the fastest shape for that phase);
+--shots-per-launch -1 --tile -1 tunes again (per-phase shapes included).
 
 Also reported: the roofline of the dominant kernel (algorithmic bytes per
 launch / average kernel time, from events that the runtime stamps with the
