@@ -236,3 +236,18 @@ def test_planner_budgets_and_per_group_checkpoints(torch):
         ctx.close()
     with pytest.raises(lsrtm.LsrtmError):
         lsrtm.context_for(w, mem_budget_mb=1)
+
+
+@pytest.mark.parametrize("n,npml", [((12, 1), 0), ((12, 2), 3), ((12, 3), 0), ((8, 9, 1), 0), ((8, 9, 2), 2)])
+def test_grids_one_to_three_nodes_wide(torch, n, npml):
+    """An axis of 1-3 nodes (all of a derivative's neighbours outside)."""
+    _check(torch, synth.small(n, nt=40, npml=npml, seed=80 + len(n), nshot=1, uneven=False))
+
+
+def test_windows_one_and_two_nodes_wide(torch):
+    w = synth.small((12, 20), nt=40, npml=3, seed=81, nshot=2, uneven=False)
+    w.win = [((0, 12), (5, 6)), ((0, 12), (7, 9))]
+    w.src = [(3, 5), (3, 8)]
+    w.rec = [np.array([(1, 5), (11, 5)]), np.array([(1, 7), (11, 8)])]
+    _check(torch, w)
+    _check(torch, w, fused=True)
