@@ -8,7 +8,9 @@ FP64 oracle (relative L2 1e-4, or exactly zero where the oracle is zero):
 * receivers duplicated on one node and a receiver on the source node
   (injection sums every receiver of a node);
 * a grid smaller than one tile, with and without absorbing strips, in both
-  2D schedules.
+  2D schedules;
+* two contexts on two streams with their calls interleaved (bitwise equal to
+  each context used alone: the library holds no state outside a context).
 """
 import numpy as np
 import pytest
@@ -251,3 +253,34 @@ def test_windows_one_and_two_nodes_wide(torch):
     w.rec = [np.array([(1, 5), (11, 5)]), np.array([(1, 7), (11, 8)])]
     _check(torch, w)
     _check(torch, w, fused=True)
+
+
+def test_two_contexts_on_two_streams(torch):
+    """Two live contexts (2D and 3D) on two non-default streams, calls
+    interleaved: every result is bitwise that of a context used alone."""
+    from paper_2508_10405_amd import lsrtm
+    w2 = synth.small((30, 36), nt=80, npml=4, seed=90, nshot=2, uneven=True)
+    w3 = synth.small((10, 12, 9), nt=40, npml=2, seed=91, nshot=2, uneven=True)
+    alone = []
+    for w in (w2, w3):
+        ctx = lsrtm.context_for(w)
+        y = to_dev(torch, np.random.default_rng(3).standard_normal(ctx.data_len))
+        alone.append((ctx.born(to_dev(torch, w.dm)).cpu().numpy(), ctx.adjoint(y).cpu().numpy()))
+        ctx.close()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    c2 = lsrtm.context_for(w2, stream=s1)
+    c3 = lsrtm.context_for(w3, stream=s2)
+    # inputs stay referenced until both streams are done with them
+    y2 = to_dev(torch, np.random.default_rng(3).standard_normal(c2.data_len))
+    y3 = to_dev(torch, np.random.default_rng(3).standard_normal(c3.data_len))
+    m2, m3 = to_dev(torch, w2.dm), to_dev(torch, w3.dm)
+    torch.cuda.synchronize()
+    d2 = c2.born(m2)
+    d3 = c3.born(m3)
+    i2 = c2.adjoint(y2)
+    i3 = c3.adjoint(y3)
+    torch.cuda.synchronize()
+    assert np.array_equal(d2.cpu().numpy(), alone[0][0]) and np.array_equal(i2.cpu().numpy(), alone[0][1])
+    assert np.array_equal(d3.cpu().numpy(), alone[1][0]) and np.array_equal(i3.cpu().numpy(), alone[1][1])
+    c2.close()
+    c3.close()
