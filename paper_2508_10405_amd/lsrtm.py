@@ -8,9 +8,16 @@ Array conventions (same as the C ABI): physical grid arrays are torch float32
 tensors of shape (nx, nz) in 2D and (ny, nx, nz) in 3D (z fastest); model
 perturbations and images have a leading axis of 2 for (lnVp, lnIp); data
 vectors are flat, shot s occupying nt * nrec_s values laid out [it][rec].
+
+Streams: the library works on the context's stream.  A call made while another
+stream is current orders itself after the work already queued there (the
+arguments' producers) and queues the caller's later work after its own, and
+the tensors it touches are kept from reuse until the context's stream is done
+with them; a call made with the context's stream current adds nothing.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 from typing import List, Optional, Sequence
@@ -164,6 +171,21 @@ class Context:
                 msg = lib().lsrtm_last_error(self._h).decode()
             raise LsrtmError(status, f"{what}: {lib().lsrtm_strerror(status).decode()} {msg}".strip())
 
+    @contextlib.contextmanager
+    def _ordered(self, *tensors):
+        """Order a library call between the caller's current stream and the
+        context's stream (see the module docstring)."""
+        cur = self._torch.cuda.current_stream()
+        other = cur != self.stream
+        if other:
+            self.stream.wait_stream(cur)
+            for t in tensors:
+                if t is not None:
+                    t.record_stream(self.stream)
+        yield
+        if other:
+            cur.wait_stream(self.stream)
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().lsrtm_destroy(self._h)
@@ -184,7 +206,8 @@ class Context:
         _require_cuda(lnip, "lnip")
         if tuple(lnvp.shape) != self.shape or tuple(lnip.shape) != self.shape:
             raise ValueError(f"model shape must be {self.shape}")
-        self._check(lib().lsrtm_set_model(self._h, _vp(_ptr(lnvp)), _vp(_ptr(lnip))), "set_model")
+        with self._ordered(lnvp, lnip):
+            self._check(lib().lsrtm_set_model(self._h, _vp(_ptr(lnvp)), _vp(_ptr(lnip))), "set_model")
 
     def set_acquisition(self, win, src, rec: Sequence, wavelet):
         """win: per shot ((z0, z1), (x0, x1)[, (y0, y1)]); src: per shot node;
@@ -201,9 +224,10 @@ class Context:
         _require_cuda(wavelet, "wavelet")
         if tuple(wavelet.shape) != (nshot, self.nt):
             raise ValueError("wavelet must have shape (nshot, nt)")
-        self._check(lib().lsrtm_set_acquisition(
-            self._h, nshot, w.ctypes.data, s.ctypes.data, ptr.ctypes.data, r.ctypes.data,
-            _vp(_ptr(wavelet))), "set_acquisition")
+        with self._ordered(wavelet):
+            self._check(lib().lsrtm_set_acquisition(
+                self._h, nshot, w.ctypes.data, s.ctypes.data, ptr.ctypes.data, r.ctypes.data,
+                _vp(_ptr(wavelet))), "set_acquisition")
         self.nrec = counts
         self.nshot = nshot
 
@@ -263,7 +287,8 @@ class Context:
 
     def forward(self, d=None):
         d = self._data(d)
-        self._check(lib().lsrtm_forward(self._h, _vp(_ptr(d))), "forward")
+        with self._ordered(d):
+            self._check(lib().lsrtm_forward(self._h, _vp(_ptr(d))), "forward")
         return d
 
     def born(self, dm, d=None):
@@ -271,7 +296,8 @@ class Context:
         if tuple(dm.shape) != (2,) + self.shape:
             raise ValueError(f"dm must have shape {(2,) + self.shape}")
         d = self._data(d)
-        self._check(lib().lsrtm_born(self._h, _vp(_ptr(dm)), _vp(_ptr(d))), "born")
+        with self._ordered(dm, d):
+            self._check(lib().lsrtm_born(self._h, _vp(_ptr(dm)), _vp(_ptr(d))), "born")
         return d
 
     def adjoint(self, d, img=None, accumulate=False):
@@ -279,27 +305,31 @@ class Context:
         if d.numel() != self.data_len:
             raise ValueError(f"data vector must have {self.data_len} values")
         img = self._image(img)
-        self._check(lib().lsrtm_adjoint(self._h, _vp(_ptr(d)), _vp(_ptr(img)), int(bool(accumulate))),
-                    "adjoint")
+        with self._ordered(d, img):
+            self._check(lib().lsrtm_adjoint(self._h, _vp(_ptr(d)), _vp(_ptr(img)), int(bool(accumulate))),
+                        "adjoint")
         return img
 
     def cgnr(self, d_obs, niter, x=None):
         _require_cuda(d_obs, "d_obs")
         x = self._image(x)
         mis = (_c_double * (niter + 1))()
-        self._check(lib().lsrtm_cgnr(self._h, _vp(_ptr(d_obs)), int(niter), _vp(_ptr(x)), mis), "cgnr")
+        with self._ordered(d_obs, x):
+            self._check(lib().lsrtm_cgnr(self._h, _vp(_ptr(d_obs)), int(niter), _vp(_ptr(x)), mis), "cgnr")
         return x, [float(v) for v in mis]
 
     def cgnr_begin(self, d_obs, x=None):
         _require_cuda(d_obs, "d_obs")
         x = self._image(x)
-        self._check(lib().lsrtm_cgnr_begin(self._h, _vp(_ptr(d_obs)), _vp(_ptr(x))), "cgnr_begin")
+        with self._ordered(d_obs, x):
+            self._check(lib().lsrtm_cgnr_begin(self._h, _vp(_ptr(d_obs)), _vp(_ptr(x))), "cgnr_begin")
         return x
 
     def cgnr_iterate(self, x) -> float:
         _require_cuda(x, "x")
         m = _c_double()
-        self._check(lib().lsrtm_cgnr_iterate(self._h, _vp(_ptr(x)), ctypes.byref(m)), "cgnr_iterate")
+        with self._ordered(x):
+            self._check(lib().lsrtm_cgnr_iterate(self._h, _vp(_ptr(x)), ctypes.byref(m)), "cgnr_iterate")
         return m.value
 
     def cgnr_get_state(self):
@@ -308,16 +338,18 @@ class Context:
         z = torch.empty((2,) + self.shape, dtype=torch.float32, device="cuda")
         p = torch.empty_like(z)
         sc = (_c_double * 4)()
-        self._check(lib().lsrtm_cgnr_state(self._h, 1, _vp(_ptr(r)), _vp(_ptr(z)), _vp(_ptr(p)), sc),
-                    "cgnr_state")
+        with self._ordered(r, z, p):
+            self._check(lib().lsrtm_cgnr_state(self._h, 1, _vp(_ptr(r)), _vp(_ptr(z)), _vp(_ptr(p)), sc),
+                        "cgnr_state")
         return {"r": r, "z": z, "p": p, "scalars": [float(v) for v in sc]}
 
     def cgnr_set_state(self, st):
         sc = (_c_double * 4)(*st["scalars"])
         for k in ("r", "z", "p"):
             _require_cuda(st[k], k)
-        self._check(lib().lsrtm_cgnr_state(self._h, 0, _vp(_ptr(st["r"])), _vp(_ptr(st["z"])),
-                                           _vp(_ptr(st["p"])), sc), "cgnr_state")
+        with self._ordered(st["r"], st["z"], st["p"]):
+            self._check(lib().lsrtm_cgnr_state(self._h, 0, _vp(_ptr(st["r"])), _vp(_ptr(st["z"])),
+                                               _vp(_ptr(st["p"])), sc), "cgnr_state")
 
     def pseudo_hessian(self, eps_rel=1e-3, preconditioner=True):
         """Pseudo-Hessian diagonal h [shape] (lsrtm_pseudo_hessian) and, with
@@ -325,8 +357,9 @@ class Context:
         torch = self._torch
         h = torch.empty(self.shape, dtype=torch.float32, device="cuda")
         minv = torch.empty((2,) + self.shape, dtype=torch.float32, device="cuda") if preconditioner else None
-        self._check(lib().lsrtm_pseudo_hessian(self._h, _vp(_ptr(h)), _vp(_ptr(minv)), float(eps_rel)),
-                    "pseudo_hessian")
+        with self._ordered(h, minv):
+            self._check(lib().lsrtm_pseudo_hessian(self._h, _vp(_ptr(h)), _vp(_ptr(minv)), float(eps_rel)),
+                        "pseudo_hessian")
         return h, minv
 
     def set_preconditioner(self, minv):
@@ -335,14 +368,16 @@ class Context:
             _require_cuda(minv, "minv")
             if minv.numel() != 2 * int(np.prod(self.shape)):
                 raise ValueError("minv must hold 2 x grid points")
-        self._check(lib().lsrtm_set_preconditioner(self._h, _vp(_ptr(minv))), "set_preconditioner")
+        with self._ordered(minv):
+            self._check(lib().lsrtm_set_preconditioner(self._h, _vp(_ptr(minv))), "set_preconditioner")
 
     def psf_images(self, spacing):
         """PSF images [2 (scatterer parameter), 2 (response), *shape]
         (lsrtm_psf_images)."""
         torch = self._torch
         psf = torch.empty((2, 2) + self.shape, dtype=torch.float32, device="cuda")
-        self._check(lib().lsrtm_psf_images(self._h, int(spacing), _vp(_ptr(psf))), "psf_images")
+        with self._ordered(psf):
+            self._check(lib().lsrtm_psf_images(self._h, int(spacing), _vp(_ptr(psf))), "psf_images")
         return psf
 
     def _psf_vec(self, v, mono, name):
@@ -356,8 +391,9 @@ class Context:
         _require_cuda(psf, "psf")
         self._psf_vec(x, mono, "x")
         y = self._torch.empty_like(x)
-        self._check(lib().lsrtm_psf_apply(self._h, _vp(_ptr(psf)), int(spacing), int(bool(mono)),
-                                          int(bool(transpose)), _vp(_ptr(x)), _vp(_ptr(y))), "psf_apply")
+        with self._ordered(psf, x, y):
+            self._check(lib().lsrtm_psf_apply(self._h, _vp(_ptr(psf)), int(spacing), int(bool(mono)),
+                                              int(bool(transpose)), _vp(_ptr(x)), _vp(_ptr(y))), "psf_apply")
         return y
 
     def psf_cgnr(self, psf, spacing, m_rtm, niter, mono=False):
@@ -367,8 +403,9 @@ class Context:
         self._psf_vec(m_rtm, mono, "m_rtm")
         x = self._torch.empty_like(m_rtm)
         mis = (_c_double * (niter + 1))()
-        self._check(lib().lsrtm_psf_cgnr(self._h, _vp(_ptr(psf)), int(spacing), int(bool(mono)),
-                                         _vp(_ptr(m_rtm)), int(niter), _vp(_ptr(x)), mis), "psf_cgnr")
+        with self._ordered(psf, m_rtm, x):
+            self._check(lib().lsrtm_psf_cgnr(self._h, _vp(_ptr(psf)), int(spacing), int(bool(mono)),
+                                             _vp(_ptr(m_rtm)), int(niter), _vp(_ptr(x)), mis), "psf_cgnr")
         return x, [float(v) for v in mis]
 
     def mute(self, d, v_mute, t0=0.0, ntaper=0):
@@ -376,7 +413,8 @@ class Context:
         _require_cuda(d, "d")
         if d.numel() != self.data_len:
             raise ValueError("d must hold the data length")
-        self._check(lib().lsrtm_mute(self._h, _vp(_ptr(d)), float(v_mute), float(t0), int(ntaper)), "mute")
+        with self._ordered(d):
+            self._check(lib().lsrtm_mute(self._h, _vp(_ptr(d)), float(v_mute), float(t0), int(ntaper)), "mute")
         return d
 
     def wiener(self, m_ref, m_blur, m_in=None, block=64, eps_rel=1e-3):
@@ -389,9 +427,10 @@ class Context:
             if t.numel() % n or t.numel() != m_ref.numel():
                 raise ValueError(f"{name} must hold a whole number of images")
         out = self._torch.empty_like(m_ref)
-        self._check(lib().lsrtm_wiener(self._h, _vp(_ptr(m_ref)), _vp(_ptr(m_blur)), _vp(_ptr(m_in)),
-                                       m_ref.numel() // n, int(block), float(eps_rel), _vp(_ptr(out))),
-                    "wiener")
+        with self._ordered(m_ref, m_blur, m_in, out):
+            self._check(lib().lsrtm_wiener(self._h, _vp(_ptr(m_ref)), _vp(_ptr(m_blur)), _vp(_ptr(m_in)),
+                                           m_ref.numel() // n, int(block), float(eps_rel), _vp(_ptr(out))),
+                        "wiener")
         return out
 
     def dot(self, a, b) -> float:
@@ -400,8 +439,9 @@ class Context:
         if a.numel() != b.numel():
             raise ValueError("length mismatch")
         out = _c_double()
-        self._check(lib().lsrtm_dot(self._h, _vp(_ptr(a)), _vp(_ptr(b)), a.numel(), ctypes.byref(out)),
-                    "dot")
+        with self._ordered(a, b):
+            self._check(lib().lsrtm_dot(self._h, _vp(_ptr(a)), _vp(_ptr(b)), a.numel(), ctypes.byref(out)),
+                        "dot")
         return out.value
 
     def axpy(self, alpha, x, y):
@@ -409,7 +449,8 @@ class Context:
         _require_cuda(y, "y")
         if x.numel() != y.numel():
             raise ValueError("length mismatch")
-        self._check(lib().lsrtm_axpy(self._h, float(alpha), _vp(_ptr(x)), _vp(_ptr(y)), x.numel()), "axpy")
+        with self._ordered(x, y):
+            self._check(lib().lsrtm_axpy(self._h, float(alpha), _vp(_ptr(x)), _vp(_ptr(y)), x.numel()), "axpy")
         return y
 
 

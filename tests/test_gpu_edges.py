@@ -255,32 +255,71 @@ def test_windows_one_and_two_nodes_wide(torch):
     _check(torch, w, fused=True)
 
 
-def test_two_contexts_on_two_streams(torch):
-    """Two live contexts (2D and 3D) on two non-default streams, calls
-    interleaved: every result is bitwise that of a context used alone."""
+def _two_workloads():
+    return (synth.small((30, 36), nt=80, npml=4, seed=90, nshot=2, uneven=True),
+            synth.small((10, 12, 9), nt=40, npml=2, seed=91, nshot=2, uneven=True))
+
+
+def _alone(torch, ws):
     from paper_2508_10405_amd import lsrtm
-    w2 = synth.small((30, 36), nt=80, npml=4, seed=90, nshot=2, uneven=True)
-    w3 = synth.small((10, 12, 9), nt=40, npml=2, seed=91, nshot=2, uneven=True)
-    alone = []
-    for w in (w2, w3):
+    out = []
+    for w in ws:
         ctx = lsrtm.context_for(w)
         y = to_dev(torch, np.random.default_rng(3).standard_normal(ctx.data_len))
-        alone.append((ctx.born(to_dev(torch, w.dm)).cpu().numpy(), ctx.adjoint(y).cpu().numpy()))
+        out.append((ctx.born(to_dev(torch, w.dm)).cpu().numpy(), ctx.adjoint(y).cpu().numpy()))
         ctx.close()
-    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
-    c2 = lsrtm.context_for(w2, stream=s1)
-    c3 = lsrtm.context_for(w3, stream=s2)
-    # inputs stay referenced until both streams are done with them
-    y2 = to_dev(torch, np.random.default_rng(3).standard_normal(c2.data_len))
-    y3 = to_dev(torch, np.random.default_rng(3).standard_normal(c3.data_len))
-    m2, m3 = to_dev(torch, w2.dm), to_dev(torch, w3.dm)
+    return out
+
+
+def test_two_contexts_on_two_streams(torch):
+    """Two live contexts (2D and 3D), each driven with its own stream current,
+    calls interleaved so that the streams run side by side: every result is
+    bitwise that of a context used alone."""
+    from paper_2508_10405_amd import lsrtm
+    ws = _two_workloads()
+    alone = _alone(torch, ws)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    ctxs, ins = [], []
+    for w, s in zip(ws, streams):
+        with torch.cuda.stream(s):
+            c = lsrtm.context_for(w)
+            ins.append((to_dev(torch, w.dm),
+                        to_dev(torch, np.random.default_rng(3).standard_normal(c.data_len))))
+            ctxs.append(c)
     torch.cuda.synchronize()
-    d2 = c2.born(m2)
-    d3 = c3.born(m3)
-    i2 = c2.adjoint(y2)
-    i3 = c3.adjoint(y3)
+    res = [[None, None], [None, None]]
+    for k in range(2):
+        for j in range(2):
+            with torch.cuda.stream(streams[j]):
+                res[j][k] = ctxs[j].born(ins[j][0]) if k == 0 else ctxs[j].adjoint(ins[j][1])
     torch.cuda.synchronize()
-    assert np.array_equal(d2.cpu().numpy(), alone[0][0]) and np.array_equal(i2.cpu().numpy(), alone[0][1])
-    assert np.array_equal(d3.cpu().numpy(), alone[1][0]) and np.array_equal(i3.cpu().numpy(), alone[1][1])
-    c2.close()
-    c3.close()
+    for j in range(2):
+        assert np.array_equal(res[j][0].cpu().numpy(), alone[j][0])
+        assert np.array_equal(res[j][1].cpu().numpy(), alone[j][1])
+        ctxs[j].close()
+
+
+def test_context_stream_orders_with_caller_stream(torch):
+    """A context bound to a side stream, called from the default stream: the
+    inputs come from kernels still queued on the default stream, are dropped
+    right after the call, and the results are read on the default stream with
+    no explicit synchronisation; the results are bitwise those of a context
+    on the default stream."""
+    from paper_2508_10405_amd import lsrtm
+    ws = _two_workloads()
+    alone = _alone(torch, ws)
+    side = torch.cuda.Stream()
+    for w, ref in zip(ws, alone):
+        ctx = lsrtm.context_for(w, stream=side)
+        n = ctx.data_len
+        # producers queued on the default stream (a copy, then a scaling by one)
+        dm = to_dev(torch, w.dm).clone().mul_(1.0)
+        d = ctx.born(dm)
+        del dm
+        y = to_dev(torch, np.random.default_rng(3).standard_normal(n)).clone().mul_(1.0)
+        img = ctx.adjoint(y)
+        del y
+        # default-stream consumers, then a copy that waits for the default stream only
+        assert np.array_equal((d * 1.0).cpu().numpy(), ref[0])
+        assert np.array_equal((img * 1.0).cpu().numpy(), ref[1])
+        ctx.close()
