@@ -108,6 +108,17 @@ def cpu_worker(args):
     return time.perf_counter() - t0
 
 
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(nt_s, workers, padded_per_shot):
     from multiprocessing import get_context
     ctx = get_context("spawn")
@@ -117,7 +128,7 @@ def cpu_baseline(nt_s, workers, padded_per_shot):
     wall = time.perf_counter() - t0
     busy = max(times)
     gpts = workers * 2 * padded_per_shot * nt_s / busy / 1e9
-    return {"value": gpts, "unit": "Gpts/s", "cores": workers, "kind": "oracle",
+    return {"value": gpts, "unit": "Gpts/s", "cores": workers, "kind": "oracle", "cpu": cpu_model(),
             "sample": f"{workers} shots x {nt_s} of 4000 steps (Born + migration, one shot per "
                       f"process, FP64 numpy); slowest process {busy:.1f} s, wall {wall:.1f} s"}
 
