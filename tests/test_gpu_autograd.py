@@ -90,8 +90,8 @@ def test_dot_product_through_autograd(torch):
 def test_checkpoint_interval_and_dtype(torch, k, dtype):
     """Gradient through the autograd op for every checkpoint interval and
     snapshot precision, against the FP64 oracle: FP32 snapshots meet the
-    1e-4 bar; compressed ones report their error under this build's bounds
-    (2e-3 FP16, 2e-2 BF16)."""
+    1e-4 bar; compressed ones report their error under the bounds stated for
+    compressed snapshots (2e-3 FP16, 2e-2 BF16)."""
     from paper_2508_10405_amd import autograd
     w, ctx = _setup(torch, k=k, dtype=dtype)
     rng = np.random.default_rng(4)

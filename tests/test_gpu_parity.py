@@ -203,7 +203,8 @@ def test_config1_full(torch):
 @pytest.mark.parametrize("dtype,bound", [("f16", 2e-3), ("bf16", 2e-2)])
 def test_compressed_checkpoints_error(torch, dtype, bound):
     """FP16/BF16 snapshots with per-snapshot max-abs scaling: the image error
-    against the FP64 oracle is reported; the bound is this build's stated one."""
+    against the FP64 oracle is reported and held to the bound stated for
+    compressed snapshots (the paper gives none)."""
     from paper_2508_10405_amd import lsrtm
     w = synth.small((60, 80), nt=300, npml=10, seed=21, nshot=2, uneven=True)
     prob = oracle_problem(w)
