@@ -159,6 +159,10 @@ def main():
                     help="tile shape id of the adjoint A phase (-1 = the stencil tile; default: 2 = "
                          "32 x 32 for the 2D workloads, the fastest shape for that phase on MI355X, and "
                          "-1 for config5)")
+    ap.add_argument("--replay-cache-gb", type=float, default=-1,
+                    help="HBM that may keep the background replays of the last checkpoint segments across "
+                         "CG iterations (they depend on the background only); -1 = what the memory plan "
+                         "leaves (default), 0 = off")
     ap.add_argument("--tune-steps", type=int, default=24)
     ap.add_argument("--pcgnr", type=int, default=0,
                     help="also run N CGNR and N pseudo-Hessian-preconditioned CGNR iterations from x = 0 "
@@ -203,6 +207,7 @@ def main():
     log(f"[bench] workload {w.name}: {w.nshot} shots, nt={w.nt}, padded points {w.padded_points()}")
     ctx = lsrtm.context_for(w, shots_per_launch=max(0, args.shots_per_launch), tile=args.tile, timing=True,
                             tile_v=args.tile_v, tile_adj_a=args.tile_adj_a,
+                            replay_cache_mb=1 << 30 if args.replay_cache_gb < 0 else int(args.replay_cache_gb * 1024),
                             ckpt_dtype=ckdt, progress=nd == 3)
     if args.tile < 0:
         t0 = time.perf_counter()
@@ -410,6 +415,7 @@ def main():
                                + (f" [time axis truncated to nt={w.nt}]" if args.nt > 0 else ""),
                    "shots": w.nshot, "nt": w.nt, "padded_points": padded,
                    "shots_per_launch": sz["shots_per_launch"], "ckpt_every": sz["ckpt_every"],
+                   "replay_cache_segments": sz["replay_cache_segments"],
                    "tile": list(lsrtm.tile_shape(nd, sz["tile"])),
                    "tile_v": list(lsrtm.tile_shape(nd, sz["tile_v"])) if sz["tile_v"] >= 0 else None,
                    "tile_adj_a": list(lsrtm.tile_shape(nd, sz["tile_adj_a"])) if sz["tile_adj_a"] >= 0 else None,

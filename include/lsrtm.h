@@ -108,8 +108,20 @@ enum {
                                        and inject nothing; -1 = LSRTM_OPT_TILE
                                        (default).  Results do not depend on it;
                                        ignored by the fused 2D schedule.        */
-    LSRTM_OPT_TILE_ADJ_A = 10       /* likewise for the adjoint pressure phase
+    LSRTM_OPT_TILE_ADJ_A = 10,      /* likewise for the adjoint pressure phase
                                        (A); -1 = LSRTM_OPT_TILE (default)       */
+    LSRTM_OPT_REPLAY_CACHE_MB = 11  /* device memory (MB) that may keep the
+                                       background replays of the last segments
+                                       of every launch group across migration
+                                       passes (App. A: the history is the
+                                       background's, independent of dm and of
+                                       the data), capped by what the memory
+                                       budget leaves; the first migration pass
+                                       fills it, later ones skip the replay of
+                                       those segments.  Results are bitwise the
+                                       same.  Two-phase steps with checkpoints
+                                       for the whole plan only; 0 = off
+                                       (default).  Re-plans when changed.       */
 };
 
 /* Create a context for one grid on one HIP stream (hipStream_t, may be 0).
@@ -291,8 +303,9 @@ lsrtm_status lsrtm_autotune(lsrtm_ctx* ctx, int nsteps, int tune_groups, double*
  * launch groups, out[5] = padded points summed over shots, out[6] = device
  * bytes planned, out[7] = tile id in use, out[8] = 1 if checkpoints are held
  * per launch group, out[9] = 1 for the fused 2D schedule, out[10] / out[11] =
- * tile id of the velocity phases / of the adjoint A phase (-1 = out[7]).
- * HOST long long [nout]; the first min(nout, 12) entries are written. */
+ * tile id of the velocity phases / of the adjoint A phase (-1 = out[7]),
+ * out[12] = segments per launch group held by the replay cache.
+ * HOST long long [nout]; the first min(nout, 13) entries are written. */
 lsrtm_status lsrtm_sizes(lsrtm_ctx* ctx, long long* out, int nout);
 
 /* Timing statistics of the last pass (HOST double [nout]); see

@@ -83,6 +83,10 @@ struct Group {
     };
     std::vector<AltTiles> alt;
     std::vector<Rec> h_rec;        // receivers of the group (host copy)
+    // replay cache: descriptors of the cached segments ([rc_m][ns], equal to
+    // d_slots but for seg), and whether the cache holds this group's replays
+    Slot* d_rc = nullptr;
+    bool rc_valid = false;
     long long max_npts = 0;
     long long bg_used = 0, sc_used = 0, img_used = 0;   // floats
 };
@@ -123,6 +127,8 @@ struct lsrtm_ctx {
     long long bg_region = 0, sc_region = 0, img_region = 0;
     float* pool = nullptr;
     float* segbuf = nullptr;
+    float* rcache = nullptr;       // replay cache: the last rc_m segments of every group
+    int rc_m = 0;
     char* ckbuf = nullptr;
     float* ckscales = nullptr;     // [nseg][nshot][1+ndim]
     float* partial = nullptr;      // reduction workspace of set_model
@@ -166,6 +172,7 @@ struct lsrtm_ctx {
     int opt_progress = 0;
     int opt_tile_v = -1;           // two-phase steps: tile of the velocity phases (-1: tile)
     int opt_tile_a = -1;           // two-phase steps: tile of the adjoint A phase (-1: tile)
+    long long opt_rcache_mb = 0;   // HBM the replay cache may take (0: none)
     // timing
     std::vector<EvPair> evpool;
     size_t evused = 0;
@@ -230,6 +237,13 @@ lsrtm_status dalloc_t(lsrtm_ctx* c, T** p, size_t n, bool acq) {
     return dalloc(c, reinterpret_cast<void**>(p), n * sizeof(T), acq);
 }
 
+// The background changed (model, or a failed snapshot): stored checkpoints
+// and cached replays are stale.
+void background_changed(lsrtm_ctx* c) {
+    c->ckpt_valid = false;
+    for (auto& gr : c->groups) gr.rc_valid = false;
+}
+
 void clear_graphs(lsrtm_ctx* c) {
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
@@ -246,6 +260,8 @@ void free_acq(lsrtm_ctx* c) {
     c->ckpt_valid = false;
     c->pool = nullptr;
     c->segbuf = nullptr;
+    c->rcache = nullptr;
+    c->rc_m = 0;
     c->ckbuf = nullptr;
     c->ckscales = nullptr;
     c->ckpart = nullptr;
@@ -533,7 +549,7 @@ lsrtm_status check_flag(lsrtm_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(&f, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     if (f) {
-        c->ckpt_valid = false;
+        background_changed(c);
         HIPCHK(c, launch_fill(reinterpret_cast<float*>(c->d_flag), 1, 0.f, c->st));
         FAIL(c, LSRTM_ENONFINITE, "non-finite value in a stored background snapshot");
     }
@@ -590,16 +606,22 @@ lsrtm_status group_adjoint(lsrtm_ctx* c, Group& gr, const float* d) {
     };
     tstep(c, nt - 1);
     CHK(inject(nt - 1));
+    // segments j >= jc replay into the replay cache, and only when it does
+    // not hold this group's replays yet
+    const int jc = c->nseg - c->rc_m;
     for (int j = c->nseg - 1; j >= 0; --j) {
         const int n0 = j * c->k, n1 = std::min(n0 + c->k, nt);
+        const Slot* rcd = j >= jc ? gr.d_rc + (long long)(j - jc) * gr.ns : nullptr;
         tstep(c, n0);
-        if (j == 0) CHK(fill(c, c->pool, gr.bg_used));
-        else CHK(ckpt(c, gr, j, false, desc(gr, fz ? n0 : 0)));
-        for (int n = n0; n < n1; ++n) {
-            tstep(c, n);
-            const Slot* cur = desc(gr, fz ? n : 0);
-            CHK(stencil(c, gr, K_SEG_V, n, n - n0, 0, cur));
-            if (!fz) CHK(stencil(c, gr, K_SEG_P, n, n - n0, 0, cur));
+        if (!rcd || !gr.rc_valid) {
+            if (j == 0) CHK(fill(c, c->pool, gr.bg_used));
+            else CHK(ckpt(c, gr, j, false, desc(gr, fz ? n0 : 0)));
+            for (int n = n0; n < n1; ++n) {
+                tstep(c, n);
+                const Slot* cur = rcd ? rcd : desc(gr, fz ? n : 0);
+                CHK(stencil(c, gr, K_SEG_V, n, n - n0, 0, cur));
+                if (!fz) CHK(stencil(c, gr, K_SEG_P, n, n - n0, 0, cur));
+            }
         }
         // 2D: the adjoint velocity kernel of step n injects the data of step
         // n - 1 into the new adjoint pressure; 3D uses the injection kernel
@@ -608,7 +630,7 @@ lsrtm_status group_adjoint(lsrtm_ctx* c, Group& gr, const float* d) {
         for (int n = n1 - 1; n >= n0; --n) {
             tstep(c, n);
             if (n < nt - 1 && c->ndim == 3) CHK(inject(n));
-            const Slot* cur = desc(gr, apar(n));
+            const Slot* cur = rcd ? rcd : desc(gr, apar(n));
             CHK(stencil(c, gr, K_ADJ_A, n, n - n0, n == nt - 1 ? 1 : 0, cur, fz ? tr : none));
             if (!fz) CHK(stencil(c, gr, K_ADJ_B, n, n - n0, 0, cur, tr));
         }
@@ -678,7 +700,10 @@ lsrtm_status run_group_impl(lsrtm_ctx* c, Group& gr, int gi, int pass, float* d,
         HIPCHK(c, hipEventCreateWithFlags(&c->gin, hipEventDisableTiming));
         HIPCHK(c, hipEventCreateWithFlags(&c->gout, hipEventDisableTiming));
     }
-    const auto key = std::make_tuple(pass * 2 + (write_ck ? 1 : 0), gi, (const void*)d, c->tile);
+    // a migration pass that fills the replay cache and one that reads it are
+    // different graphs
+    const int rcv = pass == P_ADJ && gr.rc_valid ? 1 : 0;
+    const auto key = std::make_tuple((pass * 2 + (write_ck ? 1 : 0)) * 2 + rcv, gi, (const void*)d, c->tile);
     auto it = c->graphs.find(key);
     hipGraphExec_t exec = nullptr;
     if (it == c->graphs.end()) {
@@ -713,6 +738,8 @@ lsrtm_status run_group_impl(lsrtm_ctx* c, Group& gr, int gi, int pass, float* d,
 // for and reported on stderr.
 lsrtm_status run_group(lsrtm_ctx* c, Group& gr, int gi, int pass, float* d, bool write_ck) {
     CHK(run_group_impl(c, gr, gi, pass, d, write_ck));
+    // the pass just queued leaves the group's replays in the cache (stream order)
+    if (pass == P_ADJ && c->rc_m > 0) gr.rc_valid = true;
     if (c->opt_progress) {
         static const char* name[4] = {"forward", "Born", "background", "migration"};
         HIPCHK(c, hipStreamSynchronize(c->st));
@@ -784,7 +811,7 @@ lsrtm_status prep_model_windows(lsrtm_ctx* c) {
         }
     }
     HIPCHK(c, hipStreamSynchronize(c->st));
-    c->ckpt_valid = false;
+    background_changed(c);
     return LSRTM_OK;
 }
 
@@ -980,6 +1007,18 @@ lsrtm_status plan(lsrtm_ctx* c) {
     }
     CHK(dalloc_t(c, &c->pool, c->bg_region + c->sc_region + c->img_region, true));
     CHK(dalloc_t(c, &c->segbuf, seg_floats, true));
+    // Replay cache: the replays of the last rc_m segments of every group are
+    // kept across migration passes in HBM the budget leaves over (they depend
+    // on the background only, like the checkpoints).  Two-phase steps with
+    // checkpoints held for the whole plan only.
+    long long rc_seg = 0;          // floats of one cached segment over all groups
+    for (auto& gr : c->groups) rc_seg += (long long)c->k * (nd + 1) * (gr.bg_used / nbg);
+    if (c->opt_rcache_mb > 0 && !c->fused && !c->ck_group && rc_seg > 0) {
+        const long long cap = std::min(c->opt_rcache_mb * 1024LL * 1024LL, budget - need);
+        c->rc_m = (int)std::max(0LL, std::min((long long)c->nseg, cap / (rc_seg * 4)));
+        if (c->rc_m > 0) CHK(dalloc_t(c, &c->rcache, (size_t)c->rc_m * rc_seg, true));
+        c->plan_bytes += (long long)c->rc_m * rc_seg * 4;
+    }
     const long long ck_total = c->ck_group ? (long long)(c->nseg - 1) * G * max_ck : (long long)(c->nseg - 1) * ck_per_shot_sum;
     CHK(dalloc(c, reinterpret_cast<void**>(&c->ckbuf), (size_t)std::max(1LL, ck_total), true));
     CHK(dalloc_t(c, &c->ckscales, (size_t)c->nseg * nshot * (1 + nd), true));
@@ -1007,6 +1046,7 @@ lsrtm_status plan(lsrtm_ctx* c) {
         }
     }
     // descriptors, receivers
+    long long rc_base = 0;         // floats of the replay cache taken by earlier groups
     for (auto& gr : c->groups) {
         long long obg = 0, osc = 0, oimg = 0, oseg = 0;
         float* bgb = c->pool;
@@ -1095,6 +1135,21 @@ lsrtm_status plan(lsrtm_ctx* c) {
         }
         CHK(dalloc_t(c, &gr.d_slots, gr.ns, true));
         HIPCHK(c, hipMemcpy(gr.d_slots, gr.h_slots.data(), gr.ns * sizeof(Slot), hipMemcpyHostToDevice));
+        if (c->rc_m > 0) {
+            // cached segment m of this group: its slots' replay buffers at the
+            // offsets they have in segbuf, inside block m of the group's range
+            const long long gseg = (long long)c->k * (nd + 1) * (gr.bg_used / nbg);
+            std::vector<Slot> rc;
+            for (int m = 0; m < c->rc_m; ++m)
+                for (const Slot& S0 : gr.h_slots) {
+                    Slot S = S0;
+                    S.seg = c->rcache + rc_base + m * gseg + (S0.seg - c->segbuf);
+                    rc.push_back(S);
+                }
+            CHK(dalloc_t(c, &gr.d_rc, rc.size(), true));
+            HIPCHK(c, hipMemcpy(gr.d_rc, rc.data(), rc.size() * sizeof(Slot), hipMemcpyHostToDevice));
+            rc_base += (long long)c->rc_m * gseg;
+        }
         if (c->fused) {
             std::vector<Slot> alt = gr.h_slots;
             for (Slot& S : alt) {
@@ -1480,6 +1535,12 @@ lsrtm_status lsrtm_set_option(lsrtm_ctx* c, int key, long long v) {
         clear_graphs(c);
         return LSRTM_OK;
     }
+    case LSRTM_OPT_REPLAY_CACHE_MB:
+        if (v < 0) FAIL(c, LSRTM_EINVAL, "replay cache size must be >= 0");
+        if (c->opt_rcache_mb == v) return LSRTM_OK;
+        c->opt_rcache_mb = v;
+        if (c->have_acq) return plan(c);
+        return LSRTM_OK;
     case LSRTM_OPT_CKPT_PER_GROUP:
         if (c->opt_ckg == (v != 0)) return LSRTM_OK;
         c->opt_ckg = v != 0;
@@ -1533,7 +1594,7 @@ lsrtm_status lsrtm_set_model(lsrtm_ctx* c, const float* lnvp, const float* lnip)
     c->vmax = vmax;
     c->have_model = true;
     if (c->have_acq) CHK(prep_model_windows(c));
-    c->ckpt_valid = false;
+    background_changed(c);
     return LSRTM_OK;
 }
 
@@ -1573,15 +1634,15 @@ lsrtm_status lsrtm_autotune(lsrtm_ctx* c, int nsteps, int tune_groups, double* o
     if (nsteps < 1) FAIL(c, LSRTM_EINVAL, "nsteps must be >= 1");
     c->opt_tile = -1;
     CHK(autotune(c, nsteps, tune_groups != 0, out));
-    c->ckpt_valid = false;
+    background_changed(c);
     return LSRTM_OK;
 }
 
 lsrtm_status lsrtm_sizes(lsrtm_ctx* c, long long* out, int nout) {
     if (!c || !out) return LSRTM_EINVAL;
-    long long v[12] = {c->data_len, c->gpts, c->G, c->k, (long long)c->groups.size(), c->padded_total, c->plan_bytes,
-                       c->tile, c->ck_group ? 1 : 0, c->fused ? 1 : 0, c->opt_tile_v, c->opt_tile_a};
-    for (int i = 0; i < nout && i < 12; ++i) out[i] = v[i];
+    long long v[13] = {c->data_len, c->gpts, c->G, c->k, (long long)c->groups.size(), c->padded_total, c->plan_bytes,
+                       c->tile, c->ck_group ? 1 : 0, c->fused ? 1 : 0, c->opt_tile_v, c->opt_tile_a, c->rc_m};
+    for (int i = 0; i < nout && i < 13; ++i) out[i] = v[i];
     return LSRTM_OK;
 }
 

@@ -31,7 +31,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "lsrtm.h")
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
 CKPT = {"f32": 0, "f16": 1, "bf16": 2}
 OPT_SHOTS_PER_LAUNCH, OPT_TILE, OPT_GRAPH, OPT_TIMING, OPT_MEM_BUDGET_MB, OPT_CKPT_PER_GROUP, OPT_FUSED, \
-    OPT_PROGRESS, OPT_TILE_V, OPT_TILE_ADJ_A = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
+    OPT_PROGRESS, OPT_TILE_V, OPT_TILE_ADJ_A, OPT_REPLAY_CACHE_MB = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
 NKERNEL = 8
 KERNEL_NAMES = ("born_v", "born_p", "bg_v", "bg_p", "adj_a", "adj_b", "ckpt", "rec")
 
@@ -122,13 +122,16 @@ class Context:
     parameters pml_R and pml_f0, checkpoint interval (0 = planner) and
     checkpoint storage ("f32", "f16", "bf16").  tile_v and tile_adj_a give
     the velocity phases and the adjoint A phase tile shapes of their own
-    (-1 = the stencil tile); results do not depend on them.
+    (-1 = the stencil tile); results do not depend on them.  replay_cache_mb
+    lets the plan keep the background replays of the last checkpoint segments
+    across migration passes (LSRTM_OPT_REPLAY_CACHE_MB; bitwise the same
+    results, 0 = off).
     """
 
     def __init__(self, n, h, nt, dt, npml=20, pml_R=1e-4, pml_f0=10.0, ckpt_every=0,
                  ckpt_dtype="f32", stream=None, shots_per_launch=0, tile=-1, graph=True,
                  timing=False, mem_budget_mb=0, ckpt_per_group=False, fused=False, progress=False,
-                 tile_v=-1, tile_adj_a=-1):
+                 tile_v=-1, tile_adj_a=-1, replay_cache_mb=0):
         import torch
         L = lib()
         self._torch = torch
@@ -160,6 +163,7 @@ class Context:
         self.set_option(OPT_PROGRESS, int(bool(progress)))
         self.set_option(OPT_TILE_V, tile_v)
         self.set_option(OPT_TILE_ADJ_A, tile_adj_a)
+        self.set_option(OPT_REPLAY_CACHE_MB, replay_cache_mb)
         self.nrec: List[int] = []
         self._keep = []
 
@@ -239,10 +243,11 @@ class Context:
                 "tile_v": int(out[3]), "tile_adj_a": int(out[4])}
 
     def sizes(self):
-        out = (_c_ll * 12)()
-        self._check(lib().lsrtm_sizes(self._h, out, 12), "sizes")
+        out = (_c_ll * 13)()
+        self._check(lib().lsrtm_sizes(self._h, out, 13), "sizes")
         keys = ("data_len", "grid_points", "shots_per_launch", "ckpt_every", "groups",
-                "padded_points", "plan_bytes", "tile", "ckpt_per_group", "fused", "tile_v", "tile_adj_a")
+                "padded_points", "plan_bytes", "tile", "ckpt_per_group", "fused", "tile_v", "tile_adj_a",
+                "replay_cache_segments")
         return dict(zip(keys, [int(x) for x in out]))
 
     @property
