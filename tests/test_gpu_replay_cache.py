@@ -4,8 +4,8 @@ passes.  They depend on the background model and the acquisition only
 (appendix A: the history the adjoint reads is the background's), so every
 result must be bitwise that of a plan without the cache: on the pass that
 fills the cache, on the passes that read it, with and without graphs, with
-one or several launch groups, with a partial last segment, in CGNR, and
-after the model changes (the cache is refilled).
+one or several launch groups, with a partial last segment, in CGNR, after
+the model changes (the cache is refilled), in 3D and with a single segment.
 """
 import dataclasses
 import math
@@ -119,3 +119,24 @@ def test_replay_cache_off_where_not_planned(torch):
             ctx.set_option(lsrtm.OPT_REPLAY_CACHE_MB, -1)
         finally:
             ctx.close()
+
+
+@pytest.mark.parametrize("case", ["3d", "one_segment"])
+def test_replay_cache_3d_and_single_segment(torch, case):
+    """A 3D plan (injection kernels of their own) and a plan whose only
+    segment starts from rest (no checkpoint to restore)."""
+    from paper_2508_10405_amd import lsrtm
+    if case == "3d":
+        w, k = synth.small((14, 18, 12), nt=40, npml=3, seed=36, nshot=2, uneven=True), 7
+    else:
+        w, k = _w(nt=60), 100
+    print(f"[case] replay cache {case}", flush=True)
+    ref = lsrtm.context_for(w, ckpt_every=k)
+    y = to_dev(torch, np.random.default_rng(6).standard_normal(ref.data_len))
+    ref_i = ref.adjoint(y).cpu().numpy()
+    ref.close()
+    ctx = lsrtm.context_for(w, ckpt_every=k, replay_cache_mb=1 << 20)
+    assert ctx.sizes()["replay_cache_segments"] == math.ceil(w.nt / k)
+    for rep in range(3):
+        assert np.array_equal(ctx.adjoint(y).cpu().numpy(), ref_i), rep
+    ctx.close()
