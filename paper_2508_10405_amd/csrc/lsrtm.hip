@@ -15,7 +15,10 @@
 //             are added in shot order into an FP64 accumulator and mapped to
 //             (lnVp, lnIp) by the chain rule of section 3.
 // Checkpoints do not depend on the perturbation, so they are stored once per
-// model and acquisition and reused by every later pass.
+// model and acquisition and reused by every later pass; for the same reason
+// the replays of the last segments of every launch group may be kept in HBM
+// the memory plan leaves over (the replay cache) and read by every later
+// migration pass instead of being recomputed.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
