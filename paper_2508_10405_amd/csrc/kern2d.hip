@@ -23,6 +23,10 @@
 //   P : p <- p - dt kappa q, q = sum_a (D_a v_a + phi_a), plus the source.
 //       BORN adds the scattered pressure with the bulk-modulus source
 //       dlnkappa (-dt kappa q); SEG stores q for migration.
+//   BORN and SEG together: the scattered V and P phases alone, the background
+//       G_a p + psi_a and q of the step read from a replay buffer that a
+//       migration pass filled (they are what the background phases would
+//       compute, bit for bit); the background fields are not touched.
 //   A : adjoint pressure phase (transpose of P), imaging of lnkappa.
 //   B : adjoint velocity phase (transpose of V), imaging of lnrho.
 // The adjoint CPML memories are advanced in the phase that does not read them
@@ -69,10 +73,14 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
-    constexpr int K = BORN ? 2 : 1;
+    // BORN && SEG: the scattered phase alone on a background read from the
+    // replay cache (the stored G_a p + psi_a of this step); the background
+    // fields are neither read nor written
+    constexpr bool CB = BORN && SEG;
+    constexpr int K = BORN && !CB ? 2 : 1;
     using RZ = Cells<0, T::LZ, HW, BX>;                    // interior columns with the z-halo
     using RX = Cells<HW, BZ, 0, 2 * HW, 0, 0, HW, BX>;     // both x-halo strips
-    __shared__ float sp[T::NL];
+    __shared__ float sp[CB ? 1 : T::NL];
     __shared__ float sq[BORN ? T::NL : 1];
     const int tix = xcd_remap(blockIdx.x, gridDim.x);
     const int4 tl = tiles[tix];
@@ -86,6 +94,7 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const gfloat* achx = S.cpml[1];
     const gfloat* bchx = S.cpml[1] + nx;
     const bool pml = tile_in_pml<BZ, BX>(z0, x0, nz, nx, npml);
+    gfloat* __restrict__ seg = S.seg + (long long)sstep * 3 * S.npts;
     // pointwise loads, CPML coefficients and (inside the strips) memories
     float vz[R], vx[R], s0[R], s1z[R], s1x[R], wz[R], wx[R], r0[R], r1z[R], r1x[R];
     float az[R], ax[R], cz[R], cx[R], m0[R], m1[R], n0[R], n1[R];
@@ -99,8 +108,8 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const long long i = ok[r] ? gx * ldz + gz : 0;
         const long long iz = ok[r] && in_pml(gz, nz, npml) ? i : 0;
         const long long ix = ok[r] && in_pml(gx, nx, npml) ? i : 0;
-        vz[r] = S.v[0][i];
-        vx[r] = S.v[1][i];
+        vz[r] = CB ? seg[i] : S.v[0][i];            // cached: G_z p + psi_z
+        vx[r] = CB ? seg[S.npts + i] : S.v[1][i];   // cached: G_x p + psi_x
         s0[r] = S.sb[i];   // dt b_a = sb at the node times sb at its upper neighbour
         s1z[r] = S.sb[gz + 1 < nz ? i + 1 : i];
         s1x[r] = S.sb[gx + 1 < nx ? i + ldz : i];
@@ -108,8 +117,8 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         ax[r] = pml ? achx[ok[r] ? gx : 0] : 0.f;
         cz[r] = pml ? bchz[ok[r] ? gz : 0] : 0.f;
         cx[r] = pml ? bchx[ok[r] ? gx : 0] : 0.f;
-        m0[r] = pml ? S.psi[0][iz] : 0.f;
-        m1[r] = pml ? S.psi[1][ix] : 0.f;
+        m0[r] = pml && !CB ? S.psi[0][iz] : 0.f;
+        m1[r] = pml && !CB ? S.psi[1][ix] : 0.f;
         if (BORN) {
             n0[r] = pml ? S.xi[0][iz] : 0.f;
             n1[r] = pml ? S.xi[1][ix] : 0.f;
@@ -126,14 +135,22 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     };
     auto ld = [&](int lz, int lx, float* v) {
         const long long i = inside(lz, lx) ? (x0 + lx - HW) * ldz + (z0 + lz - HW) : 0;
-        v[0] = S.p[i];
-        if (BORN) v[1] = S.q[i];
+        if (CB) {
+            v[0] = S.q[i];
+        } else {
+            v[0] = S.p[i];
+            if (BORN) v[1] = S.q[i];
+        }
     };
     auto st = [&](int lz, int lx, const float* v) {
         const int c = lx * T::LZ + lz;
         const bool in = inside(lz, lx);
-        sp[c] = in ? v[0] : 0.f;
-        if (BORN) sq[c] = in ? v[1] : 0.f;
+        if (CB) {
+            sq[c] = in ? v[0] : 0.f;
+        } else {
+            sp[c] = in ? v[0] : 0.f;
+            if (BORN) sq[c] = in ? v[1] : 0.f;
+        }
     };
     float hz[RZ::IT][K], hx[RX::IT][K];
     RZ::load(ld, hz);
@@ -141,7 +158,6 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     RZ::store(st, hz);
     RX::store(st, hx);
     __syncthreads();
-    gfloat* __restrict__ seg = S.seg + (long long)sstep * 3 * S.npts;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (!ok[r]) continue;
@@ -150,24 +166,29 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const int gz = z0 + lz, gx = x0 + lx;
         const long long i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
-        float gzp = d_half(sp, c, 1, C.c[0]);
-        float gxp = d_half(sp, c, T::LZ, C.c[1]);
-        if (az[r] != 0.f) {
-            const float ps = fmaf(cz[r], m0[r], az[r] * gzp);
-            S.psi[0][i] = ps;
-            gzp = gzp + ps;
-        }
-        if (ax[r] != 0.f) {
-            const float ps = fmaf(cx[r], m1[r], ax[r] * gxp);
-            S.psi[1][i] = ps;
-            gxp = gxp + ps;
+        float gzp = vz[r], gxp = vx[r];
+        if (!CB) {
+            gzp = d_half(sp, c, 1, C.c[0]);
+            gxp = d_half(sp, c, T::LZ, C.c[1]);
+            if (az[r] != 0.f) {
+                const float ps = fmaf(cz[r], m0[r], az[r] * gzp);
+                S.psi[0][i] = ps;
+                gzp = gzp + ps;
+            }
+            if (ax[r] != 0.f) {
+                const float ps = fmaf(cx[r], m1[r], ax[r] * gxp);
+                S.psi[1][i] = ps;
+                gxp = gxp + ps;
+            }
         }
         const float bz = s0[r] * s1z[r], bx = s0[r] * s1x[r];
         const float dvz = -bz * gzp;
         const float dvx = -bx * gxp;
-        S.v[0][i] = vz[r] + dvz;
-        S.v[1][i] = vx[r] + dvx;
-        if (SEG) {
+        if (!CB) {
+            S.v[0][i] = vz[r] + dvz;
+            S.v[1][i] = vx[r] + dvx;
+        }
+        if (SEG && !BORN) {
             // the replay buffer is read back only k steps later: streaming stores
             __builtin_nontemporal_store(gzp, &seg[i]);
             __builtin_nontemporal_store(gxp, &seg[S.npts + i]);
@@ -206,11 +227,14 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
 {
     using T = Tile2<BZ, BX>;
     constexpr int R = T::R;
-    constexpr int K = BORN ? 2 : 1;
+    // BORN && SEG: the scattered phase alone, q of this step read from the
+    // replay cache; the background fields are neither read nor written
+    constexpr bool CB = BORN && SEG;
+    constexpr int K = BORN && !CB ? 2 : 1;
     using RZ = Cells<0, T::LZ, HW, BX>;   // v_z (and w_z) with the z-halo
     using RX = Cells<HW, BZ, 0, T::LX>;   // v_x (and w_x) with the x-halo
-    __shared__ float svz[T::NL];
-    __shared__ float svx[T::NL];
+    __shared__ float svz[CB ? 1 : T::NL];
+    __shared__ float svx[CB ? 1 : T::NL];
     __shared__ float swz[BORN ? T::NL : 1];
     __shared__ float swx[BORN ? T::NL : 1];
     const int tix = xcd_remap(blockIdx.x, gridDim.x);
@@ -225,6 +249,7 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const gfloat* acix = S.cpml[1] + 2 * nx;
     const gfloat* bcix = S.cpml[1] + 3 * nx;
     const bool pml = tile_in_pml<BZ, BX>(z0, x0, nz, nx, npml);
+    gfloat* __restrict__ seg = S.seg + (long long)sstep * 3 * S.npts + 2 * S.npts;
     // pointwise loads, CPML coefficients and (inside the strips) memories
     float pp[R], kk[R], qq[R], lk[R], az[R], ax[R], cz[R], cx[R], m0[R], m1[R], n0[R], n1[R];
     bool ok[R];
@@ -237,14 +262,14 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const long long i = ok[r] ? gx * ldz + gz : 0;
         const long long iz = ok[r] && in_pml(gz, nz, npml) ? i : 0;
         const long long ix = ok[r] && in_pml(gx, nx, npml) ? i : 0;
-        pp[r] = S.p[i];
+        pp[r] = CB ? seg[i] : S.p[i];   // cached: q
         kk[r] = S.kdt[i];
         az[r] = pml ? aciz[ok[r] ? gz : 0] : 0.f;
         ax[r] = pml ? acix[ok[r] ? gx : 0] : 0.f;
         cz[r] = pml ? bciz[ok[r] ? gz : 0] : 0.f;
         cx[r] = pml ? bcix[ok[r] ? gx : 0] : 0.f;
-        m0[r] = pml ? S.phi[0][iz] : 0.f;
-        m1[r] = pml ? S.phi[1][ix] : 0.f;
+        m0[r] = pml && !CB ? S.phi[0][iz] : 0.f;
+        m1[r] = pml && !CB ? S.phi[1][ix] : 0.f;
         if (BORN) {
             qq[r] = S.q[i];
             lk[r] = S.dlnk[i];
@@ -260,25 +285,41 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     };
     auto ldz_ = [&](int lz, int lx, float* v) {
         const long long i = index(lz, lx);
-        v[0] = S.v[0][i];
-        if (BORN) v[1] = S.w[0][i];
+        if (CB) {
+            v[0] = S.w[0][i];
+        } else {
+            v[0] = S.v[0][i];
+            if (BORN) v[1] = S.w[0][i];
+        }
     };
     auto ldx_ = [&](int lz, int lx, float* v) {
         const long long i = index(lz, lx);
-        v[0] = S.v[1][i];
-        if (BORN) v[1] = S.w[1][i];
+        if (CB) {
+            v[0] = S.w[1][i];
+        } else {
+            v[0] = S.v[1][i];
+            if (BORN) v[1] = S.w[1][i];
+        }
     };
     auto stz_ = [&](int lz, int lx, const float* v) {
         const int c = lx * T::LZ + lz;
         const bool in = inside(lz, lx);
-        svz[c] = in ? v[0] : 0.f;
-        if (BORN) swz[c] = in ? v[1] : 0.f;
+        if (CB) {
+            swz[c] = in ? v[0] : 0.f;
+        } else {
+            svz[c] = in ? v[0] : 0.f;
+            if (BORN) swz[c] = in ? v[1] : 0.f;
+        }
     };
     auto stx_ = [&](int lz, int lx, const float* v) {
         const int c = lx * T::LZ + lz;
         const bool in = inside(lz, lx);
-        svx[c] = in ? v[0] : 0.f;
-        if (BORN) swx[c] = in ? v[1] : 0.f;
+        if (CB) {
+            swx[c] = in ? v[0] : 0.f;
+        } else {
+            svx[c] = in ? v[0] : 0.f;
+            if (BORN) swx[c] = in ? v[1] : 0.f;
+        }
     };
     float hz[RZ::IT][K], hx[RX::IT][K];
     RZ::load(ldz_, hz);
@@ -287,7 +328,6 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     RX::store(stx_, hx);
     const float amp = S.src >= 0 ? S.src_amp[n] : 0.f;
     __syncthreads();
-    gfloat* __restrict__ seg = S.seg + (long long)sstep * 3 * S.npts + 2 * S.npts;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (!ok[r]) continue;
@@ -296,26 +336,29 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const int gz = z0 + lz, gx = x0 + lx;
         const long long i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
-        float ez = d_node(svz, c, 1, C.c[0]);
-        float ex = d_node(svx, c, T::LZ, C.c[1]);
-        if (az[r] != 0.f) {
-            const float ph = fmaf(cz[r], m0[r], az[r] * ez);
-            S.phi[0][i] = ph;
-            ez = ez + ph;
-        }
-        if (ax[r] != 0.f) {
-            const float ph = fmaf(cx[r], m1[r], ax[r] * ex);
-            S.phi[1][i] = ph;
-            ex = ex + ph;
-        }
-        const float q = ez + ex;
+        float q = pp[r];
         const float k = kk[r];
-        float pn = pp[r] - k * q;
-        if (i == S.src) pn = pn + amp;
-        S.p[i] = pn;
-        if (SEG) __builtin_nontemporal_store(q, &seg[i]);
-        if (!BORN && !SEG && (flag & PH_ACCUMULATE)) S.gk[i] = S.gk[i] + q * q;   // pseudo-Hessian: sum of q^2
-        if (!BORN && tr.d) tile_gather(tr, tix, lz + BZ * lx, n, pn);
+        if (!CB) {
+            float ez = d_node(svz, c, 1, C.c[0]);
+            float ex = d_node(svx, c, T::LZ, C.c[1]);
+            if (az[r] != 0.f) {
+                const float ph = fmaf(cz[r], m0[r], az[r] * ez);
+                S.phi[0][i] = ph;
+                ez = ez + ph;
+            }
+            if (ax[r] != 0.f) {
+                const float ph = fmaf(cx[r], m1[r], ax[r] * ex);
+                S.phi[1][i] = ph;
+                ex = ex + ph;
+            }
+            q = ez + ex;
+            float pn = pp[r] - k * q;
+            if (i == S.src) pn = pn + amp;
+            S.p[i] = pn;
+            if (SEG) __builtin_nontemporal_store(q, &seg[i]);
+            if (!BORN && !SEG && (flag & PH_ACCUMULATE)) S.gk[i] = S.gk[i] + q * q;   // pseudo-Hessian: sum of q^2
+            if (!BORN && tr.d) tile_gather(tr, tix, lz + BZ * lx, n, pn);
+        }
         if (BORN) {
             float fz = d_node(swz, c, 1, C.c[0]);
             float fx = d_node(swx, c, T::LZ, C.c[1]);
@@ -635,6 +678,8 @@ static hipError_t launch2_t(int kind, int ntiles, hipStream_t st, const Slot* sl
     case K_SEG_P:   launch_k(k2_p<BZ, BX, false, true>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag, tr); break;
     case K_BORN_V:  launch_k(k2_v<BZ, BX, true, false>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag, tr); break;
     case K_BORN_P:  launch_k(k2_p<BZ, BX, true, false>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag, tr); break;
+    case K_BORN_V_RC: launch_k(k2_v<BZ, BX, true, true>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag, tr); break;
+    case K_BORN_P_RC: launch_k(k2_p<BZ, BX, true, true>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag, tr); break;
     case K_ADJ_A:   launch_k(k2_a<BZ, BX>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag, tr); break;
     case K_ADJ_B:   launch_k(k2_b<BZ, BX>, g, b, st, e0, e1, ds, tiles, C, n, sstep, flag, tr); break;
     default: return hipErrorInvalidValue;

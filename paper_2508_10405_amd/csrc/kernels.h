@@ -14,7 +14,9 @@ enum Kind {
     K_BORN_V = 4,  // background + scattered velocity phase
     K_BORN_P = 5,  // background + scattered pressure phase
     K_ADJ_A = 6,   // adjoint pressure phase + lnkappa imaging
-    K_ADJ_B = 7    // adjoint velocity phase + lnrho imaging
+    K_ADJ_B = 7,   // adjoint velocity phase + lnrho imaging
+    K_BORN_V_RC = 8,   // 2D scattered velocity phase on a background read from the replay cache
+    K_BORN_P_RC = 9    // 2D scattered pressure phase on a background read from the replay cache
 };
 
 extern const int kTiles2[][2];

@@ -493,8 +493,11 @@ const Slot* desc(const Group& gr, int par) { return ((par & 1) && gr.d_alt) ? gr
 lsrtm_status stencil(lsrtm_ctx* c, Group& gr, int kind, int n, int sstep, int flag, const Slot* sl,
                      TileRec tr = TileRec{nullptr, nullptr, nullptr, nullptr}) {
     static const int cls_of[8] = {2, 3, 2, 3, 0, 1, 4, 5};
-    // a sampled launch carries its own start / end events
-    EvPair* ev = tpick(c, cls_of[kind]);
+    // a sampled launch carries its own start / end events; the Born phases on
+    // a cached background move fewer bytes and are not sampled, so that the
+    // per-kernel figures stay those of one kernel
+    const bool rc = kind == K_BORN_V_RC || kind == K_BORN_P_RC;
+    EvPair* ev = rc ? nullptr : tpick(c, cls_of[kind]);
     hipEvent_t e0 = ev ? ev->a : nullptr, e1 = ev ? ev->b : nullptr;
     hipError_t e;
     if (c->fused) e = launch2f(kind, c->tile, gr.ntiles, c->st, sl, gr.d_tiles, c->C, n, sstep, flag, tr, e0, e1);
@@ -502,7 +505,7 @@ lsrtm_status stencil(lsrtm_ctx* c, Group& gr, int kind, int n, int sstep, int fl
         // the velocity phases and the adjoint A phase touch no receivers (in
         // 3D none of the phases does; the 2D P and B phases use the stencil
         // tile's receiver lists) and may walk a table of their own tile shape
-        const bool vph = kind == K_BG_V || kind == K_SEG_V || kind == K_BORN_V;
+        const bool vph = kind == K_BG_V || kind == K_SEG_V || kind == K_BORN_V || kind == K_BORN_V_RC;
         const int want = vph ? c->opt_tile_v : kind == K_ADJ_A ? c->opt_tile_a : -1;
         int tile = c->tile, nt = gr.ntiles;
         const int4* tab = gr.d_tiles;
@@ -569,18 +572,26 @@ lsrtm_status group_forward(lsrtm_ctx* c, Group& gr, int mode, float* d, bool wri
     CHK(build_tiles(c, gr, c->tile));
     CHK(fill(c, c->pool, gr.bg_used));
     if (mode == 1) CHK(fill(c, c->pool + c->bg_region, gr.sc_used));
-    const int kv = mode == 1 ? K_BORN_V : K_BG_V;
-    const int kp = mode == 1 ? K_BORN_P : K_BG_P;
     const bool fz = c->fused;
+    // 2D Born steps inside the segments whose replays the cache holds read
+    // the background from there instead of advancing it (nothing after them
+    // needs the background state)
+    const int jc = c->nseg - c->rc_m;
+    const bool use_rc = mode == 1 && !write_ck && c->rc_m > 0 && gr.rc_valid && c->ndim == 2 && !fz;
     for (int n = 0; n < c->g.nt; ++n) {
         tstep(c, n);
-        const Slot* cur = desc(gr, fz ? n : 0);
+        const int j = n / c->k;
+        const bool rcs = use_rc && j >= jc;
+        const Slot* cur = rcs ? gr.d_rc + (long long)(j - jc) * gr.ns : desc(gr, fz ? n : 0);
         if (write_ck && n > 0 && n % c->k == 0) CHK(ckpt(c, gr, n / c->k, true, cur));
+        const int kv = rcs ? K_BORN_V_RC : mode == 1 ? K_BORN_V : K_BG_V;
+        const int kp = rcs ? K_BORN_P_RC : mode == 1 ? K_BORN_P : K_BG_P;
+        const int sstep = rcs ? n - j * c->k : 0;
         // 2D kernels record the receivers themselves
         const TileRec tr{gr.d_trp, gr.d_trec, mode != 2 ? d : nullptr, nullptr};
         const TileRec none{nullptr, nullptr, nullptr, nullptr};
-        CHK(stencil(c, gr, kv, n, 0, 0, cur, fz ? tr : none));
-        if (!fz) CHK(stencil(c, gr, kp, n, 0, 0, cur, tr));
+        CHK(stencil(c, gr, kv, n, sstep, 0, cur, fz ? tr : none));
+        if (!fz) CHK(stencil(c, gr, kp, n, sstep, 0, cur, tr));
         if (mode != 2 && c->ndim == 3) {
             tbeg(c, 7);
             hipError_t e = launch_gather(desc(gr, fz ? n + 1 : 0), gr.d_rec, gr.nrec, n, mode == 1, d, c->st);
@@ -704,8 +715,8 @@ lsrtm_status run_group_impl(lsrtm_ctx* c, Group& gr, int gi, int pass, float* d,
         HIPCHK(c, hipEventCreateWithFlags(&c->gout, hipEventDisableTiming));
     }
     // a migration pass that fills the replay cache and one that reads it are
-    // different graphs
-    const int rcv = pass == P_ADJ && gr.rc_valid ? 1 : 0;
+    // different graphs, and so are Born passes with and without it
+    const int rcv = (pass == P_ADJ || pass == P_BORN) && gr.rc_valid ? 1 : 0;
     const auto key = std::make_tuple((pass * 2 + (write_ck ? 1 : 0)) * 2 + rcv, gi, (const void*)d, c->tile);
     auto it = c->graphs.find(key);
     hipGraphExec_t exec = nullptr;

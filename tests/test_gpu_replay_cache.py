@@ -1,6 +1,7 @@
 """Replay cache (LSRTM_OPT_REPLAY_CACHE_MB): the background replays of the
 last checkpoint segments of every launch group are kept across migration
-passes.  They depend on the background model and the acquisition only
+passes, and 2D Born passes read the background of those segments from them
+instead of advancing it.  They depend on the background model and the acquisition only
 (appendix A: the history the adjoint reads is the background's), so every
 result must be bitwise that of a plan without the cache: on the pass that
 fills the cache, on the passes that read it, with and without graphs, with
@@ -83,12 +84,16 @@ def test_replay_cache_refilled_after_model_change(torch):
     y = to_dev(torch, np.random.default_rng(5).standard_normal(ctx.data_len))
     ctx.adjoint(y)
     ctx.adjoint(y)
+    ctx.born(to_dev(torch, w.dm))
     ctx.set_model(to_dev(torch, w2.lnvp), to_dev(torch, w2.lnip))
+    d = ctx.born(to_dev(torch, w.dm)).cpu().numpy()
     img = ctx.adjoint(y).cpu().numpy()
+    d2 = ctx.born(to_dev(torch, w.dm)).cpu().numpy()
     ctx.close()
     w3 = dataclasses.replace(w, lnvp=w2.lnvp, lnip=w2.lnip)
-    _, ref = _ref(torch, w3, y)
+    ref_d, ref = _ref(torch, w3, y)
     assert np.array_equal(img, ref)
+    assert np.array_equal(d, ref_d) and np.array_equal(d2, ref_d)
 
 
 def test_replay_cache_cgnr_bitwise(torch):
@@ -131,12 +136,15 @@ def test_replay_cache_3d_and_single_segment(torch, case):
     else:
         w, k = _w(nt=60), 100
     print(f"[case] replay cache {case}", flush=True)
+    dm = to_dev(torch, w.dm)
     ref = lsrtm.context_for(w, ckpt_every=k)
     y = to_dev(torch, np.random.default_rng(6).standard_normal(ref.data_len))
     ref_i = ref.adjoint(y).cpu().numpy()
+    ref_d = ref.born(dm).cpu().numpy()
     ref.close()
     ctx = lsrtm.context_for(w, ckpt_every=k, replay_cache_mb=1 << 20)
     assert ctx.sizes()["replay_cache_segments"] == math.ceil(w.nt / k)
     for rep in range(3):
         assert np.array_equal(ctx.adjoint(y).cpu().numpy(), ref_i), rep
+        assert np.array_equal(ctx.born(dm).cpu().numpy(), ref_d), rep
     ctx.close()
