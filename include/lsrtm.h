@@ -118,8 +118,10 @@ enum {
                                        the data), capped by what the memory
                                        budget leaves; the first migration pass
                                        fills it, later ones skip the replay of
-                                       those segments.  Results are bitwise the
-                                       same.  Two-phase steps with checkpoints
+                                       those segments, and later 2D Born passes
+                                       run only the scattered phases there,
+                                       reading the background from it.  Results
+                                       are bitwise the same.  Two-phase steps with checkpoints
                                        for the whole plan only; 0 = off
                                        (default).  Re-plans when changed.       */
 };
