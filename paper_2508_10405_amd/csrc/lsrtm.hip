@@ -18,7 +18,8 @@
 // model and acquisition and reused by every later pass; for the same reason
 // the replays of the last segments of every launch group may be kept in HBM
 // the memory plan leaves over (the replay cache) and read by every later
-// migration pass instead of being recomputed.
+// migration pass instead of being recomputed, and by every later 2D Born pass
+// in place of the background steps of those segments.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -1022,9 +1023,10 @@ lsrtm_status plan(lsrtm_ctx* c) {
     CHK(dalloc_t(c, &c->pool, c->bg_region + c->sc_region + c->img_region, true));
     CHK(dalloc_t(c, &c->segbuf, seg_floats, true));
     // Replay cache: the replays of the last rc_m segments of every group are
-    // kept across migration passes in HBM the budget leaves over (they depend
-    // on the background only, like the checkpoints).  Two-phase steps with
-    // checkpoints held for the whole plan only.
+    // kept across passes in HBM the budget leaves over (they depend on the
+    // background only, like the checkpoints) and read by later migration and
+    // 2D Born passes.  Two-phase steps with checkpoints held for the whole
+    // plan only.
     long long rc_seg = 0;          // floats of one cached segment over all groups
     for (auto& gr : c->groups) rc_seg += (long long)c->k * (nd + 1) * (gr.bg_used / nbg);
     if (c->opt_rcache_mb > 0 && !c->fused && !c->ck_group && rc_seg > 0) {
