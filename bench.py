@@ -350,6 +350,24 @@ def main():
     del ctx, d_obs, x
     torch.cuda.empty_cache()
 
+    # the same batched plan without the replay cache: one CG iteration after a
+    # Born pass and the initial migration (checkpoints reused as above)
+    no_cache = None
+    if sz["replay_cache_segments"] > 0:
+        cn = lsrtm.context_for(w, shots_per_launch=sz["shots_per_launch"], tile=sz["tile"],
+                               tile_v=sz["tile_v"], tile_adj_a=sz["tile_adj_a"], ckpt_dtype=ckdt, timing=True)
+        dn = cn.born(dm)
+        xn = cn.cgnr_begin(dn)
+        torch.cuda.synchronize()
+        tn0 = time.perf_counter()
+        cn.cgnr_iterate(xn)
+        torch.cuda.synchronize()
+        no_cache = time.perf_counter() - tn0
+        log(f"[bench] CG iteration without the replay cache: {no_cache:.2f} s")
+        cn.close()
+        del cn, dn, xn
+        torch.cuda.empty_cache()
+
     # plain per-shot form on a sample of shots
     plain = None
     if args.plain_shots > 0 and nd == 2:
@@ -429,6 +447,7 @@ def main():
         "cpu_baseline": cpu,
         "cg_iter_s_batched": sec,
         "cg_iter_s_plain": plain,
+        "cg_iter_s_no_replay_cache": no_cache,
         "speedup_batched_vs_plain": (plain["cg_iter_s"] / sec) if plain else None,
         "misfit": misfit,
         "passes": passes,
