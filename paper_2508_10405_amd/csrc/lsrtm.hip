@@ -972,6 +972,49 @@ lsrtm_status plan(lsrtm_ctx* c) {
     }
     if (!fits)
         FAIL(c, LSRTM_ENOMEM, "memory plan needs %.2f GB, budget %.2f GB", need / 1e9, budget / 1e9);
+    // With a replay cache (whole segments only), a checkpoint interval the
+    // planner chose may shrink, down to half, when the cache then holds more
+    // steps; results do not depend on the interval.
+    if (c->opt_rcache_mb > 0 && !c->fused && !ckg && c->g.ckpt_every <= 0) {
+        long long grp_pts = 0, all_pts = 0;
+        {
+            int s = 0;
+            for (int gs : group_sizes(nshot, G)) {
+                long long cur = 0;
+                for (int e = 0; e < gs; ++e, ++s) cur += c->wins[c->shots[s].win].npts;
+                grp_pts = std::max(grp_pts, cur);
+                all_pts += cur;
+            }
+        }
+        const long long seg_step = grp_pts * (nd + 1) * 4;   // replay buffer bytes per step
+        const long long step_all = all_pts * (nd + 1) * 4;   // cache bytes per step, all groups
+        auto need_of = [&](int kk) -> long long {
+            const int ns = (nt + kk - 1) / kk;
+            return fixed + grp_pts * (nbg + nsc + 2) * 4LL + (long long)kk * seg_step +
+                   (long long)((ns - 1) * (double)ck_per_shot_sum) + (long long)ns * nshot * (1 + nd) * 4;
+        };
+        auto held = [&](int kk) -> long long {   // steps of every group the cache would hold
+            const long long nk = need_of(kk);
+            if (nk > budget) return -1;
+            const long long cap = std::min(c->opt_rcache_mb * 1024LL * 1024LL, budget - nk);
+            const int ns = (nt + kk - 1) / kk;
+            const long long m = std::min<long long>(ns, cap / ((long long)kk * step_all));
+            return m >= ns ? nt : m * kk;
+        };
+        int bk = k;
+        long long best = held(k);
+        for (int kk = k - 1; kk >= std::max(1, k / 2); --kk) {
+            const long long h = held(kk);
+            if (h > best) {
+                best = h;
+                bk = kk;
+            }
+        }
+        if (bk != k) {
+            k = bk;
+            need = need_of(k);
+        }
+    }
     c->ck_group = ckg;
     c->G = group_sizes(nshot, G)[0];
     c->k = k;

@@ -148,3 +148,26 @@ def test_replay_cache_3d_and_single_segment(torch, case):
         assert np.array_equal(ctx.adjoint(y).cpu().numpy(), ref_i), rep
         assert np.array_equal(ctx.born(dm).cpu().numpy(), ref_d), rep
     ctx.close()
+
+
+def test_replay_cache_with_planner_interval(torch):
+    """Checkpoint interval left to the planner, which may shorten it so that
+    a cache of part of the history holds more steps: bitwise the results of
+    the planner's plan without the cache."""
+    from paper_2508_10405_amd import lsrtm
+    w = _w(nt=200)
+    dm = to_dev(torch, w.dm)
+    ref = lsrtm.context_for(w)
+    y = to_dev(torch, np.random.default_rng(7).standard_normal(ref.data_len))
+    ref_i = ref.adjoint(y).cpu().numpy()
+    ref_d = ref.born(dm).cpu().numpy()
+    mb = math.ceil(0.4 * w.nt * 3 * ref.sizes()["padded_points"] * 4 / 2 ** 20)
+    ref.close()
+    ctx = lsrtm.context_for(w, replay_cache_mb=mb)
+    sz = ctx.sizes()
+    print(f"[case] planner interval {sz['ckpt_every']}, cached segments {sz['replay_cache_segments']}", flush=True)
+    assert 1 <= sz["replay_cache_segments"] < math.ceil(w.nt / sz["ckpt_every"])
+    for rep in range(2):
+        assert np.array_equal(ctx.adjoint(y).cpu().numpy(), ref_i), rep
+        assert np.array_equal(ctx.born(dm).cpu().numpy(), ref_d), rep
+    ctx.close()
