@@ -86,3 +86,20 @@ def test_calls_before_setup_report_state():
     assert L.lsrtm_set_option(h, 99, 0) == lsrtm.EINVAL
     assert L.lsrtm_set_option(h, lsrtm.OPT_TILE, 42) == lsrtm.EINVAL
     L.lsrtm_destroy(h)
+
+
+def test_binding_constants_match_the_header():
+    """Every option key, status code, snapshot storage code and the kernel
+    class count the binding passes are the header's values."""
+    src = open(HEADER).read()
+    opts = dict((k, int(v)) for k, v in re.findall(r"LSRTM_OPT_(\w+)\s*=\s*(\d+)", src))
+    assert opts, "no options found"
+    for name, val in opts.items():
+        assert getattr(lsrtm, f"OPT_{name}") == val, name
+    status = dict((k, int(v)) for k, v in re.findall(r"LSRTM_(OK|E[A-Z]+)\s*=\s*(-?\d+)", src))
+    for name, val in status.items():
+        assert getattr(lsrtm, name) == val, name
+    ck = dict((k.lower(), int(v)) for k, v in re.findall(r"LSRTM_CKPT_(\w+)\s*=\s*(\d+)", src))
+    assert ck == lsrtm.CKPT
+    nk = int(re.search(r"LSRTM_NKERNEL\s*=\s*(\d+)", src).group(1))
+    assert nk == lsrtm.NKERNEL == len(lsrtm.KERNEL_NAMES)
