@@ -85,6 +85,11 @@ def test_calls_before_setup_report_state():
     assert L.lsrtm_set_acquisition(h, 1, None, None, None, None, None) == lsrtm.ESTATE
     assert L.lsrtm_set_option(h, 99, 0) == lsrtm.EINVAL
     assert L.lsrtm_set_option(h, lsrtm.OPT_TILE, 42) == lsrtm.EINVAL
+    assert L.lsrtm_set_option(h, lsrtm.OPT_REPLAY_CACHE_MB, -1) == lsrtm.EINVAL
+    assert L.lsrtm_set_option(h, lsrtm.OPT_REPLAY_CACHE_MB, 512) == lsrtm.OK   # planned with the acquisition
+    out = (ctypes.c_longlong * 14)(*([-7] * 14))
+    assert L.lsrtm_sizes(h, out, 14) == lsrtm.OK
+    assert out[12] == 0 and out[13] == -7   # no segment held before a plan; 13 entries written
     L.lsrtm_destroy(h)
 
 
