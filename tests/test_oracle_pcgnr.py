@@ -6,6 +6,13 @@ The paper prints no values for either; the pins are mathematical:
 * the vectorised pseudo-Hessian equals, node by node, the energy of the Born
   secondary source obtained by running the oracle's own Born step with a unit
   perturbation at that node (brute force through a different code path);
+* the assembled diagonal for (lnVp, lnIp) equals, node by node, the
+  time-integrated energy of the derivative of one background step with
+  respect to the model (complex step through the model preparation, with
+  the velocity part weighted by rho^2, rho = Ip / Vp taken from the inputs,
+  and the 1 / dt of the time integral), summed over lnrho and lnkappa as
+  appendix B states; replacing rho^2 by rho or 1 / rho^2, dropping 1 / dt or
+  subtracting the two parts is far outside the tolerance;
 * it is quadratic in the source amplitude and additive over shots;
 * PCGNR with the identity preconditioner is CGNR operation for operation;
 * PCGNR with minv = D^2 is CGNR on the column-scaled operator L D (x = D y);
@@ -66,6 +73,88 @@ def test_pseudo_hessian_brute_force(n, npml):
     assert np.max(np.abs(h_r - bf_r)) <= 1e-12 * np.max(np.abs(bf_r))
     assert np.max(np.abs(h_k - bf_k)) <= 1e-12 * np.max(np.abs(bf_k))
     assert np.max(bf_r) > 0 and np.max(bf_k) > 0
+
+
+def _step_energy(states, med, si, dvp, dip):
+    """Sum over the recorded steps of the squared complex-step derivative of
+    one background step along the model direction (dvp, dip): returns the
+    velocity part and the pressure part separately."""
+    eps = 1e-20
+    lnvp_pad, lnip_pad, args = med
+    mp = O.make_medium(lnvp_pad + 1j * eps * dvp, lnip_pad + 1j * eps * dip, *args)
+    ev = ep = 0.0
+    for st0, amp in states:
+        st = st0.copy()
+        O.step_background(st, mp, si, amp)
+        ev += sum(float(np.sum((np.imag(v) / eps) ** 2)) for v in st.v)
+        ep += float(np.sum((np.imag(st.p) / eps) ** 2))
+    return ev, ep
+
+
+@pytest.mark.parametrize("n,npml,nshot", [((6, 8), 2, 2), ((4, 5, 3), 1, 1), ((5, 6), 0, 1)])
+def test_pseudo_hessian_assembly_complex_step(n, npml, nshot):
+    """Appendix B: H_lnVp = H_lnIp = H_lnrho + H_lnkappa with
+    H_lnrho = rho^2 int (d_t v)^2 dt and H_lnkappa = int (kappa div v)^2 dt.
+
+    Discretely, the Born source of a unit perturbation in one step is the
+    derivative of that step with respect to the model at a fixed state.  A
+    complex step through make_medium gives it without the Born code: along
+    lnrho (lnIp + 1/2, lnVp - 1/2) the velocity part is the density source,
+    along lnkappa (lnIp + 1/2, lnVp + 1/2) the pressure part is the bulk
+    modulus source.  The time integral of a squared rate is the sum of the
+    squared increments divided by dt; rho = exp(lnIp) / exp(lnVp) at the
+    node.  Two shots on different windows check the shot sum; npml = 0
+    puts the clamped last half node inside the physical grid.
+
+    The two parts of the sum have different units; with velocities of km/s
+    in SI units the lnkappa part outweighs the lnrho part by about 10^6 and
+    would hide a wrong density factor, so the medium's velocity is scaled
+    down by 60 (density unchanged), which brings the two parts to the same
+    order."""
+    w = synth.small(n, nt=6, npml=npml, seed=23, nshot=nshot, uneven=nshot > 1)
+    rng = np.random.default_rng(3)
+    wav = rng.standard_normal((nshot, w.nt))
+    prob = _problem(w, wav)
+    lnvp, lnip = _f64(w)
+    lnvp, lnip = lnvp - np.log(60.0), lnip - np.log(60.0)
+    H = O.pseudo_hessian(prob, lnvp, lnip)
+    ndim = len(n)
+    vmax = float(np.exp(lnvp.max()))
+    e_r = np.zeros(lnvp.shape)
+    e_k = np.zeros(lnvp.shape)
+    for s in range(nshot):
+        win = prob.win[s]
+        sl = tuple(slice(win[a][0], win[a][1]) for a in reversed(range(ndim)))
+        vp_pad = np.pad(lnvp[sl], npml, mode="edge")
+        ip_pad = np.pad(lnip[sl], npml, mode="edge")
+        args = (prob.h, prob.dt, npml, vmax, prob.pml_R, prob.pml_f0)
+        med = O.make_medium(vp_pad, ip_pad, *args)
+        si = tuple(prob.src[s][a] - win[a][0] + npml for a in reversed(range(ndim)))
+        st = O.State.zeros(med.shape, ndim, np.complex128)
+        states = []
+        for k in range(prob.nt):
+            states.append((st.copy(), wav[s, k]))
+            O.step_background(st, med, si, wav[s, k])
+        for phys in np.ndindex(*lnvp[sl].shape):
+            e = np.zeros(med.shape)
+            e[tuple(i + npml for i in phys)] = 1.0
+            g = tuple(sl[ax].start + phys[ax] for ax in range(ndim))
+            ev, _ = _step_energy(states, (vp_pad, ip_pad, args), si, -0.5 * e, 0.5 * e)
+            _, ep = _step_energy(states, (vp_pad, ip_pad, args), si, 0.5 * e, 0.5 * e)
+            e_r[g] += ev
+            e_k[g] += ep
+    rho = np.exp(lnip) / np.exp(lnvp)
+    dt = prob.dt
+    bf = rho ** 2 * e_r / dt + e_k / dt
+    scale = np.max(np.abs(bf))
+    assert scale > 0 and np.max(e_r) > 0 and np.max(e_k) > 0
+    part_r, part_k = np.max(rho ** 2 * e_r / dt), np.max(e_k / dt)
+    assert 0.05 < part_r / part_k < 20
+    assert np.max(np.abs(H - bf)) <= 1e-10 * scale
+    # the comparison tells the plausible misreadings apart
+    for bad in (rho * e_r / dt + e_k / dt, e_r / rho ** 2 / dt + e_k / dt,
+                rho ** 2 * e_r + e_k / dt, rho ** 2 * e_r / dt - e_k / dt):
+        assert np.max(np.abs(H - bad)) > 1e-2 * scale
 
 
 def test_pseudo_hessian_quadratic_and_additive():
