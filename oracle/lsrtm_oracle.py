@@ -354,13 +354,49 @@ def born_shot(med: Medium, src_idx, rec_idx, wav: np.ndarray, nt: int,
     return dd, d0
 
 
-def background_history(med: Medium, src_idx, wav, nt, ckpt_every: int = 0):
+def round_significand(x: np.ndarray, bits: int) -> np.ndarray:
+    """x rounded to the nearest number with `bits` significant bits, ties to
+    even (no exponent limits)."""
+    m, e = np.frexp(x)
+    return np.ldexp(np.rint(np.ldexp(m, bits)), e - bits)
+
+
+def compress_field(x: np.ndarray, dtype: str) -> np.ndarray:
+    """One stored-and-restored snapshot field (appendix A names compression
+    as a way to keep the background history; the format is a reading): the
+    field is divided by a per-snapshot scale s, rounded to nearest with ties
+    to even, and multiplied by s again.
+
+    f16 : s = max|x| / 2^14, IEEE binary16 (11 significant bits, spacing
+          2^-24 below 2^-14), the conversion numpy implements;
+    bf16: s = max|x|, 8 significant bits (bfloat16; values below 2^-126 of
+          max|x|, which bfloat16 would hold as subnormals, are kept at 8 bits);
+    f64 : unchanged.  A zero field stays zero."""
+    if dtype in ("f64", "f32"):
+        return x.copy()
+    mx = float(np.max(np.abs(x))) if x.size else 0.0
+    if mx == 0.0:
+        return np.zeros_like(x)
+    if dtype == "f16":
+        s = mx / 2.0 ** 14
+        return (x / s).astype(np.float16).astype(np.float64) * s
+    if dtype == "bf16":
+        s = mx
+        return round_significand(x / s, 8) * s
+    raise ValueError(dtype)
+
+
+def background_history(med: Medium, src_idx, wav, nt, ckpt_every: int = 0,
+                       ckpt_dtype: str = "f64"):
     """Source-side quantities (dv^n, q^n) for n = 0..nt-1, served in reverse.
 
     With ckpt_every = 0 the whole history is stored.  Otherwise the state is
     stored every ckpt_every steps and each segment is recomputed on demand;
     in FP64 the recomputation repeats the same operations, so it returns the
-    same numbers as storing everything.
+    same numbers as storing everything.  With ckpt_dtype "f16" or "bf16" the
+    pressure and velocities of every stored state go through compress_field
+    (the CPML memories are kept exactly), so the replayed history is that of
+    compressed snapshots.
     """
     if ckpt_every <= 0:
         st = State.zeros(med.shape, med.ndim, np.result_type(med.kappa, np.float64))
@@ -372,7 +408,10 @@ def background_history(med: Medium, src_idx, wav, nt, ckpt_every: int = 0):
     st = State.zeros(med.shape, med.ndim, np.result_type(med.kappa, np.float64))
     for n in range(nt):
         if n % ckpt_every == 0:
-            ckpts[n] = st.copy()
+            c = st.copy()
+            c.p = compress_field(c.p, ckpt_dtype)
+            c.v = [compress_field(v, ckpt_dtype) for v in c.v]
+            ckpts[n] = c
         step_background(st, med, src_idx, wav[n])
     cache = {"seg": None, "vals": None}
 
@@ -389,7 +428,7 @@ def background_history(med: Medium, src_idx, wav, nt, ckpt_every: int = 0):
 
 
 def adjoint_shot(med: Medium, src_idx, rec_idx, wav: np.ndarray, nt: int,
-                 y: np.ndarray, ckpt_every: int = 0):
+                 y: np.ndarray, ckpt_every: int = 0, ckpt_dtype: str = "f64"):
     """Exact discrete transpose of born_shot, y -> (g_lnrho, g_lnkappa).
 
     Appendix A derives the adjoint-state gradient: the adjoint field runs
@@ -400,7 +439,7 @@ def adjoint_shot(med: Medium, src_idx, rec_idx, wav: np.ndarray, nt: int,
     recursion is the paper's compliance form (appendix A, the equation after
     eq. adjnotused) run backwards.
     """
-    hist = background_history(med, src_idx, wav, nt, ckpt_every)
+    hist = background_history(med, src_idx, wav, nt, ckpt_every, ckpt_dtype)
     dtype = np.result_type(med.kappa, y, np.float64)
     pt = np.zeros(med.shape, dtype=dtype)            # adjoint of dp
     vt = [np.zeros(med.shape, dtype=dtype) for _ in range(med.ndim)]   # of dv_a
@@ -521,7 +560,7 @@ def born(prob: Problem, lnvp, lnip, dm) -> List[np.ndarray]:
 
 
 def adjoint(prob: Problem, lnvp, lnip, ys: Sequence[np.ndarray],
-            ckpt_every: int = 0) -> np.ndarray:
+            ckpt_every: int = 0, ckpt_dtype: str = "f64") -> np.ndarray:
     """L^T y summed over shots: image (2, *physical shape) = (lnVp, lnIp).
 
     Per shot, g_lnrho and g_lnkappa are mapped with the gradient chain rule
@@ -535,7 +574,7 @@ def adjoint(prob: Problem, lnvp, lnip, ys: Sequence[np.ndarray],
                   for _ in range(ndim))
     for s in range(prob.nshot):
         med, si, ri, sl = shot_setup(prob, lnvp, lnip, s, vmax)
-        g_r, g_k = adjoint_shot(med, si, ri, prob.wavelet[s], prob.nt, ys[s], ckpt_every)
+        g_r, g_k = adjoint_shot(med, si, ri, prob.wavelet[s], prob.nt, ys[s], ckpt_every, ckpt_dtype)
         img[0][sl] += (-g_r + g_k)[inner]
         img[1][sl] += (g_r + g_k)[inner]
     return img

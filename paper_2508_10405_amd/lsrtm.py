@@ -166,6 +166,7 @@ class Context:
         self.set_option(OPT_REPLAY_CACHE_MB, replay_cache_mb)
         self.nrec: List[int] = []
         self._keep = []
+        self._minv = None
 
     # -- plumbing -----------------------------------------------------------
     def _check(self, status, what):
@@ -356,6 +357,38 @@ class Context:
             self._check(lib().lsrtm_cgnr_state(self._h, 0, _vp(_ptr(st["r"])), _vp(_ptr(st["z"])),
                                                _vp(_ptr(st["p"])), sc), "cgnr_state")
 
+    def cgnr_save(self, path, x):
+        """Write the CG run to `path` (numpy .npz of plain arrays, nothing
+        pickled): the iterate x and the solver state r, z, p in FP32 as the
+        library holds them (so that a resumed run continues bit for bit), the
+        scalars (<z, s>, <r0, r0>, <r, r>, k) in FP64, and the preconditioner
+        in use, if any."""
+        _require_cuda(x, "x")
+        st = self.cgnr_get_state()
+        arrays = {"x": x.cpu().numpy(), "r": st["r"].cpu().numpy(), "z": st["z"].cpu().numpy(),
+                  "p": st["p"].cpu().numpy(), "scalars": np.asarray(st["scalars"], dtype=np.float64),
+                  "shape": np.asarray(self.shape, dtype=np.int64),
+                  "data_len": np.asarray(self.data_len, dtype=np.int64)}
+        if self._minv is not None:
+            arrays["minv"] = self._minv.cpu().numpy()
+        with open(path, "wb") as f:
+            np.savez(f, **arrays)
+
+    def cgnr_load(self, path):
+        """Resume a CG run written by cgnr_save on a context with the same grid
+        and acquisition: restores its preconditioner (or none) and its solver
+        state, and returns the iterate x as a device tensor for
+        cgnr_iterate."""
+        torch = self._torch
+        with np.load(path, allow_pickle=False) as f:
+            if tuple(f["shape"]) != tuple(self.shape) or int(f["data_len"]) != self.data_len:
+                raise ValueError(f"{path}: CG state of another problem")
+            dev = lambda k: torch.from_numpy(np.ascontiguousarray(f[k], dtype=np.float32)).cuda()
+            self.set_preconditioner(dev("minv") if "minv" in f.files else None)
+            self.cgnr_set_state({"r": dev("r"), "z": dev("z"), "p": dev("p"),
+                                 "scalars": [float(v) for v in f["scalars"]]})
+            return dev("x")
+
     def pseudo_hessian(self, eps_rel=1e-3, preconditioner=True):
         """Pseudo-Hessian diagonal h [shape] (lsrtm_pseudo_hessian) and, with
         preconditioner=True, minv [2, *shape] = 1 / (h + eps_rel max h)."""
@@ -375,6 +408,7 @@ class Context:
                 raise ValueError("minv must hold 2 x grid points")
         with self._ordered(minv):
             self._check(lib().lsrtm_set_preconditioner(self._h, _vp(_ptr(minv))), "set_preconditioner")
+        self._minv = None if minv is None else minv.detach().clone()
 
     def psf_images(self, spacing):
         """PSF images [2 (scatterer parameter), 2 (response), *shape]

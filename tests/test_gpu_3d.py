@@ -4,7 +4,7 @@ import pytest
 
 from oracle import lsrtm_oracle as O
 from paper_2508_10405_amd import synth
-from gpu_common import concat, f64, oracle_problem, rel, require_gpu, to_dev
+from gpu_common import BF16_BOUND, concat, f64, oracle_problem, rel, require_gpu, to_dev
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -82,3 +82,50 @@ def test_3d_dot_product(torch):
     b = ctx.dot(x.view(-1), ctx.adjoint(y).view(-1))
     print("3d dot", a, b)
     assert abs(a - b) <= TOL * abs(a)
+
+
+def test_config5_launch_configuration_window(torch):
+    """The 3D workload's launch configuration (one shot per launch, 64 x 4 x 32
+    tiles with the velocity phases on 64 x 8 x 32, BF16 checkpoints) on a
+    window of the config-5 model (salt flank, 110 x 36 x 34 physical nodes,
+    150 x 76 x 74 padded: 3 tiles along z and y, 19 along x, every axis
+    ragged) against the FP64 oracle: Born data and the migration with FP32
+    checkpoints within 1e-4, the migration with the BF16 checkpoints within
+    the stated BF16 bound."""
+    import oracle_jobs as J
+    from paper_2508_10405_amd import lsrtm
+    nt = 150
+    full = synth.config5(nt=nt)
+    y0, x0, nz, nx, ny = 183, 180, 110, 36, 34
+    sl = (slice(y0, y0 + ny), slice(x0, x0 + nx), slice(0, nz))
+    rx, ry = np.meshgrid(np.arange(0, nx, 5), np.arange(0, ny, 5), indexing="xy")
+    rec = np.stack([np.full(rx.size, 2), rx.ravel(), ry.ravel()], axis=1)
+    w = synth.Workload("config5 window", full.h, full.dt, nt, full.npml, full.f0,
+                       np.ascontiguousarray(full.lnvp[sl]), np.ascontiguousarray(full.lnip[sl]),
+                       np.ascontiguousarray(full.dm[(slice(None),) + sl]),
+                       [((0, nz), (0, nx), (0, ny))], [(2, 18, 17)], [rec],
+                       np.ascontiguousarray(full.wavelet[:1, :nt]), pml_R=full.pml_R, pml_f0=full.pml_f0)
+    del full
+    print(f"[case] config5 window {w.n} nt={nt}, launch configuration of the 3D benchmark", flush=True)
+    rng = np.random.default_rng(12)
+    ys = [rng.standard_normal((nt, len(rec)))]
+    running = J.Running([J.born_job(w, [0], nt, w.dm), J.adjoint_job(w, [0], nt, ys, ckpt_every=30)])
+    cfg = dict(shots_per_launch=1, tile=0, tile_v=1)
+    assert lsrtm.tile_shape(3, 0) == (64, 4) and lsrtm.tile_shape(3, 1) == (64, 8)
+    out = {}
+    for dtype in ("f32", "bf16"):
+        ctx = lsrtm.context_for(w, ckpt_dtype=dtype, **cfg)
+        print("plan", dtype, ctx.sizes(), flush=True)
+        out[dtype] = (ctx.born(to_dev(torch, w.dm)).cpu().numpy(),
+                      ctx.adjoint(to_dev(torch, concat(ys))).cpu().numpy())
+        ctx.close()
+    ref_d, ref_i = running.results()
+    assert np.array_equal(out["f32"][0], out["bf16"][0])
+    e = rel(out["f32"][0], concat(ref_d))
+    print("config5 window born rel", e, flush=True)
+    assert e <= TOL
+    for dtype, bound in (("f32", TOL), ("bf16", BF16_BOUND)):
+        for k in range(2):
+            e = rel(out[dtype][1][k], ref_i[k])
+            print(f"config5 window image {k} ({dtype} checkpoints) rel {e:.2e}", flush=True)
+            assert e <= bound

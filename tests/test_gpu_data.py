@@ -13,7 +13,7 @@ import pytest
 
 from oracle import lsrtm_oracle as O
 from paper_2508_10405_amd import synth
-from gpu_common import concat, f64, oracle_problem, rel, require_gpu, to_dev
+from gpu_common import cg_step_parity, concat, f64, oracle_problem, rel, require_gpu, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -61,6 +61,16 @@ def test_nonlinear_residual_vs_oracle(torch):
 
 
 def test_monoparameter_inversion_by_mask(torch):
+    """lnIp-only inversion as PCGNR with the mask diag(0, I), against the
+    oracle's CGNR on the operator restricted to lnIp.
+
+    Every iteration from the GPU's own state matches one FP64 oracle
+    iteration within 1e-4 (x, r, z, p), and the first two iterates of the
+    chain match within 1e-4.  The third iterate of this problem amplifies
+    operator errors strongly: on the oracle alone, a relative perturbation of
+    1e-6 of every operator output moves it by 2.3e-4 (against 8e-6 for the
+    second), so the GPU's operator rounding (about 1e-6) moves it by about
+    2e-4; it is held to 1e-3."""
     from paper_2508_10405_amd import lsrtm
     w = synth.small((36, 48), nt=110, npml=6, seed=75, nshot=2, uneven=True)
     prob = oracle_problem(w)
@@ -70,15 +80,21 @@ def test_monoparameter_inversion_by_mask(torch):
     mask = torch.zeros((2,) + ctx.shape, device="cuda")
     mask[1] = 1.0
     ctx.set_preconditioner(mask)
-    x, hist = ctx.cgnr(to_dev(torch, concat(dobs)), 3)
-    assert float(x[0].abs().max()) == 0.0
     zero = np.zeros(lnvp.shape)
-    x_ref, hist_ref = O.cgnr(lambda m2: O.born(prob, lnvp, lnip, np.stack([zero, m2])),
-                             lambda d: O.adjoint(prob, lnvp, lnip, d)[1], dobs, 3)
-    e = rel(x[1].cpu().numpy(), x_ref)
-    print("mono x rel", e, hist, hist_ref, flush=True)
-    assert e <= 1e-3
-    assert np.allclose(hist, hist_ref, atol=1e-4)
+    L2 = lambda m2: O.born(prob, lnvp, lnip, np.stack([zero, m2]))
+    Lt2 = lambda d: O.adjoint(prob, lnvp, lnip, d)[1]
+    for k, tol in ((2, 1e-4), (3, 1e-3)):
+        x, hist = ctx.cgnr(to_dev(torch, concat(dobs)), k)
+        assert float(x[0].abs().max()) == 0.0
+        x_ref, hist_ref = O.cgnr(L2, Lt2, dobs, k)
+        e = rel(x[1].cpu().numpy(), x_ref)
+        print(f"mono x rel after {k} iterations", e, hist, hist_ref, flush=True)
+        assert e <= tol
+        assert np.allclose(hist, hist_ref, rtol=1e-4, atol=0)
+    L = lambda m: O.born(prob, lnvp, lnip, m)
+    Lt = lambda d: O.adjoint(prob, lnvp, lnip, d)
+    cg_step_parity(torch, ctx, L, Lt, to_dev(torch, concat(dobs)), 3,
+                   minv=np.stack([zero, np.ones(lnvp.shape)]))
     ctx.close()
 
 

@@ -10,7 +10,7 @@ import pytest
 
 from oracle import lsrtm_oracle as O
 from paper_2508_10405_amd import synth
-from gpu_common import concat, f64, oracle_problem, rel, require_gpu, to_dev
+from gpu_common import BF16_BOUND, FP16_BOUND, cg_step_parity, concat, f64, oracle_problem, rel, require_gpu, to_dev
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -165,20 +165,24 @@ def test_adjoint_accumulate(torch):
 
 def test_cgnr_vs_oracle(torch):
     """Three CGNR iterations: iterate and normalised misfit history against
-    the FP64 oracle's CGNR on the same operators."""
+    the FP64 oracle's CGNR on the same operators (1e-4), and every single
+    iteration from the GPU's own state against one FP64 oracle iteration
+    (1e-4 on x, r, z and p)."""
     w = synth.small((36, 52), nt=110, npml=6, seed=14, nshot=2, uneven=True)
     prob = oracle_problem(w)
     lnvp, lnip = f64(w.lnvp), f64(w.lnip)
-    dobs = O.born(prob, lnvp, lnip, f64(w.dm))
-    x_ref, hist_ref = O.cgnr(lambda m: O.born(prob, lnvp, lnip, m),
-                             lambda d: O.adjoint(prob, lnvp, lnip, d), dobs, 3)
+    L = lambda m: O.born(prob, lnvp, lnip, m)
+    Lt = lambda d: O.adjoint(prob, lnvp, lnip, d)
+    dobs = L(f64(w.dm))
+    x_ref, hist_ref = O.cgnr(L, Lt, dobs, 3)
     ctx = _ctx(torch, w)
     x, hist = ctx.cgnr(to_dev(torch, concat(dobs)), 3)
     e = rel(x.cpu().numpy(), x_ref)
     print("cgnr x rel", e, hist, hist_ref)
-    assert e <= 1e-3
-    assert np.allclose(hist, hist_ref, atol=1e-4)
+    assert e <= TOL
+    assert np.allclose(hist, hist_ref, rtol=TOL, atol=0)
     assert all(hist[i + 1] <= hist[i] for i in range(3))
+    cg_step_parity(torch, ctx, L, Lt, to_dev(torch, concat(dobs)), 3)
 
 
 def test_config1_full(torch):
@@ -200,11 +204,19 @@ def test_config1_full(torch):
         assert e <= TOL
 
 
-@pytest.mark.parametrize("dtype,bound", [("f16", 2e-3), ("bf16", 2e-2)])
-def test_compressed_checkpoints_error(torch, dtype, bound):
-    """FP16/BF16 snapshots with per-snapshot max-abs scaling: the image error
-    against the FP64 oracle is reported and held to the bound stated for
-    compressed snapshots (the paper gives none)."""
+@pytest.mark.parametrize("dtype,bound,flip_bound", [("f16", FP16_BOUND, 2e-4), ("bf16", BF16_BOUND, 6e-4)])
+def test_compressed_checkpoints_error(torch, dtype, bound, flip_bound):
+    """FP16/BF16 snapshots with per-snapshot max-abs scaling.
+
+    Against the oracle with exact history the image error is held to the
+    stated bound (4 u).  Against the oracle replaying from snapshots
+    compressed the same way (scale, round to nearest even) the two sides
+    differ only where the FP32 state and the FP64 state fall on different
+    sides of a rounding boundary: with a relative state difference delta the
+    expected error is about sqrt(2 delta u), amplified up to twice by the
+    imaging derivatives; delta <= 1e-5 gives the bounds 2e-4 (FP16) and 6e-4
+    (BF16), 10 to 30 times tighter than the bound against the exact history,
+    so that a wrong scale or rounding mode fails."""
     from paper_2508_10405_amd import lsrtm
     w = synth.small((60, 80), nt=300, npml=10, seed=21, nshot=2, uneven=True)
     prob = oracle_problem(w)
@@ -213,12 +225,17 @@ def test_compressed_checkpoints_error(torch, dtype, bound):
     ys = [rng.standard_normal((w.nt, len(r))) for r in w.rec]
     refi = O.adjoint(prob, lnvp, lnip, ys)
     for k in (10, 50):
+        refc = O.adjoint(prob, lnvp, lnip, ys, ckpt_every=k, ckpt_dtype=dtype)
         ctx = lsrtm.context_for(w, ckpt_every=k, ckpt_dtype=dtype)
         img = ctx.adjoint(to_dev(torch, concat(ys))).cpu().numpy()
         ctx.close()
         e = max(rel(img[i], refi[i]) for i in range(2))
-        print(f"[compressed] {dtype} k={k} image rel err {e:.3e}")
+        ec = max(rel(img[i], refc[i]) for i in range(2))
+        eo = max(rel(refc[i], refi[i]) for i in range(2))
+        print(f"[compressed] {dtype} k={k} image rel err {e:.3e} (oracle with the same snapshots: {eo:.3e}); "
+              f"against that oracle {ec:.3e}", flush=True)
         assert e <= bound
+        assert ec <= flip_bound
 
 
 def test_error_paths(torch):

@@ -9,7 +9,7 @@ import pytest
 
 from oracle import lsrtm_oracle as O
 from paper_2508_10405_amd import synth
-from gpu_common import rel, require_gpu, to_dev
+from gpu_common import f64, oracle_problem, rel, require_gpu, to_dev
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -75,6 +75,17 @@ def test_wiener_on_migrated_images(torch):
     single = ctx.wiener(m_rtm[1].contiguous(), m_rem[1].contiguous(), block=16, eps_rel=1e-3)
     assert torch.equal(single, out[1])
     ctx.close()
+    # oracle-only chain: the oracle's RTM image and remigration, then its filter
+    prob = oracle_problem(w)
+    lnvp, lnip = f64(w.lnvp), f64(w.lnip)
+    LtL = lambda m: O.adjoint(prob, lnvp, lnip, O.born(prob, lnvp, lnip, m))
+    r_rtm = LtL(f64(w.dm))
+    r_rem = LtL(r_rtm)
+    for k in range(2):
+        expect = O.wiener_deblur(r_rtm[k], r_rem[k], r_rtm[k], 16, 1e-3)
+        e = rel(out[k].cpu().numpy(), expect)
+        print("migrated wiener, oracle-only chain", k, e, flush=True)
+        assert e <= TOL
 
 
 def test_wiener_errors(torch):
