@@ -52,6 +52,28 @@ BYTES_PER_PT = {
 KERNEL_SYMBOL = {"born_v": "k2_v<*, true, false>", "born_p": "k2_p<*, true, false>",
                  "bg_v": "k2_v<*, false, true>", "bg_p": "k2_p<*, false, true>",
                  "adj_a": "k2_a", "adj_b": "k2_b"}
+# Minimum HBM bytes of one whole time step per padded node (every array of
+# the step read once and written once), and the kernels that make up the
+# step in the two-phase schedule.  Every node of a CPML strip adds 16 B per
+# axis whose strip it lies in (two memories read and written).
+STEP_BYTES = {2: {"born": 68, "replay": 48, "adjoint": 64}, 3: {"born": 88, "replay": 64, "adjoint": 80}}
+STEP_KERNELS = {"born": ("born_v", "born_p"), "replay": ("bg_v", "bg_p"), "adjoint": ("adj_a", "adj_b")}
+STRIP_BYTES = 16
+
+
+def strip_nodes(w):
+    """Sum over shots and axes of the padded nodes inside that axis' two
+    absorbing strips."""
+    tot = 0
+    for win in w.win:
+        N = [(hi - lo) + 2 * w.npml for lo, hi in win]
+        for a in range(len(N)):
+            other = 1
+            for b in range(len(N)):
+                if b != a:
+                    other *= N[b]
+            tot += 2 * min(w.npml, N[a]) * other
+    return tot
 
 
 def log(*a):
@@ -129,11 +151,68 @@ def cpu_baseline(nt_s, workers, padded_per_shot):
     busy = max(times)
     gpts = workers * 2 * padded_per_shot * nt_s / busy / 1e9
     return {"value": gpts, "unit": "Gpts/s", "cores": workers, "kind": "oracle", "cpu": cpu_model(),
+            "host_cores": os.cpu_count(),
             "sample": f"{workers} shots x {nt_s} of 4000 steps (Born + migration, one shot per "
-                      f"process, FP64 numpy); slowest process {busy:.1f} s, wall {wall:.1f} s"}
+                      f"process, FP64 numpy); slowest process {busy:.1f} s, wall {wall:.1f} s; "
+                      f"{workers} processes = the host cores allotted to one GPU "
+                      f"({os.cpu_count()} logical cores on the host)"}
 
 
 # ---------------------------------------------------------------------------
+def form2_block(lsrtm, synth, torch, dev, steps=2, plain_shots=16):
+    """Uneven-aperture workload (256 shots, windows of 200..737 x 240 nodes,
+    nt = 4000): CG-iteration time of the batched form (launch groups of up to
+    32 shots over one tile table, every pass replayed from its HIP graph,
+    checkpoints and replay cache reused) against the plain form (one launch
+    per shot, no graphs, no replay cache) on the same GPU.  The plain form is
+    timed on the first plain_shots shots and scaled by padded nodes (per-shot
+    passes run one after another); its Born data for those shots are
+    compared bit for bit with the batched form's, so both forms have the same
+    error against the oracle."""
+    import numpy as np
+    w = synth.config3()
+    padded = w.padded_points()
+    ctx = lsrtm.context_for(w, shots_per_launch=32, tile=1, tile_adj_a=2, replay_cache_mb=1 << 30)
+    sz = ctx.sizes()
+    dm = torch.from_numpy(w.dm).to(dev)
+    d_obs = ctx.born(dm)
+    x = ctx.cgnr_begin(d_obs)
+    ctx.cgnr_iterate(x)                       # captures the graphs of the reading passes
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.cgnr_iterate(x)
+    torch.cuda.synchronize()
+    batched = (time.perf_counter() - t0) / steps
+    d_b = [p.cpu().numpy() for p in ctx.split(d_obs)[:plain_shots]]
+    ctx.close()
+    del ctx, d_obs, x
+    torch.cuda.empty_cache()
+    P = min(plain_shots, w.nshot)
+    wp = synth.Workload(w.name, w.h, w.dt, w.nt, w.npml, w.f0, w.lnvp, w.lnip, w.dm,
+                        w.win[:P], w.src[:P], w.rec[:P], w.wavelet[:P])
+    cp = lsrtm.context_for(wp, shots_per_launch=1, tile=1, graph=False)
+    dp = cp.born(dm)
+    same = all(np.array_equal(a.cpu().numpy(), b) for a, b in zip(cp.split(dp), d_b))
+    xp = cp.cgnr_begin(dp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cp.cgnr_iterate(xp)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    cp.close()
+    del cp, dp, xp
+    torch.cuda.empty_cache()
+    plain = tp * padded / wp.padded_points()
+    return {"workload": "2D LSRTM, 256 shots on uneven windows of 200..737 x 240 nodes, nt=4000, 15 Hz",
+            "shots": w.nshot, "padded_points": padded, "groups": sz["groups"],
+            "shots_per_launch": sz["shots_per_launch"], "ckpt_every": sz["ckpt_every"],
+            "replay_cache_segments": sz["replay_cache_segments"], "graphs": True,
+            "cg_iter_s_batched": batched, "gpts_batched": 2.0 * padded * w.nt / batched / 1e9,
+            "cg_iter_s_plain": plain, "plain_sample": f"{P} shots, one launch per shot, scaled by padded nodes",
+            "speedup": plain / batched, "plain_bitwise_equal_to_batched": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,8 +223,11 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=100, help="time steps of the oracle sample")
     ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes (0 = min(16, cores))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-config3", action="store_true",
+                    help="skip the uneven-aperture (batched vs per-shot) block of the default run")
     ap.add_argument("--calibrate", action="store_true",
-                    help="also run a 1 GiB axpy (known traffic) for counter calibration")
+                    help="accepted for the counter-profile commands; the 1 GiB axpy of known traffic "
+                         "(streaming rate, counter calibration) always runs")
     ap.add_argument("--shots-per-launch", type=int, default=None,
                     help="shots per launch group; -1 = autotuned together with the tile shape "
                          "(default: 32 for the 2D workloads, the autotuner's pick on MI355X; "
@@ -205,7 +287,9 @@ def main():
     nd = w.ndim
     ckdt = "bf16" if args.workload == "config5" else "f32"
     log(f"[bench] workload {w.name}: {w.nshot} shots, nt={w.nt}, padded points {w.padded_points()}")
-    ctx = lsrtm.context_for(w, shots_per_launch=max(0, args.shots_per_launch), tile=args.tile, timing=True,
+    # the timed iterations run as the library runs them for a user: every
+    # pass of every launch group replayed from its captured HIP graph
+    ctx = lsrtm.context_for(w, shots_per_launch=max(0, args.shots_per_launch), tile=args.tile, timing=False,
                             tile_v=args.tile_v, tile_adj_a=args.tile_adj_a,
                             replay_cache_mb=1 << 30 if args.replay_cache_gb < 0 else int(args.replay_cache_gb * 1024),
                             ckpt_dtype=ckdt, progress=nd == 3)
@@ -227,16 +311,10 @@ def main():
         m = ctx.cgnr_iterate(x)
         log(f"[bench] warmup iteration {i}: misfit {m:.6f}")
     torch.cuda.synchronize()
-    kms = {k: 0.0 for k in lsrtm.KERNEL_NAMES}
-    kcnt = {k: 0 for k in lsrtm.KERNEL_NAMES}
     misfit = []
     t0 = time.perf_counter()
     for i in range(args.steps):
         misfit.append(ctx.cgnr_iterate(x))
-        st = ctx.stats()
-        for k in lsrtm.KERNEL_NAMES:
-            kms[k] += st[k][0]
-            kcnt[k] += st[k][1]
         log(f"[bench] step {i}: misfit {misfit[-1]:.6f}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -244,34 +322,87 @@ def main():
     padded = sz["padded_points"]
     value = 2.0 * padded * w.nt / sec / 1e9
 
-    # roofline of the dominant kernel
+    # per-kernel times: one more CG iteration (untimed for value) with plain
+    # launches, every 16th step's stencil kernels stamped with their own start
+    # and end by the runtime
+    ctx.set_option(lsrtm.OPT_TIMING, 1)
+    torch.cuda.synchronize()
+    ts0 = time.perf_counter()
+    ctx.cgnr_iterate(x)
+    torch.cuda.synchronize()
+    sec_direct = time.perf_counter() - ts0
+    st = ctx.stats()
+    ctx.set_option(lsrtm.OPT_TIMING, 0)
+    kms = {k: st[k][0] for k in lsrtm.KERNEL_NAMES}
+    kcnt = {k: st[k][1] for k in lsrtm.KERNEL_NAMES}
+    log(f"[bench] sampled iteration (direct launches, events): {sec_direct:.3f} s")
+
+    # streaming rate of this GPU: a 1 GiB axpy (reads 8 B, writes 4 B per element)
+    n_ax = 1 << 28
+    a_ax = torch.ones(n_ax, device=dev)
+    b_ax = torch.ones(n_ax, device=dev)
+    ctx.axpy(0.5, a_ax, b_ax)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        ctx.axpy(0.5, a_ax, b_ax)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_ax = e0.elapsed_time(e1) / 5
+    stream_gbs = 12 * n_ax / (ms_ax * 1e-3) / 1e9
+    calib = {"kernel": "k_axpy", "elements": n_ax, "read_bytes": 8 * n_ax, "write_bytes": 4 * n_ax,
+             "avg_ms": ms_ax, "GBs": stream_gbs}
+    del a_ax, b_ax
+    log(f"[bench] streaming axpy {stream_gbs:.0f} GB/s")
+
+    # roofline: the dominant time step of the plan (SURVEY 8(d) accounting:
+    # the step's minimum bytes per node plus the strip surcharge, over the
+    # summed average durations of the step's kernels)
     pts_per_launch = padded / sz["groups"]
-    dom = max((k for k in btab), key=lambda k: kms[k])
-    avg_ms = kms[dom] / max(1, kcnt[dom])
-    bytes_launch = btab[dom] * pts_per_launch
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    traffic = read_traffic(tag + ("_fused" if (nd == 2 and sz["fused"]) else ""), dom, pts_per_launch, nd)
+    strip_per_launch = STRIP_BYTES * strip_nodes(w) / sz["groups"]
+    ptag = tag + ("_fused" if (nd == 2 and sz["fused"]) else "")
     kernels = {}
     for k in lsrtm.KERNEL_NAMES:
         if kcnt[k] == 0:
             continue
         t = kms[k] / kcnt[k] * 1e-3
-        tr = read_traffic(tag + ("_fused" if (nd == 2 and sz["fused"]) else ""), k, pts_per_launch, nd) \
-            if k in btab else None
-        kernels[k] = {"avg_ms": t * 1e3, "launches_timed": kcnt[k],
-                      "GBs": btab[k] * pts_per_launch / t / 1e9 if k in btab else None,
-                      "counter_GBs": tr / t / 1e9 if tr else None}
-
-    # per-pass rates (outside the timed region): one Born pass, one migration pass
+        tr = read_traffic(ptag, k, pts_per_launch, nd) if k in btab else None
+        gbs = btab[k] * pts_per_launch / t / 1e9 if k in btab else None
+        kernels[k] = {"avg_ms": t * 1e3, "launches_timed": kcnt[k], "GBs": gbs,
+                      "frac": gbs / HBM_PEAK_GBS if gbs else None,
+                      "counter_GBs": tr / t / 1e9 if tr else None,
+                      "above_streaming_rate": (gbs > stream_gbs) if gbs else None}
+    steps = {}
+    fused = nd == 2 and sz["fused"]
+    for name, ks in STEP_KERNELS.items():
+        ks = tuple(k for k in ks if k in btab) if fused else ks
+        if not ks or any(kcnt[k] == 0 for k in ks):
+            continue
+        t = sum(kms[k] / kcnt[k] for k in ks) * 1e-3
+        byt = STEP_BYTES[nd][name] * pts_per_launch + strip_per_launch
+        trs = [read_traffic(ptag, k, pts_per_launch, nd) for k in ks]
+        steps[name] = {"kernels": list(ks), "step_ms": t * 1e3, "bytes_per_launch": byt,
+                       "GBs": byt / t / 1e9, "frac": byt / t / 1e9 / HBM_PEAK_GBS,
+                       "traffic": sum(trs) if all(trs) else None}
+    # the dominant step by the event time the sampled iteration spent in it
+    dom = max(steps, key=lambda n: sum(kms[k] for k in steps[n]["kernels"])) if steps else None
+    ds = steps.get(dom, {})
+    dk = max((k for k in btab if kcnt[k]), key=lambda k: kms[k])
+    # per-pass rates (outside the timed region): one Born pass, one migration
+    # pass, each run once first so that its graphs are captured
+    dtmp = torch.empty(ctx.data_len, device=dev)
+    itmp = torch.empty_like(x)
+    ctx.born(x, d=dtmp)
+    ctx.adjoint(dtmp, img=itmp)
     torch.cuda.synchronize()
     tb0 = time.perf_counter()
-    dtmp = ctx.born(x)
+    ctx.born(x, d=dtmp)
     torch.cuda.synchronize()
     tb1 = time.perf_counter()
-    ctx.adjoint(dtmp)
+    ctx.adjoint(dtmp, img=itmp)
     torch.cuda.synchronize()
     tb2 = time.perf_counter()
-    del dtmp
+    del dtmp, itmp
     passes = {"born_s": tb1 - tb0, "migration_s": tb2 - tb1,
               "born_gpts": padded * w.nt / (tb1 - tb0) / 1e9,
               "migration_gpts": padded * w.nt / (tb2 - tb1) / 1e9}
@@ -386,23 +517,10 @@ def main():
         log(f"[bench] plain per-shot CG iteration: {tp:.2f} s for {P} shots")
         cp.close()
 
-    calib = None
-    if args.calibrate:
-        n = 1 << 28
-        a = torch.ones(n, device=dev)
-        b = torch.ones(n, device=dev)
-        c2 = lsrtm.Context((4, 4), (10.0, 10.0), 1, 1e-3)
-        c2.axpy(0.5, a, b)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(3):
-            c2.axpy(0.5, a, b)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 3
-        calib = {"kernel": "k_axpy", "elements": n, "read_bytes": 8 * n, "write_bytes": 4 * n,
-                 "avg_ms": ms, "GBs": 12 * n / (ms * 1e-3) / 1e9}
-        log(f"[bench] calibration axpy {calib}")
+    form2 = None
+    if not args.no_config3 and args.workload == "config2" and args.nt == 0:
+        form2 = form2_block(lsrtm, synth, torch, dev)
+        log(f"[bench] config3 {form2}")
 
     cpu = None
     if not args.no_cpu_baseline and args.workload == "config2":
@@ -441,14 +559,24 @@ def main():
                    "ckpt_per_group": bool(sz["ckpt_per_group"]),
                    "schedule": "fused step" if sz["fused"] else "two-phase step",
                    "parallelism": "shots batched on 1 GPU"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms},
+        "roofline": {"bound": "hbm", "kernel": f"{dom} step ({' + '.join(ds['kernels'])})" if ds else None,
+                     "achieved": ds.get("GBs"), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ds.get("frac"), "traffic": ds.get("traffic"),
+                     "bytes_per_launch": ds.get("bytes_per_launch"), "avg_launch_ms": ds.get("step_ms"),
+                     "accounting": "minimum bytes of one time step per padded node plus 16 B per node and "
+                                   "axis in the absorbing strips, times the nodes of one launch group, over "
+                                   "the summed average durations of the step's kernels",
+                     "dominant_kernel": {"kernel": dk, "GBs": kernels[dk]["GBs"], "frac": kernels[dk]["frac"],
+                                         "above_streaming_rate": kernels[dk]["above_streaming_rate"]},
+                     "streaming_GBs": stream_gbs},
+        "steps": steps,
         "cpu_baseline": cpu,
         "cg_iter_s_batched": sec,
+        "cg_iter_s_direct_launches": sec_direct,
         "cg_iter_s_plain": plain,
         "cg_iter_s_no_replay_cache": no_cache,
         "speedup_batched_vs_plain": (plain["cg_iter_s"] / sec) if plain else None,
+        "config3": form2,
         "misfit": misfit,
         "passes": passes,
         "pcgnr": pcg,

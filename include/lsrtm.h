@@ -110,7 +110,7 @@ enum {
                                        ignored by the fused 2D schedule.        */
     LSRTM_OPT_TILE_ADJ_A = 10,      /* likewise for the adjoint pressure phase
                                        (A); -1 = LSRTM_OPT_TILE (default)       */
-    LSRTM_OPT_REPLAY_CACHE_MB = 11  /* device memory (MB) that may keep the
+    LSRTM_OPT_REPLAY_CACHE_MB = 11, /* device memory (MB) that may keep the
                                        background replays of the last segments
                                        of every launch group across migration
                                        passes (App. A: the history is the
@@ -124,6 +124,11 @@ enum {
                                        are bitwise the same.  Two-phase steps with checkpoints
                                        for the whole plan only; 0 = off
                                        (default).  Re-plans when changed.       */
+    LSRTM_OPT_GRAPH_CACHE = 12      /* most pass graphs kept (least recently
+                                       used replaced first; a pass graph is
+                                       keyed by pass kind, launch group, data
+                                       pointer and tile); 0 = 8 per launch
+                                       group plus 8 (default)                   */
 };
 
 /* Create a context for one grid on one HIP stream (hipStream_t, may be 0).
@@ -306,8 +311,9 @@ lsrtm_status lsrtm_autotune(lsrtm_ctx* ctx, int nsteps, int tune_groups, double*
  * bytes planned, out[7] = tile id in use, out[8] = 1 if checkpoints are held
  * per launch group, out[9] = 1 for the fused 2D schedule, out[10] / out[11] =
  * tile id of the velocity phases / of the adjoint A phase (-1 = out[7]),
- * out[12] = segments per launch group held by the replay cache.
- * HOST long long [nout]; the first min(nout, 13) entries are written. */
+ * out[12] = segments per launch group held by the replay cache, out[13] =
+ * pass graphs currently instantiated.
+ * HOST long long [nout]; the first min(nout, 14) entries are written. */
 lsrtm_status lsrtm_sizes(lsrtm_ctx* ctx, long long* out, int nout);
 
 /* Timing statistics of the last pass (HOST double [nout]); see

@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <list>
 #include <map>
 #include <string>
 #include <vector>
@@ -190,8 +191,11 @@ struct lsrtm_ctx {
     // acquisition inputs (kept so that the plan can be rebuilt)
     std::vector<int> a_win, a_src, a_recptr, a_rec;
     float* wavelet = nullptr;      // device copy [nshot][nt]
-    // HIP graphs of whole passes, per launch group
+    // HIP graphs of whole passes, per launch group, least recently used
+    // first in graph_lru; at most graph_cap of them are kept
     std::map<std::tuple<int, int, const void*, int>, hipGraphExec_t> graphs;
+    std::list<std::tuple<int, int, const void*, int>> graph_lru;
+    size_t graph_cap = 0;
     hipStream_t gst = nullptr;     // capture/replay stream (default priority)
     hipEvent_t gin = nullptr, gout = nullptr;
     bool tuned = false;
@@ -251,6 +255,7 @@ void background_changed(lsrtm_ctx* c) {
 void clear_graphs(lsrtm_ctx* c) {
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
+    c->graph_lru.clear();
 }
 
 void free_acq(lsrtm_ctx* c) {
@@ -722,6 +727,23 @@ lsrtm_status run_group_impl(lsrtm_ctx* c, Group& gr, int gi, int pass, float* d,
     auto it = c->graphs.find(key);
     hipGraphExec_t exec = nullptr;
     if (it == c->graphs.end()) {
+        // a caller that hands in a new data buffer on every call (a training
+        // loop through the autograd operator) would otherwise add a graph per
+        // call: keep the most recently used ones, four per launch group and
+        // pass kind in use (a replaced graph is destroyed after the stream
+        // has finished its last launch)
+        const size_t cap = c->graph_cap ? c->graph_cap : 8 * c->groups.size() + 8;
+        if (c->graphs.size() >= cap) {
+            HIPCHK(c, hipStreamSynchronize(c->gst));
+            while (c->graphs.size() >= cap && !c->graph_lru.empty()) {
+                auto old = c->graphs.find(c->graph_lru.front());
+                if (old != c->graphs.end()) {
+                    (void)hipGraphExecDestroy(old->second);
+                    c->graphs.erase(old);
+                }
+                c->graph_lru.pop_front();
+            }
+        }
         hipStream_t user = c->st;
         HIPCHK(c, hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal));
         c->st = c->gst;
@@ -738,8 +760,11 @@ lsrtm_status run_group_impl(lsrtm_ctx* c, Group& gr, int gi, int pass, float* d,
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "graph instantiate: %s", hipGetErrorString(e));
         c->graphs[key] = exec;
+        c->graph_lru.push_back(key);
     } else {
         exec = it->second;
+        c->graph_lru.remove(key);
+        c->graph_lru.push_back(key);
     }
     HIPCHK(c, hipEventRecord(c->gin, c->st));
     HIPCHK(c, hipStreamWaitEvent(c->gst, c->gin, 0));
@@ -1594,6 +1619,10 @@ lsrtm_status lsrtm_set_option(lsrtm_ctx* c, int key, long long v) {
         clear_graphs(c);
         return LSRTM_OK;
     }
+    case LSRTM_OPT_GRAPH_CACHE:
+        if (v < 0) FAIL(c, LSRTM_EINVAL, "graph cache size must be >= 0");
+        c->graph_cap = (size_t)v;
+        return LSRTM_OK;
     case LSRTM_OPT_REPLAY_CACHE_MB:
         if (v < 0) FAIL(c, LSRTM_EINVAL, "replay cache size must be >= 0");
         if (c->opt_rcache_mb == v) return LSRTM_OK;
@@ -1699,9 +1728,10 @@ lsrtm_status lsrtm_autotune(lsrtm_ctx* c, int nsteps, int tune_groups, double* o
 
 lsrtm_status lsrtm_sizes(lsrtm_ctx* c, long long* out, int nout) {
     if (!c || !out) return LSRTM_EINVAL;
-    long long v[13] = {c->data_len, c->gpts, c->G, c->k, (long long)c->groups.size(), c->padded_total, c->plan_bytes,
-                       c->tile, c->ck_group ? 1 : 0, c->fused ? 1 : 0, c->opt_tile_v, c->opt_tile_a, c->rc_m};
-    for (int i = 0; i < nout && i < 13; ++i) out[i] = v[i];
+    long long v[14] = {c->data_len, c->gpts, c->G, c->k, (long long)c->groups.size(), c->padded_total, c->plan_bytes,
+                       c->tile, c->ck_group ? 1 : 0, c->fused ? 1 : 0, c->opt_tile_v, c->opt_tile_a, c->rc_m,
+                       (long long)c->graphs.size()};
+    for (int i = 0; i < nout && i < 14; ++i) out[i] = v[i];
     return LSRTM_OK;
 }
 

@@ -31,7 +31,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "lsrtm.h")
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
 CKPT = {"f32": 0, "f16": 1, "bf16": 2}
 OPT_SHOTS_PER_LAUNCH, OPT_TILE, OPT_GRAPH, OPT_TIMING, OPT_MEM_BUDGET_MB, OPT_CKPT_PER_GROUP, OPT_FUSED, \
-    OPT_PROGRESS, OPT_TILE_V, OPT_TILE_ADJ_A, OPT_REPLAY_CACHE_MB = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
+    OPT_PROGRESS, OPT_TILE_V, OPT_TILE_ADJ_A, OPT_REPLAY_CACHE_MB, OPT_GRAPH_CACHE = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12
 NKERNEL = 8
 KERNEL_NAMES = ("born_v", "born_p", "bg_v", "bg_p", "adj_a", "adj_b", "ckpt", "rec")
 
@@ -244,11 +244,11 @@ class Context:
                 "tile_v": int(out[3]), "tile_adj_a": int(out[4])}
 
     def sizes(self):
-        out = (_c_ll * 13)()
-        self._check(lib().lsrtm_sizes(self._h, out, 13), "sizes")
+        out = (_c_ll * 14)()
+        self._check(lib().lsrtm_sizes(self._h, out, 14), "sizes")
         keys = ("data_len", "grid_points", "shots_per_launch", "ckpt_every", "groups",
                 "padded_points", "plan_bytes", "tile", "ckpt_per_group", "fused", "tile_v", "tile_adj_a",
-                "replay_cache_segments")
+                "replay_cache_segments", "graphs")
         return dict(zip(keys, [int(x) for x in out]))
 
     @property

@@ -87,9 +87,12 @@ def test_calls_before_setup_report_state():
     assert L.lsrtm_set_option(h, lsrtm.OPT_TILE, 42) == lsrtm.EINVAL
     assert L.lsrtm_set_option(h, lsrtm.OPT_REPLAY_CACHE_MB, -1) == lsrtm.EINVAL
     assert L.lsrtm_set_option(h, lsrtm.OPT_REPLAY_CACHE_MB, 512) == lsrtm.OK   # planned with the acquisition
-    out = (ctypes.c_longlong * 14)(*([-7] * 14))
-    assert L.lsrtm_sizes(h, out, 14) == lsrtm.OK
-    assert out[12] == 0 and out[13] == -7   # no segment held before a plan; 13 entries written
+    assert L.lsrtm_set_option(h, lsrtm.OPT_GRAPH_CACHE, -1) == lsrtm.EINVAL
+    assert L.lsrtm_set_option(h, lsrtm.OPT_GRAPH_CACHE, 4) == lsrtm.OK
+    out = (ctypes.c_longlong * 15)(*([-7] * 15))
+    assert L.lsrtm_sizes(h, out, 15) == lsrtm.OK
+    # no segment held and no graph before a plan; 14 entries written
+    assert out[12] == 0 and out[13] == 0 and out[14] == -7
     L.lsrtm_destroy(h)
 
 
