@@ -154,7 +154,10 @@ lsrtm_status lsrtm_set_model(lsrtm_ctx* ctx, const float* lnvp, const float* lni
  *           library injects dt * w / (dz dx [dy]) into p at the source node.
  * Data vectors then have length sum_s nt*nrec_s, shot s at offset
  * nt * rec_ptr[s], laid out [it][rec].  Plans the device memory (shots per
- * launch, checkpoint interval) and allocates it. */
+ * launch, checkpoint interval) and allocates it.  A shot's padded window
+ * (z rounded up to 32) must hold fewer than 2^30 nodes.  Errors: EINVAL
+ * (windows, sources or receivers outside the grid, a window of 2^30 nodes or
+ * more), ENOMEM (the plan does not fit), ESTATE (no model), EHIP. */
 lsrtm_status lsrtm_set_acquisition(lsrtm_ctx* ctx, int nshot, const int* win, const int* src,
                                    const int* rec_ptr, const int* rec, const float* wavelet);
 
@@ -281,8 +284,11 @@ lsrtm_status lsrtm_mute(lsrtm_ctx* ctx, float* d, double v_mute, double t0, int 
 lsrtm_status lsrtm_wiener(lsrtm_ctx* ctx, const float* m_ref, const float* m_blur, const float* m_in,
                           int nimg, int block, double eps_rel, float* out);
 
-/* FP64-accumulated inner product of two DEVICE float vectors of length n;
- * *out is a HOST double.  Deterministic (fixed reduction tree). */
+/* Inner product of the CGNR iteration (section 3, the CGNR paragraph: step
+ * lengths and the normalised misfit are ratios of such products) of two
+ * DEVICE float vectors of length n, accumulated in FP64; *out is a HOST
+ * double.  Deterministic (fixed reduction tree); synchronises the stream.
+ * Errors: EINVAL (ctx or out NULL, n < 0, a or b NULL with n > 0), EHIP. */
 lsrtm_status lsrtm_dot(lsrtm_ctx* ctx, const float* a, const float* b, long long n, double* out);
 
 /* y <- y + alpha * x on DEVICE float vectors of length n, each element

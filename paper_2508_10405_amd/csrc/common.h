@@ -103,6 +103,24 @@ inline void launch_k(F k, dim3 g, dim3 b, hipStream_t st, hipEvent_t e0, hipEven
     else k<<<g, b, 0, st>>>(args...);
 }
 
+// Element i of a device array whose base is uniform over the workgroup (read
+// from the slot table), addressed as that base plus a 32-bit byte offset.
+// The empty asm makes the offset opaque, so the compiler keeps it as one
+// 32-bit register and emits global loads and stores with a scalar base and
+// a vector offset (one offset register serves every array read at the same
+// node) instead of a 64-bit address per array.  Needs arrays below 4 GiB.
+__device__ __forceinline__ unsigned boff(unsigned i) {
+    unsigned o = i << 2;
+    asm("" : "+v"(o));
+    return o;
+}
+__device__ __forceinline__ gfloat& elem(gfloat* a, unsigned i) {
+    return *reinterpret_cast<gfloat*>(reinterpret_cast<gchar*>(a) + boff(i));
+}
+__device__ __forceinline__ const gfloat& elem(const gfloat* a, unsigned i) {
+    return *reinterpret_cast<const gfloat*>(reinterpret_cast<const gchar*>(a) + boff(i));
+}
+
 // Receiver entry of a launch group.
 struct Rec {
     int slot;

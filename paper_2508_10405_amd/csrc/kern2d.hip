@@ -87,7 +87,7 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const DSlot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
-    const long long ldz = S.ldz;
+    const unsigned ldz = (unsigned)S.ldz;
     const int npml = S.npml;
     const gfloat* achz = S.cpml[0];
     const gfloat* bchz = S.cpml[0] + nz;
@@ -105,28 +105,28 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         node_of<BZ>(r, lz, lx);
         const int gz = z0 + lz, gx = x0 + lx;
         ok[r] = gz < nz && gx < nx;
-        const long long i = ok[r] ? gx * ldz + gz : 0;
-        const long long iz = ok[r] && in_pml(gz, nz, npml) ? i : 0;
-        const long long ix = ok[r] && in_pml(gx, nx, npml) ? i : 0;
-        vz[r] = CB ? seg[i] : S.v[0][i];            // cached: G_z p + psi_z
-        vx[r] = CB ? seg[S.npts + i] : S.v[1][i];   // cached: G_x p + psi_x
-        s0[r] = S.sb[i];   // dt b_a = sb at the node times sb at its upper neighbour
-        s1z[r] = S.sb[gz + 1 < nz ? i + 1 : i];
-        s1x[r] = S.sb[gx + 1 < nx ? i + ldz : i];
-        az[r] = pml ? achz[ok[r] ? gz : 0] : 0.f;
-        ax[r] = pml ? achx[ok[r] ? gx : 0] : 0.f;
-        cz[r] = pml ? bchz[ok[r] ? gz : 0] : 0.f;
-        cx[r] = pml ? bchx[ok[r] ? gx : 0] : 0.f;
-        m0[r] = pml && !CB ? S.psi[0][iz] : 0.f;
-        m1[r] = pml && !CB ? S.psi[1][ix] : 0.f;
+        const unsigned i = ok[r] ? gx * ldz + gz : 0;
+        const unsigned iz = ok[r] && in_pml(gz, nz, npml) ? i : 0;
+        const unsigned ix = ok[r] && in_pml(gx, nx, npml) ? i : 0;
+        vz[r] = CB ? elem(seg, i) : elem(S.v[0], i);            // cached: G_z p + psi_z
+        vx[r] = CB ? elem(seg, S.npts + i) : elem(S.v[1], i);   // cached: G_x p + psi_x
+        s0[r] = elem(S.sb, i);   // dt b_a = sb at the node times sb at its upper neighbour
+        s1z[r] = elem(S.sb, gz + 1 < nz ? i + 1 : i);
+        s1x[r] = elem(S.sb, gx + 1 < nx ? i + ldz : i);
+        az[r] = pml ? elem(achz, ok[r] ? gz : 0) : 0.f;
+        ax[r] = pml ? elem(achx, ok[r] ? gx : 0) : 0.f;
+        cz[r] = pml ? elem(bchz, ok[r] ? gz : 0) : 0.f;
+        cx[r] = pml ? elem(bchx, ok[r] ? gx : 0) : 0.f;
+        m0[r] = pml && !CB ? elem(S.psi[0], iz) : 0.f;
+        m1[r] = pml && !CB ? elem(S.psi[1], ix) : 0.f;
         if (BORN) {
-            n0[r] = pml ? S.xi[0][iz] : 0.f;
-            n1[r] = pml ? S.xi[1][ix] : 0.f;
-            wz[r] = S.w[0][i];
-            wx[r] = S.w[1][i];
-            r0[r] = S.dlnr[i];
-            r1z[r] = S.dlnr[gz + 1 < nz ? i + 1 : i];
-            r1x[r] = S.dlnr[gx + 1 < nx ? i + ldz : i];
+            n0[r] = pml ? elem(S.xi[0], iz) : 0.f;
+            n1[r] = pml ? elem(S.xi[1], ix) : 0.f;
+            wz[r] = elem(S.w[0], i);
+            wx[r] = elem(S.w[1], i);
+            r0[r] = elem(S.dlnr, i);
+            r1z[r] = elem(S.dlnr, gz + 1 < nz ? i + 1 : i);
+            r1x[r] = elem(S.dlnr, gx + 1 < nx ? i + ldz : i);
         }
     }
     // stage p (and dp): cross of z- and x-halos
@@ -134,12 +134,12 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         return (unsigned)(z0 + lz - HW) < (unsigned)nz && (unsigned)(x0 + lx - HW) < (unsigned)nx;
     };
     auto ld = [&](int lz, int lx, float* v) {
-        const long long i = inside(lz, lx) ? (x0 + lx - HW) * ldz + (z0 + lz - HW) : 0;
+        const unsigned i = inside(lz, lx) ? (x0 + lx - HW) * ldz + (z0 + lz - HW) : 0;
         if (CB) {
-            v[0] = S.q[i];
+            v[0] = elem(S.q, i);
         } else {
-            v[0] = S.p[i];
-            if (BORN) v[1] = S.q[i];
+            v[0] = elem(S.p, i);
+            if (BORN) v[1] = elem(S.q, i);
         }
     };
     auto st = [&](int lz, int lx, const float* v) {
@@ -164,7 +164,7 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         int lz, lx;
         node_of<BZ>(r, lz, lx);
         const int gz = z0 + lz, gx = x0 + lx;
-        const long long i = gx * ldz + gz;
+        const unsigned i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
         float gzp = vz[r], gxp = vx[r];
         if (!CB) {
@@ -172,12 +172,12 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             gxp = d_half(sp, c, T::LZ, C.c[1]);
             if (az[r] != 0.f) {
                 const float ps = fmaf(cz[r], m0[r], az[r] * gzp);
-                S.psi[0][i] = ps;
+                elem(S.psi[0], i) = ps;
                 gzp = gzp + ps;
             }
             if (ax[r] != 0.f) {
                 const float ps = fmaf(cx[r], m1[r], ax[r] * gxp);
-                S.psi[1][i] = ps;
+                elem(S.psi[1], i) = ps;
                 gxp = gxp + ps;
             }
         }
@@ -185,35 +185,35 @@ k2_v(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const float dvz = -bz * gzp;
         const float dvx = -bx * gxp;
         if (!CB) {
-            S.v[0][i] = vz[r] + dvz;
-            S.v[1][i] = vx[r] + dvx;
+            elem(S.v[0], i) = vz[r] + dvz;
+            elem(S.v[1], i) = vx[r] + dvx;
         }
         if (SEG && !BORN) {
             // the replay buffer is read back only k steps later: streaming stores
-            __builtin_nontemporal_store(gzp, &seg[i]);
-            __builtin_nontemporal_store(gxp, &seg[S.npts + i]);
+            __builtin_nontemporal_store(gzp, &elem(seg, i));
+            __builtin_nontemporal_store(gxp, &elem(seg, S.npts + i));
         }
         if (!BORN && !SEG && (flag & PH_ACCUMULATE)) {   // pseudo-Hessian: sum of dv_a^2
-            S.w[0][i] = S.w[0][i] + dvz * dvz;
-            S.w[1][i] = S.w[1][i] + dvx * dvx;
+            elem(S.w[0], i) = elem(S.w[0], i) + dvz * dvz;
+            elem(S.w[1], i) = elem(S.w[1], i) + dvx * dvx;
         }
         if (BORN) {
             float gzq = d_half(sq, c, 1, C.c[0]);
             float gxq = d_half(sq, c, T::LZ, C.c[1]);
             if (az[r] != 0.f) {
                 const float ps = fmaf(cz[r], n0[r], az[r] * gzq);
-                S.xi[0][i] = ps;
+                elem(S.xi[0], i) = ps;
                 gzq = gzq + ps;
             }
             if (ax[r] != 0.f) {
                 const float ps = fmaf(cx[r], n1[r], ax[r] * gxq);
-                S.xi[1][i] = ps;
+                elem(S.xi[1], i) = ps;
                 gxq = gxq + ps;
             }
             const float rz = 0.5f * (r0[r] + r1z[r]);
             const float rx = 0.5f * (r0[r] + r1x[r]);
-            S.w[0][i] = (wz[r] - bz * gzq) - rz * dvz;
-            S.w[1][i] = (wx[r] - bx * gxq) - rx * dvx;
+            elem(S.w[0], i) = (wz[r] - bz * gzq) - rz * dvz;
+            elem(S.w[1], i) = (wx[r] - bx * gxq) - rx * dvx;
         }
     }
 }
@@ -242,7 +242,7 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const DSlot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1];
-    const long long ldz = S.ldz;
+    const unsigned ldz = (unsigned)S.ldz;
     const int npml = S.npml;
     const gfloat* aciz = S.cpml[0] + 2 * nz;
     const gfloat* bciz = S.cpml[0] + 3 * nz;
@@ -259,46 +259,46 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         node_of<BZ>(r, lz, lx);
         const int gz = z0 + lz, gx = x0 + lx;
         ok[r] = gz < nz && gx < nx;
-        const long long i = ok[r] ? gx * ldz + gz : 0;
-        const long long iz = ok[r] && in_pml(gz, nz, npml) ? i : 0;
-        const long long ix = ok[r] && in_pml(gx, nx, npml) ? i : 0;
-        pp[r] = CB ? seg[i] : S.p[i];   // cached: q
-        kk[r] = S.kdt[i];
-        az[r] = pml ? aciz[ok[r] ? gz : 0] : 0.f;
-        ax[r] = pml ? acix[ok[r] ? gx : 0] : 0.f;
-        cz[r] = pml ? bciz[ok[r] ? gz : 0] : 0.f;
-        cx[r] = pml ? bcix[ok[r] ? gx : 0] : 0.f;
-        m0[r] = pml && !CB ? S.phi[0][iz] : 0.f;
-        m1[r] = pml && !CB ? S.phi[1][ix] : 0.f;
+        const unsigned i = ok[r] ? gx * ldz + gz : 0;
+        const unsigned iz = ok[r] && in_pml(gz, nz, npml) ? i : 0;
+        const unsigned ix = ok[r] && in_pml(gx, nx, npml) ? i : 0;
+        pp[r] = CB ? elem(seg, i) : elem(S.p, i);   // cached: q
+        kk[r] = elem(S.kdt, i);
+        az[r] = pml ? elem(aciz, ok[r] ? gz : 0) : 0.f;
+        ax[r] = pml ? elem(acix, ok[r] ? gx : 0) : 0.f;
+        cz[r] = pml ? elem(bciz, ok[r] ? gz : 0) : 0.f;
+        cx[r] = pml ? elem(bcix, ok[r] ? gx : 0) : 0.f;
+        m0[r] = pml && !CB ? elem(S.phi[0], iz) : 0.f;
+        m1[r] = pml && !CB ? elem(S.phi[1], ix) : 0.f;
         if (BORN) {
-            qq[r] = S.q[i];
-            lk[r] = S.dlnk[i];
-            n0[r] = pml ? S.eta[0][iz] : 0.f;
-            n1[r] = pml ? S.eta[1][ix] : 0.f;
+            qq[r] = elem(S.q, i);
+            lk[r] = elem(S.dlnk, i);
+            n0[r] = pml ? elem(S.eta[0], iz) : 0.f;
+            n1[r] = pml ? elem(S.eta[1], ix) : 0.f;
         }
     }
     auto inside = [&](int lz, int lx) {
         return (unsigned)(z0 + lz - HW) < (unsigned)nz && (unsigned)(x0 + lx - HW) < (unsigned)nx;
     };
-    auto index = [&](int lz, int lx) -> long long {
+    auto index = [&](int lz, int lx) -> unsigned {
         return inside(lz, lx) ? (x0 + lx - HW) * ldz + (z0 + lz - HW) : 0;
     };
     auto ldz_ = [&](int lz, int lx, float* v) {
-        const long long i = index(lz, lx);
+        const unsigned i = index(lz, lx);
         if (CB) {
-            v[0] = S.w[0][i];
+            v[0] = elem(S.w[0], i);
         } else {
-            v[0] = S.v[0][i];
-            if (BORN) v[1] = S.w[0][i];
+            v[0] = elem(S.v[0], i);
+            if (BORN) v[1] = elem(S.w[0], i);
         }
     };
     auto ldx_ = [&](int lz, int lx, float* v) {
-        const long long i = index(lz, lx);
+        const unsigned i = index(lz, lx);
         if (CB) {
-            v[0] = S.w[1][i];
+            v[0] = elem(S.w[1], i);
         } else {
-            v[0] = S.v[1][i];
-            if (BORN) v[1] = S.w[1][i];
+            v[0] = elem(S.v[1], i);
+            if (BORN) v[1] = elem(S.w[1], i);
         }
     };
     auto stz_ = [&](int lz, int lx, const float* v) {
@@ -326,7 +326,7 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     RX::load(ldx_, hx);
     RZ::store(stz_, hz);
     RX::store(stx_, hx);
-    const float amp = S.src >= 0 ? S.src_amp[n] : 0.f;
+    const float amp = S.src >= 0 ? elem(S.src_amp, n) : 0.f;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -334,7 +334,7 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         int lz, lx;
         node_of<BZ>(r, lz, lx);
         const int gz = z0 + lz, gx = x0 + lx;
-        const long long i = gx * ldz + gz;
+        const unsigned i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
         float q = pp[r];
         const float k = kk[r];
@@ -343,20 +343,20 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             float ex = d_node(svx, c, T::LZ, C.c[1]);
             if (az[r] != 0.f) {
                 const float ph = fmaf(cz[r], m0[r], az[r] * ez);
-                S.phi[0][i] = ph;
+                elem(S.phi[0], i) = ph;
                 ez = ez + ph;
             }
             if (ax[r] != 0.f) {
                 const float ph = fmaf(cx[r], m1[r], ax[r] * ex);
-                S.phi[1][i] = ph;
+                elem(S.phi[1], i) = ph;
                 ex = ex + ph;
             }
             q = ez + ex;
             float pn = pp[r] - k * q;
             if (i == S.src) pn = pn + amp;
-            S.p[i] = pn;
-            if (SEG) __builtin_nontemporal_store(q, &seg[i]);
-            if (!BORN && !SEG && (flag & PH_ACCUMULATE)) S.gk[i] = S.gk[i] + q * q;   // pseudo-Hessian: sum of q^2
+            elem(S.p, i) = pn;
+            if (SEG) __builtin_nontemporal_store(q, &elem(seg, i));
+            if (!BORN && !SEG && (flag & PH_ACCUMULATE)) elem(S.gk, i) = elem(S.gk, i) + q * q;   // pseudo-Hessian: sum of q^2
             if (!BORN && tr.d) tile_gather(tr, tix, lz + BZ * lx, n, pn);
         }
         if (BORN) {
@@ -364,17 +364,17 @@ k2_p(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             float fx = d_node(swx, c, T::LZ, C.c[1]);
             if (az[r] != 0.f) {
                 const float ph = fmaf(cz[r], n0[r], az[r] * fz);
-                S.eta[0][i] = ph;
+                elem(S.eta[0], i) = ph;
                 fz = fz + ph;
             }
             if (ax[r] != 0.f) {
                 const float ph = fmaf(cx[r], n1[r], ax[r] * fx);
-                S.eta[1][i] = ph;
+                elem(S.eta[1], i) = ph;
                 fx = fx + ph;
             }
             const float dq = fz + fx;
             const float qn = (qq[r] - k * dq) + lk[r] * (-k * q);
-            S.q[i] = qn;
+            elem(S.q, i) = qn;
             if (tr.d) tile_gather(tr, tix, lz + BZ * lx, n, qn);
         }
     }
@@ -407,7 +407,7 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const DSlot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1], npml = S.npml;
-    const long long ldz = S.ldz;
+    const unsigned ldz = (unsigned)S.ldz;
     const gfloat* __restrict__ segq = S.seg + (long long)sstep * 3 * S.npts + 2 * S.npts;
     const gfloat* aciz = S.cpml[0] + 2 * nz;
     const gfloat* acix = S.cpml[1] + 2 * nx;
@@ -420,15 +420,15 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     auto lde = [&](int lz, int lx, float* v, bool wz, bool wx) {
         const int gz = z0 + lz - HW, gx = x0 + lx - HW;
         const bool in = inside(lz, lx);
-        const long long i = in ? gx * ldz + gz : 0;
-        v[0] = S.q[i];
+        const unsigned i = in ? gx * ldz + gz : 0;
+        v[0] = elem(S.q, i);
         if (wz) {
-            v[1] = pml ? aciz[in ? gz : 0] : 0.f;
-            v[2] = pml ? S.eta[0][in && in_pml(gz, nz, npml) ? i : 0] : 0.f;
+            v[1] = pml ? elem(aciz, in ? gz : 0) : 0.f;
+            v[2] = pml ? elem(S.eta[0], in && in_pml(gz, nz, npml) ? i : 0) : 0.f;
         }
         if (wx) {
-            v[3] = pml ? acix[in ? gx : 0] : 0.f;
-            v[4] = pml ? S.eta[1][in && in_pml(gx, nx, npml) ? i : 0] : 0.f;
+            v[3] = pml ? elem(acix, in ? gx : 0) : 0.f;
+            v[4] = pml ? elem(S.eta[1], in && in_pml(gx, nx, npml) ? i : 0) : 0.f;
         }
     };
     auto ete = [&](bool in, const float* v, bool wz, bool wx, float& ez, float& ex, float& qt) {
@@ -458,24 +458,24 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         node_of<BZ>(r, lz, lx);
         const int gz = z0 + lz, gx = x0 + lx;
         ok[r] = gz < nz && gx < nx;
-        const long long i = ok[r] ? gx * ldz + gz : 0;
-        vz[r] = S.w[0][i];
-        vx[r] = S.w[1][i];
-        gk[r] = S.gk[i];
-        qn[r] = __builtin_nontemporal_load(&segq[i]);
-        s0[r] = S.sb[i];
-        s1z[r] = S.sb[gz + 1 < nz ? i + 1 : i];
-        s1x[r] = S.sb[gx + 1 < nx ? i + ldz : i];
+        const unsigned i = ok[r] ? gx * ldz + gz : 0;
+        vz[r] = elem(S.w[0], i);
+        vx[r] = elem(S.w[1], i);
+        gk[r] = elem(S.gk, i);
+        qn[r] = __builtin_nontemporal_load(&elem(segq, i));
+        s0[r] = elem(S.sb, i);
+        s1z[r] = elem(S.sb, gz + 1 < nz ? i + 1 : i);
+        s1x[r] = elem(S.sb, gx + 1 < nx ? i + ldz : i);
         lde(lz + HW, lx + HW, ev[r], true, true);
         if (!flag && pml) {
-            const long long iz = ok[r] && in_pml(gz, nz, npml) ? i : 0;
-            const long long ix = ok[r] && in_pml(gx, nx, npml) ? i : 0;
-            hz_[r] = achz[ok[r] ? gz : 0];
-            hx_[r] = achx[ok[r] ? gx : 0];
-            cz[r] = bchz[ok[r] ? gz : 0];
-            cx[r] = bchx[ok[r] ? gx : 0];
-            xz[r] = S.xi[0][iz];
-            xx[r] = S.xi[1][ix];
+            const unsigned iz = ok[r] && in_pml(gz, nz, npml) ? i : 0;
+            const unsigned ix = ok[r] && in_pml(gx, nx, npml) ? i : 0;
+            hz_[r] = elem(achz, ok[r] ? gz : 0);
+            hx_[r] = elem(achx, ok[r] ? gx : 0);
+            cz[r] = elem(bchz, ok[r] ? gz : 0);
+            cx[r] = elem(bchx, ok[r] ? gx : 0);
+            xz[r] = elem(S.xi[0], iz);
+            xx[r] = elem(S.xi[1], ix);
         } else {
             hz_[r] = hx_[r] = cz[r] = cx[r] = xz[r] = xx[r] = 0.f;
         }
@@ -513,16 +513,16 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         int lz, lx;
         node_of<BZ>(r, lz, lx);
         const int gz = z0 + lz, gx = x0 + lx;
-        const long long i = gx * ldz + gz;
+        const unsigned i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
         if (!flag) {
-            if (hz_[r] != 0.f) S.xi[0][i] = cz[r] * (xz[r] + vz[r]);
-            if (hx_[r] != 0.f) S.xi[1][i] = cx[r] * (xx[r] + vx[r]);
+            if (hz_[r] != 0.f) elem(S.xi[0], i) = cz[r] * (xz[r] + vz[r]);
+            if (hx_[r] != 0.f) elem(S.xi[1], i) = cx[r] * (xx[r] + vx[r]);
         }
-        S.gk[i] = gk[r] + qn[r] * qt[r];
+        elem(S.gk, i) = gk[r] + qn[r] * qt[r];
         const float bz = s0[r] * s1z[r], bx = s0[r] * s1x[r];
-        S.w[0][i] = vz[r] + bz * d_half(sez, c, 1, C.c[0]);
-        S.w[1][i] = vx[r] + bx * d_half(sex, c, T::LZ, C.c[1]);
+        elem(S.w[0], i) = vz[r] + bz * d_half(sez, c, 1, C.c[0]);
+        elem(S.w[1], i) = vx[r] + bx * d_half(sex, c, T::LZ, C.c[1]);
     }
 }
 
@@ -551,7 +551,7 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     const DSlot& S = slots[tl.x];
     const int z0 = tl.y, x0 = tl.z;
     const int nz = S.n[0], nx = S.n[1], npml = S.npml;
-    const long long ldz = S.ldz;
+    const unsigned ldz = (unsigned)S.ldz;
     const gfloat* __restrict__ segz = S.seg + (long long)sstep * 3 * S.npts;
     const gfloat* __restrict__ segx = segz + S.npts;
     const gfloat* aciz = S.cpml[0] + 2 * nz;
@@ -569,17 +569,17 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         node_of<BZ>(r, lz, lx);
         const int gz = z0 + lz, gx = x0 + lx;
         ok[r] = gz < nz && gx < nx;
-        const long long i = ok[r] ? gx * ldz + gz : 0;
+        const unsigned i = ok[r] ? gx * ldz + gz : 0;
         const bool mz = ok[r] && in_pml(gz, nz, npml), mx = ok[r] && in_pml(gx, nx, npml);
-        pt[r] = S.q[i];
-        gr[r] = S.gr[i];
-        az[r] = pml ? aciz[ok[r] ? gz : 0] : 0.f;
-        ax[r] = pml ? acix[ok[r] ? gx : 0] : 0.f;
-        cz[r] = pml ? bciz[ok[r] ? gz : 0] : 0.f;
-        cx[r] = pml ? bcix[ok[r] ? gx : 0] : 0.f;
-        ez[r] = pml ? S.eta[0][mz ? i : 0] : 0.f;
-        ex[r] = pml ? S.eta[1][mx ? i : 0] : 0.f;
-        kk[r] = S.kdt[i];
+        pt[r] = elem(S.q, i);
+        gr[r] = elem(S.gr, i);
+        az[r] = pml ? elem(aciz, ok[r] ? gz : 0) : 0.f;
+        ax[r] = pml ? elem(acix, ok[r] ? gx : 0) : 0.f;
+        cz[r] = pml ? elem(bciz, ok[r] ? gz : 0) : 0.f;
+        cx[r] = pml ? elem(bcix, ok[r] ? gx : 0) : 0.f;
+        ez[r] = pml ? elem(S.eta[0], mz ? i : 0) : 0.f;
+        ex[r] = pml ? elem(S.eta[1], mx ? i : 0) : 0.f;
+        kk[r] = elem(S.kdt, i);
     }
     const gfloat* achz = S.cpml[0];
     const gfloat* achx = S.cpml[1];
@@ -594,20 +594,20 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
     auto ldz_ = [&](int lz, int lx, float* v) {
         const int gz = z0 + lz - HW, gx = x0 + lx - HW;
         const bool in = inside(lz, lx);
-        const long long i = in ? gx * ldz + gz : 0;
-        v[0] = pml ? achz[in ? gz : 0] : 0.f;
-        v[1] = pml ? S.xi[0][in && in_pml(gz, nz, npml) ? i : 0] : 0.f;
-        v[2] = S.w[0][i];
-        v[3] = segz[in && lz >= HW - 1 && lz < HW + BZ ? i : 0];
+        const unsigned i = in ? gx * ldz + gz : 0;
+        v[0] = pml ? elem(achz, in ? gz : 0) : 0.f;
+        v[1] = pml ? elem(S.xi[0], in && in_pml(gz, nz, npml) ? i : 0) : 0.f;
+        v[2] = elem(S.w[0], i);
+        v[3] = elem(segz, in && lz >= HW - 1 && lz < HW + BZ ? i : 0);
     };
     auto ldx_ = [&](int lz, int lx, float* v) {
         const int gz = z0 + lz - HW, gx = x0 + lx - HW;
         const bool in = inside(lz, lx);
-        const long long i = in ? gx * ldz + gz : 0;
-        v[0] = pml ? achx[in ? gx : 0] : 0.f;
-        v[1] = pml ? S.xi[1][in && in_pml(gx, nx, npml) ? i : 0] : 0.f;
-        v[2] = S.w[1][i];
-        v[3] = segx[in && lx >= HW - 1 && lx < HW + BX ? i : 0];
+        const unsigned i = in ? gx * ldz + gz : 0;
+        v[0] = pml ? elem(achx, in ? gx : 0) : 0.f;
+        v[1] = pml ? elem(S.xi[1], in && in_pml(gx, nx, npml) ? i : 0) : 0.f;
+        v[2] = elem(S.w[1], i);
+        v[3] = elem(segx, in && lx >= HW - 1 && lx < HW + BX ? i : 0);
     };
     auto stz_ = [&](int lz, int lx, const float* v) {
         const int c = lx * T::LZ + lz;
@@ -643,21 +643,21 @@ k2_b(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         int lz, lx;
         node_of<BZ>(r, lz, lx);
         const int gz = z0 + lz, gx = x0 + lx;
-        const long long i = gx * ldz + gz;
+        const unsigned i = gx * ldz + gz;
         const int c = (lx + HW) * T::LZ + lz + HW;
-        if (az[r] != 0.f) S.eta[0][i] = cz[r] * (ez[r] + pt[r]);
-        if (ax[r] != 0.f) S.eta[1][i] = cx[r] * (ex[r] + pt[r]);
+        if (az[r] != 0.f) elem(S.eta[0], i) = cz[r] * (ez[r] + pt[r]);
+        if (ax[r] != 0.f) elem(S.eta[1], i) = cx[r] * (ex[r] + pt[r]);
         // transpose of the half-node average: the last node of an axis also
         // takes the other half of its own product (the forward average there
         // clamps the upper neighbour to the node itself)
         const float tz = 0.5f * (sxz[c] + sxz[c - 1]) + (gz + 1 == nz ? 0.5f * sxz[c] : 0.f);
         const float tx = 0.5f * (sxx[c] + sxx[c - T::LZ]) + (gx + 1 == nx ? 0.5f * sxx[c] : 0.f);
-        S.gr[i] = gr[r] + (tz + tx);
+        elem(S.gr, i) = gr[r] + (tz + tx);
         const float dz = d_node(sgz, c, 1, C.c[0]);
         const float dx = d_node(sgx, c, T::LZ, C.c[1]);
         float qn = pt[r] + kk[r] * (dz + dx);
         if (tr.y && n > 0) qn = qn - kk[r] * tile_inject(tr, tix, lz + BZ * lx, n - 1);
-        S.q[i] = qn;
+        elem(S.q, i) = qn;
     }
 }
 

@@ -66,11 +66,11 @@ __device__ __forceinline__ float d_queue(const float* Q, const float* ck) {
     const DSlot& S = slots[tl.x];                                             \
     const int z0 = tl.y, x0 = tl.z, y0 = tl.w;                                \
     const int nz = S.n[0], nx = S.n[1], ny = S.n[2], npml = S.npml;           \
-    const long long sx = S.sx, sy = S.sy;                                     \
+    const unsigned sx = (unsigned)S.sx, sy = (unsigned)S.sy;                  \
     const int y1 = y0 + BY < ny ? y0 + BY : ny;                               \
     int lzr[R], lxr[R];                                                       \
     bool ok[R], pz[R], px[R];                                                 \
-    long long ib[R];                                                          \
+    unsigned ib[R];                                                           \
     _Pragma("unroll") for (int r = 0; r < R; ++r) {                           \
         const int e = threadIdx.x + NTHREADS * r;                             \
         lzr[r] = e % BZ;                                                      \
@@ -81,21 +81,21 @@ __device__ __forceinline__ float d_queue(const float* Q, const float* ck) {
         px[r] = PML && ok[r] && in_pml(x0 + lxr[r], nx, npml);                \
     }                                                                         \
     /* CPML coefficient or memory: zero on tiles away from the strips */      \
-    auto cp = [&](const gfloat* a, long long j) -> float {                    \
-        return PML ? a[j] : 0.f;                                              \
+    auto cp = [&](const gfloat* a, unsigned j) -> float {                    \
+        return PML ? elem(a, j) : 0.f;                                              \
     };                                                                        \
     auto inside = [&](int lz, int lx) {                                       \
         return (unsigned)(z0 + lz - HW) < (unsigned)nz &&                     \
                (unsigned)(x0 + lx - HW) < (unsigned)nx;                       \
     };                                                                        \
     /* index of LDS cell (lz, lx) on plane offset py, element py outside */   \
-    auto cidx = [&](int lz, int lx, long long py) -> long long {              \
+    auto cidx = [&](int lz, int lx, unsigned py) -> unsigned {                \
         return (inside(lz, lx) ? (x0 + lx - HW) * sx + (z0 + lz - HW) : 0) + py; \
     };                                                                        \
     /* value of f at node r of plane y, zero outside the grid */              \
     auto at = [&](const gfloat* f, int r, int y) -> float {                   \
         const bool v = ok[r] && (unsigned)y < (unsigned)ny;                   \
-        const float x = f[v ? ib[r] + y * sy : 0];                            \
+        const float x = elem(f, v ? ib[r] + y * sy : 0u);                     \
         return v ? x : 0.f;                                                   \
     };
 
@@ -140,9 +140,9 @@ v3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
     // the next plane is kept for the next plane's own value
     float sbq[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) sbq[r] = S.sb[ib[r] + y0 * sy];
+    for (int r = 0; r < R; ++r) sbq[r] = elem(S.sb, ib[r] + y0 * sy);
     for (int y = y0; y < y1; ++y) {
-        const long long py = y * sy;
+        const unsigned py = y * sy;
         const bool py_ = PML && in_pml(y, ny, npml);
         float vz[R], vx[R], vy[R], s0[R], s1z[R], s1x[R], wz[R], wx[R], wy[R], r0[R], r1z[R], r1x[R], r1y[R];
         float m0[R], m1[R], m2[R], n0[R], n1[R], n2[R];
@@ -155,35 +155,35 @@ v3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
             }
             Qp[r][7] = at(S.p, r, y + 4);
             if (BORN) Qq[r][7] = at(S.q, r, y + 4);
-            const long long i = ib[r] + py;
-            vz[r] = S.v[0][i];
-            vx[r] = S.v[1][i];
-            vy[r] = S.v[2][i];
+            const unsigned i = ib[r] + py;
+            vz[r] = elem(S.v[0], i);
+            vx[r] = elem(S.v[1], i);
+            vy[r] = elem(S.v[2], i);
             s0[r] = sbq[r];
-            s1z[r] = S.sb[ok[r] && z0 + lzr[r] + 1 < nz ? i + 1 : i];
-            s1x[r] = S.sb[ok[r] && x0 + lxr[r] + 1 < nx ? i + sx : i];
-            sbq[r] = S.sb[y + 1 < ny ? i + sy : i];
+            s1z[r] = elem(S.sb, ok[r] && z0 + lzr[r] + 1 < nz ? i + 1 : i);
+            s1x[r] = elem(S.sb, ok[r] && x0 + lxr[r] + 1 < nx ? i + sx : i);
+            sbq[r] = elem(S.sb, y + 1 < ny ? i + sy : i);
             m0[r] = cp(S.psi[0], pz[r] ? i : 0);
             m1[r] = cp(S.psi[1], px[r] ? i : 0);
             m2[r] = cp(S.psi[2], ok[r] && py_ ? i : 0);
             if (BORN) {
                 const int gz = z0 + lzr[r], gx = x0 + lxr[r];
-                wz[r] = S.w[0][i];
-                wx[r] = S.w[1][i];
-                wy[r] = S.w[2][i];
-                r0[r] = S.dlnr[i];
-                r1z[r] = S.dlnr[gz + 1 < nz ? i + 1 : i];
-                r1x[r] = S.dlnr[gx + 1 < nx ? i + sx : i];
-                r1y[r] = S.dlnr[y + 1 < ny ? i + sy : i];
+                wz[r] = elem(S.w[0], i);
+                wx[r] = elem(S.w[1], i);
+                wy[r] = elem(S.w[2], i);
+                r0[r] = elem(S.dlnr, i);
+                r1z[r] = elem(S.dlnr, gz + 1 < nz ? i + 1 : i);
+                r1x[r] = elem(S.dlnr, gx + 1 < nx ? i + sx : i);
+                r1y[r] = elem(S.dlnr, y + 1 < ny ? i + sy : i);
                 n0[r] = cp(S.xi[0], pz[r] ? i : 0);
                 n1[r] = cp(S.xi[1], px[r] ? i : 0);
                 n2[r] = cp(S.xi[2], ok[r] && py_ ? i : 0);
             }
         }
         auto ld = [&](int lz, int lx, float* v) {
-            const long long i = cidx(lz, lx, py);
-            v[0] = S.p[i];
-            if (BORN) v[1] = S.q[i];
+            const unsigned i = cidx(lz, lx, py);
+            v[0] = elem(S.p, i);
+            if (BORN) v[1] = elem(S.q, i);
         };
         auto st = [&](int lz, int lx, const float* v) {
             const int c = lx * T::LZ + lz;
@@ -209,7 +209,7 @@ v3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
         for (int r = 0; r < R; ++r) {
             if (!ok[r]) continue;
             const int gz = z0 + lzr[r], gx = x0 + lxr[r];
-            const long long i = ib[r] + py;
+            const unsigned i = ib[r] + py;
             const int c = (lxr[r] + HW) * T::LZ + lzr[r] + HW;
             const float az = achz_[r], ax = achx_[r];
             float gzp = d_half(sp, c, 1, C.c[0]);
@@ -217,35 +217,35 @@ v3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
             float gyp = d_queue(Qp[r], C.c[2]);
             if (az != 0.f) {
                 const float ps = fmaf(bchz_[r], m0[r], az * gzp);
-                S.psi[0][i] = ps;
+                elem(S.psi[0], i) = ps;
                 gzp = gzp + ps;
             }
             if (ax != 0.f) {
                 const float ps = fmaf(bchx_[r], m1[r], ax * gxp);
-                S.psi[1][i] = ps;
+                elem(S.psi[1], i) = ps;
                 gxp = gxp + ps;
             }
             if (ay != 0.f) {
-                const float ps = fmaf(bchy[y], m2[r], ay * gyp);
-                S.psi[2][i] = ps;
+                const float ps = fmaf(elem(bchy, y), m2[r], ay * gyp);
+                elem(S.psi[2], i) = ps;
                 gyp = gyp + ps;
             }
             const float bz = s0[r] * s1z[r], bx = s0[r] * s1x[r], by = s0[r] * sbq[r];
             const float dvz = -bz * gzp;
             const float dvx = -bx * gxp;
             const float dvy = -by * gyp;
-            S.v[0][i] = vz[r] + dvz;
-            S.v[1][i] = vx[r] + dvx;
-            S.v[2][i] = vy[r] + dvy;
+            elem(S.v[0], i) = vz[r] + dvz;
+            elem(S.v[1], i) = vx[r] + dvx;
+            elem(S.v[2], i) = vy[r] + dvy;
             if (SEG) {   // read back only k steps later: streaming stores
-                __builtin_nontemporal_store(gzp, &seg[i]);
-                __builtin_nontemporal_store(gxp, &seg[S.npts + i]);
-                __builtin_nontemporal_store(gyp, &seg[2 * S.npts + i]);
+                __builtin_nontemporal_store(gzp, &elem(seg, i));
+                __builtin_nontemporal_store(gxp, &elem(seg, S.npts + i));
+                __builtin_nontemporal_store(gyp, &elem(seg, 2 * S.npts + i));
             }
             if (!BORN && !SEG && (flag & PH_ACCUMULATE)) {   // pseudo-Hessian: sum of dv_a^2
-                S.w[0][i] = S.w[0][i] + dvz * dvz;
-                S.w[1][i] = S.w[1][i] + dvx * dvx;
-                S.w[2][i] = S.w[2][i] + dvy * dvy;
+                elem(S.w[0], i) = elem(S.w[0], i) + dvz * dvz;
+                elem(S.w[1], i) = elem(S.w[1], i) + dvx * dvx;
+                elem(S.w[2], i) = elem(S.w[2], i) + dvy * dvy;
             }
             if (BORN) {
                 float gzq = d_half(sq, c, 1, C.c[0]);
@@ -253,22 +253,22 @@ v3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
                 float gyq = d_queue(Qq[r], C.c[2]);
                 if (az != 0.f) {
                     const float ps = fmaf(bchz_[r], n0[r], az * gzq);
-                    S.xi[0][i] = ps;
+                    elem(S.xi[0], i) = ps;
                     gzq = gzq + ps;
                 }
                 if (ax != 0.f) {
                     const float ps = fmaf(bchx_[r], n1[r], ax * gxq);
-                    S.xi[1][i] = ps;
+                    elem(S.xi[1], i) = ps;
                     gxq = gxq + ps;
                 }
                 if (ay != 0.f) {
-                    const float ps = fmaf(bchy[y], n2[r], ay * gyq);
-                    S.xi[2][i] = ps;
+                    const float ps = fmaf(elem(bchy, y), n2[r], ay * gyq);
+                    elem(S.xi[2], i) = ps;
                     gyq = gyq + ps;
                 }
-                S.w[0][i] = (wz[r] - bz * gzq) - 0.5f * (r0[r] + r1z[r]) * dvz;
-                S.w[1][i] = (wx[r] - bx * gxq) - 0.5f * (r0[r] + r1x[r]) * dvx;
-                S.w[2][i] = (wy[r] - by * gyq) - 0.5f * (r0[r] + r1y[r]) * dvy;
+                elem(S.w[0], i) = (wz[r] - bz * gzq) - 0.5f * (r0[r] + r1z[r]) * dvz;
+                elem(S.w[1], i) = (wx[r] - bx * gxq) - 0.5f * (r0[r] + r1x[r]) * dvx;
+                elem(S.w[2], i) = (wy[r] - by * gyq) - 0.5f * (r0[r] + r1y[r]) * dvy;
             }
         }
     }
@@ -323,10 +323,10 @@ p3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
         acix_[r] = cp(acix, gx);
         bcix_[r] = cp(bcix, gx);
     }
-    const float amp = S.src >= 0 ? S.src_amp[n] : 0.f;
+    const float amp = S.src >= 0 ? elem(S.src_amp, n) : 0.f;
     gfloat* __restrict__ seg = S.seg + (long long)sstep * 4 * S.npts + 3 * S.npts;
     for (int y = y0; y < y1; ++y) {
-        const long long py = y * sy;
+        const unsigned py = y * sy;
         const bool py_ = PML && in_pml(y, ny, npml);
         float pp[R], kk[R], qq[R], lk[R], m0[R], m1[R], m2[R], n0[R], n1[R], n2[R];
 #pragma unroll
@@ -338,15 +338,15 @@ p3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
             }
             Qv[r][7] = at(S.v[2], r, y + 3);
             if (BORN) Qw[r][7] = at(S.w[2], r, y + 3);
-            const long long i = ib[r] + py;
-            pp[r] = S.p[i];
-            kk[r] = S.kdt[i];
+            const unsigned i = ib[r] + py;
+            pp[r] = elem(S.p, i);
+            kk[r] = elem(S.kdt, i);
             m0[r] = cp(S.phi[0], pz[r] ? i : 0);
             m1[r] = cp(S.phi[1], px[r] ? i : 0);
             m2[r] = cp(S.phi[2], ok[r] && py_ ? i : 0);
             if (BORN) {
-                qq[r] = S.q[i];
-                lk[r] = S.dlnk[i];
+                qq[r] = elem(S.q, i);
+                lk[r] = elem(S.dlnk, i);
                 n0[r] = cp(S.eta[0], pz[r] ? i : 0);
                 n1[r] = cp(S.eta[1], px[r] ? i : 0);
                 n2[r] = cp(S.eta[2], ok[r] && py_ ? i : 0);
@@ -354,14 +354,14 @@ p3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
         }
         float hz[CZ::IT][K], hx[CX::IT][K];
         CZ::load([&](int lz, int lx, float* v) {
-            const long long i = cidx(lz, lx, py);
-            v[0] = S.v[0][i];
-            if (BORN) v[1] = S.w[0][i];
+            const unsigned i = cidx(lz, lx, py);
+            v[0] = elem(S.v[0], i);
+            if (BORN) v[1] = elem(S.w[0], i);
         }, hz);
         CX::load([&](int lz, int lx, float* v) {
-            const long long i = cidx(lz, lx, py);
-            v[0] = S.v[1][i];
-            if (BORN) v[1] = S.w[1][i];
+            const unsigned i = cidx(lz, lx, py);
+            v[0] = elem(S.v[1], i);
+            if (BORN) v[1] = elem(S.w[1], i);
         }, hx);
         __syncthreads();
         CZ::store([&](int lz, int lx, const float* v) {
@@ -382,7 +382,7 @@ p3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
         for (int r = 0; r < R; ++r) {
             if (!ok[r]) continue;
             const int gz = z0 + lzr[r], gx = x0 + lxr[r];
-            const long long i = ib[r] + py;
+            const unsigned i = ib[r] + py;
             const int c = (lxr[r] + HW) * T::LZ + lzr[r] + HW;
             const float az = aciz_[r], ax = acix_[r];
             float ez = d_node(svz, c, 1, C.c[0]);
@@ -390,47 +390,47 @@ p3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
             float ey = d_queue(Qv[r], C.c[2]);
             if (az != 0.f) {
                 const float ph = fmaf(bciz_[r], m0[r], az * ez);
-                S.phi[0][i] = ph;
+                elem(S.phi[0], i) = ph;
                 ez = ez + ph;
             }
             if (ax != 0.f) {
                 const float ph = fmaf(bcix_[r], m1[r], ax * ex);
-                S.phi[1][i] = ph;
+                elem(S.phi[1], i) = ph;
                 ex = ex + ph;
             }
             if (ay != 0.f) {
-                const float ph = fmaf(bciy[y], m2[r], ay * ey);
-                S.phi[2][i] = ph;
+                const float ph = fmaf(elem(bciy, y), m2[r], ay * ey);
+                elem(S.phi[2], i) = ph;
                 ey = ey + ph;
             }
             const float q = (ez + ex) + ey;
             const float k = kk[r];
             float pn = pp[r] - k * q;
             if (i == S.src) pn = pn + amp;
-            S.p[i] = pn;
-            if (SEG) __builtin_nontemporal_store(q, &seg[i]);
-            if (!BORN && !SEG && (flag & PH_ACCUMULATE)) S.gk[i] = S.gk[i] + q * q;   // pseudo-Hessian
+            elem(S.p, i) = pn;
+            if (SEG) __builtin_nontemporal_store(q, &elem(seg, i));
+            if (!BORN && !SEG && (flag & PH_ACCUMULATE)) elem(S.gk, i) = elem(S.gk, i) + q * q;   // pseudo-Hessian
             if (BORN) {
                 float fz = d_node(swz, c, 1, C.c[0]);
                 float fx = d_node(swx, c, T::LZ, C.c[1]);
                 float fy = d_queue(Qw[r], C.c[2]);
                 if (az != 0.f) {
                     const float ph = fmaf(bciz_[r], n0[r], az * fz);
-                    S.eta[0][i] = ph;
+                    elem(S.eta[0], i) = ph;
                     fz = fz + ph;
                 }
                 if (ax != 0.f) {
                     const float ph = fmaf(bcix_[r], n1[r], ax * fx);
-                    S.eta[1][i] = ph;
+                    elem(S.eta[1], i) = ph;
                     fx = fx + ph;
                 }
                 if (ay != 0.f) {
-                    const float ph = fmaf(bciy[y], n2[r], ay * fy);
-                    S.eta[2][i] = ph;
+                    const float ph = fmaf(elem(bciy, y), n2[r], ay * fy);
+                    elem(S.eta[2], i) = ph;
                     fy = fy + ph;
                 }
                 const float dq = (fz + fx) + fy;
-                S.q[i] = (qq[r] - k * dq) + lk[r] * (-k * q);
+                elem(S.q, i) = (qq[r] - k * dq) + lk[r] * (-k * q);
             }
         }
     }
@@ -489,8 +489,8 @@ a3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
     float E[R][8], QT[R][5];
     auto front = [&](int r, int y, float& fq, float& fe) {
         const bool v = ok[r] && (unsigned)y < (unsigned)ny;
-        const long long i = v ? ib[r] + y * sy : 0;
-        fq = S.q[i];
+        const unsigned i = v ? ib[r] + y * sy : 0;
+        fq = elem(S.q, i);
         fe = cp(S.eta[2], v && in_pml(y, ny, npml) ? i : 0);
     };
     auto combine = [&](int r, int y, float fq, float fe, float& qt, float& ey) {
@@ -519,23 +519,23 @@ a3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
     // next plane is kept for the next plane's own value
     float sbq[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) sbq[r] = S.sb[ib[r] + y0 * sy];
+    for (int r = 0; r < R; ++r) sbq[r] = elem(S.sb, ib[r] + y0 * sy);
     // loads of e~ at a halo cell: the CPML coefficient, phi~, Q
-    auto ldz_ = [&](int lz, int lx, long long py, float* v) {
+    auto ldz_ = [&](int lz, int lx, unsigned py, float* v) {
         const int gz = z0 + lz - HW;
-        const long long i = cidx(lz, lx, py);
+        const unsigned i = cidx(lz, lx, py);
         const bool in = inside(lz, lx);
         v[0] = cp(aciz, in ? gz : 0);
         v[1] = cp(S.eta[0], in && in_pml(gz, nz, npml) ? i : py);
-        v[2] = S.q[i];
+        v[2] = elem(S.q, i);
     };
-    auto ldx_ = [&](int lz, int lx, long long py, float* v) {
+    auto ldx_ = [&](int lz, int lx, unsigned py, float* v) {
         const int gx = x0 + lx - HW;
-        const long long i = cidx(lz, lx, py);
+        const unsigned i = cidx(lz, lx, py);
         const bool in = inside(lz, lx);
         v[0] = cp(acix, in ? gx : 0);
         v[1] = cp(S.eta[1], in && in_pml(gx, nx, npml) ? i : py);
-        v[2] = S.q[i];
+        v[2] = elem(S.q, i);
     };
     auto ete = [&](bool in, const float* v) {
         float e = 0.f;
@@ -546,27 +546,27 @@ a3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
         return e;
     };
     for (int y = y0; y < y1; ++y) {
-        const long long py = y * sy;
+        const unsigned py = y * sy;
         const bool py_ = PML && in_pml(y, ny, npml);
         float vz[R], vx[R], vy[R], gk[R], qn[R], e0[R], e1[R], fq[R], fe[R];
         float c0[R], c1[R], c2[R], s0[R], s1z[R], s1x[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             front(r, y + 4, fq[r], fe[r]);
-            const long long i = ib[r] + py;
-            vz[r] = S.w[0][i];
-            vx[r] = S.w[1][i];
-            vy[r] = S.w[2][i];
-            gk[r] = S.gk[i];
-            qn[r] = __builtin_nontemporal_load(&segq[i]);
+            const unsigned i = ib[r] + py;
+            vz[r] = elem(S.w[0], i);
+            vx[r] = elem(S.w[1], i);
+            vy[r] = elem(S.w[2], i);
+            gk[r] = elem(S.gk, i);
+            qn[r] = __builtin_nontemporal_load(&elem(segq, i));
             s0[r] = sbq[r];
-            s1z[r] = S.sb[ok[r] && z0 + lzr[r] + 1 < nz ? i + 1 : i];
-            s1x[r] = S.sb[ok[r] && x0 + lxr[r] + 1 < nx ? i + sx : i];
-            sbq[r] = S.sb[y + 1 < ny ? i + sy : i];
+            s1z[r] = elem(S.sb, ok[r] && z0 + lzr[r] + 1 < nz ? i + 1 : i);
+            s1x[r] = elem(S.sb, ok[r] && x0 + lxr[r] + 1 < nx ? i + sx : i);
+            sbq[r] = elem(S.sb, y + 1 < ny ? i + sy : i);
             e0[r] = cp(S.eta[0], pz[r] ? i : 0);
             e1[r] = cp(S.eta[1], px[r] ? i : 0);
             if (!flag) {
-                const long long jz = pz[r] ? i : 0, jx = px[r] ? i : 0, jy = ok[r] && py_ ? i : 0;
+                const unsigned jz = pz[r] ? i : 0u, jx = px[r] ? i : 0u, jy = ok[r] && py_ ? i : 0u;
                 c0[r] = cp(S.xi[0], jz);
                 c1[r] = cp(S.xi[1], jx);
                 c2[r] = cp(S.xi[2], jy);
@@ -604,19 +604,19 @@ a3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
         for (int r = 0; r < R; ++r) {
             if (!ok[r]) continue;
             const int gz = z0 + lzr[r], gx = x0 + lxr[r];
-            const long long i = ib[r] + py;
+            const unsigned i = ib[r] + py;
             const int c = (lxr[r] + HW) * T::LZ + lzr[r] + HW;
             if (!flag) {
                 const float a = achz_[r], b = achx_[r];
-                if (a != 0.f) S.xi[0][i] = bchz_[r] * (c0[r] + vz[r]);
-                if (b != 0.f) S.xi[1][i] = bchx_[r] * (c1[r] + vx[r]);
-                if (hyc != 0.f) S.xi[2][i] = bchy[y] * (c2[r] + vy[r]);
+                if (a != 0.f) elem(S.xi[0], i) = bchz_[r] * (c0[r] + vz[r]);
+                if (b != 0.f) elem(S.xi[1], i) = bchx_[r] * (c1[r] + vx[r]);
+                if (hyc != 0.f) elem(S.xi[2], i) = elem(bchy, y) * (c2[r] + vy[r]);
             }
-            S.gk[i] = gk[r] + qn[r] * QT[r][0];
+            elem(S.gk, i) = gk[r] + qn[r] * QT[r][0];
             const float bz = s0[r] * s1z[r], bx = s0[r] * s1x[r], by = s0[r] * sbq[r];
-            S.w[0][i] = vz[r] + bz * d_half(sez, c, 1, C.c[0]);
-            S.w[1][i] = vx[r] + bx * d_half(sex, c, T::LZ, C.c[1]);
-            S.w[2][i] = vy[r] + by * d_queue(E[r], C.c[2]);
+            elem(S.w[0], i) = vz[r] + bz * d_half(sez, c, 1, C.c[0]);
+            elem(S.w[1], i) = vx[r] + bx * d_half(sex, c, T::LZ, C.c[1]);
+            elem(S.w[2], i) = vy[r] + by * d_queue(E[r], C.c[2]);
         }
     }
 }
@@ -674,8 +674,8 @@ b3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
     float Gq[R][8], Xp[R];
     auto front = [&](int r, int y, float* f) {
         const bool v = ok[r] && (unsigned)y < (unsigned)ny;
-        const long long i = v ? ib[r] + y * sy : 0;
-        f[0] = S.w[2][i];
+        const unsigned i = v ? ib[r] + y * sy : 0;
+        f[0] = elem(S.w[2], i);
         f[1] = cp(S.xi[2], v && in_pml(y, ny, npml) ? i : 0);
     };
     auto gy_of = [&](int r, int y, const float* f) -> float {
@@ -691,8 +691,8 @@ b3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
 #pragma unroll
         for (int m = 0; m < 7; ++m) front(r, y0 - 4 + m, f[m]);
         const bool pv = ok[r] && y0 > 0;
-        const long long ip = pv ? ib[r] + (y0 - 1) * sy : 0;
-        const float s_ = segy[ip], w_ = S.w[2][ip];
+        const unsigned ip = pv ? ib[r] + (y0 - 1) * sy : 0u;
+        const float s_ = elem(segy, ip), w_ = elem(S.w[2], ip);
 #pragma unroll
         for (int m = 0; m < 7; ++m) Gq[r][m + 1] = gy_of(r, y0 - 4 + m, f[m]);
         Xp[r] = pv ? -s_ * w_ : 0.f;
@@ -700,37 +700,37 @@ b3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
     // loads of g~_a and of the image product at a cell: the CPML coefficient,
     // chi_a, U_a and G_a p + psi_a (on the rows / columns whose product is
     // needed)
-    auto ldz_ = [&](int lz, int lx, long long py, float* v) {
+    auto ldz_ = [&](int lz, int lx, unsigned py, float* v) {
         const int gz = z0 + lz - HW;
         const bool in = inside(lz, lx);
-        const long long i = cidx(lz, lx, py);
+        const unsigned i = cidx(lz, lx, py);
         v[0] = cp(achz, in ? gz : 0);
         v[1] = cp(S.xi[0], in && in_pml(gz, nz, npml) ? i : py);
-        v[2] = S.w[0][i];
-        v[3] = segz[in && lz >= HW - 1 && lz < HW + BZ ? i : py];
+        v[2] = elem(S.w[0], i);
+        v[3] = elem(segz, in && lz >= HW - 1 && lz < HW + BZ ? i : py);
     };
-    auto ldx_ = [&](int lz, int lx, long long py, float* v) {
+    auto ldx_ = [&](int lz, int lx, unsigned py, float* v) {
         const int gx = x0 + lx - HW;
         const bool in = inside(lz, lx);
-        const long long i = cidx(lz, lx, py);
+        const unsigned i = cidx(lz, lx, py);
         v[0] = cp(achx, in ? gx : 0);
         v[1] = cp(S.xi[1], in && in_pml(gx, nx, npml) ? i : py);
-        v[2] = S.w[1][i];
-        v[3] = segx[in && lx >= HW - 1 && lx < HW + BX ? i : py];
+        v[2] = elem(S.w[1], i);
+        v[3] = elem(segx, in && lx >= HW - 1 && lx < HW + BX ? i : py);
     };
     for (int y = y0; y < y1; ++y) {
-        const long long py = y * sy;
+        const unsigned py = y * sy;
         const bool py_ = PML && in_pml(y, ny, npml);
         float pt[R], gr[R], sy_[R], wy_[R], kk[R], e0[R], e1[R], e2[R], fr[R][2];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             front(r, y + 3, fr[r]);
-            const long long i = ib[r] + py;
-            pt[r] = S.q[i];
-            gr[r] = S.gr[i];
-            sy_[r] = segy[i];
-            wy_[r] = S.w[2][i];
-            kk[r] = S.kdt[i];
+            const unsigned i = ib[r] + py;
+            pt[r] = elem(S.q, i);
+            gr[r] = elem(S.gr, i);
+            sy_[r] = elem(segy, i);
+            wy_[r] = elem(S.w[2], i);
+            kk[r] = elem(S.kdt, i);
             e0[r] = cp(S.eta[0], pz[r] ? i : 0);
             e1[r] = cp(S.eta[1], px[r] ? i : 0);
             e2[r] = cp(S.eta[2], ok[r] && py_ ? i : 0);
@@ -770,24 +770,24 @@ b3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
             Gq[r][7] = gy_of(r, y + 3, fr[r]);
             if (!ok[r]) continue;
             const int gz = z0 + lzr[r], gx = x0 + lxr[r];
-            const long long i = ib[r] + py;
+            const unsigned i = ib[r] + py;
             const int c = (lxr[r] + HW) * T::LZ + lzr[r] + HW;
             const float az = aciz_[r], ax = acix_[r];
-            if (az != 0.f) S.eta[0][i] = bciz_[r] * (e0[r] + pt[r]);
-            if (ax != 0.f) S.eta[1][i] = bcix_[r] * (e1[r] + pt[r]);
-            if (ay != 0.f) S.eta[2][i] = bciy[y] * (e2[r] + pt[r]);
+            if (az != 0.f) elem(S.eta[0], i) = bciz_[r] * (e0[r] + pt[r]);
+            if (ax != 0.f) elem(S.eta[1], i) = bcix_[r] * (e1[r] + pt[r]);
+            if (ay != 0.f) elem(S.eta[2], i) = elem(bciy, y) * (e2[r] + pt[r]);
             const float xy0 = -sy_[r] * wy_[r];
             // the last node of an axis also takes the other half of its own
             // product (transpose of the clamped forward average)
             const float tz = 0.5f * (sxz[c] + sxz[c - 1]) + (gz + 1 == nz ? 0.5f * sxz[c] : 0.f);
             const float tx = 0.5f * (sxx[c] + sxx[c - T::LZ]) + (gx + 1 == nx ? 0.5f * sxx[c] : 0.f);
             const float ty = 0.5f * (xy0 + Xp[r]) + (y + 1 == ny ? 0.5f * xy0 : 0.f);
-            S.gr[i] = gr[r] + ((tz + tx) + ty);
+            elem(S.gr, i) = gr[r] + ((tz + tx) + ty);
             Xp[r] = xy0;
             const float dz = d_node(sgz, c, 1, C.c[0]);
             const float dx = d_node(sgx, c, T::LZ, C.c[1]);
             const float dy = d_queue(Gq[r], C.c[2]);
-            S.q[i] = pt[r] + kk[r] * ((dz + dx) + dy);
+            elem(S.q, i) = pt[r] + kk[r] * ((dz + dx) + dy);
         }
     }
 }

@@ -895,6 +895,10 @@ lsrtm_status plan(lsrtm_ctx* c) {
             W.sx = W.ldz;
             W.sy = W.sx * W.N[1];
             W.npts = W.sy * W.N[2];
+            // the stencil kernels address a shot's arrays with 32-bit byte offsets
+            if (W.npts >= (1LL << 30))
+                FAIL(c, LSRTM_EINVAL, "shot %d: padded window of %lld nodes; at most 2^30 - 1 per shot", s,
+                     W.npts);
             w = (int)c->wins.size();
             wid[key] = w;
             c->wins.push_back(W);
