@@ -25,7 +25,9 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-4
 M = 300   # sampled time steps
 # the launch configuration bench.py times for the 2D workloads: 32 shots per
-# launch (balanced groups), 32 x 16 tiles, 32 x 32 tiles for the adjoint A phase
+# launch (balanced groups), 32 x 16 tiles, 32 x 32 tiles for the adjoint A
+# phase; the benchmark also keeps a replay cache, which the sampled tests
+# below leave off and test_config2_replay_cache_plan turns on
 BENCH_2D = dict(shots_per_launch=32, tile=1, tile_adj_a=2)
 
 
