@@ -267,6 +267,20 @@ lsrtm_status lsrtm_psf_cgnr(lsrtm_ctx* ctx, const float* psf, int spacing, int m
  * ntaper < 0, NULL d), ESTATE (no acquisition), EHIP. */
 lsrtm_status lsrtm_mute(lsrtm_ctx* ctx, float* d, double v_mute, double t0, int ntaper);
 
+/* lsrtm_mute for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same mute, with its per-receiver tables computed on the device from the
+ * acquisition the plan holds, into a file-scope device array of 5 MiB (one
+ * per GPU, kept until the process ends) instead of buffers allocated per
+ * call.  Calls no hipMalloc, hipFree or allocating routine and does not
+ * synchronise; the first call on a device looks up the array's address.
+ * Arguments as for lsrtm_mute, with the context's device current.  At most
+ * 2^18 receivers over all shots.  Every call on one GPU shares the array:
+ * calls that overlap on one GPU (several contexts or threads at once) race.
+ * Errors: EINVAL (as lsrtm_mute, or more than 2^18 receivers), ESTATE
+ * (no acquisition), EHIP. */
+lsrtm_status lsrtm_mute_noalloc(lsrtm_ctx* ctx, float* d, double v_mute, double t0, int ntaper);
+
 /* Nonstationary Wiener deblurring (appendix D).  The Hessian is taken as
  * locally translation invariant, hence diagonal in the Fourier basis of each
  * local block; per block (F its Fourier transform) the regularised inverse

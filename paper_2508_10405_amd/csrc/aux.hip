@@ -318,6 +318,41 @@ __global__ void k_mute(float* __restrict__ d, const long long* __restrict__ off,
     }
 }
 
+// Per-receiver tables of the mute from the device-resident acquisition of a
+// launch group: the trace offset and row length of receiver j (its Rec
+// entry) and its cut time tc = t0 + |x_r - x_s| / v_mute, the distance taken
+// from the padded-grid coordinates of the receiver and of its shot's source
+// (the padding cancels), summed over the axes in the order z, x, y.
+__global__ void k_mute_tables(const DSlot* __restrict__ slots, const Rec* __restrict__ rec, int nrec, int ndim,
+                              double hz, double hx, double hy, double t0, double v_mute, long long* __restrict__ off,
+                              int* __restrict__ stride, double* __restrict__ tc) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nrec) return;
+    const Rec R = rec[j];
+    const DSlot& S = slots[R.slot];
+    const long long ldz = S.ldz, nx = S.n[1];
+    const long long ir = R.idx, is = S.src;
+    const double h[3] = {hz, hx, hy};
+    const long long cr[3] = {ir % ldz, (ir / ldz) % nx, ir / (ldz * nx)};
+    const long long cs[3] = {is % ldz, (is / ldz) % nx, is / (ldz * nx)};
+    double d2 = 0.0;
+    for (int a = 0; a < ndim; ++a) {
+        const double x = (double)(cr[a] - cs[a]) * h[a];
+        d2 = d2 + x * x;
+    }
+    off[j] = R.out;
+    stride[j] = R.stride;
+    tc[j] = t0 + sqrt(d2) / v_mute;
+}
+
+hipError_t launch_mute_tables(const Slot* slots, const Rec* rec, int nrec, int ndim, const double* h, double t0,
+                              double v_mute, long long* off, int* stride, double* tc, hipStream_t st) {
+    if (nrec <= 0) return hipSuccess;
+    k_mute_tables<<<(nrec + NTHREADS - 1) / NTHREADS, NTHREADS, 0, st>>>(dev_slots(slots), rec, nrec, ndim, h[0], h[1],
+                                                                         h[2], t0, v_mute, off, stride, tc);
+    return hipGetLastError();
+}
+
 hipError_t launch_mute(float* d, const long long* off, const int* stride, const double* tc, int nrec, int nt,
                        double dt, int ntaper, hipStream_t st) {
     if (nrec <= 0 || nt <= 0) return hipSuccess;

@@ -111,6 +111,8 @@ hipError_t launch_ph_minv(const float* h, double eps, float* minv, long long n, 
 hipError_t launch_mul(const float* a, const float* b, float* out, long long n, hipStream_t st);
 
 // Top mute of recorded data, in place (aux.hip).
+hipError_t launch_mute_tables(const Slot* slots, const Rec* rec, int nrec, int ndim, const double* h, double t0,
+                              double v_mute, long long* off, int* stride, double* tc, hipStream_t st);
 hipError_t launch_mute(float* d, const long long* off, const int* stride, const double* tc, int nrec, int nt,
                        double dt, int ntaper, hipStream_t st);
 

@@ -27,6 +27,7 @@
 #include <cstring>
 #include <list>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2103,6 +2104,68 @@ lsrtm_status lsrtm_mute(lsrtm_ctx* c, float* d, double v_mute, double t0, int nt
     (void)hipFree(d_stride);
     (void)hipFree(d_tc);
     if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "mute: %s", hipGetErrorString(e));
+    return LSRTM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The mute without allocations: its per-receiver tables (trace offset, row
+// length, cut time) are computed on the device from the acquisition the
+// plan already holds, into a file-scope device array (one copy per GPU,
+// shared by every call on that GPU) instead of buffers allocated per call.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr long long kMuteMaxRec = 1LL << 18;   // receivers over all shots
+constexpr long long kMuteScratchBytes = kMuteMaxRec * (8 + 8 + 4);
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+// In host code this name is a stand-in, not a device address: host code uses
+// the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char mute_scratch[kMuteScratchBytes];
+
+static void* g_mute_scratch[kMaxDevices] = {};
+static std::mutex g_mute_scratch_mu;
+
+// Device address of mute_scratch on the current device (looked up on the
+// first call on each device, then kept).
+static lsrtm_status mute_scratch_address(lsrtm_ctx* c, unsigned char** out) {
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) FAIL(c, LSRTM_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_mute_scratch_mu);
+    if (!g_mute_scratch[dev]) {
+        void* p = nullptr;
+        HIPCHK(c, hipGetSymbolAddress(&p, HIP_SYMBOL(mute_scratch)));
+        if (!p) FAIL(c, LSRTM_EHIP, "no device address for the mute scratch");
+        g_mute_scratch[dev] = p;
+    }
+    *out = static_cast<unsigned char*>(g_mute_scratch[dev]);
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_mute_noalloc(lsrtm_ctx* c, float* d, double v_mute, double t0, int ntaper) {
+    if (!c) return LSRTM_EINVAL;
+    if (!c->have_acq) FAIL(c, LSRTM_ESTATE, "set_acquisition must precede lsrtm_mute_noalloc");
+    if (!(v_mute > 0.0) || ntaper < 0 || !std::isfinite(t0)) FAIL(c, LSRTM_EINVAL, "bad mute parameters");
+    if (!d && c->data_len > 0) FAIL(c, LSRTM_EINVAL, "d is NULL");
+    const long long total = c->a_recptr[c->nshot];
+    if (total > kMuteMaxRec)
+        FAIL(c, LSRTM_EINVAL, "%lld receivers; lsrtm_mute_noalloc handles at most %lld (use lsrtm_mute)", total,
+             kMuteMaxRec);
+    if (total == 0) return LSRTM_OK;
+    unsigned char* scr = nullptr;
+    CHK(mute_scratch_address(c, &scr));
+    long long* off = reinterpret_cast<long long*>(scr);
+    double* tc = reinterpret_cast<double*>(scr + 8 * kMuteMaxRec);
+    int* stride = reinterpret_cast<int*>(scr + 16 * kMuteMaxRec);
+    long long base = 0;
+    for (auto& gr : c->groups) {
+        HIPCHK(c, launch_mute_tables(gr.d_slots, gr.d_rec, gr.nrec, c->ndim, c->g.h, t0, v_mute, off + base,
+                                     stride + base, tc + base, c->st));
+        base += gr.nrec;
+    }
+    if (base != total) FAIL(c, LSRTM_EHIP, "receiver count mismatch (%lld of %lld)", base, total);
+    HIPCHK(c, launch_mute(d, off, stride, tc, (int)total, c->g.nt, c->g.dt, ntaper, c->st));
     return LSRTM_OK;
 }
 

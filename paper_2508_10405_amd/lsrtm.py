@@ -69,6 +69,7 @@ SIGNATURES = {
     "lsrtm_psf_images": (_c_int, [_vp, _c_int, _vp]),
     "lsrtm_wiener": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _c_int, _c_double, _vp]),
     "lsrtm_mute": (_c_int, [_vp, _vp, _c_double, _c_double, _c_int]),
+    "lsrtm_mute_noalloc": (_c_int, [_vp, _vp, _c_double, _c_double, _c_int]),
     "lsrtm_psf_apply": (_c_int, [_vp, _vp, _c_int, _c_int, _c_int, _vp, _vp]),
     "lsrtm_psf_cgnr": (_c_int, [_vp, _vp, _c_int, _c_int, _vp, _c_int, _vp, ctypes.POINTER(_c_double)]),
     "lsrtm_dot": (_c_int, [_vp, _vp, _vp, _c_ll, ctypes.POINTER(_c_double)]),
@@ -454,6 +455,17 @@ class Context:
             raise ValueError("d must hold the data length")
         with self._ordered(d):
             self._check(lib().lsrtm_mute(self._h, _vp(_ptr(d)), float(v_mute), float(t0), int(ntaper)), "mute")
+        return d
+
+    def mute_noalloc(self, d, v_mute, t0=0.0, ntaper=0):
+        """The same mute without device allocations (lsrtm_mute_noalloc; at
+        most 2^18 receivers); returns d."""
+        _require_cuda(d, "d")
+        if d.numel() != self.data_len:
+            raise ValueError("d must hold the data length")
+        with self._ordered(d):
+            self._check(lib().lsrtm_mute_noalloc(self._h, _vp(_ptr(d)), float(v_mute), float(t0), int(ntaper)),
+                        "mute_noalloc")
         return d
 
     def wiener(self, m_ref, m_blur, m_in=None, block=64, eps_rel=1e-3):
