@@ -10,7 +10,8 @@ data are Born data of the seeded true perturbation (synthetic).
 One "step" = one CGNR iteration over all 120 shots: a Born pass, a migration
 pass (checkpoint replay + adjoint + imaging), FP64 inner products and vector
 updates, all in the HIP library.  Timed region: K iterations after W warm-up
-iterations, bracketed by device synchronisation.
+iterations, bracketed by device synchronisation, every pass of every launch
+group replayed from its captured HIP graph.
 
 value = grid-point updates per second of the two operator passes
         2 * (sum over shots of padded nodes) * nt * K / time   [Gpts/s]
@@ -20,12 +21,15 @@ and 32 x 16 tiles, the autotuner's pick for this workload on MI355X, with
 32 x 32 tiles for the adjoint A phase (the fastest shape for that phase);
 --shots-per-launch -1 --tile -1 tunes again (per-phase shapes included).
 
-Also reported: the roofline of the dominant kernel (algorithmic bytes per
-launch / average kernel time, from events that the runtime stamps with the
-start and end of every 16th step's kernels, against the 8 TB/s HBM peak),
-the plain per-shot CG-iteration time (one launch per shot, measured on a
-sample of shots and scaled by the shot count), and the FP64 oracle timed on
-the host cores on a bounded sample.
+Also reported: the roofline of the dominant time step (its minimum bytes per
+padded node plus the strips' CPML memories, times the nodes of a launch group,
+over the summed average durations of the step's kernels, against the 8 TB/s
+HBM peak; kernel durations from one further, untimed iteration in which the
+runtime stamps the start and end of every 16th step's kernels), the streaming
+rate of a 1 GiB axpy, the plain per-shot CG-iteration time (one launch per
+shot, measured on a sample of shots and scaled by the shot count), the
+uneven-aperture workload batched against shot by shot, and the FP64 oracle
+timed on the host cores on a bounded sample.
 """
 import argparse
 import hashlib
@@ -223,6 +227,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=100, help="time steps of the oracle sample")
     ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes (0 = min(16, cores))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-passes", action="store_true",
+                    help="skip the separately timed Born and migration passes (long 3D runs)")
     ap.add_argument("--no-config3", action="store_true",
                     help="skip the uneven-aperture (batched vs per-shot) block of the default run")
     ap.add_argument("--calibrate", action="store_true",
@@ -390,23 +396,25 @@ def main():
     dk = max((k for k in btab if kcnt[k]), key=lambda k: kms[k])
     # per-pass rates (outside the timed region): one Born pass, one migration
     # pass, each run once first so that its graphs are captured
-    dtmp = torch.empty(ctx.data_len, device=dev)
-    itmp = torch.empty_like(x)
-    ctx.born(x, d=dtmp)
-    ctx.adjoint(dtmp, img=itmp)
-    torch.cuda.synchronize()
-    tb0 = time.perf_counter()
-    ctx.born(x, d=dtmp)
-    torch.cuda.synchronize()
-    tb1 = time.perf_counter()
-    ctx.adjoint(dtmp, img=itmp)
-    torch.cuda.synchronize()
-    tb2 = time.perf_counter()
-    del dtmp, itmp
-    passes = {"born_s": tb1 - tb0, "migration_s": tb2 - tb1,
-              "born_gpts": padded * w.nt / (tb1 - tb0) / 1e9,
-              "migration_gpts": padded * w.nt / (tb2 - tb1) / 1e9}
-    log(f"[bench] passes {passes}")
+    passes = None
+    if not args.no_passes:
+        dtmp = torch.empty(ctx.data_len, device=dev)
+        itmp = torch.empty_like(x)
+        ctx.born(x, d=dtmp)
+        ctx.adjoint(dtmp, img=itmp)
+        torch.cuda.synchronize()
+        tb0 = time.perf_counter()
+        ctx.born(x, d=dtmp)
+        torch.cuda.synchronize()
+        tb1 = time.perf_counter()
+        ctx.adjoint(dtmp, img=itmp)
+        torch.cuda.synchronize()
+        tb2 = time.perf_counter()
+        del dtmp, itmp
+        passes = {"born_s": tb1 - tb0, "migration_s": tb2 - tb1,
+                  "born_gpts": padded * w.nt / (tb1 - tb0) / 1e9,
+                  "migration_gpts": padded * w.nt / (tb2 - tb1) / 1e9}
+        log(f"[bench] passes {passes}")
 
     pcg = None
     if args.pcgnr > 0:
