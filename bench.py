@@ -251,6 +251,8 @@ def main():
                     help="HBM that may keep the background replays of the last checkpoint segments across "
                          "CG iterations (they depend on the background only); -1 = what the memory plan "
                          "leaves (default), 0 = off")
+    ap.add_argument("--fused", action="store_true",
+                    help="2D: one fused kernel per time step instead of the two-phase step (default two-phase)")
     ap.add_argument("--tune-steps", type=int, default=24)
     ap.add_argument("--pcgnr", type=int, default=0,
                     help="also run N CGNR and N pseudo-Hessian-preconditioned CGNR iterations from x = 0 "
@@ -298,7 +300,7 @@ def main():
     ctx = lsrtm.context_for(w, shots_per_launch=max(0, args.shots_per_launch), tile=args.tile, timing=False,
                             tile_v=args.tile_v, tile_adj_a=args.tile_adj_a,
                             replay_cache_mb=1 << 30 if args.replay_cache_gb < 0 else int(args.replay_cache_gb * 1024),
-                            ckpt_dtype=ckdt, progress=nd == 3)
+                            ckpt_dtype=ckdt, progress=nd == 3, fused=args.fused)
     if args.tile < 0:
         t0 = time.perf_counter()
         tuned = ctx.autotune(nsteps=args.tune_steps, groups=args.shots_per_launch < 0)
