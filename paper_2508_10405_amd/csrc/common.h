@@ -174,22 +174,26 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 // block stages: rows ZL + jz (jz < NZ) and columns XL + jx (jx < NX), where
 // an index jz >= ZW moves down by ZS rows and jx >= XW right by XS columns,
 // so that the two halo strips of one axis form one set.  Cell k of the set
-// goes to thread k % 256, pass k / 256.  load() issues every pass's loads
-// before store() combines them, so a thread's loads are all in flight at
-// once.
-template <int ZL, int NZ, int XL, int NX, int ZW = 0, int ZS = 0, int XW = 0, int XS = 0>
-struct Cells {
+// goes to thread k % NT, pass k / NT (NT threads per block).  load() issues
+// every pass's loads before store() combines them, so a thread's loads are
+// all in flight at once.
+template <int NT, int ZL, int NZ, int XL, int NX, int ZW = 0, int ZS = 0, int XW = 0, int XS = 0>
+struct CellsT {
     static constexpr int N = NZ * NX;
-    static constexpr int IT = (N + NTHREADS - 1) / NTHREADS;
+    static constexpr int IT = (N + NT - 1) / NT;
     __device__ static __forceinline__ void cell(int t, int& lz, int& lx) {
-        const int e = threadIdx.x + NTHREADS * t;
+        const int e = threadIdx.x + NT * t;
         const int jz = e % NZ, jx = e / NZ;
         lz = ZL + jz + ((ZS != 0 && jz >= ZW) ? ZS : 0);
         lx = XL + jx + ((XS != 0 && jx >= XW) ? XS : 0);
+        // past the end of the set: a row far outside every grid, so that the
+        // load goes to the clamped address (a line every block reads) rather
+        // than to a node of another tile
+        if (N % NT != 0 && e >= N) lz = -(1 << 20);
     }
     // ld(lz, lx, vals) issues the K loads of a cell from addresses that are
-    // valid for any (lz, lx): passes past the end of the set load too but
-    // store nothing.
+    // valid for any (lz, lx) (clamped outside the grid): passes past the end
+    // of the set load too but store nothing.
     template <int K, typename LD>
     __device__ static __forceinline__ void load(LD ld, float (&v)[IT][K]) {
 #pragma unroll
@@ -204,13 +208,16 @@ struct Cells {
     __device__ static __forceinline__ void store(ST st, float (&v)[IT][K]) {
 #pragma unroll
         for (int t = 0; t < IT; ++t) {
-            if (N % NTHREADS != 0 && threadIdx.x + NTHREADS * t >= N) continue;
+            if (N % NT != 0 && threadIdx.x + NT * t >= N) continue;
             int lz, lx;
             cell(t, lz, lx);
             st(lz, lx, v[t]);
         }
     }
 };
+// Blocks of NTHREADS threads (every 2D kernel).
+template <int ZL, int NZ, int XL, int NX, int ZW = 0, int ZS = 0, int XW = 0, int XS = 0>
+using Cells = CellsT<NTHREADS, ZL, NZ, XL, NX, ZW, ZS, XW, XS>;
 
 // Whether the CPML coefficients of index g (node or half node) on an axis
 // of n nodes may be nonzero: the absorbing strips are the first npml and the

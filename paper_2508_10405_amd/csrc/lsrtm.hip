@@ -407,16 +407,20 @@ void tile_shape(int ndim, int id, int* bz, int* bx, int* by) {
     }
 }
 
-// Tile table of a group: (slot, z0, x0, y0) of every tile of every slot.
+// Tile table of a group: (slot, z0, x0, w) of every tile of every slot; in
+// 3D w = y0 | y1 << 16, the planes y0 .. y1 - 1 of the tile's march.
 void tile_list(const lsrtm_ctx* c, const Group& gr, int tile, std::vector<int4>& t) {
     int bz, bx, by;
     tile_shape(c->ndim, tile, &bz, &bx, &by);
     t.clear();
     for (int s = 0; s < gr.ns; ++s) {
         const Slot& S = gr.h_slots[s];
-        for (int y0 = 0; y0 < S.n[2]; y0 += by)
+        for (int y0 = 0; y0 < S.n[2]; y0 += by) {
+            const int y1 = std::min(y0 + by, S.n[2]);
             for (int x0 = 0; x0 < S.n[1]; x0 += bx)
-                for (int z0 = 0; z0 < S.n[0]; z0 += bz) t.push_back(make_int4(s, z0, x0, y0));
+                for (int z0 = 0; z0 < S.n[0]; z0 += bz)
+                    t.push_back(make_int4(s, z0, x0, c->ndim == 3 ? y0 | (y1 << 16) : 0));
+        }
     }
 }
 
@@ -900,6 +904,9 @@ lsrtm_status plan(lsrtm_ctx* c) {
             if (W.npts >= (1LL << 30))
                 FAIL(c, LSRTM_EINVAL, "shot %d: padded window of %lld nodes; at most 2^30 - 1 per shot", s,
                      W.npts);
+            // a 3D tile carries its first and last plane in 16 bits each
+            if (W.N[2] > 0xffff)
+                FAIL(c, LSRTM_EINVAL, "shot %d: padded window of %d planes along y; at most 65535", s, W.N[2]);
             w = (int)c->wins.size();
             wid[key] = w;
             c->wins.push_back(W);

@@ -60,7 +60,9 @@ def test_3d_invariances(torch):
     for opts in ({"tile": 0}, {"tile": 1, "shots_per_launch": 1}, {"tile": 2, "ckpt_every": 7},
                  {"tile": 3, "ckpt_every": 50}, {"tile": 4, "ckpt_per_group": True, "shots_per_launch": 2},
                  {"tile": 5, "graph": False}, {"tile": 0, "tile_v": 1, "tile_adj_a": 2},
-                 {"tile": 3, "tile_v": 5, "tile_adj_a": 0, "ckpt_per_group": True}):
+                 {"tile": 3, "tile_v": 5, "tile_adj_a": 0, "ckpt_per_group": True},
+                 {"tile": 6}, {"tile": 7, "shots_per_launch": 1, "ckpt_every": 7},
+                 {"tile": 8, "tile_v": 6, "tile_adj_a": 7, "graph": False}):
         ctx = lsrtm.context_for(w, **opts)
         out = (ctx.born(dm).cpu().numpy(), ctx.adjoint(y).cpu().numpy())
         ctx.close()
@@ -69,6 +71,28 @@ def test_3d_invariances(torch):
         else:
             assert np.array_equal(out[0], ref[0]), opts
             assert np.array_equal(out[1], ref[1]), opts
+
+
+def test_3d_tall_tiles(torch):
+    """The tall tiles in blocks of 1024 threads (256 x 4, 256 x 8 and 128 x 8
+    columns) give the 64 x 4 tile's results bit for bit, on a grid whose
+    padded z extent (162 nodes) is spanned by one 256-row tile (no z-halo)
+    and needs two 128-row tiles (a z-halo between them)."""
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((150, 21, 40), nt=40, npml=6, seed=5, nshot=2, uneven=True, h=12.5)
+    dm = to_dev(torch, w.dm)
+    y = to_dev(torch, np.random.default_rng(2).standard_normal(sum(w.nt * len(r) for r in w.rec)))
+    ref = None
+    for opts in ({"tile": 0}, {"tile": 6}, {"tile": 7}, {"tile": 8},
+                 {"tile": 0, "tile_v": 7, "tile_adj_a": 6}, {"tile": 8, "tile_v": 6, "tile_adj_a": 7}):
+        ctx = lsrtm.context_for(w, **opts)
+        out = (ctx.forward().cpu().numpy(), ctx.born(dm).cpu().numpy(), ctx.adjoint(y).cpu().numpy())
+        ctx.close()
+        if ref is None:
+            ref = out
+        else:
+            for a, b in zip(out, ref):
+                assert np.array_equal(a, b), opts
 
 
 def test_3d_dot_product(torch):
@@ -119,6 +143,12 @@ def test_config5_launch_configuration_window(torch):
         out[dtype] = (ctx.born(to_dev(torch, w.dm)).cpu().numpy(),
                       ctx.adjoint(to_dev(torch, concat(ys))).cpu().numpy())
         ctx.close()
+    # the tall 256 x 4 tiles (blocks of 1024 threads, no z-halo) give the
+    # same results bit for bit
+    ctx = lsrtm.context_for(w, ckpt_dtype="f32", shots_per_launch=1, tile=6, tile_v=7)
+    tall = (ctx.born(to_dev(torch, w.dm)).cpu().numpy(), ctx.adjoint(to_dev(torch, concat(ys))).cpu().numpy())
+    ctx.close()
+    assert np.array_equal(tall[0], out["f32"][0]) and np.array_equal(tall[1], out["f32"][1])
     ref_d, ref_i = running.results()
     assert np.array_equal(out["f32"][0], out["bf16"][0])
     e = rel(out["f32"][0], concat(ref_d))
