@@ -116,6 +116,40 @@ def read_traffic(workload_tag, kernel, pts_per_launch, ndim=2):
     return float(v) * pts_per_launch if v not in (None, "", "null") else None
 
 
+# Array mixes of the stencil phases (reads, writes per node): the 3D Born
+# velocity phase reads 10 arrays and writes 6, its pressure phase 10 and 2,
+# the replay phases 5 and 6 / 5 and 2.
+MIXES = ((10, 6), (10, 2), (5, 6), (5, 2))
+
+
+def mix_calibration(ctx, torch, dev, w, reps=3):
+    """Streaming rate of the stencils' array mixes without the stencil
+    (lsrtm_stream_mix: every element of nread arrays read once, of nwrite
+    arrays written once), walking the elements in order and, for a 3D
+    workload, in the 3D tiles' y-march order over its padded grid; the best
+    of reps passes per mix."""
+    grid = None
+    if w.ndim == 3:
+        N = [(hi - lo) + 2 * w.npml for lo, hi in w.win[0]]
+        ldz = (N[0] + 31) // 32 * 32
+        grid = (N[0], N[1], N[2], ldz)
+        n = ldz * N[1] * N[2]
+    else:
+        n = 1 << 26
+    buf = torch.zeros(16 * n, device=dev)
+    out = {"floats_per_array": n, "grid": list(grid) if grid else None}
+    for nr, nw in MIXES:
+        for order, g in (("flat", None), ("march", grid)):
+            if order == "march" and g is None:
+                continue
+            ctx.stream_mix(buf, n, nr, nw, g)
+            ms = min(ctx.stream_mix(buf, n, nr, nw, g) for _ in range(reps))
+            out[f"{nr}r{nw}w_{order}_GBs"] = 4.0 * (nr + nw) * n / (ms * 1e-3) / 1e9
+    del buf
+    torch.cuda.empty_cache()
+    return out
+
+
 # ---------------------------------------------------------------------------
 def cpu_worker(args):
     """FP64 oracle on one shot of the workload: Born + migration of nt_s steps."""
@@ -362,6 +396,8 @@ def main():
              "avg_ms": ms_ax, "GBs": stream_gbs}
     del a_ax, b_ax
     log(f"[bench] streaming axpy {stream_gbs:.0f} GB/s")
+    calib["stream_mix"] = mix_calibration(ctx, torch, dev, w)
+    log(f"[bench] streaming mixes {calib['stream_mix']}")
 
     # roofline: the dominant time step of the plan (SURVEY 8(d) accounting:
     # the step's minimum bytes per node plus the strip surcharge, over the

@@ -309,6 +309,23 @@ lsrtm_status lsrtm_dot(lsrtm_ctx* ctx, const float* a, const float* b, long long
  * computed in FP64 and rounded once. */
 lsrtm_status lsrtm_axpy(lsrtm_ctx* ctx, double alpha, const float* x, float* y, long long n);
 
+/* Calibration, not a step of the method: the HBM streaming rate of a mix of
+ * arrays like the stencil kernels' (the 3D Born velocity phase reads 10
+ * arrays and writes 6 per node, its pressure phase reads 10 and writes 2).
+ * One pass over nread + nwrite DEVICE arrays of n floats laid out one after
+ * another in buf ((nread + nwrite) * n floats, caller-owned, contents
+ * overwritten): every element of the first nread arrays is read once and
+ * every element of the last nwrite arrays written once.  (nread, nwrite) is
+ * one of (10, 6), (10, 2), (5, 6), (5, 2), (2, 1).  grid = NULL walks the
+ * elements in order; grid = HOST int[4] (nz, nx, ny, ldz), with
+ * n = ldz * nx * ny and nz <= ldz, walks them as the 3D stencil tiles do
+ * (blocks of 64 x 4 z-x columns marching 32 planes along y).  Enqueued on the
+ * context's stream; waits for it and sets *ms (HOST) to the kernel's own
+ * execution time.  Errors: EINVAL (NULL, n < 1, unsupported mix, grid not
+ * matching n), EHIP. */
+lsrtm_status lsrtm_stream_mix(lsrtm_ctx* ctx, float* buf, long long n, int nread, int nwrite, const int* grid,
+                              double* ms);
+
 /* Set an LSRTM_OPT_* option. */
 lsrtm_status lsrtm_set_option(lsrtm_ctx* ctx, int key, long long value);
 

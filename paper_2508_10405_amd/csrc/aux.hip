@@ -477,6 +477,77 @@ hipError_t launch_copy(const float* x, float* y, long long n, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// Calibration: streaming rate of a mix of arrays like the stencil kernels'
+// ---------------------------------------------------------------------------
+struct MixArrays {
+    float* a[16];
+};
+
+// Every element of arrays 0 .. NR-1 read once, of arrays NR .. NR+NW-1
+// written once (the sum of the reads times the array's rank, so that no load
+// is dead), walking the elements in order.
+template <int NR, int NW>
+__global__ void __launch_bounds__(NTHREADS) k_mix_flat(MixArrays A, long long n) {
+    for (long long i = blockIdx.x * (long long)NTHREADS + threadIdx.x; i < n; i += (long long)gridDim.x * NTHREADS) {
+        float s = 0.f;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) s += A.a[k][i];
+#pragma unroll
+        for (int k = 0; k < NW; ++k) A.a[NR + k][i] = s * (float)(k + 1);
+    }
+}
+
+// The same, walking the elements as the 3D stencil tiles do: a block owns a
+// column of 64 x 4 nodes of an nz x nx x ny grid (z stride ldz) and marches
+// 32 planes along y; blocks are remapped onto the XCDs as the tiles are.
+template <int NR, int NW>
+__global__ void __launch_bounds__(NTHREADS) k_mix_march(MixArrays A, int nz, int nx, int ny, int ldz) {
+    const int ntz = (nz + 63) / 64, ntx = (nx + 3) / 4;
+    int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int tz = b % ntz;
+    b /= ntz;
+    const int tx = b % ntx;
+    const int y0 = (b / ntx) * 32, y1 = min(y0 + 32, ny);
+    const int z = tz * 64 + (int)threadIdx.x % 64, x = tx * 4 + (int)threadIdx.x / 64;
+    if (z >= nz || x >= nx) return;
+    for (int y = y0; y < y1; ++y) {
+        const long long i = ((long long)y * nx + x) * ldz + z;
+        float s = 0.f;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) s += A.a[k][i];
+#pragma unroll
+        for (int k = 0; k < NW; ++k) A.a[NR + k][i] = s * (float)(k + 1);
+    }
+}
+
+template <int NR, int NW>
+static hipError_t mix_t(float* buf, long long n, const int* grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    MixArrays A;
+    for (int k = 0; k < 16; ++k) A.a[k] = buf + (long long)(k < NR + NW ? k : 0) * n;
+    if (!grid) {
+        launch_k(k_mix_flat<NR, NW>, dim3(nblocks(n)), dim3(NTHREADS), st, e0, e1, A, n);
+    } else {
+        const long long nb = (long long)((grid[0] + 63) / 64) * ((grid[1] + 3) / 4) * ((grid[2] + 31) / 32);
+        launch_k(k_mix_march<NR, NW>, dim3((unsigned)nb), dim3(NTHREADS), st, e0, e1, A, grid[0], grid[1],
+                 grid[2], grid[3]);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_mix(float* buf, long long n, int nread, int nwrite, const int* grid, hipStream_t st,
+                             hipEvent_t e0, hipEvent_t e1) {
+    const int key = nread * 16 + nwrite;
+    switch (key) {
+    case 10 * 16 + 6: return mix_t<10, 6>(buf, n, grid, st, e0, e1);
+    case 10 * 16 + 2: return mix_t<10, 2>(buf, n, grid, st, e0, e1);
+    case 5 * 16 + 6: return mix_t<5, 6>(buf, n, grid, st, e0, e1);
+    case 5 * 16 + 2: return mix_t<5, 2>(buf, n, grid, st, e0, e1);
+    case 2 * 16 + 1: return mix_t<2, 1>(buf, n, grid, st, e0, e1);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Checkpoints
 // ---------------------------------------------------------------------------
 // Field f of a slot: 0 = p, 1 + a = v_a.

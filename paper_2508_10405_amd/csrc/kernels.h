@@ -149,6 +149,12 @@ hipError_t launch_dot(const float* a, const float* b, long long n, double* parti
 hipError_t launch_axpy(double alpha, const float* x, float* y, long long n, hipStream_t st);
 hipError_t launch_xpby(const float* x, double beta, float* y, long long n, hipStream_t st);
 hipError_t launch_copy(const float* x, float* y, long long n, hipStream_t st);
+// Calibration: one streaming pass over a mix of nread + nwrite arrays of n
+// floats in buf, in order (grid = NULL) or in the 3D tiles' order over the
+// grid (nz, nx, ny, ldz); (nread, nwrite) one of (10, 6), (10, 2), (5, 6),
+// (5, 2), (2, 1), else hipErrorInvalidValue.
+hipError_t launch_stream_mix(float* buf, long long n, int nread, int nwrite, const int* grid, hipStream_t st,
+                             hipEvent_t e0, hipEvent_t e1);
 
 // Checkpoints: per slot, fields p, v_a as FP32/FP16/BF16 with a max-abs scale
 // per field, CPML memories of the strips as FP32.

@@ -1855,6 +1855,29 @@ lsrtm_status lsrtm_axpy(lsrtm_ctx* c, double alpha, const float* x, float* y, lo
     return LSRTM_OK;
 }
 
+lsrtm_status lsrtm_stream_mix(lsrtm_ctx* c, float* buf, long long n, int nread, int nwrite, const int* grid,
+                              double* ms) {
+    if (!c || !buf || !ms || n < 1) return LSRTM_EINVAL;
+    const int key = nread * 16 + nwrite;
+    if (key != 10 * 16 + 6 && key != 10 * 16 + 2 && key != 5 * 16 + 6 && key != 5 * 16 + 2 && key != 2 * 16 + 1)
+        FAIL(c, LSRTM_EINVAL, "stream_mix: unsupported mix (%d reads, %d writes)", nread, nwrite);
+    if (grid && (grid[0] < 1 || grid[1] < 1 || grid[2] < 1 || grid[0] > grid[3] ||
+                 (long long)grid[3] * grid[1] * grid[2] != n))
+        FAIL(c, LSRTM_EINVAL, "stream_mix: grid does not match n = ldz * nx * ny with nz <= ldz");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(c, hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch_stream_mix(buf, n, nread, nwrite, grid, c->st, e0, e1);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) FAIL(c, LSRTM_EHIP, "stream_mix: %s", hipGetErrorString(e));
+    *ms = t;
+    return LSRTM_OK;
+}
+
 // z = M^-1 L^T r (preconditioned run: s = L^T r kept), or z = L^T r.
 static lsrtm_status normal_residual(lsrtm_ctx* c) {
     const long long nm = 2 * c->gpts;

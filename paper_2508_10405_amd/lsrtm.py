@@ -74,6 +74,8 @@ SIGNATURES = {
     "lsrtm_psf_cgnr": (_c_int, [_vp, _vp, _c_int, _c_int, _vp, _c_int, _vp, ctypes.POINTER(_c_double)]),
     "lsrtm_dot": (_c_int, [_vp, _vp, _vp, _c_ll, ctypes.POINTER(_c_double)]),
     "lsrtm_axpy": (_c_int, [_vp, _c_double, _vp, _vp, _c_ll]),
+    "lsrtm_stream_mix": (_c_int, [_vp, _vp, _c_ll, _c_int, _c_int, ctypes.POINTER(_c_int),
+                                  ctypes.POINTER(_c_double)]),
     "lsrtm_set_option": (_c_int, [_vp, _c_int, _c_ll]),
     "lsrtm_sizes": (_c_int, [_vp, ctypes.POINTER(_c_ll), _c_int]),
     "lsrtm_autotune": (_c_int, [_vp, _c_int, _c_int, ctypes.POINTER(_c_double)]),
@@ -503,6 +505,22 @@ class Context:
         with self._ordered(x, y):
             self._check(lib().lsrtm_axpy(self._h, float(alpha), _vp(_ptr(x)), _vp(_ptr(y)), x.numel()), "axpy")
         return y
+
+
+    def stream_mix(self, buf, n, nread, nwrite, grid=None) -> float:
+        """Calibration (lsrtm_stream_mix): kernel time in ms of one streaming
+        pass over nread + nwrite arrays of n floats in buf (a device float
+        tensor of at least (nread + nwrite) * n elements, overwritten); grid =
+        (nz, nx, ny, ldz) walks them in the 3D tiles' order."""
+        _require_cuda(buf, "buf")
+        if buf.numel() < (nread + nwrite) * n:
+            raise ValueError("buf too small")
+        g = (_c_int * 4)(*grid) if grid is not None else None
+        ms = _c_double()
+        with self._ordered(buf):
+            self._check(lib().lsrtm_stream_mix(self._h, _vp(_ptr(buf)), int(n), int(nread), int(nwrite), g,
+                                               ctypes.byref(ms)), "stream_mix")
+        return ms.value
 
 
 def tile_shape(ndim: int, tile_id: int):

@@ -89,6 +89,17 @@ def test_calls_before_setup_report_state():
     assert L.lsrtm_set_option(h, lsrtm.OPT_REPLAY_CACHE_MB, 512) == lsrtm.OK   # planned with the acquisition
     assert L.lsrtm_set_option(h, lsrtm.OPT_GRAPH_CACHE, -1) == lsrtm.EINVAL
     assert L.lsrtm_set_option(h, lsrtm.OPT_GRAPH_CACHE, 4) == lsrtm.OK
+    # the streaming calibration refuses unsupported mixes and grids that do
+    # not match n before it touches the device
+    ms = ctypes.c_double()
+    buf = ctypes.c_void_p(16)
+    assert L.lsrtm_stream_mix(h, buf, 1024, 3, 3, None, ctypes.byref(ms)) == lsrtm.EINVAL
+    assert L.lsrtm_stream_mix(h, None, 1024, 10, 6, None, ctypes.byref(ms)) == lsrtm.EINVAL
+    assert L.lsrtm_stream_mix(h, buf, 0, 10, 6, None, ctypes.byref(ms)) == lsrtm.EINVAL
+    grid = (ctypes.c_int * 4)(40, 8, 4, 32)      # n would be 32 * 8 * 4; nz > ldz
+    assert L.lsrtm_stream_mix(h, buf, 1024, 10, 6, grid, ctypes.byref(ms)) == lsrtm.EINVAL
+    grid = (ctypes.c_int * 4)(30, 8, 4, 32)
+    assert L.lsrtm_stream_mix(h, buf, 1000, 10, 6, grid, ctypes.byref(ms)) == lsrtm.EINVAL
     out = (ctypes.c_longlong * 15)(*([-7] * 15))
     assert L.lsrtm_sizes(h, out, 15) == lsrtm.OK
     # no segment held and no graph before a plan; 14 entries written

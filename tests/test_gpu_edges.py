@@ -323,3 +323,32 @@ def test_context_stream_orders_with_caller_stream(torch):
         assert np.array_equal((d * 1.0).cpu().numpy(), ref[0])
         assert np.array_equal((img * 1.0).cpu().numpy(), ref[1])
         ctx.close()
+
+
+def test_stream_mix_calibration(torch):
+    """The streaming calibration reads and writes exactly the arrays it
+    names: written array k holds (k + 1) times the sum of the read arrays,
+    in order and in the 3D tiles' order (there only the grid's nodes, not the
+    z padding up to ldz)."""
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((8, 9), nt=10, npml=2, seed=1)
+    ctx = lsrtm.context_for(w)
+    nz, nx, ny, ldz = 30, 9, 41, 32
+    n = ldz * nx * ny
+    for grid in (None, (nz, nx, ny, ldz)):
+        for nr, nw in ((10, 6), (10, 2), (5, 6), (5, 2), (2, 1)):
+            rng = np.random.default_rng(nr * 16 + nw)
+            src = rng.integers(-50, 50, (nr, n)).astype(np.float32)
+            buf = torch.zeros((nr + nw) * n, device="cuda")
+            buf[:nr * n] = torch.from_numpy(src.ravel()).cuda()
+            ms = ctx.stream_mix(buf, n, nr, nw, grid)
+            assert ms > 0
+            out = buf[nr * n:].view(nw, n).cpu().numpy()
+            s = src.sum(axis=0)
+            mask = np.ones(n, bool) if grid is None else (np.arange(n) % ldz < nz)
+            for k in range(nw):
+                assert np.array_equal(out[k][mask], (s * (k + 1))[mask]), (grid, nr, nw, k)
+                assert not out[k][~mask].any()
+    with pytest.raises(lsrtm.LsrtmError):
+        ctx.stream_mix(torch.zeros(8 * n, device="cuda"), n, 4, 4)
+    ctx.close()
