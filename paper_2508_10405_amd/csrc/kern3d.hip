@@ -1006,12 +1006,13 @@ static hipError_t launch3_t(int kind, int ntiles, hipStream_t st, const Slot* sl
 }
 
 // Tile shapes (z, x extents and the planes of a march).  Shapes 0-5 run in
-// blocks of 256 threads; the tall shapes 6-8 in blocks of 1024 (one column
-// of 256 rows per four waves, so a tile of 256 rows spans the whole padded z
-// extent of grids up to 256 nodes deep).
+// blocks of 256 threads, 9 and 10 in blocks of 512 (one node per thread);
+// the tall shapes 6-8 in blocks of 1024 (one column of 256 rows per four
+// waves, so a tile of 256 rows spans the whole padded z extent of grids up
+// to 256 nodes deep).
 const int kTiles3[][3] = {{64, 4, 32}, {64, 8, 32}, {64, 8, 64}, {32, 8, 64}, {128, 4, 64}, {64, 4, 64},
-                          {256, 4, 32}, {256, 8, 32}, {128, 8, 32}, {64, 8, 32}, {32, 16, 32}, {128, 4, 32}};
-const int kNumTiles3 = 12;
+                          {256, 4, 32}, {256, 8, 32}, {128, 8, 32}, {64, 8, 32}, {128, 4, 32}};
+const int kNumTiles3 = 11;
 
 hipError_t launch3d(int kind, int tile_id, int ntiles, hipStream_t st, const Slot* slots,
                     const int4* tiles, const Coef& C, int n, int sstep, int flag,
@@ -1027,8 +1028,7 @@ hipError_t launch3d(int kind, int tile_id, int ntiles, hipStream_t st, const Slo
     case 7: return launch3_t<256, 8, 1024>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, e0, e1);
     case 8: return launch3_t<128, 8, 1024>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, e0, e1);
     case 9: return launch3_t<64, 8, 512>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, e0, e1);
-    case 10: return launch3_t<32, 16, 512>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, e0, e1);
-    case 11: return launch3_t<128, 4, 512>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, e0, e1);
+    case 10: return launch3_t<128, 4, 512>(kind, ntiles, st, slots, tiles, C, n, sstep, flag, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
