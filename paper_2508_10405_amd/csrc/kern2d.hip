@@ -461,7 +461,8 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
         const unsigned i = ok[r] ? gx * ldz + gz : 0;
         vz[r] = elem(S.w[0], i);
         vx[r] = elem(S.w[1], i);
-        gk[r] = elem(S.gk, i);
+        gk[r] = __builtin_nontemporal_load(&elem(S.gk, i));   // read once: leaves L2 / the
+                                                              // Infinity Cache to the adjoint state
         qn[r] = __builtin_nontemporal_load(&elem(segq, i));
         s0[r] = elem(S.sb, i);
         s1z[r] = elem(S.sb, gz + 1 < nz ? i + 1 : i);
@@ -519,7 +520,7 @@ k2_a(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, Coef C, in
             if (hz_[r] != 0.f) elem(S.xi[0], i) = cz[r] * (xz[r] + vz[r]);
             if (hx_[r] != 0.f) elem(S.xi[1], i) = cx[r] * (xx[r] + vx[r]);
         }
-        elem(S.gk, i) = gk[r] + qn[r] * qt[r];
+        __builtin_nontemporal_store(gk[r] + qn[r] * qt[r], &elem(S.gk, i));
         const float bz = s0[r] * s1z[r], bx = s0[r] * s1x[r];
         elem(S.w[0], i) = vz[r] + bz * d_half(sez, c, 1, C.c[0]);
         elem(S.w[1], i) = vx[r] + bx * d_half(sex, c, T::LZ, C.c[1]);

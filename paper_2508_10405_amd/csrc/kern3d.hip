@@ -42,10 +42,12 @@ struct Tile3 {
     static_assert(NP % NT == 0, "tile must hold a multiple of the block's threads");
 };
 
-// Loads and stores of arrays that a launch touches at a node's own position
-// only (each value read once and written once): non-temporal, so that they
-// do not evict from L2 the lines of the staged fields, which neighbouring
-// tiles read again as halos.
+// Loads and stores of a shot's arrays that a launch touches at a node's own
+// position only (each value read once and written once): non-temporal, so
+// that they do not evict from L2 the lines of the staged fields, which
+// neighbouring tiles read again as halos.  The model arrays (dt kappa, sb,
+// dlnrho, dlnkappa) are shared by every shot on the same window and keep
+// ordinary loads: the other shots of a launch read them again.
 #ifndef K3_STREAM
 #define K3_STREAM 1
 #endif
@@ -484,13 +486,13 @@ p3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
             if (BORN) Qw[r][7] = ato(S.w[2], r, y + 3);
             const unsigned i = ib[r] + py;
             pp[r] = ldo(S.p, i);
-            kk[r] = ldo(S.kdt, i);
+            kk[r] = elem(S.kdt, i);
             m0[r] = cpo(S.phi[0], pz[r] ? i : 0);
             m1[r] = cpo(S.phi[1], px[r] ? i : 0);
             m2[r] = cpo(S.phi[2], ok[r] && py_ ? i : 0);
             if (BORN) {
                 qq[r] = ldo(S.q, i);
-                lk[r] = ldo(S.dlnk, i);
+                lk[r] = elem(S.dlnk, i);
                 n0[r] = cpo(S.eta[0], pz[r] ? i : 0);
                 n1[r] = cpo(S.eta[1], px[r] ? i : 0);
                 n2[r] = cpo(S.eta[2], ok[r] && py_ ? i : 0);
@@ -903,7 +905,7 @@ b3_tile(const DSlot* __restrict__ slots, const int4* __restrict__ tiles, const C
             pt[r] = ldo(S.q, i);
             gr[r] = ldo(S.gr, i);
             sy_[r] = __builtin_nontemporal_load(&elem(segy, i));
-            kk[r] = ldo(S.kdt, i);
+            kk[r] = elem(S.kdt, i);
             e0[r] = cpo(S.eta[0], pz[r] ? i : 0);
             e1[r] = cpo(S.eta[1], px[r] ? i : 0);
             e2[r] = cpo(S.eta[2], ok[r] && py_ ? i : 0);
