@@ -78,23 +78,26 @@ def test_3d_tall_tiles(torch):
     columns) and the tiles in blocks of 512 (64 x 8, 128 x 4) give the 64 x 4
     tile's results bit for bit, on a grid whose padded z extent (162 nodes)
     is spanned by one 256-row tile (no z-halo) and needs two 128-row tiles
-    (a z-halo between them)."""
+    (a z-halo between them); and on a grid 270 nodes deep (282 padded), where
+    the 256-row tiles too stage a z-halo between two tiles of a column."""
     from paper_2508_10405_amd import lsrtm
-    w = synth.small((150, 21, 40), nt=40, npml=6, seed=5, nshot=2, uneven=True, h=12.5)
-    dm = to_dev(torch, w.dm)
-    y = to_dev(torch, np.random.default_rng(2).standard_normal(sum(w.nt * len(r) for r in w.rec)))
-    ref = None
-    for opts in ({"tile": 0}, {"tile": 6}, {"tile": 7}, {"tile": 8},
-                 {"tile": 0, "tile_v": 7, "tile_adj_a": 6}, {"tile": 8, "tile_v": 6, "tile_adj_a": 7},
-                 {"tile": 9}, {"tile": 10, "tile_v": 9, "tile_adj_a": 10}):
-        ctx = lsrtm.context_for(w, **opts)
-        out = (ctx.forward().cpu().numpy(), ctx.born(dm).cpu().numpy(), ctx.adjoint(y).cpu().numpy())
-        ctx.close()
-        if ref is None:
-            ref = out
-        else:
-            for a, b in zip(out, ref):
-                assert np.array_equal(a, b), opts
+    for n, npml, nt in (((150, 21, 40), 6, 40), ((270, 9, 14), 6, 30)):
+        print(f"[case] tall tiles on {n}, npml {npml}, nt {nt}", flush=True)
+        w = synth.small(n, nt=nt, npml=npml, seed=5, nshot=2, uneven=True, h=12.5)
+        dm = to_dev(torch, w.dm)
+        y = to_dev(torch, np.random.default_rng(2).standard_normal(sum(w.nt * len(r) for r in w.rec)))
+        ref = None
+        for opts in ({"tile": 0}, {"tile": 6}, {"tile": 7}, {"tile": 8},
+                     {"tile": 0, "tile_v": 7, "tile_adj_a": 6}, {"tile": 8, "tile_v": 6, "tile_adj_a": 7},
+                     {"tile": 9}, {"tile": 10, "tile_v": 9, "tile_adj_a": 10}):
+            ctx = lsrtm.context_for(w, **opts)
+            out = (ctx.forward().cpu().numpy(), ctx.born(dm).cpu().numpy(), ctx.adjoint(y).cpu().numpy())
+            ctx.close()
+            if ref is None:
+                ref = out
+            else:
+                for a, b in zip(out, ref):
+                    assert np.array_equal(a, b), (n, opts)
 
 
 def test_3d_dot_product(torch):
