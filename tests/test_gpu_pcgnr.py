@@ -68,6 +68,23 @@ def test_pseudo_hessian_invariant_to_launch_layout(torch):
         assert np.array_equal(h, ref), (spl, tile, fused)
 
 
+def test_pseudo_hessian_3d_invariant_to_tiles(torch):
+    """3D: the accumulation inside the velocity and pressure kernels gives
+    the same bits on every kind of tile (64-row tiles in blocks of 256 and
+    512 threads, tall tiles spanning the whole z extent in blocks of 1024)."""
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((20, 18, 30), nt=40, npml=4, seed=46, nshot=2, uneven=True, h=12.5)
+    ref = None
+    for spl, tile in ((0, 0), (1, 6), (0, 7), (2, 9), (0, 10)):
+        ctx = lsrtm.context_for(w, shots_per_launch=spl, tile=tile)
+        h, _ = ctx.pseudo_hessian(preconditioner=False)
+        h = h.cpu().numpy()
+        ctx.close()
+        if ref is None:
+            ref = h
+        assert np.array_equal(h, ref), (spl, tile)
+
+
 def test_pseudo_hessian_leaves_checkpoints_valid(torch):
     """The pseudo-Hessian pass runs through the field buffers; Born data and
     images computed afterwards are unchanged."""
