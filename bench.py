@@ -26,7 +26,9 @@ padded node plus the strips' CPML memories, times the nodes of a launch group,
 over the summed average durations of the step's kernels, against the 8 TB/s
 HBM peak; kernel durations from one further, untimed iteration in which the
 runtime stamps the start and end of every 16th step's kernels), the streaming
-rate of a 1 GiB axpy, the plain per-shot CG-iteration time (one launch per
+rate of a 1 GiB axpy and of the stencils' array mixes without the stencil
+(lsrtm_stream_mix: in order, and for a 3D workload in the 3D tiles' order),
+the plain per-shot CG-iteration time (one launch per
 shot, measured on a sample of shots and scaled by the shot count), the
 uneven-aperture workload batched against shot by shot, and the FP64 oracle
 timed on the host cores on a bounded sample.
