@@ -364,7 +364,17 @@ enum {
 lsrtm_status lsrtm_stats(lsrtm_ctx* ctx, double* out, int nout);
 
 /* Tile shape of a tile id: out[0] = BZ, out[1] = BX.  Returns LSRTM_EINVAL
- * for an unknown id.  HOST int [2]. */
+ * for an unknown id.  HOST int [2].  In 3D an id also fixes the threads per
+ * block and the planes a tile marches through (results are the same bits
+ * for every id):
+ *   0: 64 x 4 (256 threads, 32 planes)   1: 64 x 8 (256, 32)
+ *   2: 64 x 8 (256, 64)                  3: 32 x 8 (256, 64)
+ *   4: 128 x 4 (256, 64)                 5: 64 x 4 (256, 64)
+ *   6: 256 x 4 (1024, 32)                7: 256 x 8 (1024, 32)
+ *   8: 128 x 8 (1024, 32)                9: 64 x 8 (512, 32)
+ *   10: 128 x 4 (512, 32)
+ * (a tile of 256 rows spans the whole padded z extent of grids up to 256
+ * nodes deep; deeper grids stack such tiles with a z-halo between them). */
 lsrtm_status lsrtm_tile_shape(int ndim, int tile_id, int* out);
 
 /* Release every device resource of the context. */
