@@ -194,6 +194,15 @@ lsrtm_status lsrtm_cgnr_begin(lsrtm_ctx* ctx, const float* d_obs, float* x);
 lsrtm_status lsrtm_cgnr_iterate(lsrtm_ctx* ctx, float* x, double* misfit);
 lsrtm_status lsrtm_cgnr_state(lsrtm_ctx* ctx, int get, float* r, float* z, float* p, double* scal);
 
+/* The step of the last lsrtm_cgnr_iterate (section 3, the CGNR paragraph:
+ * alpha = <z, s> / ||L p||^2, beta = <z, s>_new / <z, s>_old), for logging:
+ * out (HOST double[5]) = (k, alpha, beta, ||L p||^2, normalised misfit
+ * ||r_k||^2 / ||r_0||^2), all FP64 as the solver computed them; alpha, beta
+ * and ||L p||^2 are 0 before the first iteration and for an iteration that
+ * found the residual already zero.  Errors: EINVAL (NULL), ESTATE (no CGNR
+ * run begun). */
+lsrtm_status lsrtm_cgnr_step(lsrtm_ctx* ctx, double* out);
+
 /* Pseudo-Hessian diagonal (appendix B): the diagonal of the Hessian is
  * approximated by the time-integrated energy of the Born secondary source
  * that a unit perturbation radiates in each shot's incident field, summed

@@ -153,6 +153,7 @@ struct lsrtm_ctx {
     float* cg_z = nullptr;
     float* cg_p = nullptr;
     double cg_zz = 0.0, cg_r0 = 0.0, cg_rr = 0.0;   // cg_zz = <z, s> (= <z, z> unpreconditioned)
+    double cg_alpha = 0.0, cg_beta = 0.0, cg_ww = 0.0;   // step of the last iteration
     int cg_k = 0;
     bool cg_active = false;
     // diagonal preconditioner M^-1 of the normal residual (pseudo-Hessian)
@@ -1901,6 +1902,7 @@ lsrtm_status lsrtm_cgnr_begin(lsrtm_ctx* c, const float* d_obs, float* x) {
     CHK(dot_impl(c, c->cg_r, c->cg_r, nd, &c->cg_r0));
     c->cg_rr = c->cg_r0;
     c->cg_k = 0;
+    c->cg_alpha = c->cg_beta = c->cg_ww = 0.0;
     c->cg_active = true;
     CHK(pass_end(c));
     return LSRTM_OK;
@@ -1912,18 +1914,22 @@ lsrtm_status lsrtm_cgnr_iterate(lsrtm_ctx* c, float* x, double* misfit) {
     if (!x) FAIL(c, LSRTM_EINVAL, "x is NULL");
     const long long nm = 2 * c->gpts, nd = c->data_len;
     CHK(pass_begin(c));
+    c->cg_alpha = c->cg_beta = c->cg_ww = 0.0;
     if (c->cg_zz > 0.0 && c->cg_r0 > 0.0) {
         CHK(born_impl(c, c->cg_p, c->cg_w));
         double ww;
         CHK(dot_impl(c, c->cg_w, c->cg_w, nd, &ww));
+        c->cg_ww = ww;
         if (ww > 0.0) {
             const double alpha = c->cg_zz / ww;
+            c->cg_alpha = alpha;
             HIPCHK(c, launch_axpy(alpha, c->cg_p, x, nm, c->st));
             HIPCHK(c, launch_axpy(-alpha, c->cg_w, c->cg_r, nd, c->st));
             CHK(normal_residual(c));
             double zz1;
             CHK(dot_impl(c, c->cg_z, c->cg_pre ? c->cg_s : c->cg_z, nm, &zz1));
             const double beta = zz1 / c->cg_zz;
+            c->cg_beta = beta;
             HIPCHK(c, launch_xpby(c->cg_z, beta, c->cg_p, nm, c->st));
             c->cg_zz = zz1;
         }
@@ -1940,6 +1946,17 @@ lsrtm_status lsrtm_cgnr(lsrtm_ctx* c, const float* d_obs, int niter, float* x, d
     CHK(lsrtm_cgnr_begin(c, d_obs, x));
     if (misfit) misfit[0] = 1.0;
     for (int it = 0; it < niter; ++it) CHK(lsrtm_cgnr_iterate(c, x, misfit ? misfit + it + 1 : nullptr));
+    return LSRTM_OK;
+}
+
+lsrtm_status lsrtm_cgnr_step(lsrtm_ctx* c, double* out) {
+    if (!c || !out) return LSRTM_EINVAL;
+    if (!c->cg_active) FAIL(c, LSRTM_ESTATE, "no CGNR run");
+    out[0] = (double)c->cg_k;
+    out[1] = c->cg_alpha;
+    out[2] = c->cg_beta;
+    out[3] = c->cg_ww;
+    out[4] = c->cg_r0 > 0.0 ? c->cg_rr / c->cg_r0 : 0.0;
     return LSRTM_OK;
 }
 
@@ -1965,6 +1982,7 @@ lsrtm_status lsrtm_cgnr_state(lsrtm_ctx* c, int get, float* r, float* z, float* 
         c->cg_r0 = scal[1];
         c->cg_rr = scal[2];
         c->cg_k = (int)scal[3];
+        c->cg_alpha = c->cg_beta = c->cg_ww = 0.0;
         c->cg_active = true;
         c->cg_pre = c->precond;
     }

@@ -76,6 +76,7 @@ SIGNATURES = {
     "lsrtm_axpy": (_c_int, [_vp, _c_double, _vp, _vp, _c_ll]),
     "lsrtm_stream_mix": (_c_int, [_vp, _vp, _c_ll, _c_int, _c_int, ctypes.POINTER(_c_int),
                                   ctypes.POINTER(_c_double)]),
+    "lsrtm_cgnr_step": (_c_int, [_vp, ctypes.POINTER(_c_double)]),
     "lsrtm_set_option": (_c_int, [_vp, _c_int, _c_ll]),
     "lsrtm_sizes": (_c_int, [_vp, ctypes.POINTER(_c_ll), _c_int]),
     "lsrtm_autotune": (_c_int, [_vp, _c_int, _c_int, ctypes.POINTER(_c_double)]),
@@ -319,13 +320,44 @@ class Context:
                         "adjoint")
         return img
 
-    def cgnr(self, d_obs, niter, x=None):
+    def cgnr(self, d_obs, niter, x=None, log=None):
+        """niter CGNR iterations from x = 0; returns (x, normalised misfits).
+        With log (a path), one JSON line per iteration is appended to it:
+        the iteration, misfit, alpha, beta and ||L p||^2 (lsrtm_cgnr_step),
+        the iteration's wall time and its Gpts/s (padded nodes x nt x 2
+        passes)."""
         _require_cuda(d_obs, "d_obs")
-        x = self._image(x)
-        mis = (_c_double * (niter + 1))()
-        with self._ordered(d_obs, x):
-            self._check(lib().lsrtm_cgnr(self._h, _vp(_ptr(d_obs)), int(niter), _vp(_ptr(x)), mis), "cgnr")
-        return x, [float(v) for v in mis]
+        if log is None:
+            x = self._image(x)
+            mis = (_c_double * (niter + 1))()
+            with self._ordered(d_obs, x):
+                self._check(lib().lsrtm_cgnr(self._h, _vp(_ptr(d_obs)), int(niter), _vp(_ptr(x)), mis), "cgnr")
+            return x, [float(v) for v in mis]
+        import json
+        import time
+        torch = self._torch
+        x = self.cgnr_begin(d_obs, x)
+        mis = [1.0]
+        pts = self.sizes()["padded_points"]
+        with open(log, "a") as f:
+            for _ in range(int(niter)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                self.cgnr_iterate(x)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                st = self.cgnr_step()
+                mis.append(st["misfit"])
+                f.write(json.dumps({**st, "seconds": dt, "gpts": 2.0 * pts * self.nt / dt / 1e9}) + "\n")
+                f.flush()
+        return x, mis
+
+    def cgnr_step(self):
+        """The last iteration's step (lsrtm_cgnr_step): k, alpha, beta,
+        ||L p||^2 and the normalised misfit, as the solver computed them."""
+        out = (_c_double * 5)()
+        self._check(lib().lsrtm_cgnr_step(self._h, out), "cgnr_step")
+        return {"iter": int(out[0]), "alpha": out[1], "beta": out[2], "ww": out[3], "misfit": out[4]}
 
     def cgnr_begin(self, d_obs, x=None):
         _require_cuda(d_obs, "d_obs")

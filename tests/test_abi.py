@@ -83,6 +83,9 @@ def test_calls_before_setup_report_state():
     assert L.lsrtm_create(ctypes.byref(g), None, ctypes.byref(h)) == 0
     assert L.lsrtm_born(h, ctypes.c_void_p(16), ctypes.c_void_p(16)) == lsrtm.ESTATE
     assert L.lsrtm_set_acquisition(h, 1, None, None, None, None, None) == lsrtm.ESTATE
+    step = (ctypes.c_double * 5)()
+    assert L.lsrtm_cgnr_step(h, step) == lsrtm.ESTATE          # no CGNR run begun
+    assert L.lsrtm_cgnr_step(h, None) == lsrtm.EINVAL
     assert L.lsrtm_set_option(h, 99, 0) == lsrtm.EINVAL
     assert L.lsrtm_set_option(h, lsrtm.OPT_TILE, 42) == lsrtm.EINVAL
     assert L.lsrtm_set_option(h, lsrtm.OPT_REPLAY_CACHE_MB, -1) == lsrtm.EINVAL

@@ -366,3 +366,34 @@ def test_cgnr_resume_from_saved_state(torch):
     m3 = ctx.cgnr_iterate(x)
     assert np.array_equal(x.cpu().numpy(), x_ref)
     assert m3 == m[2]
+
+
+def test_cgnr_step_log(torch, tmp_path):
+    """The CG log: one JSON line per iteration with the solver's own alpha,
+    beta, ||L p||^2 and misfit.  alpha is <z, s> / ||L p||^2 of the state
+    before the iteration (recomputed here with the library's Born pass and
+    FP64 dot, bit for bit), beta the ratio of the new and old <z, s>, and the
+    misfits equal those of the plain solver call."""
+    import json
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((36, 50), nt=90, npml=5, seed=18, nshot=2, uneven=True)
+    ctx = lsrtm.context_for(w, tile=1)
+    dobs = ctx.born(to_dev(torch, w.dm)).clone()
+    _, m_plain = ctx.cgnr(dobs, 3)
+    log = tmp_path / "cg.jsonl"
+    x, m_log = ctx.cgnr(dobs, 3, log=str(log))
+    assert m_log == m_plain
+    lines = [json.loads(s) for s in log.read_text().splitlines()]
+    assert [e["iter"] for e in lines] == [1, 2, 3]
+    assert [e["misfit"] for e in lines] == m_plain[1:]
+    assert all(e["seconds"] > 0 and e["gpts"] > 0 for e in lines)
+    # alpha and beta of one more iteration against the exported state
+    st = ctx.cgnr_get_state()
+    zs = st["scalars"][0]
+    wp = ctx.born(st["p"])
+    ww = ctx.dot(wp, wp)
+    ctx.cgnr_iterate(x)
+    step = ctx.cgnr_step()
+    assert step["iter"] == 4 and step["ww"] == ww and step["alpha"] == zs / ww
+    assert step["beta"] == ctx.cgnr_get_state()["scalars"][0] / zs
+    ctx.close()
