@@ -17,9 +17,9 @@ value = grid-point updates per second of the two operator passes
         2 * (sum over shots of padded nodes) * nt * K / time   [Gpts/s]
 
 Launch configuration: 32 shots per launch group (balanced to 4 groups of 30)
-and 32 x 16 tiles, the autotuner's pick for this workload on MI355X, with
-32 x 32 tiles for the adjoint A phase (the fastest shape for that phase);
---shots-per-launch -1 --tile -1 tunes again (per-phase shapes included).
+and 32 x 16 tiles for every phase, the autotuner's pick for this workload on
+MI355X; --shots-per-launch -1 --tile -1 --tile-adj-a -1 tunes again (per-phase
+shapes included).
 
 Also reported: the roofline of the dominant time step (its minimum bytes per
 padded node plus the strips' CPML memories, times the nodes of a launch group,
@@ -212,7 +212,7 @@ def form2_block(lsrtm, synth, torch, dev, steps=2, plain_shots=16):
     import numpy as np
     w = synth.config3()
     padded = w.padded_points()
-    ctx = lsrtm.context_for(w, shots_per_launch=32, tile=1, tile_adj_a=2, replay_cache_mb=1 << 30)
+    ctx = lsrtm.context_for(w, shots_per_launch=32, tile=1, replay_cache_mb=1 << 30)
     sz = ctx.sizes()
     dm = torch.from_numpy(w.dm).to(dev)
     d_obs = ctx.born(dm)
@@ -280,9 +280,8 @@ def main():
                     help="tile shape id of the velocity phases (-1 = the stencil tile; default: -1 for "
                          "the 2D workloads, 1 = 64 x 8 x 32 for config5)")
     ap.add_argument("--tile-adj-a", type=int, default=None,
-                    help="tile shape id of the adjoint A phase (-1 = the stencil tile; default: 2 = "
-                         "32 x 32 for the 2D workloads, the fastest shape for that phase on MI355X, and "
-                         "-1 for config5)")
+                    help="tile shape id of the adjoint A phase (-1 = the stencil tile, the default; the "
+                         "autotuner's pick for the 2D workloads on MI355X)")
     ap.add_argument("--replay-cache-gb", type=float, default=-1,
                     help="HBM that may keep the background replays of the last checkpoint segments across "
                          "CG iterations (they depend on the background only); -1 = what the memory plan "
@@ -313,7 +312,7 @@ def main():
     if args.tile_v is None:
         args.tile_v = 1 if args.workload == "config5" else -1
     if args.tile_adj_a is None:
-        args.tile_adj_a = -1 if args.workload == "config5" else 2
+        args.tile_adj_a = -1
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the shot-parallel "
               "multi-GPU layout is not built", file=sys.stderr)

@@ -28,7 +28,7 @@ M = 300   # sampled time steps
 # launch (balanced groups), 32 x 16 tiles, 32 x 32 tiles for the adjoint A
 # phase; the benchmark also keeps a replay cache, which the sampled tests
 # below leave off and test_config2_replay_cache_plan turns on
-BENCH_2D = dict(shots_per_launch=32, tile=1, tile_adj_a=2)
+BENCH_2D = dict(shots_per_launch=32, tile=1)
 
 
 @pytest.fixture(scope="module")
