@@ -48,23 +48,8 @@ struct Tile3 {
 // neighbouring tiles read again as halos.  The model arrays (dt kappa, sb,
 // dlnrho, dlnkappa) are shared by every shot on the same window and keep
 // ordinary loads: the other shots of a launch read them again.
-#ifndef K3_STREAM
-#define K3_STREAM 1
-#endif
-__device__ __forceinline__ float ldo(const gfloat* a, unsigned i) {
-#if K3_STREAM
-    return __builtin_nontemporal_load(&elem(a, i));
-#else
-    return elem(a, i);
-#endif
-}
-__device__ __forceinline__ void sto(gfloat* a, unsigned i, float v) {
-#if K3_STREAM
-    __builtin_nontemporal_store(v, &elem(a, i));
-#else
-    elem(a, i) = v;
-#endif
-}
+__device__ __forceinline__ float ldo(const gfloat* a, unsigned i) { return __builtin_nontemporal_load(&elem(a, i)); }
+__device__ __forceinline__ void sto(gfloat* a, unsigned i, float v) { __builtin_nontemporal_store(v, &elem(a, i)); }
 
 // Whether a tile spans the whole padded z extent: its z-halo then lies
 // outside the grid on both sides and is zero.
