@@ -25,9 +25,9 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-4
 M = 300   # sampled time steps
 # the launch configuration bench.py times for the 2D workloads: 32 shots per
-# launch (balanced groups), 32 x 16 tiles, 32 x 32 tiles for the adjoint A
-# phase; the benchmark also keeps a replay cache, which the sampled tests
-# below leave off and test_config2_replay_cache_plan turns on
+# launch (balanced groups), 32 x 16 tiles for every phase; the benchmark also
+# keeps a replay cache, which the sampled tests below leave off and
+# test_config2_replay_cache_plan turns on
 BENCH_2D = dict(shots_per_launch=32, tile=1)
 
 
@@ -135,8 +135,8 @@ def test_config5_full_size_dot(torch):
 
 def test_config2_replay_cache_plan(torch):
     """The benchmark's plan with the replay cache on the full config-2 grid and
-    all 120 shots: launch groups of 30, 32 x 16 tiles (32 x 32 for the adjoint
-    A phase), checkpoint interval 131, the replays of the last segments kept
+    all 120 shots: launch groups of 30, 32 x 16 tiles for every phase,
+    checkpoint interval 131, the replays of the last segments kept
     in HBM.  The time axis is cut to 600 steps (5 segments, the last one
     partial) so that the oracle can run two whole shots; the cache holds 3 of
     the segments.  The first migration fills the cache; the second Born pass
