@@ -32,6 +32,9 @@
  *     The library owns only its internal workspaces.
  *   - Every call returns LSRTM_OK or a negative lsrtm_status; nothing aborts.
  *     lsrtm_last_error(ctx) returns a description of the last failure.
+ *   - A NULL ctx is LSRTM_EINVAL for every call that takes one, checked before
+ *     any other argument (lsrtm_destroy ignores it, lsrtm_last_error returns
+ *     an empty string).
  *   - Call order: create -> set_model -> set_acquisition ->
  *     {forward | born | adjoint | cgnr}*.  set_model may be called again
  *     later; other orders return LSRTM_ESTATE.
@@ -179,7 +182,9 @@ lsrtm_status lsrtm_adjoint(lsrtm_ctx* ctx, const float* d, float* img, int accum
 /* niter CGNR iterations on L^T L x = L^T d_obs from x = 0 (section 3).
  * d_obs: DEVICE float [data]; x: DEVICE float [2][nz*nx*ny] output;
  * misfit: HOST double [niter+1] receives ||r_k||^2 / ||r_0||^2 (may be NULL).
- * Workspace vectors are owned by the library. */
+ * Workspace vectors are owned by the library.  Errors: EINVAL (NULL ctx or x,
+ * niter < 0, NULL d_obs with data), ESTATE (no model or acquisition), ENOMEM,
+ * EHIP. */
 lsrtm_status lsrtm_cgnr(lsrtm_ctx* ctx, const float* d_obs, int niter, float* x, double* misfit);
 
 /* Step-wise CGNR (the same iteration as lsrtm_cgnr).

@@ -1942,6 +1942,7 @@ lsrtm_status lsrtm_cgnr_iterate(lsrtm_ctx* c, float* x, double* misfit) {
 }
 
 lsrtm_status lsrtm_cgnr(lsrtm_ctx* c, const float* d_obs, int niter, float* x, double* misfit) {
+    if (!c) return LSRTM_EINVAL;
     if (niter < 0) FAIL(c, LSRTM_EINVAL, "niter < 0");
     CHK(lsrtm_cgnr_begin(c, d_obs, x));
     if (misfit) misfit[0] = 1.0;

@@ -110,6 +110,91 @@ def test_calls_before_setup_report_state():
     L.lsrtm_destroy(h)
 
 
+def test_every_entry_point_refuses_a_null_context():
+    """A NULL context is an invalid argument for every entry point that takes
+    one (checked before anything else, also where another argument is bad
+    too, such as a negative iteration count); destroy ignores it and
+    last_error returns an empty string.  Every other pointer passed here is a
+    dummy that must not be touched."""
+    L = lsrtm.lib()
+    P = ctypes.c_void_p(16)
+    dbl = ctypes.c_double()
+    dbls = (ctypes.c_double * 16)()
+    lls = (ctypes.c_longlong * 16)()
+    grid = (ctypes.c_int * 4)(32, 8, 4, 32)
+    calls = {
+        "set_option": lambda: L.lsrtm_set_option(None, lsrtm.OPT_TILE, 0),
+        "set_model": lambda: L.lsrtm_set_model(None, P, P),
+        "set_acquisition": lambda: L.lsrtm_set_acquisition(None, 1, P, P, P, P, P),
+        "autotune": lambda: L.lsrtm_autotune(None, 4, 0, dbls),
+        "sizes": lambda: L.lsrtm_sizes(None, lls, 15),
+        "stats": lambda: L.lsrtm_stats(None, dbls, 16),
+        "forward": lambda: L.lsrtm_forward(None, P),
+        "born": lambda: L.lsrtm_born(None, P, P),
+        "adjoint": lambda: L.lsrtm_adjoint(None, P, P, 0),
+        "dot": lambda: L.lsrtm_dot(None, P, P, 4, ctypes.byref(dbl)),
+        "axpy": lambda: L.lsrtm_axpy(None, 1.0, P, P, 4),
+        "stream_mix": lambda: L.lsrtm_stream_mix(None, P, 1024, 10, 6, grid, ctypes.byref(dbl)),
+        "cgnr_begin": lambda: L.lsrtm_cgnr_begin(None, P, P),
+        "cgnr_iterate": lambda: L.lsrtm_cgnr_iterate(None, P, dbls),
+        "cgnr": lambda: L.lsrtm_cgnr(None, P, 1, P, dbls),
+        "cgnr negative niter": lambda: L.lsrtm_cgnr(None, P, -1, P, dbls),
+        "cgnr_step": lambda: L.lsrtm_cgnr_step(None, dbls),
+        "cgnr_state": lambda: L.lsrtm_cgnr_state(None, 1, P, P, P, dbls),
+        "pseudo_hessian": lambda: L.lsrtm_pseudo_hessian(None, P, P, 1e-3),
+        "set_preconditioner": lambda: L.lsrtm_set_preconditioner(None, P),
+        "psf_images": lambda: L.lsrtm_psf_images(None, 4, P),
+        "psf_apply": lambda: L.lsrtm_psf_apply(None, P, 4, 0, 0, P, P),
+        "psf_cgnr": lambda: L.lsrtm_psf_cgnr(None, P, 4, 0, P, 1, P, dbls),
+        "mute": lambda: L.lsrtm_mute(None, P, 1500.0, 0.0, 0),
+        "mute_noalloc": lambda: L.lsrtm_mute_noalloc(None, P, 1500.0, 0.0, 0),
+        "wiener": lambda: L.lsrtm_wiener(None, P, P, P, 1, 16, 1e-3, P),
+    }
+    got = {name: call() for name, call in calls.items()}
+    assert got == {name: lsrtm.EINVAL for name in calls}
+    L.lsrtm_destroy(None)
+    assert L.lsrtm_last_error(None) == b""
+
+
+def test_calls_before_the_model_report_state():
+    """On a fresh context (no model, no acquisition) every call that needs
+    them returns ESTATE before it touches its (dummy) device pointers, and
+    leaves a description in last_error."""
+    L = lsrtm.lib()
+    g = lsrtm.Grid()
+    g.ndim = 2
+    g.n[0], g.n[1], g.n[2] = 10, 12, 1
+    g.h[0] = g.h[1] = g.h[2] = 10.0
+    g.npml, g.pml_R, g.pml_f0, g.nt, g.dt = 4, 1e-4, 10.0, 10, 1e-3
+    h = ctypes.c_void_p()
+    assert L.lsrtm_create(ctypes.byref(g), None, ctypes.byref(h)) == 0
+    P = ctypes.c_void_p(16)
+    dbls = (ctypes.c_double * 16)()
+    calls = {
+        "autotune": lambda: L.lsrtm_autotune(h, 4, 0, dbls),
+        "forward": lambda: L.lsrtm_forward(h, P),
+        "born": lambda: L.lsrtm_born(h, P, P),
+        "adjoint": lambda: L.lsrtm_adjoint(h, P, P, 0),
+        "cgnr_begin": lambda: L.lsrtm_cgnr_begin(h, P, P),
+        "cgnr_iterate": lambda: L.lsrtm_cgnr_iterate(h, P, dbls),
+        "cgnr": lambda: L.lsrtm_cgnr(h, P, 2, P, dbls),
+        "cgnr_state": lambda: L.lsrtm_cgnr_state(h, 1, P, P, P, dbls),
+        "pseudo_hessian": lambda: L.lsrtm_pseudo_hessian(h, P, P, 1e-3),
+        "psf_images": lambda: L.lsrtm_psf_images(h, 4, P),
+        "psf_cgnr": lambda: L.lsrtm_psf_cgnr(h, P, 4, 0, P, 1, P, dbls),
+        "mute": lambda: L.lsrtm_mute(h, P, 1500.0, 0.0, 0),
+        "mute_noalloc": lambda: L.lsrtm_mute_noalloc(h, P, 1500.0, 0.0, 0),
+    }
+    try:
+        for name, call in calls.items():
+            assert call() == lsrtm.ESTATE, name
+            assert L.lsrtm_last_error(h), name
+        # a negative iteration count is refused as an argument error first
+        assert L.lsrtm_cgnr(h, P, -1, P, dbls) == lsrtm.EINVAL
+    finally:
+        L.lsrtm_destroy(h)
+
+
 def test_binding_constants_match_the_header():
     """Every option key, status code, snapshot storage code and the kernel
     class count the binding passes are the header's values."""
