@@ -286,14 +286,26 @@ class Context:
             raise ValueError(f"data vector must have {self.data_len} values")
         return d
 
-    def _image(self, img):
+    def _image(self, img, name="image"):
         torch = self._torch
         if img is None:
             img = torch.empty((2,) + self.shape, dtype=torch.float32, device="cuda")
-        _require_cuda(img, "img")
+        _require_cuda(img, name)
         if tuple(img.shape) != (2,) + self.shape:
-            raise ValueError(f"image must have shape {(2,) + self.shape}")
+            raise ValueError(f"{name} must have shape {(2,) + self.shape}")
         return img
+
+    def _data_in(self, d, name):
+        _require_cuda(d, name)
+        if d.numel() != self.data_len:
+            raise ValueError(f"{name} must have {self.data_len} values")
+        return d
+
+    def _psf(self, psf):
+        _require_cuda(psf, "psf")
+        if tuple(psf.shape) != (2, 2) + self.shape:
+            raise ValueError(f"psf must have shape {(2, 2) + self.shape}")
+        return psf
 
     def forward(self, d=None):
         d = self._data(d)
@@ -311,9 +323,7 @@ class Context:
         return d
 
     def adjoint(self, d, img=None, accumulate=False):
-        _require_cuda(d, "d")
-        if d.numel() != self.data_len:
-            raise ValueError(f"data vector must have {self.data_len} values")
+        self._data_in(d, "d")
         img = self._image(img)
         with self._ordered(d, img):
             self._check(lib().lsrtm_adjoint(self._h, _vp(_ptr(d)), _vp(_ptr(img)), int(bool(accumulate))),
@@ -326,7 +336,9 @@ class Context:
         the iteration, misfit, alpha, beta and ||L p||^2 (lsrtm_cgnr_step),
         the iteration's wall time and its Gpts/s (padded nodes x nt x 2
         passes)."""
-        _require_cuda(d_obs, "d_obs")
+        self._data_in(d_obs, "d_obs")
+        if niter < 0:
+            raise ValueError("niter must be >= 0")
         if log is None:
             x = self._image(x)
             mis = (_c_double * (niter + 1))()
@@ -360,14 +372,14 @@ class Context:
         return {"iter": int(out[0]), "alpha": out[1], "beta": out[2], "ww": out[3], "misfit": out[4]}
 
     def cgnr_begin(self, d_obs, x=None):
-        _require_cuda(d_obs, "d_obs")
-        x = self._image(x)
+        self._data_in(d_obs, "d_obs")
+        x = self._image(x, "x")
         with self._ordered(d_obs, x):
             self._check(lib().lsrtm_cgnr_begin(self._h, _vp(_ptr(d_obs)), _vp(_ptr(x))), "cgnr_begin")
         return x
 
     def cgnr_iterate(self, x) -> float:
-        _require_cuda(x, "x")
+        self._image(x, "x")
         m = _c_double()
         with self._ordered(x):
             self._check(lib().lsrtm_cgnr_iterate(self._h, _vp(_ptr(x)), ctypes.byref(m)), "cgnr_iterate")
@@ -385,9 +397,12 @@ class Context:
         return {"r": r, "z": z, "p": p, "scalars": [float(v) for v in sc]}
 
     def cgnr_set_state(self, st):
+        if len(st["scalars"]) != 4:
+            raise ValueError("the CG state holds 4 scalars")
         sc = (_c_double * 4)(*st["scalars"])
-        for k in ("r", "z", "p"):
-            _require_cuda(st[k], k)
+        self._data_in(st["r"], "r")
+        self._image(st["z"], "z")
+        self._image(st["p"], "p")
         with self._ordered(st["r"], st["z"], st["p"]):
             self._check(lib().lsrtm_cgnr_state(self._h, 0, _vp(_ptr(st["r"])), _vp(_ptr(st["z"])),
                                                _vp(_ptr(st["p"])), sc), "cgnr_state")
@@ -462,7 +477,7 @@ class Context:
 
     def psf_apply(self, psf, spacing, x, transpose=False, mono=False):
         """y = H x or H^T x with the interpolated PSF Hessian (lsrtm_psf_apply)."""
-        _require_cuda(psf, "psf")
+        self._psf(psf)
         self._psf_vec(x, mono, "x")
         y = self._torch.empty_like(x)
         with self._ordered(psf, x, y):
@@ -473,8 +488,10 @@ class Context:
     def psf_cgnr(self, psf, spacing, m_rtm, niter, mono=False):
         """Image-domain CGNR with the PSF Hessian; returns x and the misfit
         history (lsrtm_psf_cgnr)."""
-        _require_cuda(psf, "psf")
+        self._psf(psf)
         self._psf_vec(m_rtm, mono, "m_rtm")
+        if niter < 0:
+            raise ValueError("niter must be >= 0")
         x = self._torch.empty_like(m_rtm)
         mis = (_c_double * (niter + 1))()
         with self._ordered(psf, m_rtm, x):
@@ -484,9 +501,7 @@ class Context:
 
     def mute(self, d, v_mute, t0=0.0, ntaper=0):
         """Top mute of a data vector in place (lsrtm_mute); returns d."""
-        _require_cuda(d, "d")
-        if d.numel() != self.data_len:
-            raise ValueError("d must hold the data length")
+        self._data_in(d, "d")
         with self._ordered(d):
             self._check(lib().lsrtm_mute(self._h, _vp(_ptr(d)), float(v_mute), float(t0), int(ntaper)), "mute")
         return d
@@ -494,9 +509,7 @@ class Context:
     def mute_noalloc(self, d, v_mute, t0=0.0, ntaper=0):
         """The same mute without device allocations (lsrtm_mute_noalloc; at
         most 2^18 receivers); returns d."""
-        _require_cuda(d, "d")
-        if d.numel() != self.data_len:
-            raise ValueError("d must hold the data length")
+        self._data_in(d, "d")
         with self._ordered(d):
             self._check(lib().lsrtm_mute_noalloc(self._h, _vp(_ptr(d)), float(v_mute), float(t0), int(ntaper)),
                         "mute_noalloc")

@@ -8,6 +8,8 @@
 * A CG run saved to a file after two iterations and resumed in a new
   context continues with the same iterates, bit for bit (plain and
   preconditioned).
+* Tensors of the wrong size, device or dtype are refused by the binding
+  before any launch.
 """
 import os
 
@@ -86,3 +88,59 @@ def test_cg_state_file_resume(torch, tmp_path, precond):
     with pytest.raises(ValueError):
         lsrtm.context_for(synth.small((30, 50), nt=90, npml=5, seed=92, nshot=2, uneven=True)).cgnr_load(path)
     ctx.close()
+
+
+def test_binding_refuses_wrong_sizes(torch):
+    """Every binding method that hands a caller's tensor to the library checks
+    its device, dtype, contiguity and size first (the library trusts the sizes
+    it is given), so a wrong tensor raises before any launch and leaves the
+    context usable: a Born call afterwards equals one on a fresh context."""
+    from paper_2508_10405_amd import lsrtm
+    w = synth.small((30, 40), nt=60, npml=5, seed=93, nshot=2, uneven=True)
+    ctx = lsrtm.context_for(w, tile=1)
+    shape, nd = ctx.shape, ctx.data_len
+    dm = to_dev(torch, w.dm)
+    good_d = torch.zeros(nd, device="cuda")
+    short_d = torch.zeros(nd - 1, device="cuda")
+    bad_img = torch.zeros((1,) + shape, device="cuda")
+    x = ctx.cgnr_begin(good_d.clone() + 1.0)
+    st = ctx.cgnr_get_state()
+    refused = {
+        "born dm": lambda: ctx.born(bad_img),
+        "born d": lambda: ctx.born(dm, short_d),
+        "adjoint d": lambda: ctx.adjoint(short_d),
+        "adjoint img": lambda: ctx.adjoint(good_d, bad_img),
+        "cgnr d_obs": lambda: ctx.cgnr(short_d, 1),
+        "cgnr niter": lambda: ctx.cgnr(good_d, -1),
+        "cgnr x": lambda: ctx.cgnr(good_d, 1, bad_img),
+        "cgnr_begin d_obs": lambda: ctx.cgnr_begin(short_d),
+        "cgnr_begin x": lambda: ctx.cgnr_begin(good_d, bad_img),
+        "cgnr_iterate x": lambda: ctx.cgnr_iterate(x[:1]),
+        "cgnr_set_state r": lambda: ctx.cgnr_set_state({**st, "r": st["r"][:-1]}),
+        "cgnr_set_state z": lambda: ctx.cgnr_set_state({**st, "z": st["z"][:1]}),
+        "cgnr_set_state p": lambda: ctx.cgnr_set_state({**st, "p": st["p"][:1]}),
+        "cgnr_set_state scalars": lambda: ctx.cgnr_set_state({**st, "scalars": st["scalars"][:3]}),
+        "set_preconditioner": lambda: ctx.set_preconditioner(bad_img),
+        "psf_apply psf": lambda: ctx.psf_apply(torch.zeros((2, 1) + shape, device="cuda"), 8, dm),
+        "psf_apply x": lambda: ctx.psf_apply(torch.zeros((2, 2) + shape, device="cuda"), 8, bad_img),
+        "psf_cgnr psf": lambda: ctx.psf_cgnr(torch.zeros((1, 2) + shape, device="cuda"), 8, dm, 1),
+        "psf_cgnr niter": lambda: ctx.psf_cgnr(torch.zeros((2, 2) + shape, device="cuda"), 8, dm, -1),
+        "mute": lambda: ctx.mute(short_d, 1500.0),
+        "mute_noalloc": lambda: ctx.mute_noalloc(short_d, 1500.0),
+        "dot": lambda: ctx.dot(good_d, short_d),
+        "axpy": lambda: ctx.axpy(1.0, good_d, short_d),
+    }
+    for name, call in refused.items():
+        print("[case]", name, flush=True)
+        with pytest.raises(ValueError):
+            call()
+    with pytest.raises(TypeError):
+        ctx.adjoint(good_d.cpu())
+    with pytest.raises(TypeError):
+        ctx.adjoint(good_d.double())
+    torch.cuda.synchronize()
+    d = ctx.born(dm).cpu().numpy()
+    ctx.close()
+    fresh = lsrtm.context_for(w, tile=1)
+    assert np.array_equal(d, fresh.born(dm).cpu().numpy())
+    fresh.close()
