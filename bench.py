@@ -400,9 +400,10 @@ def main():
     calib["stream_mix"] = mix_calibration(ctx, torch, dev, w)
     log(f"[bench] streaming mixes {calib['stream_mix']}")
 
-    # roofline: the dominant time step of the plan (SURVEY 8(d) accounting:
-    # the step's minimum bytes per node plus the strip surcharge, over the
-    # summed average durations of the step's kernels)
+    # roofline: the dominant time step of the plan, priced at the step's
+    # minimum bytes per padded node (each array of one time step read and
+    # written once) plus the CPML strip surcharge, over the summed average
+    # durations of the step's kernels
     pts_per_launch = padded / sz["groups"]
     strip_per_launch = STRIP_BYTES * strip_nodes(w) / sz["groups"]
     ptag = tag + ("_fused" if (nd == 2 and sz["fused"]) else "")
