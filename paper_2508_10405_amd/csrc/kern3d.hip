@@ -6,9 +6,10 @@
 // y-derivative comes from a queue of the eight neighbouring planes kept in
 // registers, so every value of the staged field is read from memory once per
 // march.  The halos hold exactly the cells a derivative reads (three on one
-// side, four on the other).  A tile as tall as the padded z extent (256 rows
-// in blocks of 1024 threads, one column per four waves) has no z-halo at all:
-// its halo rows lie outside the grid and stay zero.  Arrays read at a node's
+// side, four on the other).  A tile of 128 rows or more that spans the whole
+// padded z extent (256 rows in blocks of 1024 threads, one column per four
+// waves, on a grid of up to 256 padded rows) has no z-halo at all: its halo
+// rows lie outside the grid and stay zero.  Arrays read at a node's
 // upper neighbours (sb for dt b_a, dlnrho for the density source) are read
 // once per plane: the next plane's values are carried in registers and the
 // z+1 and x+1 neighbours come from LDS, so that no line of them is fetched
