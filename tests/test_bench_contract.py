@@ -6,7 +6,7 @@
   benchmark reads, and the algorithmic bytes it reports per kernel never
   exceed what the counters measured for that kernel (the byte model counts
   every array once; the counters add halo re-reads, partial lines and the
-  absorbing strips).
+  absorbing strips), and were taken on the kernel sources in the tree.
 """
 import os
 import subprocess
@@ -45,3 +45,13 @@ def test_profiles_bound_the_byte_model(tag, ndim):
     for kernel, alg in bench.BYTES_PER_PT[ndim].items():
         measured = float(vals[f"traffic_bytes_per_point.{kernel}"])
         assert alg <= measured <= 2.0 * alg, (kernel, alg, measured)
+
+
+@pytest.mark.parametrize("tag,ndim", [("config2_batched", 2), ("config5_batched", 3)])
+def test_profiles_describe_the_committed_kernels(tag, ndim):
+    """The committed counter profile was taken on the kernel sources in the
+    tree (the benchmark reports its traffic only then): a kernel edit must
+    come with a new profile."""
+    import bench
+    assert _profile_values(tag)["kernel_source_sha"] == bench.kernel_source_hash(ndim)
+    assert bench.read_traffic(tag, "adj_a", 1.0, ndim) is not None
