@@ -139,7 +139,7 @@ struct lsrtm_ctx {
     float* ckscales = nullptr;     // [nseg][nshot][1+ndim]
     float* partial = nullptr;      // reduction workspace of set_model
     float* ckpart = nullptr;       // checkpoint max-abs partials [G][1+ndim][nblk]
-    int nblk = 64;
+    int nblk = 64;                 // blocks per field of the max-abs pass (set by the plan)
     double* dpart = nullptr;
     double* dscal = nullptr;       // device scalar results
     int* d_flag = nullptr;
@@ -1119,6 +1119,10 @@ lsrtm_status plan(lsrtm_ctx* c) {
     const long long ck_total = c->ck_group ? (long long)(c->nseg - 1) * G * max_ck : (long long)(c->nseg - 1) * ck_per_shot_sum;
     CHK(dalloc(c, reinterpret_cast<void**>(&c->ckbuf), (size_t)std::max(1LL, ck_total), true));
     CHK(dalloc_t(c, &c->ckscales, (size_t)c->nseg * nshot * (1 + nd), true));
+    // blocks per field of a snapshot's max-abs pass: enough for the pass to
+    // fill the GPU (about 8192 blocks) also when a group holds one or a few
+    // large shots; the maximum is exact in any order, so this changes no scale
+    c->nblk = (int)std::min<long long>(1024, std::max<long long>(64, (8192 + (1 + nd) * G - 1) / ((1 + nd) * G)));
     CHK(dalloc_t(c, &c->ckpart, (size_t)G * (1 + nd) * c->nblk, true));
     CHK(dalloc_t(c, &c->acc64, 2 * c->gpts, true));
     CHK(dalloc_t(c, &c->src_amp, (size_t)nshot * nt, true));
