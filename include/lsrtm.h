@@ -135,8 +135,11 @@ enum {
 };
 
 /* Create a context for one grid on one HIP stream (hipStream_t, may be 0).
- * Validates the grid (positive sizes, ndim in {2,3}); *out receives the
- * context.  Allocates nothing on the device yet. */
+ * Validates the grid; *out receives the context (NULL on failure).
+ * Allocates nothing on the device yet and makes no HIP call.  Errors: EINVAL
+ * (NULL grid or out, ndim not 2 or 3, a size < 1 or a spacing <= 0, ny != 1
+ * in 2D, npml < 0, nt < 1, dt <= 0, pml_R outside (0, 1) with npml > 0,
+ * ckpt_every < 0 or an unknown ckpt_dtype). */
 lsrtm_status lsrtm_create(const lsrtm_grid* grid, void* hip_stream, lsrtm_ctx** out);
 
 /* Background model in logs (section 2: lnkappa = lnIp + lnVp,
@@ -144,7 +147,8 @@ lsrtm_status lsrtm_create(const lsrtm_grid* grid, void* hip_stream, lsrtm_ctx** 
  * physical grid, copied by the library.  Checks that every value is finite
  * (LSRTM_ENONFINITE) and the CFL bound
  *   vmax * dt * sqrt(sum_a 1/h_a^2) * sum_k |c_k| < 1   (LSRTM_EUNSTABLE).
- * Invalidates stored checkpoints. */
+ * Invalidates stored checkpoints.  Errors: EINVAL (NULL), ENONFINITE,
+ * EUNSTABLE (the context then has no model), ENOMEM, EHIP. */
 lsrtm_status lsrtm_set_model(lsrtm_ctx* ctx, const float* lnvp, const float* lnip);
 
 /* Acquisition of nshot shots, each on its own window of the physical grid
@@ -165,7 +169,11 @@ lsrtm_status lsrtm_set_acquisition(lsrtm_ctx* ctx, int nshot, const int* win, co
                                    const int* rec_ptr, const int* rec, const float* wavelet);
 
 /* Background data d = R u0 (section 2, A(m0) u0 = f), DEVICE float [data].
- * Also stores the background checkpoints used by lsrtm_adjoint. */
+ * Also stores the background checkpoints used by lsrtm_adjoint.
+ * Errors of lsrtm_forward, lsrtm_born and lsrtm_adjoint: EINVAL (NULL ctx, a
+ * NULL model vector, a NULL data vector while there are data), ESTATE (no
+ * model or no acquisition), ENONFINITE (a stored background snapshot holds
+ * NaN or Inf; the checkpoints are then dropped), ENOMEM, EHIP. */
 lsrtm_status lsrtm_forward(lsrtm_ctx* ctx, float* d);
 
 /* Born data d = L dm (section 3).  dm: DEVICE float [2][nz*nx*ny] =
@@ -194,7 +202,10 @@ lsrtm_status lsrtm_cgnr(lsrtm_ctx* ctx, const float* d_obs, int niter, float* x,
  * lsrtm_cgnr_state: get = 1 copies the solver state out (r: data length,
  *   z and p: [2][nz*nx*ny], DEVICE), scal = HOST double[4] = (<z,z>,
  *   <r0,r0>, <r,r>, k); get = 0 loads such a state back, so that a stopped
- *   run resumes to the same iterates (x is the caller's vector). */
+ *   run resumes to the same iterates (x is the caller's vector).
+ * Errors: EINVAL (NULL ctx, x, state pointers, or d_obs while there are
+ * data), ESTATE (no model or acquisition; lsrtm_cgnr_iterate or a state
+ * export before lsrtm_cgnr_begin), ENONFINITE, ENOMEM, EHIP. */
 lsrtm_status lsrtm_cgnr_begin(lsrtm_ctx* ctx, const float* d_obs, float* x);
 lsrtm_status lsrtm_cgnr_iterate(lsrtm_ctx* ctx, float* x, double* misfit);
 lsrtm_status lsrtm_cgnr_state(lsrtm_ctx* ctx, int get, float* r, float* z, float* p, double* scal);
@@ -320,7 +331,9 @@ lsrtm_status lsrtm_wiener(lsrtm_ctx* ctx, const float* m_ref, const float* m_blu
 lsrtm_status lsrtm_dot(lsrtm_ctx* ctx, const float* a, const float* b, long long n, double* out);
 
 /* y <- y + alpha * x on DEVICE float vectors of length n, each element
- * computed in FP64 and rounded once. */
+ * computed in FP64 and rounded once (the iterate and residual updates of
+ * section 3's CGNR).  Errors: EINVAL (NULL ctx, n < 0, x or y NULL with
+ * n > 0), EHIP. */
 lsrtm_status lsrtm_axpy(lsrtm_ctx* ctx, double alpha, const float* x, float* y, long long n);
 
 /* Calibration, not a step of the method: the HBM streaming rate of a mix of
@@ -340,7 +353,11 @@ lsrtm_status lsrtm_axpy(lsrtm_ctx* ctx, double alpha, const float* x, float* y, 
 lsrtm_status lsrtm_stream_mix(lsrtm_ctx* ctx, float* buf, long long n, int nread, int nwrite, const int* grid,
                               double* ms);
 
-/* Set an LSRTM_OPT_* option. */
+/* Set an LSRTM_OPT_* option.  Counts lie in [0, 2^31 - 1] (-1 allowed for
+ * the tile ids), sizes in MB in [0, 2^30].  Options that change the launch
+ * groups or the memory plan re-plan at once when an acquisition is set.
+ * Errors: EINVAL (NULL ctx, unknown key, value out of range), and the
+ * errors of lsrtm_set_acquisition for a re-plan. */
 lsrtm_status lsrtm_set_option(lsrtm_ctx* ctx, int key, long long value);
 
 /* Autotuner: times the stencil kernels of a Born, replay and adjoint step
@@ -353,7 +370,9 @@ lsrtm_status lsrtm_set_option(lsrtm_ctx* ctx, int key, long long value);
  * launch, ms per time step, velocity-phase tile, adjoint-A tile).  With
  * LSRTM_TUNE_CACHE naming a file, results are read from and appended to it.
  * Invalidates stored checkpoints.  When no tile is set, the same tile tuning
- * (without group sizes and schedules) runs on the first pass by itself. */
+ * (without group sizes and schedules) runs on the first pass by itself.
+ * Errors: EINVAL (NULL ctx, nsteps < 1), ESTATE (no model or acquisition),
+ * ENOMEM, EHIP. */
 lsrtm_status lsrtm_autotune(lsrtm_ctx* ctx, int nsteps, int tune_groups, double* out);
 
 /* Sizes: out[0] = data length, out[1] = physical grid points (one image),
@@ -364,11 +383,13 @@ lsrtm_status lsrtm_autotune(lsrtm_ctx* ctx, int nsteps, int tune_groups, double*
  * tile id of the velocity phases / of the adjoint A phase (-1 = out[7]),
  * out[12] = segments per launch group held by the replay cache, out[13] =
  * pass graphs currently instantiated.
- * HOST long long [nout]; the first min(nout, 14) entries are written. */
+ * HOST long long [nout]; the first min(nout, 14) entries are written.
+ * Errors: EINVAL (NULL ctx or out). */
 lsrtm_status lsrtm_sizes(lsrtm_ctx* ctx, long long* out, int nout);
 
 /* Timing statistics of the last pass (HOST double [nout]); see
- * LSRTM_STAT_* for the layout.  Per-kernel times need LSRTM_OPT_TIMING. */
+ * LSRTM_STAT_* for the layout.  Per-kernel times need LSRTM_OPT_TIMING.
+ * Errors: EINVAL (NULL ctx or out). */
 enum {
     LSRTM_STAT_PASS_MS = 0,       /* wall time of the last pass (HIP events)        */
     LSRTM_STAT_KERNEL_MS = 1,     /* [1 + 2*k], [2 + 2*k]: total ms and launch count */
@@ -391,10 +412,11 @@ lsrtm_status lsrtm_stats(lsrtm_ctx* ctx, double* out, int nout);
  * nodes deep; deeper grids stack such tiles with a z-halo between them). */
 lsrtm_status lsrtm_tile_shape(int ndim, int tile_id, int* out);
 
-/* Release every device resource of the context. */
+/* Wait for the context's stream and release every device resource of the
+ * context; NULL is ignored. */
 void lsrtm_destroy(lsrtm_ctx* ctx);
 
-/* Static description of a status code. */
+/* Static description of a status code ("unknown status" for other values). */
 const char* lsrtm_strerror(int status);
 
 /* Description of the last error on this context ("" if none). */

@@ -22,6 +22,7 @@
 // in place of the background steps of those segments.
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1598,11 +1599,14 @@ void lsrtm_destroy(lsrtm_ctx* c) {
     delete c;
 }
 
+// sizes in MB beyond any device (2^30 MB = 1 PiB), so that MB * 2^20 never overflows
+constexpr long long kMaxMB = 1LL << 30;
+
 lsrtm_status lsrtm_set_option(lsrtm_ctx* c, int key, long long v) {
     if (!c) return LSRTM_EINVAL;
     switch (key) {
     case LSRTM_OPT_SHOTS_PER_LAUNCH:
-        if (v < 0) FAIL(c, LSRTM_EINVAL, "shots per launch must be >= 0");
+        if (v < 0 || v > INT_MAX) FAIL(c, LSRTM_EINVAL, "shots per launch must be in [0, %d]", INT_MAX);
         if (c->opt_spl == (int)v) return LSRTM_OK;
         c->opt_spl = (int)v;
         if (c->have_acq) return plan(c);   // rebuild the launch groups
@@ -1619,7 +1623,7 @@ lsrtm_status lsrtm_set_option(lsrtm_ctx* c, int key, long long v) {
     case LSRTM_OPT_GRAPH: c->opt_graph = v != 0; return LSRTM_OK;
     case LSRTM_OPT_TIMING: c->opt_timing = v != 0; return LSRTM_OK;
     case LSRTM_OPT_MEM_BUDGET_MB:
-        if (v < 0) FAIL(c, LSRTM_EINVAL, "memory budget must be >= 0");
+        if (v < 0 || v > kMaxMB) FAIL(c, LSRTM_EINVAL, "memory budget must be in [0, %lld] MB", kMaxMB);
         c->opt_budget_mb = v;
         return LSRTM_OK;
     case LSRTM_OPT_FUSED:
@@ -1637,11 +1641,11 @@ lsrtm_status lsrtm_set_option(lsrtm_ctx* c, int key, long long v) {
         return LSRTM_OK;
     }
     case LSRTM_OPT_GRAPH_CACHE:
-        if (v < 0) FAIL(c, LSRTM_EINVAL, "graph cache size must be >= 0");
+        if (v < 0 || v > INT_MAX) FAIL(c, LSRTM_EINVAL, "graph cache size must be in [0, %d]", INT_MAX);
         c->graph_cap = (size_t)v;
         return LSRTM_OK;
     case LSRTM_OPT_REPLAY_CACHE_MB:
-        if (v < 0) FAIL(c, LSRTM_EINVAL, "replay cache size must be >= 0");
+        if (v < 0 || v > kMaxMB) FAIL(c, LSRTM_EINVAL, "replay cache size must be in [0, %lld] MB", kMaxMB);
         if (c->opt_rcache_mb == v) return LSRTM_OK;
         c->opt_rcache_mb = v;
         if (c->have_acq) return plan(c);

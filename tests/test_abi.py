@@ -92,6 +92,15 @@ def test_calls_before_setup_report_state():
     assert L.lsrtm_set_option(h, lsrtm.OPT_REPLAY_CACHE_MB, 512) == lsrtm.OK   # planned with the acquisition
     assert L.lsrtm_set_option(h, lsrtm.OPT_GRAPH_CACHE, -1) == lsrtm.EINVAL
     assert L.lsrtm_set_option(h, lsrtm.OPT_GRAPH_CACHE, 4) == lsrtm.OK
+    # counts that would wrap in an int and sizes whose byte count would
+    # overflow are argument errors, not silently different plans
+    assert L.lsrtm_set_option(h, lsrtm.OPT_SHOTS_PER_LAUNCH, 2 ** 31) == lsrtm.EINVAL
+    assert L.lsrtm_set_option(h, lsrtm.OPT_GRAPH_CACHE, 2 ** 32) == lsrtm.EINVAL
+    assert L.lsrtm_set_option(h, lsrtm.OPT_MEM_BUDGET_MB, 2 ** 44) == lsrtm.EINVAL
+    assert L.lsrtm_set_option(h, lsrtm.OPT_REPLAY_CACHE_MB, 2 ** 44) == lsrtm.EINVAL
+    assert L.lsrtm_set_option(h, lsrtm.OPT_MEM_BUDGET_MB, 2 ** 30) == lsrtm.OK
+    assert L.lsrtm_set_option(h, lsrtm.OPT_MEM_BUDGET_MB, 0) == lsrtm.OK
+    assert L.lsrtm_set_option(h, lsrtm.OPT_SHOTS_PER_LAUNCH, 0) == lsrtm.OK
     # the streaming calibration refuses unsupported mixes and grids that do
     # not match n before it touches the device
     ms = ctypes.c_double()
