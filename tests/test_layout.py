@@ -77,3 +77,20 @@ def test_no_committed_file_refers_to_the_working_folder():
         if re.search(r"(^|[^A-Za-z0-9])" + WORK + "/", text):
             hits.append(f)
     assert not hits, hits
+
+
+def test_oracle_does_not_touch_the_gpu_path():
+    """The oracle imports only numpy, scipy and the standard library: nothing
+    of the package (not even the input generators, which the tests hand it)
+    and no compiled library."""
+    odir = os.path.join(ROOT, "oracle")
+    for f in os.listdir(odir):
+        if not f.endswith(".py"):
+            continue
+        path = os.path.join(odir, f)
+        _, imps = _imports(path)
+        roots = {m.split(".")[0] for m, _ in imps}
+        assert roots <= {"__future__", "dataclasses", "fractions", "typing", "numpy", "scipy", "math",
+                         "functools", "itertools", "collections", ""}, (f, roots)
+        text = open(path).read()
+        assert "paper_2508_10405_amd" not in text and "liblsrtm" not in text and "ctypes" not in text, f
