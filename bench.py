@@ -28,7 +28,9 @@ HBM peak; kernel durations from one further, untimed iteration in which the
 runtime stamps the start and end of every 16th step's kernels), the streaming
 rate of a 1 GiB axpy and of the stencils' array mixes without the stencil
 (lsrtm_stream_mix: in order, and for a 3D workload in the 3D tiles' order),
-the plain per-shot CG-iteration time (one launch per
+the Born and migration passes timed on their own (grid-point updates per
+second, and field updates per second counting the two wavefields of every
+time step), the plain per-shot CG-iteration time (one launch per
 shot, measured on a sample of shots and scaled by the shot count), the
 uneven-aperture workload batched against shot by shot, and the FP64 oracle
 timed on the host cores on a bounded sample.
@@ -451,9 +453,15 @@ def main():
         torch.cuda.synchronize()
         tb2 = time.perf_counter()
         del dtmp, itmp
+        # per pass: grid-point updates, and field updates counting the two
+        # wavefields every time step of the pass stands for (Born: background
+        # and scattered; migration: background history and adjoint field,
+        # whether the history is replayed or read from the replay cache)
         passes = {"born_s": tb1 - tb0, "migration_s": tb2 - tb1,
                   "born_gpts": padded * w.nt / (tb1 - tb0) / 1e9,
-                  "migration_gpts": padded * w.nt / (tb2 - tb1) / 1e9}
+                  "migration_gpts": padded * w.nt / (tb2 - tb1) / 1e9,
+                  "born_field_updates_gps": 2 * padded * w.nt / (tb1 - tb0) / 1e9,
+                  "migration_field_updates_gps": 2 * padded * w.nt / (tb2 - tb1) / 1e9}
         log(f"[bench] passes {passes}")
 
     pcg = None
