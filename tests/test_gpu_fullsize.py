@@ -29,6 +29,9 @@ M = 300   # sampled time steps
 # keeps a replay cache, which the sampled tests below leave off and
 # test_config2_replay_cache_plan turns on
 BENCH_2D = dict(shots_per_launch=32, tile=1)
+# the uneven-aperture workload's launch configuration in bench.py: groups of
+# up to 52 shots (5 groups), 32 x 16 tiles
+BENCH_3 = dict(shots_per_launch=52, tile=1)
 
 
 @pytest.fixture(scope="module")
@@ -84,8 +87,10 @@ def test_config2_full_size_sampled(torch):
 
 
 def test_config3_full_size_sampled(torch):
+    import bench
+    assert bench.CONFIG3_SHOTS_PER_LAUNCH == BENCH_3["shots_per_launch"]
     w = synth.config3()
-    _check_sampled(torch, w, [5], **BENCH_2D)
+    _check_sampled(torch, w, [5], **BENCH_3)
 
 
 def test_config5_full_size_dot(torch):
