@@ -208,8 +208,9 @@ def form2_block(lsrtm, synth, torch, dev, steps=2, plain_shots=16):
     """Uneven-aperture workload (256 shots, windows of 200..737 x 240 nodes,
     nt = 4000): CG-iteration time of the batched form (launch groups of up to
     52 shots over one tile table -- 5 groups, about as many padded nodes per
-    launch as config 2's groups of 30, and measured 3 % faster than groups of
-    32 or 64 --, every pass replayed from its HIP graph,
+    launch as config 2's groups of 30; about 1.5 % faster than groups of 32 on
+    average over interleaved runs, whose spread is 2-4 %, and faster than
+    groups of 64 --, every pass replayed from its HIP graph,
     checkpoints and replay cache reused) against the plain form (one launch
     per shot, no graphs, no replay cache) on the same GPU.  The plain form is
     timed on the first plain_shots shots and scaled by padded nodes (per-shot
